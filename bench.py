@@ -1,0 +1,142 @@
+"""Benchmark: incremental hashed-TSDF meshing on one MI355X.
+
+A step is one pass of the hot path over the depth-fusion workload: the
+100-frame synthetic room sequence (640x480 depth, 8 mm voxels, 2^20 hash
+slots) fused and meshed frame by frame (integrate + extract + gc) into a
+volume that starts empty.  The reported value is fused frames per second
+over the timed steps, with every depth frame already resident in HBM.
+
+Prints one JSON line.  The single-sphere extraction (blocks meshed per
+second) and the CPU oracle timed on a bounded sample of the same sequence
+are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def render_frames(seq, ks, workers):
+    if workers <= 1:
+        return [seq.frame(k) for k in ks]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(seq.frame, ks))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method has no multi-GPU path here "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import scenes
+    from paper_1803_03949_amd import Volume
+
+    assert torch.cuda.is_available(), "no GPU"
+    dev = torch.device("cuda:0")
+    seq = scenes.room_sequence(seed=2, n_frames=args.frames, voxel_m=0.008)
+    t0 = time.time()
+    frames = render_frames(seq, range(args.frames), args.workers)
+    print(f"[bench] rendered {args.frames} frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    depth = torch.from_numpy(np.stack(frames)).to(dev)
+    poses = [p for p in seq.poses]
+    vol = Volume(seq.voxel_m, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23,
+                 max_tri_cubes=1 << 23, device=dev)
+
+    def step():
+        vol.reset()
+        for k in range(args.frames):
+            vol.integrate(depth[k], scenes.K, poses[k], seq.min_depth, seq.max_depth)
+            vol.extract()
+            vol.gc()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = vol.status()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1000.0 * dt / args.steps
+    fps = args.frames * args.steps / dt
+    print(f"[bench] {fps:.1f} frames/s, blocks {st['blocks']}, status {st}", file=sys.stderr, flush=True)
+
+    # single-sphere extraction: 512 blocks, one extraction from a reset state
+    sv = scenes.sphere_volume(seed=1)
+    coords, d, w = sv.blocks()
+    cdev = [torch.from_numpy(a).to(dev) for a in (coords, d, w)]
+    svol = Volume(sv.voxel_m, hash_log2=16, max_blocks=1024, max_vertices=1 << 20,
+                  max_tri_cubes=1 << 20, device=dev)
+    times = []
+    for rep in range(110):
+        svol.reset()
+        svol.import_blocks(*cdev)
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record()
+        svol.extract(scope_all=True)
+        s1.record()
+        torch.cuda.synchronize()
+        if rep >= 10:
+            times.append(s0.elapsed_time(s1))
+    sphere_ms = float(np.median(times))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n = 3
+        o = oracle.OracleVolume(seq.voxel_m)
+        c0 = time.perf_counter()
+        for k in range(n):
+            o.integrate(frames[k], scenes.K, poses[k], seq.min_depth, seq.max_depth)
+            o.extract()
+            o.gc()
+        cdt = time.perf_counter() - c0
+        cpu = {"value": n / cdt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n} frames of the same sequence, integrate+extract+gc, single thread"}
+
+    out = {
+        "metric": "fused frames/s @8mm (integrate + extract + gc per frame)",
+        "value": fps,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"room sequence, {args.frames} frames 640x480, 8 mm voxels, "
+                               "8^3 blocks, 2^20 hash slots, integrate+extract+gc per frame"},
+        "sphere_blocks_per_s": 512 / (sphere_ms / 1000.0),
+        "sphere_extract_ms": sphere_ms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

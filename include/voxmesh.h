@@ -1,0 +1,238 @@
+/*
+ * voxmesh -- incremental mesh extraction over a spatially hashed TSDF volume
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Dong, Shi, Tang, Wang, Zha, "An Efficient Volumetric Mesh
+ * Representation for Real-time Scene Reconstruction using Spatial Hashing",
+ * arXiv 1803.03949.  Each depth frame is fused into 8x8x8-voxel blocks held in
+ * a hash table (Sec. III, Eqs. 1-2); every cube gets its marching-cubes type
+ * (Sec. V-B); each vertex lives exactly once, on the lattice edge that owns
+ * it (Sec. IV, V-C); triangles reference vertices and reference counts drive
+ * garbage collection (Sec. V-D, V-E); the Hamming-distance refinement snaps
+ * disturbed cubes to regular types (Sec. V-F, Eqs. 3-5).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Return value: VM_OK (0) or a negative VM_ERR_* code.
+ * - Every call is enqueued on the given HIP stream and returns without
+ *   waiting, except vm_download_mesh, vm_get_status and the vm_export_*
+ *   calls, which synchronise that stream.  A volume must be used from one
+ *   stream at a time.
+ * - The caller owns all device memory.  The library never allocates device
+ *   memory: a volume lives in one caller buffer of vm_volume_bytes() bytes,
+ *   and every input/output array is a caller pointer.  Pointers documented
+ *   as "device" must be device (or managed) memory; "host" pointers are read
+ *   before the call returns.
+ * - Capacity overflow inside a kernel (hash table, block pool, vertex pool,
+ *   triangle pool) sets a sticky error bit in the volume; the next
+ *   synchronising call returns the matching VM_ERR_* code.  The volume is
+ *   not usable for meshing after such an error (reset it).
+ * - Lattice: voxel g (integer 3-vector) sits at world position g * voxel_m;
+ *   its TSDF (voxel units) and weight live at that corner.  Block b holds the
+ *   voxels 8b .. 8b+7 per axis, stored in local order x + 8y + 64z.  Block
+ *   coordinates must lie in [-8192, 8191].
+ * - Edge keys (vm_download_mesh, vm_export_vertices): the edge that starts
+ *   at voxel g = 8b + l and runs one step along axis a (0 x, 1 y, 2 z) has
+ *   key ((b.x+8192) << 39) | ((b.y+8192) << 25) | ((b.z+8192) << 11)
+ *     | ((l.x + 8 l.y + 64 l.z) << 2) | a.
+ * - Floating point: FP32 everywhere on the hot path, without contraction of
+ *   products into fused multiply-adds and with correctly rounded division, so
+ *   fusion and cube signs are reproducible bit for bit.
+ */
+#ifndef VOXMESH_H
+#define VOXMESH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  VM_OK = 0,
+  VM_ERR_ARG = -1,             /* invalid argument or configuration */
+  VM_ERR_HASH_FULL = -2,       /* hash table probe sequence exhausted */
+  VM_ERR_BLOCK_POOL_FULL = -3, /* more blocks than max_blocks */
+  VM_ERR_VERTEX_POOL_FULL = -4,/* more live vertices than max_vertices */
+  VM_ERR_TRI_POOL_FULL = -5,   /* more triangle-holding cubes than max_tri_cubes */
+  VM_ERR_CAPACITY = -6,        /* caller output buffer too small */
+  VM_ERR_HIP = -7,             /* a HIP runtime call failed */
+  VM_ERR_RANGE = -8            /* a block coordinate outside [-8192, 8191] */
+};
+
+enum { VM_SCOPE_DIRTY = 0, VM_SCOPE_ALL = 1 };
+
+/* Volume configuration.  Sizes are capacities of the caller buffer. */
+typedef struct vm_config {
+  float voxel_m;        /* cube edge length s in metres (e.g. 0.008) */
+  float trunc_vox;      /* truncation mu in voxel units (e.g. 4) */
+  float refine_eps_vox; /* refinement threshold epsilon, voxel units (Eq. 5) */
+  int32_t hash_log2;    /* hash table holds 2^hash_log2 slots, 10..28 */
+  int32_t max_blocks;   /* block pool capacity, 1 .. 2^21 */
+  int32_t max_vertices; /* vertex pool capacity, 1 .. 2^30 */
+  int32_t max_tri_cubes;/* cubes holding triangles at one time, 1 .. 2^30 */
+  int32_t hash_mode;    /* 0: mixing hash; 1: every key starts probing at
+                           slot 0 (long probe chains, for testing only) */
+} vm_config;
+
+/* Pinhole camera, pixel (u, v) at column u, row v; depth in metres. */
+typedef struct vm_intrinsics {
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float min_depth_m, max_depth_m; /* depth outside this range is invalid */
+} vm_intrinsics;
+
+/* Counters and the sticky error, as of the last completed call. */
+typedef struct vm_status {
+  int32_t error;            /* VM_OK or the first VM_ERR_* raised on device */
+  uint32_t error_bits;      /* bit k set: error code -(k+2) was raised */
+  int64_t blocks;           /* allocated blocks */
+  int64_t frame_blocks;     /* blocks collected by the last integrate/import */
+  int64_t pending_blocks;   /* blocks touched since the last extraction */
+  int64_t dirty_blocks;     /* blocks classified by the last extract/refine */
+  int64_t vertex_blocks;    /* blocks whose owned edges were recomputed */
+  int64_t changed_cubes;    /* cubes whose triangles changed */
+  int64_t vertex_slots;     /* vertex pool high-water mark */
+  int64_t free_vertex_slots;/* recycled vertex slots awaiting reuse */
+  int64_t tri_cube_slots;   /* triangle pool high-water mark (cubes) */
+  int64_t free_tri_cube_slots;
+  int64_t new_vertices;     /* vertices created by the last extract/refine */
+  int64_t updated_vertices; /* vertices whose position was rewritten */
+  int64_t freed_vertices;   /* vertices recycled by the last vm_gc */
+  int64_t refined_cubes;    /* cubes re-typed by the last vm_refine_mesh */
+} vm_status;
+
+typedef struct vm_volume vm_volume;
+
+/* Bytes of device memory a volume with this configuration needs.
+ * Returns VM_ERR_ARG for an invalid configuration. */
+int vm_volume_bytes(const vm_config* cfg, size_t* bytes);
+
+/* Create a volume inside the caller's device buffer dev_mem (at least
+ * vm_volume_bytes() bytes, 256-byte aligned) and clear it on `stream`.
+ * *out receives a host-side handle; the buffer must outlive it.  The
+ * volume starts empty (Sec. III: blocks are allocated only where depth
+ * observations land). */
+int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes,
+                     hipStream_t stream, vm_volume** out);
+
+/* Release the host handle.  Never frees dev_mem. */
+int vm_destroy_volume(vm_volume* vol);
+
+/* Empty the volume again (blocks, mesh, errors), on `stream`. */
+int vm_reset_volume(vm_volume* vol, hipStream_t stream);
+
+/* Block collection (Eq. 1) and TSDF fusion (Eq. 2) of one depth frame.
+ * depth: device, height*width FP32 metres, row-major, 0 or non-finite =
+ * invalid.  cam_to_world: host, 4x4 row-major FP32 sensor-to-world pose
+ * [R | t] (Sec. V-A); it is inverted on the host in FP64.
+ * For every valid pixel, all blocks in the integer box spanned by the two
+ * points of its ray at camera depth D - mu and D + mu are allocated; then
+ * every voxel of those blocks that projects (nearest pixel) onto a valid
+ * pixel with (D - z)/s >= -mu takes the running average with weight 1 of
+ * min((D - z)/s, mu).  A pixel whose box leaves the block coordinate range
+ * is skipped.  The depth buffer must stay valid until the stream reaches
+ * this call. */
+int vm_integrate_depth(vm_volume* vol, const float* depth,
+                       const vm_intrinsics* K, const float cam_to_world[16],
+                       hipStream_t stream);
+
+/* Allocate the given blocks (if new) and overwrite their TSDF and weights:
+ * for volumes sampled from an analytic field rather than fused.
+ * coords: device, n*3 int32 block coordinates (distinct); tsdf, weight:
+ * device, n*512 FP32 in local voxel order.  The blocks count as touched for
+ * the next VM_SCOPE_DIRTY extraction. */
+int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
+                     const float* weight, int64_t n, hipStream_t stream);
+
+/* Mesh extraction (Sec. V-B..V-D).  VM_SCOPE_DIRTY: the blocks touched since
+ * the last extraction plus their allocated neighbours at offsets in
+ * {-1,0}^3 (all cubes with a corner in a touched block); VM_SCOPE_ALL: every
+ * block.  For each such cube: type t with bit k = [d(c_k) < 0] over the
+ * corners in cyclic order (0,0,0) (1,0,0) (1,1,0) (0,1,0) (0,0,1) (1,0,1)
+ * (1,1,1) (0,1,1); a cube with a corner in a missing block or with weight 0
+ * has type 0.  The previous type is kept (t_{i-1}).  Cubes whose type
+ * changed get new triangles; every edge used by some cube's triangles holds
+ * one vertex at t = d(g)/(d(g) - d(g+a)) (0.5 if equal), created on first
+ * use and updated when its end points move; each vertex's reference count
+ * is the number of triangles using it. */
+int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream);
+
+/* Hamming-distance refinement (Sec. V-F, Eqs. 3-5) of the cubes of the last
+ * extraction: a valid cube with type t and previous type p is set to the
+ * regular type r_j when d_H(t,p) <= 3, d_H(t,r_j) <= 3 and |d(c_k)| < eps
+ * on every corner where t and r_j differ; among several qualifying r_j,
+ * p is kept if it is one of them, else the nearest, ties in the order
+ * 11001100, 00110011, 10011001, 01100110, 11110000, 00001111 (bit 7 first).
+ * Triangles and vertices follow; vertex positions extrapolate where the
+ * regular type puts a vertex on an edge without a sign change. */
+int vm_refine_mesh(vm_volume* vol, hipStream_t stream);
+
+/* Garbage collection (Sec. V-E): recycle every vertex no triangle uses. */
+int vm_gc(vm_volume* vol, hipStream_t stream);
+
+/* Compact the mesh into caller buffers (device): verts[vcap][3] FP32
+ * metres (vertex on edge (g, a): g*s with (g_a + t)*s on axis a),
+ * edge_keys[vcap] (may be NULL), tris[tcap][3] int32 indices into verts,
+ * oriented counter-clockwise seen from the outside (d > 0).  *nv, *nt
+ * (host) receive the mesh size; returns VM_ERR_CAPACITY (after filling
+ * what fits) when it exceeds vcap or tcap.  Synchronises `stream`.  Also
+ * records which output row each vertex went to, for vm_extract_backward. */
+int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys,
+                     int32_t* tris, int64_t vcap, int64_t tcap, int64_t* nv,
+                     int64_t* nt, hipStream_t stream);
+
+/* Gradient of a loss through the vertex positions of the last download to
+ * the fused TSDF, with connectivity fixed: for the vertex on edge (g, a),
+ * dv/dt = s * e_a, dt/dd(g) = -d(g+a)/(d(g)-d(g+a))^2 and
+ * dt/dd(g+a) = d(g)/(d(g)-d(g+a))^2 (0 where the two are equal).
+ * dL_dverts: device, nv*3 FP32 (rows as downloaded); dL_dtsdf: device,
+ * blocks*512 FP32 in block pool order (see vm_export_blocks), overwritten.
+ * Each voxel gathers its at most six incident edges in a fixed order, so
+ * the result is deterministic. */
+int vm_extract_backward(vm_volume* vol, const float* dL_dverts,
+                        float* dL_dtsdf, hipStream_t stream);
+
+/* Gradient through the last vm_integrate_depth (Eq. 2) with its branches
+ * fixed: for a voxel that frame updated, dd1/dd0 = W0/(W0+1) and, unless
+ * the truncation at +mu was active, dd1/dD(p) = (1/s)/(W0+1) for its pixel
+ * p; other voxels pass dL/dd1 through unchanged.  depth: the same device
+ * frame; dL_dtsdf1, dL_dtsdf0: device, blocks*512 FP32 pool order;
+ * dL_ddepth: device height*width FP32, overwritten (accumulated with
+ * atomics, so its summation order is not fixed). */
+int vm_integrate_backward(vm_volume* vol, const float* depth,
+                          const float* dL_dtsdf1, float* dL_dtsdf0,
+                          float* dL_ddepth, hipStream_t stream);
+
+/* Synchronise `stream` and report counters and the sticky device error. */
+int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream);
+
+/* Inspection (synchronising).  vm_export_blocks writes, for the first
+ * min(cap, blocks) pool entries, their coordinates (coords: host int32
+ * cap*3) and, when non-NULL, device arrays tsdf/weight (cap*512 FP32) and
+ * type_prev/type_cur (cap*512 uint8).  *n receives the block count. */
+int vm_export_blocks(vm_volume* vol, int32_t* coords, float* tsdf,
+                     float* weight, uint8_t* type_prev, uint8_t* type_cur,
+                     int64_t cap, int64_t* n, hipStream_t stream);
+
+/* Raw vertex pool (device outputs, cap entries each): edge key, t and
+ * reference count (-1 marks a recycled slot).  *n receives the pool's
+ * high-water mark. */
+int vm_export_vertices(vm_volume* vol, uint64_t* edge_keys, float* t,
+                       int32_t* refcount, int64_t cap, int64_t* n,
+                       hipStream_t stream);
+
+/* Block lists (host int32 cap*3 coordinates): which = 0 blocks collected by
+ * the last integrate/import, 1 blocks classified by the last
+ * extraction/refinement, 2 blocks touched since the last extraction. */
+int vm_export_block_list(vm_volume* vol, int which, int32_t* coords,
+                         int64_t cap, int64_t* n, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOXMESH_H */

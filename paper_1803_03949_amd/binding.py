@@ -1,0 +1,271 @@
+"""ctypes binding of the voxmesh C-ABI (include/voxmesh.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream, every step of the method runs in the library's HIP kernels.  The
+library is loaded from this package directory; if it is missing, or no GPU
+is visible, the calls raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvoxmesh.so")
+
+VM_OK = 0
+VM_SCOPE_DIRTY, VM_SCOPE_ALL = 0, 1
+ERRORS = {
+    -1: "VM_ERR_ARG", -2: "VM_ERR_HASH_FULL", -3: "VM_ERR_BLOCK_POOL_FULL",
+    -4: "VM_ERR_VERTEX_POOL_FULL", -5: "VM_ERR_TRI_POOL_FULL", -6: "VM_ERR_CAPACITY",
+    -7: "VM_ERR_HIP", -8: "VM_ERR_RANGE",
+}
+
+
+class VmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {ERRORS.get(code, code)}")
+
+
+class vm_config(ctypes.Structure):
+    _fields_ = [("voxel_m", ctypes.c_float), ("trunc_vox", ctypes.c_float),
+                ("refine_eps_vox", ctypes.c_float), ("hash_log2", ctypes.c_int32),
+                ("max_blocks", ctypes.c_int32), ("max_vertices", ctypes.c_int32),
+                ("max_tri_cubes", ctypes.c_int32), ("hash_mode", ctypes.c_int32)]
+
+
+class vm_intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("min_depth_m", ctypes.c_float), ("max_depth_m", ctypes.c_float)]
+
+
+_STATUS_FIELDS = ["blocks", "frame_blocks", "pending_blocks", "dirty_blocks", "vertex_blocks",
+                  "changed_cubes", "vertex_slots", "free_vertex_slots", "tri_cube_slots",
+                  "free_tri_cube_slots", "new_vertices", "updated_vertices", "freed_vertices",
+                  "refined_cubes"]
+
+
+class vm_status(ctypes.Structure):
+    _fields_ = [("error", ctypes.c_int32), ("error_bits", ctypes.c_uint32)] + \
+               [(n, ctypes.c_int64) for n in _STATUS_FIELDS]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"voxmesh HIP library not built: {LIB_PATH} "
+                               "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64 = ctypes.c_void_p, ctypes.c_int64
+        PI64 = ctypes.POINTER(ctypes.c_int64)
+        sigs = {
+            "vm_volume_bytes": [ctypes.POINTER(vm_config), ctypes.POINTER(ctypes.c_size_t)],
+            "vm_create_volume": [ctypes.POINTER(vm_config), P, ctypes.c_size_t, P,
+                                 ctypes.POINTER(ctypes.c_void_p)],
+            "vm_destroy_volume": [P],
+            "vm_reset_volume": [P, P],
+            "vm_integrate_depth": [P, P, ctypes.POINTER(vm_intrinsics), P, P],
+            "vm_import_blocks": [P, P, P, P, I64, P],
+            "vm_extract_mesh": [P, ctypes.c_int, P],
+            "vm_refine_mesh": [P, P],
+            "vm_gc": [P, P],
+            "vm_download_mesh": [P, P, P, P, I64, I64, PI64, PI64, P],
+            "vm_extract_backward": [P, P, P, P],
+            "vm_integrate_backward": [P, P, P, P, P, P],
+            "vm_get_status": [P, ctypes.POINTER(vm_status), P],
+            "vm_export_blocks": [P, P, P, P, P, P, I64, PI64, P],
+            "vm_export_vertices": [P, P, P, P, I64, PI64, P],
+            "vm_export_block_list": [P, ctypes.c_int, P, I64, PI64, P],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, where: str, allow=()):
+    if code != VM_OK and code not in allow:
+        raise VmError(code, where)
+    return code
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Volume:
+    """One hashed TSDF volume with its mesh, in a torch-owned device buffer."""
+
+    def __init__(self, voxel_m: float, trunc_vox: float = 4.0, refine_eps_vox: float = 0.5,
+                 hash_log2: int = 20, max_blocks: int = 1 << 16, max_vertices: int = 1 << 22,
+                 max_tri_cubes: int = 1 << 22, hash_mode: int = 0, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("voxmesh needs a ROCm GPU (torch.cuda.is_available() is False)")
+        L = lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.cfg = vm_config(voxel_m, trunc_vox, refine_eps_vox, hash_log2, max_blocks,
+                             max_vertices, max_tri_cubes, hash_mode)
+        nbytes = ctypes.c_size_t()
+        _check(L.vm_volume_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)), "vm_volume_bytes")
+        self.nbytes = nbytes.value
+        with torch.cuda.device(self.device):
+            self.mem = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.mem.data_ptr()) % 256
+            self._base = self.mem.data_ptr() + off
+            h = ctypes.c_void_p()
+            _check(L.vm_create_volume(ctypes.byref(self.cfg), self._base, self.nbytes,
+                                      _stream(), ctypes.byref(h)), "vm_create_volume")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.vm_destroy_volume(h)
+            self.h = None
+
+    # -- method steps ---------------------------------------------------------
+    def integrate(self, depth: torch.Tensor, K, cam_to_world, min_depth=0.0, max_depth=1e30,
+                  stream=None):
+        assert depth.is_cuda and depth.dtype == torch.float32 and depth.is_contiguous()
+        H, W = depth.shape
+        fx, fy, cx, cy = K
+        intr = vm_intrinsics(fx, fy, cx, cy, W, H, min_depth, max_depth)
+        T = np.ascontiguousarray(cam_to_world, dtype=np.float32).reshape(16)
+        _check(lib().vm_integrate_depth(self.h, _ptr(depth), ctypes.byref(intr), _ptr(T),
+                                        _stream(stream)), "vm_integrate_depth")
+
+    def import_blocks(self, coords: torch.Tensor, tsdf: torch.Tensor, weight: torch.Tensor,
+                      stream=None):
+        n = coords.shape[0]
+        assert coords.is_cuda and coords.dtype == torch.int32 and coords.is_contiguous()
+        assert tsdf.dtype == torch.float32 and weight.dtype == torch.float32
+        assert tsdf.numel() == 512 * n and weight.numel() == 512 * n
+        _check(lib().vm_import_blocks(self.h, _ptr(coords), _ptr(tsdf), _ptr(weight), n,
+                                      _stream(stream)), "vm_import_blocks")
+
+    def extract(self, scope_all: bool = False, stream=None):
+        _check(lib().vm_extract_mesh(self.h, VM_SCOPE_ALL if scope_all else VM_SCOPE_DIRTY,
+                                     _stream(stream)), "vm_extract_mesh")
+
+    def refine(self, stream=None):
+        _check(lib().vm_refine_mesh(self.h, _stream(stream)), "vm_refine_mesh")
+
+    def gc(self, stream=None):
+        _check(lib().vm_gc(self.h, _stream(stream)), "vm_gc")
+
+    def reset(self, stream=None):
+        _check(lib().vm_reset_volume(self.h, _stream(stream)), "vm_reset_volume")
+
+    # -- results --------------------------------------------------------------
+    def status(self, stream=None, check: bool = True) -> dict:
+        st = vm_status()
+        r = lib().vm_get_status(self.h, ctypes.byref(st), _stream(stream))
+        out = {n: getattr(st, n) for n in ["error", "error_bits"] + _STATUS_FIELDS}
+        if check:
+            _check(r, "vm_get_status")
+        return out
+
+    def download(self, with_keys: bool = True, stream=None):
+        """(verts (V,3) f32 metres, tris (F,3) i32, keys (V,) int64 or None)."""
+        st = self.status(stream)
+        vcap = max(1, st["vertex_slots"])
+        tcap = max(1, 5 * st["tri_cube_slots"])
+        verts = torch.empty((vcap, 3), dtype=torch.float32, device=self.device)
+        tris = torch.empty((tcap, 3), dtype=torch.int32, device=self.device)
+        keys = torch.empty(vcap, dtype=torch.int64, device=self.device) if with_keys else None
+        nv, nt = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().vm_download_mesh(self.h, _ptr(verts), _ptr(keys), _ptr(tris), vcap, tcap,
+                                      ctypes.byref(nv), ctypes.byref(nt), _stream(stream)),
+               "vm_download_mesh")
+        verts, tris = verts[: nv.value], tris[: nt.value]
+        return verts, tris, (keys[: nv.value] if keys is not None else None)
+
+    def export_blocks(self, stream=None):
+        n = ctypes.c_int64()
+        _check(lib().vm_export_blocks(self.h, None, None, None, None, None, 0, ctypes.byref(n),
+                                      _stream(stream)), "vm_export_blocks")
+        m = n.value
+        coords = np.zeros((max(m, 1), 3), np.int32)
+        d = torch.empty((max(m, 1), 512), dtype=torch.float32, device=self.device)
+        w = torch.empty_like(d)
+        tp = torch.empty((max(m, 1), 512), dtype=torch.uint8, device=self.device)
+        tc = torch.empty_like(tp)
+        _check(lib().vm_export_blocks(self.h, _ptr(coords), _ptr(d), _ptr(w), _ptr(tp), _ptr(tc),
+                                      m, ctypes.byref(n), _stream(stream)), "vm_export_blocks")
+        return dict(coords=coords[:m], d=d[:m], w=w[:m], prev=tp[:m], cur=tc[:m])
+
+    def export_vertices(self, stream=None):
+        """Raw vertex pool: keys (int64, -1 for free slots), t, refcount."""
+        n = ctypes.c_int64()
+        _check(lib().vm_export_vertices(self.h, None, None, None, 0, ctypes.byref(n),
+                                        _stream(stream)), "vm_export_vertices")
+        m = n.value
+        keys = torch.empty(max(m, 1), dtype=torch.int64, device=self.device)
+        t = torch.empty(max(m, 1), dtype=torch.float32, device=self.device)
+        ref = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        _check(lib().vm_export_vertices(self.h, _ptr(keys), _ptr(t), _ptr(ref), m,
+                                        ctypes.byref(n), _stream(stream)), "vm_export_vertices")
+        return dict(keys=keys[:m], t=t[:m], ref=ref[:m])
+
+    def block_list(self, which: str, stream=None) -> np.ndarray:
+        code = {"frame": 0, "dirty": 1, "pending": 2}[which]
+        n = ctypes.c_int64()
+        _check(lib().vm_export_block_list(self.h, code, None, 0, ctypes.byref(n), _stream(stream)),
+               "vm_export_block_list")
+        out = np.zeros((max(n.value, 1), 3), np.int32)
+        _check(lib().vm_export_block_list(self.h, code, _ptr(out), n.value, ctypes.byref(n),
+                                          _stream(stream)), "vm_export_block_list")
+        return out[: n.value]
+
+    # -- gradients -------------------------------------------------------------
+    def extract_backward(self, dL_dverts: torch.Tensor, out: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+        """dL/d(fused TSDF) in block pool order, (blocks, 512)."""
+        nb = self.status(stream)["blocks"]
+        if out is None:
+            out = torch.empty((max(nb, 1), 512), dtype=torch.float32, device=self.device)
+        dL = dL_dverts.contiguous()
+        _check(lib().vm_extract_backward(self.h, _ptr(dL), _ptr(out), _stream(stream)),
+               "vm_extract_backward")
+        return out[:nb]
+
+    def integrate_backward(self, depth: torch.Tensor, dL_dtsdf1: torch.Tensor, stream=None):
+        """(dL/d(TSDF before the last fusion), dL/d(depth)) for the last frame."""
+        g1 = dL_dtsdf1.contiguous()
+        g0 = torch.empty_like(g1)
+        gD = torch.empty_like(depth)
+        _check(lib().vm_integrate_backward(self.h, _ptr(depth), _ptr(g1), _ptr(g0), _ptr(gD),
+                                           _stream(stream)), "vm_integrate_backward")
+        return g0, gD
+
+
+def key_to_edge(keys) -> np.ndarray:
+    """Edge keys -> (n, 4) int (gx, gy, gz, axis)."""
+    k = np.asarray(keys.cpu() if isinstance(keys, torch.Tensor) else keys).astype(np.int64)
+    axis = k & 3
+    local = (k >> 2) & 511
+    bz = ((k >> 11) & 0x3FFF) - 8192
+    by = ((k >> 25) & 0x3FFF) - 8192
+    bx = ((k >> 39) & 0x3FFF) - 8192
+    return np.stack([8 * bx + (local & 7), 8 * by + ((local >> 3) & 7), 8 * bz + (local >> 6),
+                     axis], axis=1)

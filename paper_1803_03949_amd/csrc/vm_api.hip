@@ -1,0 +1,457 @@
+// C-ABI of the voxmesh library: argument checks, workspace layout, pose
+// inversion and the kernel sequence of each call.  No device allocation:
+// every byte lives in the caller's buffer.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "voxmesh.h"
+#include "vm_internal.h"
+
+namespace vm {
+void build_mc_tables(uint8_t* tri, uint8_t* uses);
+}
+
+using namespace vm;
+
+struct vm_volume {
+  vm_config cfg;
+  char* mem;
+  size_t bytes;
+  VolDev dev;
+  uint32_t frame;   // last frame number handed to the device
+  uint32_t epoch;   // extraction epoch (pending-list stamps)
+  uint32_t pass;    // dirty / vertex-list stamps
+  FrameParams last_fp;
+  bool have_fp;
+  int grid_blocks;  // workgroups of per-block kernels
+  int grid_items;   // workgroups of per-item kernels
+};
+
+namespace {
+
+uint8_t g_tri[256 * 16];
+uint8_t g_uses[256 * 12];
+std::once_flag g_tables_once;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool config_ok(const vm_config* c) {
+  return c && c->voxel_m > 0.f && isfinite(c->voxel_m) && c->trunc_vox > 0.f &&
+         isfinite(c->trunc_vox) && c->refine_eps_vox >= 0.f && c->hash_log2 >= 10 &&
+         c->hash_log2 <= 28 && c->max_blocks >= 1 && c->max_blocks <= kMaxBlocks &&
+         c->max_vertices >= 1 && c->max_vertices <= (1 << 30) && c->max_tri_cubes >= 1 &&
+         c->max_tri_cubes <= (1 << 30) && (c->hash_mode == 0 || c->hash_mode == 1);
+}
+
+// Carve the workspace; with base == nullptr only the size is computed.
+size_t carve(const vm_config& c, char* base, VolDev* v) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  const size_t H = (size_t)1 << c.hash_log2, B = (size_t)c.max_blocks,
+               V = (size_t)c.max_vertices, T = (size_t)c.max_tri_cubes;
+  const size_t changed = T * 2 < 4096 ? 4096 : (T * 2 > 0x7FFFFFFF ? 0x7FFFFFFF : T * 2);
+  const size_t scan = (V > T ? V : T) / 1024 + 2;
+  v->cnt = (Counters*)take(sizeof(Counters));
+  v->tri_table = (const uint8_t*)take(256 * 16);
+  v->edge_uses = (const uint8_t*)take(256 * 12);
+  v->slots = (unsigned long long*)take(8 * H);
+  v->slot_stamp = (uint32_t*)take(4 * H);
+  v->block_key = (uint64_t*)take(8 * B);
+  v->nbr = (int32_t*)take(4 * 27 * B);
+  v->d = (float*)take(4 * kVox * B);
+  v->w = (float*)take(4 * kVox * B);
+  v->tprev = (uint8_t*)take(kVox * B);
+  v->tcur = (uint8_t*)take(kVox * B);
+  v->evtx = (int32_t*)take(4 * 3 * kVox * B);
+  v->cchunk = (int32_t*)take(4 * kVox * B);
+  v->st_pending = (uint32_t*)take(4 * B);
+  v->st_dirty = (uint32_t*)take(4 * B);
+  v->st_vtx = (uint32_t*)take(4 * B);
+  v->st_frame = (uint32_t*)take(4 * B);
+  v->frame_slots = (uint32_t*)take(4 * B);
+  v->frame_src = (uint32_t*)take(4 * B);
+  v->frame_list = (uint32_t*)take(4 * B);
+  v->pending = (uint32_t*)take(4 * B);
+  v->dirty = (uint32_t*)take(4 * B);
+  v->vblocks = (uint32_t*)take(4 * B);
+  v->changed = (uint32_t*)take(4 * changed);
+  v->vt = (float*)take(4 * V);
+  v->vowner = (uint32_t*)take(4 * V);
+  v->vref = (int32_t*)take(4 * V);
+  v->vring = (uint32_t*)take(4 * V);
+  v->vdl = (int32_t*)take(4 * V);
+  v->chunks = (uint32_t*)take(4 * kChunkWords * T);
+  v->cring = (uint32_t*)take(4 * T);
+  v->scan = (uint32_t*)take(4 * scan);
+  v->scan_cap = (uint32_t)scan;
+  v->max_blocks = (uint32_t)B;
+  v->max_vertices = (uint32_t)V;
+  v->max_chunks = (uint32_t)T;
+  v->max_changed = (uint32_t)changed;
+  v->hash_mask = (uint32_t)(H - 1);
+  v->hash_mode = c.hash_mode;
+  return off;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? VM_OK : VM_ERR_HIP; }
+
+int launched() { return hip_status(hipGetLastError()); }
+
+int clear_state(vm_volume* vol, hipStream_t stream) {
+  const VolDev& v = vol->dev;
+  const size_t H = (size_t)v.hash_mask + 1, B = v.max_blocks;
+  hipError_t e = hipSuccess;
+  auto set = [&](void* p, int val, size_t n) {
+    if (e == hipSuccess) e = hipMemsetAsync(p, val, n, stream);
+  };
+  set(v.cnt, 0, sizeof(Counters));
+  set(v.slots, 0xFF, 8 * H);
+  set(v.slot_stamp, 0, 4 * H);
+  set(v.st_pending, 0, 4 * B);
+  set(v.st_dirty, 0, 4 * B);
+  set(v.st_vtx, 0, 4 * B);
+  set(v.st_frame, 0, 4 * B);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void*)v.tri_table, g_tri, sizeof(g_tri), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void*)v.edge_uses, g_uses, sizeof(g_uses), hipMemcpyHostToDevice, stream);
+  // host copies of the tables must stay valid until the copies ran
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  vol->frame = 0;
+  vol->epoch = 1;
+  vol->pass = 0;
+  vol->have_fp = false;
+  return hip_status(e);
+}
+
+int read_counters(vm_volume* vol, Counters* c, hipStream_t stream) {
+  hipError_t e = hipMemcpyAsync(c, vol->dev.cnt, sizeof(Counters), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return hip_status(e);
+}
+
+int error_code(uint32_t bits) {
+  for (int k = 0; k < 16; ++k)
+    if (bits & (1u << k)) return -(k + 2);
+  return VM_OK;
+}
+
+void counters_op(vm_volume* vol, int op, hipStream_t s) {
+  hipLaunchKernelGGL(k_counters, dim3(1), dim3(1), 0, s, vol->dev, op, 0u);
+}
+
+}  // namespace
+
+extern "C" {
+
+int vm_volume_bytes(const vm_config* cfg, size_t* bytes) {
+  if (!config_ok(cfg) || !bytes) return VM_ERR_ARG;
+  VolDev v;
+  *bytes = carve(*cfg, nullptr, &v);
+  return VM_OK;
+}
+
+int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes, hipStream_t stream,
+                     vm_volume** out) {
+  if (!config_ok(cfg) || !dev_mem || !out || ((uintptr_t)dev_mem & 255)) return VM_ERR_ARG;
+  VolDev probe;
+  if (bytes < carve(*cfg, nullptr, &probe)) return VM_ERR_ARG;
+  std::call_once(g_tables_once, [] { build_mc_tables(g_tri, g_uses); });
+  vm_volume* vol = new (std::nothrow) vm_volume();
+  if (!vol) return VM_ERR_ARG;
+  vol->cfg = *cfg;
+  vol->mem = (char*)dev_mem;
+  vol->bytes = bytes;
+  VolDev& v = vol->dev;
+  carve(*cfg, vol->mem, &v);
+  v.s = cfg->voxel_m;
+  v.inv_s = (float)(1.0 / (double)cfg->voxel_m);
+  v.inv_block = (float)(1.0 / (8.0 * (double)cfg->voxel_m));
+  v.mu_m = (float)((double)cfg->trunc_vox * (double)cfg->voxel_m);
+  v.mu_v = cfg->trunc_vox;
+  v.eps = cfg->refine_eps_vox;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0) {
+    delete vol;
+    return VM_ERR_HIP;
+  }
+  vol->grid_blocks = cus * 4;
+  vol->grid_items = cus * 8;
+  int r = clear_state(vol, stream);
+  if (r != VM_OK) {
+    delete vol;
+    return r;
+  }
+  *out = vol;
+  return VM_OK;
+}
+
+int vm_destroy_volume(vm_volume* vol) {
+  if (!vol) return VM_ERR_ARG;
+  delete vol;
+  return VM_OK;
+}
+
+int vm_reset_volume(vm_volume* vol, hipStream_t stream) {
+  if (!vol) return VM_ERR_ARG;
+  return clear_state(vol, stream);
+}
+
+int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* K,
+                       const float cam_to_world[16], hipStream_t stream) {
+  if (!vol || !depth || !K || !cam_to_world || K->width <= 0 || K->height <= 0 ||
+      (int64_t)K->width * K->height > (1 << 28) || !(K->fx != 0.f) || !(K->fy != 0.f))
+    return VM_ERR_ARG;
+  FrameParams fp;
+  const float* T = cam_to_world;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) {
+      fp.Rcw[3 * i + j] = T[4 * i + j];
+      fp.Rwc[3 * j + i] = T[4 * i + j];
+    }
+    fp.tcw[i] = T[4 * i + 3];
+  }
+  // world -> sensor translation: -R^T t in FP64, rounded once
+  for (int i = 0; i < 3; ++i) {
+    double acc = (double)fp.Rcw[0 * 3 + i] * (double)fp.tcw[0];
+    acc = acc + (double)fp.Rcw[1 * 3 + i] * (double)fp.tcw[1];
+    acc = acc + (double)fp.Rcw[2 * 3 + i] * (double)fp.tcw[2];
+    fp.twc[i] = (float)(-acc);
+  }
+  fp.fx = K->fx, fp.fy = K->fy, fp.cx = K->cx, fp.cy = K->cy;
+  fp.dmin = K->min_depth_m, fp.dmax = K->max_depth_m;
+  fp.W = K->width, fp.H = K->height;
+  fp.frame = ++vol->frame;
+  const VolDev& v = vol->dev;
+  const int npix = K->width * K->height;
+  counters_op(vol, VM_OP_BEGIN_FRAME, stream);
+  hipLaunchKernelGGL(k_collect, dim3((npix + 255) / 256), dim3(256), 0, stream, v, fp, depth);
+  hipLaunchKernelGGL(k_assign, dim3(vol->grid_items), dim3(256), 0, stream, v, vol->epoch);
+  hipLaunchKernelGGL(k_link, dim3(vol->grid_items), dim3(256), 0, stream, v);
+  hipLaunchKernelGGL(k_fuse, dim3(vol->grid_blocks), dim3(512), 0, stream, v, fp, depth);
+  counters_op(vol, VM_OP_END_FRAME, stream);
+  vol->last_fp = fp;
+  vol->have_fp = true;
+  return launched();
+}
+
+int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
+                     const float* weight, int64_t n, hipStream_t stream) {
+  if (!vol || n < 0 || n > (int64_t)vol->dev.max_blocks || (n > 0 && (!coords || !tsdf || !weight)))
+    return VM_ERR_ARG;
+  if (n == 0) return VM_OK;
+  const VolDev& v = vol->dev;
+  const uint32_t frame = ++vol->frame;
+  counters_op(vol, VM_OP_BEGIN_FRAME, stream);
+  hipLaunchKernelGGL(k_import_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, v,
+                     coords, (uint32_t)n, frame);
+  hipLaunchKernelGGL(k_assign, dim3(vol->grid_items), dim3(256), 0, stream, v, vol->epoch);
+  hipLaunchKernelGGL(k_link, dim3(vol->grid_items), dim3(256), 0, stream, v);
+  hipLaunchKernelGGL(k_import_copy, dim3(vol->grid_blocks), dim3(512), 0, stream, v, tsdf, weight,
+                     frame);
+  counters_op(vol, VM_OP_END_FRAME, stream);
+  vol->have_fp = false;
+  return launched();
+}
+
+int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
+  if (!vol || (scope != VM_SCOPE_DIRTY && scope != VM_SCOPE_ALL)) return VM_ERR_ARG;
+  const VolDev& v = vol->dev;
+  const uint32_t pass = ++vol->pass;
+  counters_op(vol, VM_OP_BEGIN_EXTRACT, stream);
+  if (scope == VM_SCOPE_ALL)
+    hipLaunchKernelGGL(k_dirty_all, dim3(vol->grid_items), dim3(256), 0, stream, v, pass);
+  else
+    hipLaunchKernelGGL(k_dirty, dim3(vol->grid_items), dim3(256), 0, stream, v, pass);
+  counters_op(vol, VM_OP_END_PENDING, stream);
+  ++vol->epoch;
+  hipLaunchKernelGGL(k_classify, dim3(vol->grid_blocks), dim3(512), 0, stream, v, pass, 0);
+  hipLaunchKernelGGL(k_vertices, dim3(vol->grid_blocks), dim3(512), 0, stream, v);
+  counters_op(vol, VM_OP_FIN_VERTICES, stream);
+  hipLaunchKernelGGL(k_triangles, dim3(vol->grid_items), dim3(256), 0, stream, v);
+  counters_op(vol, VM_OP_FIN_TRIANGLES, stream);
+  return launched();
+}
+
+int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
+  if (!vol) return VM_ERR_ARG;
+  const VolDev& v = vol->dev;
+  const uint32_t pass = ++vol->pass;
+  counters_op(vol, VM_OP_BEGIN_REFINE, stream);
+  hipLaunchKernelGGL(k_classify, dim3(vol->grid_blocks), dim3(512), 0, stream, v, pass, 1);
+  hipLaunchKernelGGL(k_vertices, dim3(vol->grid_blocks), dim3(512), 0, stream, v);
+  counters_op(vol, VM_OP_FIN_VERTICES, stream);
+  hipLaunchKernelGGL(k_triangles, dim3(vol->grid_items), dim3(256), 0, stream, v);
+  counters_op(vol, VM_OP_FIN_TRIANGLES, stream);
+  return launched();
+}
+
+int vm_gc(vm_volume* vol, hipStream_t stream) {
+  if (!vol) return VM_ERR_ARG;
+  counters_op(vol, VM_OP_BEGIN_GC, stream);
+  hipLaunchKernelGGL(k_gc, dim3(vol->grid_items), dim3(256), 0, stream, vol->dev);
+  counters_op(vol, VM_OP_FIN_GC, stream);
+  return launched();
+}
+
+int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys, int32_t* tris,
+                     int64_t vcap, int64_t tcap, int64_t* nv, int64_t* nt, hipStream_t stream) {
+  if (!vol || !nv || !nt || vcap < 0 || tcap < 0 || (vcap > 0 && !verts) || (tcap > 0 && !tris))
+    return VM_ERR_ARG;
+  Counters c;
+  int r = read_counters(vol, &c, stream);
+  if (r != VM_OK) return r;
+  const VolDev& v = vol->dev;
+  const uint32_t pv = c.vtx_hwm / 1024 + 1, pt = c.chk_hwm / 1024 + 1;
+  const uint32_t vc = (uint32_t)(vcap > 0xFFFFFFFFll ? 0xFFFFFFFFll : vcap);
+  const uint32_t tc = (uint32_t)(tcap > 0xFFFFFFFFll ? 0xFFFFFFFFll : tcap);
+  hipLaunchKernelGGL(k_dl_count, dim3(pv), dim3(256), 0, stream, v, 0);
+  hipLaunchKernelGGL(k_dl_scan, dim3(1), dim3(1024), 0, stream, v, 0, pv);
+  hipLaunchKernelGGL(k_dl_write_vertices, dim3(pv), dim3(256), 0, stream, v, verts, edge_keys, vc);
+  hipLaunchKernelGGL(k_dl_count, dim3(pt), dim3(256), 0, stream, v, 1);
+  hipLaunchKernelGGL(k_dl_scan, dim3(1), dim3(1024), 0, stream, v, 1, pt);
+  hipLaunchKernelGGL(k_dl_write_triangles, dim3(pt), dim3(256), 0, stream, v, tris, tc);
+  r = launched();
+  if (r != VM_OK) return r;
+  r = read_counters(vol, &c, stream);
+  if (r != VM_OK) return r;
+  *nv = c.dl_nv;
+  *nt = c.dl_nt;
+  if (c.error) return error_code(c.error);
+  if ((int64_t)c.dl_nv > vcap || (int64_t)c.dl_nt > tcap) return VM_ERR_CAPACITY;
+  return VM_OK;
+}
+
+int vm_extract_backward(vm_volume* vol, const float* dL_dverts, float* dL_dtsdf,
+                        hipStream_t stream) {
+  if (!vol || !dL_dtsdf) return VM_ERR_ARG;
+  hipLaunchKernelGGL(k_bwd_tsdf, dim3(vol->grid_blocks), dim3(512), 0, stream, vol->dev,
+                     dL_dverts, dL_dtsdf);
+  return launched();
+}
+
+int vm_integrate_backward(vm_volume* vol, const float* depth, const float* dL_dtsdf1,
+                          float* dL_dtsdf0, float* dL_ddepth, hipStream_t stream) {
+  if (!vol || !depth || !dL_dtsdf1 || !dL_dtsdf0 || !dL_ddepth || !vol->have_fp) return VM_ERR_ARG;
+  const FrameParams& fp = vol->last_fp;
+  hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, stream, dL_ddepth,
+                     (uint64_t)fp.W * (uint64_t)fp.H);
+  hipLaunchKernelGGL(k_bwd_fusion, dim3(vol->grid_blocks), dim3(512), 0, stream, vol->dev, fp,
+                     depth, dL_dtsdf1, dL_dtsdf0, dL_ddepth);
+  return launched();
+}
+
+int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
+  if (!vol || !out) return VM_ERR_ARG;
+  Counters c;
+  int r = read_counters(vol, &c, stream);
+  if (r != VM_OK) return r;
+  const uint32_t B = vol->dev.max_blocks;
+  memset(out, 0, sizeof(*out));
+  out->error = error_code(c.error);
+  out->error_bits = c.error;
+  out->blocks = c.n_blocks < B ? c.n_blocks : B;
+  out->frame_blocks = c.last_frame_list;
+  out->pending_blocks = c.n_pending;
+  out->dirty_blocks = c.n_dirty;
+  out->vertex_blocks = c.n_vblocks;
+  out->changed_cubes = c.n_changed;
+  out->vertex_slots = c.vtx_hwm;
+  out->free_vertex_slots = c.vtx_tail - c.vtx_head;
+  out->tri_cube_slots = c.chk_hwm;
+  out->free_tri_cube_slots = c.chk_tail - c.chk_head;
+  out->new_vertices = c.st_new_vtx;
+  out->updated_vertices = c.st_upd_vtx;
+  out->freed_vertices = c.st_freed;
+  out->refined_cubes = c.st_refined;
+  return out->error;
+}
+
+int vm_export_blocks(vm_volume* vol, int32_t* coords, float* tsdf, float* weight,
+                     uint8_t* type_prev, uint8_t* type_cur, int64_t cap, int64_t* n,
+                     hipStream_t stream) {
+  if (!vol || !n || cap < 0 || (cap > 0 && !coords)) return VM_ERR_ARG;
+  Counters c;
+  int r = read_counters(vol, &c, stream);
+  if (r != VM_OK) return r;
+  const VolDev& v = vol->dev;
+  const size_t nb = c.n_blocks < v.max_blocks ? c.n_blocks : v.max_blocks;
+  *n = (int64_t)nb;
+  const size_t m = (size_t)cap < nb ? (size_t)cap : nb;
+  if (m == 0) return VM_OK;
+  std::vector<uint64_t> keys(m);
+  hipError_t e = hipMemcpyAsync(keys.data(), v.block_key, 8 * m, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && tsdf)
+    e = hipMemcpyAsync(tsdf, v.d, 4 * kVox * m, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && weight)
+    e = hipMemcpyAsync(weight, v.w, 4 * kVox * m, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && type_prev)
+    e = hipMemcpyAsync(type_prev, v.tprev, kVox * m, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && type_cur)
+    e = hipMemcpyAsync(type_cur, v.tcur, kVox * m, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return VM_ERR_HIP;
+  for (size_t i = 0; i < m; ++i) unpack_key(keys[i], coords[3 * i], coords[3 * i + 1], coords[3 * i + 2]);
+  return VM_OK;
+}
+
+int vm_export_vertices(vm_volume* vol, uint64_t* edge_keys, float* t, int32_t* refcount,
+                       int64_t cap, int64_t* n, hipStream_t stream) {
+  if (!vol || !n || cap < 0 || (cap > 0 && (!edge_keys || !t || !refcount))) return VM_ERR_ARG;
+  Counters c;
+  int r = read_counters(vol, &c, stream);
+  if (r != VM_OK) return r;
+  *n = c.vtx_hwm;
+  const uint32_t m = (uint32_t)((int64_t)c.vtx_hwm < cap ? c.vtx_hwm : cap);
+  if (m == 0) return VM_OK;
+  hipLaunchKernelGGL(k_export_vertices, dim3((m + 255) / 256), dim3(256), 0, stream, vol->dev,
+                     edge_keys, t, refcount, m);
+  r = launched();
+  if (r != VM_OK) return r;
+  return hip_status(hipStreamSynchronize(stream));
+}
+
+int vm_export_block_list(vm_volume* vol, int which, int32_t* coords, int64_t cap, int64_t* n,
+                         hipStream_t stream) {
+  if (!vol || !n || which < 0 || which > 2 || cap < 0 || (cap > 0 && !coords)) return VM_ERR_ARG;
+  Counters c;
+  int r = read_counters(vol, &c, stream);
+  if (r != VM_OK) return r;
+  const VolDev& v = vol->dev;
+  const uint32_t len = which == 0 ? c.last_frame_list : which == 1 ? c.n_dirty : c.n_pending;
+  const size_t cnt = len < v.max_blocks ? len : v.max_blocks;
+  *n = (int64_t)cnt;
+  const size_t m = (size_t)cap < cnt ? (size_t)cap : cnt;
+  if (m == 0) return VM_OK;
+  const uint32_t* list = which == 0 ? v.frame_list : which == 1 ? v.dirty : v.pending;
+  const size_t nb = c.n_blocks < v.max_blocks ? c.n_blocks : v.max_blocks;
+  std::vector<uint32_t> idx(m);
+  std::vector<uint64_t> keys(nb);
+  hipError_t e = hipMemcpyAsync(idx.data(), list, 4 * m, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && nb)
+    e = hipMemcpyAsync(keys.data(), v.block_key, 8 * nb, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return VM_ERR_HIP;
+  size_t k = 0;
+  for (size_t i = 0; i < m; ++i) {
+    if (idx[i] == kNone) continue;
+    const uint32_t b = idx[i] & ~kNewFlag;
+    if (b >= nb) continue;
+    unpack_key(keys[b], coords[3 * k], coords[3 * k + 1], coords[3 * k + 2]);
+    ++k;
+  }
+  *n = (int64_t)k;
+  return VM_OK;
+}
+
+}  // extern "C"

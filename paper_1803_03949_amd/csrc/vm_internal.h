@@ -1,0 +1,311 @@
+// Internal device-side layout and helpers of the voxmesh library (gfx950).
+//
+// Volume state lives in one caller-provided device buffer, carved into
+// structure-of-arrays regions (block-major, voxel-minor) so that the 512
+// lanes of a workgroup that handles one 8^3 block read and write contiguous
+// 2 KiB rows:
+//   hash      u64 slot = (42-bit block key << 22) | 22-bit pool index,
+//             all-ones = empty; open addressing with linear probing and
+//             64-bit compare-and-swap inserts, no deletion.
+//   blocks    key u64, 27-neighbour index table, TSDF f32[512],
+//             weight f32[512], previous/current cube type u8[512],
+//             edge->vertex slot i32[3][512] (the three edges every voxel
+//             owns), cube->triangle chunk i32[512], pass stamps.
+//   vertices  t f32, owner edge (index into the edge->vertex array) u32,
+//             reference count i32 (-1 = free), recycle ring, download row.
+//   triangles one 64-byte chunk per cube that holds triangles: owner cube,
+//             then up to 5 triangles as 3 vertex slots each.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace vm {
+
+constexpr int kVox = 512;                    // voxels (cubes) per block
+constexpr uint64_t kEmpty = ~0ull;           // empty hash slot
+constexpr uint32_t kIdxBits = 22;
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1;
+// Key inserted, pool index not yet assigned.  Never all-ones, so that no
+// occupied slot can read as empty.
+constexpr uint32_t kPending = kIdxMask - 1;
+constexpr int kKeyBias = 8192;               // block coords in [-8192, 8191]
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kNewFlag = 0x80000000u;   // frame-list entry: block is new
+constexpr int kChunkWords = 16;              // owner + 5 triangles * 3 slots
+constexpr int kMaxBlocks = 1 << 21;
+
+// Error bits (bit k <-> VM error code -(k+2)).
+constexpr uint32_t kErrHash = 1u << 0;
+constexpr uint32_t kErrBlocks = 1u << 1;
+constexpr uint32_t kErrVertices = 1u << 2;
+constexpr uint32_t kErrTris = 1u << 3;
+constexpr uint32_t kErrRange = 1u << 6;
+
+// Device counters (one 256-byte record at the start of the workspace).
+struct Counters {
+  uint32_t n_blocks;       // pool high-water mark (may exceed capacity on error)
+  uint32_t n_frame;        // entries of the current frame list
+  uint32_t n_pending;      // blocks touched since the last extraction
+  uint32_t n_dirty;        // blocks of the last extraction / refinement
+  uint32_t n_vblocks;      // blocks whose owned edges get recomputed
+  uint32_t n_changed;      // cubes whose triangles get rewritten
+  uint32_t vtx_hwm, vtx_head, vtx_tail, vtx_ticket, vtx_push;
+  uint32_t chk_hwm, chk_head, chk_tail, chk_ticket, chk_push;
+  uint32_t error;
+  uint32_t st_new_vtx, st_upd_vtx, st_freed, st_refined;
+  uint32_t dl_nv, dl_nt;
+  uint32_t last_frame_list;  // entries of the last frame list (for backward)
+  uint32_t pad[40];
+};
+static_assert(sizeof(Counters) == 256, "counter record size");
+
+// Everything a kernel needs, passed by value.
+struct VolDev {
+  float s, inv_s, inv_block, mu_m, mu_v, eps;
+  uint32_t hash_mask;
+  int32_t hash_mode;
+  uint32_t max_blocks, max_vertices, max_chunks, max_changed;
+  Counters* cnt;
+  const uint8_t* tri_table;   // [256][16]: count, then 15 cube-edge ids
+  const uint8_t* edge_uses;   // [256][12]: triangles of the type using the edge
+  unsigned long long* slots;  // [hash]
+  uint32_t* slot_stamp;       // [hash] frame that last collected the slot
+  uint64_t* block_key;        // [B]
+  int32_t* nbr;               // [B][27]
+  float* d;                   // [B][512]
+  float* w;                   // [B][512]
+  uint8_t* tprev;             // [B][512]
+  uint8_t* tcur;              // [B][512]
+  int32_t* evtx;              // [B][3][512]
+  int32_t* cchunk;            // [B][512]
+  uint32_t* st_pending;       // [B] extraction epoch that listed the block
+  uint32_t* st_dirty;         // [B] pass that listed the block as dirty
+  uint32_t* st_vtx;           // [B] pass that listed the block for vertices
+  uint32_t* st_frame;         // [B] last frame that fused the block
+  uint32_t* frame_slots;      // [B] hash slots collected by the frame
+  uint32_t* frame_src;        // [B] import: source row of each entry
+  uint32_t* frame_list;       // [B] pool index | kNewFlag, or kNone
+  uint32_t* pending;          // [B]
+  uint32_t* dirty;            // [B]
+  uint32_t* vblocks;          // [B]
+  uint32_t* changed;          // [max_changed] (block << 9) | cube
+  float* vt;                  // [V]
+  uint32_t* vowner;           // [V] index into evtx
+  int32_t* vref;              // [V]
+  uint32_t* vring;            // [V]
+  int32_t* vdl;               // [V] row in the last download, -1 if none
+  uint32_t* chunks;           // [T][16]
+  uint32_t* cring;            // [T]
+  uint32_t* scan;             // [scan_cap] download partial sums
+  uint32_t scan_cap;
+};
+
+// Per-frame camera parameters, passed by value.
+struct FrameParams {
+  float Rcw[9], tcw[3];   // sensor -> world
+  float Rwc[9], twc[3];   // world -> sensor (inverted on the host in FP64)
+  float fx, fy, cx, cy, dmin, dmax;
+  int32_t W, H;
+  uint32_t frame;
+};
+
+// ---- block keys ------------------------------------------------------------
+__host__ __device__ inline uint64_t pack_key(int x, int y, int z) {
+  return ((uint64_t)(uint32_t)(x + kKeyBias) << 28) | ((uint64_t)(uint32_t)(y + kKeyBias) << 14) |
+         (uint64_t)(uint32_t)(z + kKeyBias);
+}
+__host__ __device__ inline void unpack_key(uint64_t k, int& x, int& y, int& z) {
+  x = (int)((k >> 28) & 0x3FFF) - kKeyBias;
+  y = (int)((k >> 14) & 0x3FFF) - kKeyBias;
+  z = (int)(k & 0x3FFF) - kKeyBias;
+}
+__host__ __device__ inline bool key_in_range(int x, int y, int z) {
+  return x >= -kKeyBias && x < kKeyBias && y >= -kKeyBias && y < kKeyBias && z >= -kKeyBias &&
+         z < kKeyBias;
+}
+// Public edge key: block coords (14 bits each), local voxel (9), axis (2).
+__host__ __device__ inline uint64_t edge_key(uint64_t bkey, int local, int axis) {
+  return (bkey << 11) | ((uint64_t)local << 2) | (uint64_t)axis;
+}
+
+__device__ inline uint32_t hash_home(uint64_t key, uint32_t mask, int mode) {
+  if (mode == 1) return 0;
+  uint64_t h = key + 0x9E3779B97F4A7C15ull;  // splitmix64 finaliser
+  h = (h ^ (h >> 30)) * 0xBF58476D1CE4E5B9ull;
+  h = (h ^ (h >> 27)) * 0x94D049BB133111EBull;
+  h ^= h >> 31;
+  return (uint32_t)h & mask;
+}
+
+__device__ inline unsigned long long load_slot(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Find-or-insert a block key.  Returns the slot, or -1 when the table is
+// full.  *inserted tells whether this call created the entry (its pool index
+// is then kPending until the assignment pass).
+__device__ inline int64_t hash_insert(const VolDev& v, uint64_t key, bool* inserted) {
+  uint32_t h = hash_home(key, v.hash_mask, v.hash_mode);
+  *inserted = false;
+  for (uint32_t probe = 0; probe <= v.hash_mask; ++probe) {
+    uint32_t s = (h + probe) & v.hash_mask;
+    unsigned long long cur = load_slot(&v.slots[s]);
+    if (cur == kEmpty) {
+      unsigned long long want = ((unsigned long long)key << kIdxBits) | kPending;
+      unsigned long long prev = atomicCAS(&v.slots[s], (unsigned long long)kEmpty, want);
+      if (prev == kEmpty) {
+        *inserted = true;
+        return s;
+      }
+      cur = prev;
+    }
+    if ((cur >> kIdxBits) == key) return s;
+  }
+  return -1;
+}
+
+// Pool index of a key, or -1 if absent (or not yet assigned).
+__device__ inline int32_t hash_find(const VolDev& v, uint64_t key) {
+  uint32_t h = hash_home(key, v.hash_mask, v.hash_mode);
+  for (uint32_t probe = 0; probe <= v.hash_mask; ++probe) {
+    uint32_t s = (h + probe) & v.hash_mask;
+    unsigned long long cur = load_slot(&v.slots[s]);
+    if (cur == kEmpty) return -1;
+    if ((cur >> kIdxBits) == key) {
+      uint32_t idx = (uint32_t)(cur & kIdxMask);
+      return idx == kPending ? -1 : (int32_t)idx;
+    }
+  }
+  return -1;
+}
+
+// ---- neighbour directions --------------------------------------------------
+__host__ __device__ inline int nbr_dir(int dx, int dy, int dz) {
+  return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+}
+constexpr int kSelf = 13;
+
+// ---- wave helpers (wave64) -------------------------------------------------
+__device__ inline uint64_t lanes_below() {
+  return (1ull << __lane_id()) - 1ull;
+}
+
+// Wave-aggregated ticket: one atomic per wave.  Every active lane must call.
+__device__ inline uint32_t wave_ticket(uint32_t* counter, bool want) {
+  uint64_t m = __ballot(want);
+  uint32_t base = 0;
+  if (m) {
+    int leader = __ffsll((unsigned long long)m) - 1;
+    if ((int)__lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+  }
+  return base + (uint32_t)__popcll(m & lanes_below());
+}
+
+// Slot number of allocation ticket k from a recycle ring + bump pool, or
+// kNone when the pool is exhausted.  head/tail/hwm are fixed for the
+// duration of the allocating kernel.
+__device__ inline uint32_t ticket_slot(uint32_t k, const uint32_t* ring, uint32_t head,
+                                       uint32_t tail, uint32_t hwm, uint32_t cap) {
+  uint32_t avail = tail - head;
+  if (k < avail) return ring[(uint32_t)(((uint64_t)head + k) % cap)];
+  uint64_t s = (uint64_t)hwm + (k - avail);
+  return s < cap ? (uint32_t)s : kNone;
+}
+
+__device__ inline bool depth_ok(float D, float dmin, float dmax) {
+  return isfinite(D) && D > 0.f && D >= dmin && D <= dmax;
+}
+
+// One voxel's fusion sample (Eq. 2): projection to the nearest pixel and
+// the truncated projective distance.  Shared by the forward fusion and its
+// backward pass so both take identical branches.
+struct FuseSample {
+  bool upd;
+  bool clamped;
+  int pixel;
+  float dt;
+};
+
+__device__ inline FuseSample fuse_sample(const VolDev& v, const FrameParams& fp,
+                                         const float* __restrict__ depth, int gx, int gy,
+                                         int gz) {
+  FuseSample r{false, false, -1, 0.f};
+  float X = (float)gx * v.s, Y = (float)gy * v.s, Z = (float)gz * v.s;
+  float xc[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float a = fp.Rwc[3 * i] * X;
+    a = a + fp.Rwc[3 * i + 1] * Y;
+    a = a + fp.Rwc[3 * i + 2] * Z;
+    a = a + fp.twc[i];
+    xc[i] = a;
+  }
+  if (!(xc[2] > 0.f)) return r;
+  float u = fp.fx * (xc[0] / xc[2]) + fp.cx;
+  float vv = fp.fy * (xc[1] / xc[2]) + fp.cy;
+  float fu = floorf(u + 0.5f), fv = floorf(vv + 0.5f);
+  if (!(fu >= 0.f && fu < (float)fp.W && fv >= 0.f && fv < (float)fp.H)) return r;
+  int pix = (int)fv * fp.W + (int)fu;
+  float D = depth[pix];
+  if (!depth_ok(D, fp.dmin, fp.dmax)) return r;
+  float sdf = (D - xc[2]) * v.inv_s;
+  if (sdf < -v.mu_v) return r;
+  r.upd = true;
+  r.clamped = sdf >= v.mu_v;
+  r.pixel = pix;
+  r.dt = fminf(sdf, v.mu_v);
+  return r;
+}
+
+__device__ inline float edge_param(float da, float db) {
+  if (da == db) return 0.5f;
+  return da / (da - db);
+}
+
+}  // namespace vm
+
+// ---- kernels (defined in vm_kernels.hip, launched from vm_api.hip) ----------
+namespace vm {
+__global__ void k_counters(VolDev v, int op, uint32_t arg);
+__global__ void k_collect(VolDev v, FrameParams fp, const float* __restrict__ depth);
+__global__ void k_import_insert(VolDev v, const int32_t* __restrict__ coords, uint32_t n,
+                                uint32_t frame);
+__global__ void k_assign(VolDev v, uint32_t epoch);
+__global__ void k_link(VolDev v);
+__global__ void k_fuse(VolDev v, FrameParams fp, const float* __restrict__ depth);
+__global__ void k_import_copy(VolDev v, const float* __restrict__ tsdf,
+                              const float* __restrict__ weight, uint32_t frame);
+__global__ void k_dirty(VolDev v, uint32_t pass);
+__global__ void k_dirty_all(VolDev v, uint32_t pass);
+__global__ void k_classify(VolDev v, uint32_t pass, int refine);
+__global__ void k_vertices(VolDev v);
+__global__ void k_triangles(VolDev v);
+__global__ void k_gc(VolDev v);
+__global__ void k_dl_count(VolDev v, int what);
+__global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
+__global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,
+                                    uint64_t* __restrict__ keys, uint32_t vcap);
+__global__ void k_dl_write_triangles(VolDev v, int32_t* __restrict__ tris, uint32_t tcap);
+__global__ void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv, float* __restrict__ out);
+__global__ void k_bwd_fusion(VolDev v, FrameParams fp, const float* __restrict__ depth,
+                             const float* __restrict__ g1, float* __restrict__ g0,
+                             float* __restrict__ gD);
+__global__ void k_zero_f32(float* p, uint64_t n);
+__global__ void k_export_vertices(VolDev v, uint64_t* keys, float* t, int32_t* ref, uint32_t n);
+}  // namespace vm
+
+// Counter operations of k_counters.
+enum {
+  VM_OP_BEGIN_FRAME = 0,   // n_frame = 0
+  VM_OP_BEGIN_EXTRACT = 1, // n_dirty = n_vblocks = n_changed = 0, stats = 0
+  VM_OP_END_PENDING = 2,   // n_pending = 0
+  VM_OP_FIN_VERTICES = 3,  // consume vertex tickets
+  VM_OP_FIN_TRIANGLES = 4, // consume chunk tickets and pushes
+  VM_OP_BEGIN_GC = 5,
+  VM_OP_FIN_GC = 6,
+  VM_OP_BEGIN_REFINE = 7,  // n_vblocks = n_changed = 0
+  VM_OP_END_FRAME = 8      // last_frame_list = n_frame
+};
