@@ -105,6 +105,42 @@ typedef struct vm_status {
   int64_t refined_cubes;    /* cubes re-typed by the last vm_refine_mesh */
 } vm_status;
 
+/* Running totals of work done since the volume was created (kept across
+ * vm_reset_volume), read with vm_get_totals.  Benchmarks turn them into
+ * bytes moved per kernel. */
+enum {
+  VM_TOTAL_FRAMES = 0,          /* integrations and imports */
+  VM_TOTAL_FRAME_BLOCKS = 1,    /* blocks collected over all of them */
+  VM_TOTAL_DIRTY_BLOCKS = 2,    /* blocks classified (extract and refine) */
+  VM_TOTAL_VERTEX_BLOCKS = 3,   /* blocks whose owned edges were recomputed */
+  VM_TOTAL_NEW_VERTICES = 4,
+  VM_TOTAL_UPDATED_VERTICES = 5,
+  VM_TOTAL_CHANGED_CUBES = 6,   /* cubes whose triangles were rewritten */
+  VM_TOTAL_GC_SCANNED = 7,      /* vertex slots examined by vm_gc */
+  VM_TOTAL_FREED_VERTICES = 8,
+  VM_TOTAL_REFINED_CUBES = 9,
+  VM_TOTAL_COUNT = 10
+};
+
+/* Kernels, for vm_profile_read. */
+enum {
+  VM_K_COLLECT = 0,      /* block collection along pixel rays (Eq. 1) */
+  VM_K_ASSIGN = 1,       /* pool indices for new blocks */
+  VM_K_LINK = 2,         /* neighbour links of new blocks */
+  VM_K_FUSE = 3,         /* TSDF fusion (Eq. 2) */
+  VM_K_IMPORT = 4,       /* vm_import_blocks copy and insert */
+  VM_K_DIRTY = 5,        /* dirty block list */
+  VM_K_CLASSIFY = 6,     /* cube types */
+  VM_K_REFINE = 7,       /* cube types, refinement pass */
+  VM_K_VERTICES = 8,     /* edge-owned vertices and reference counts */
+  VM_K_TRIANGLES = 9,    /* triangle chunks of changed cubes */
+  VM_K_GC = 10,          /* garbage collection */
+  VM_K_DOWNLOAD = 11,    /* download compaction (all its kernels) */
+  VM_K_BACKWARD = 12,    /* backward passes */
+  VM_K_COUNTERS = 13,    /* single-lane bookkeeping kernels */
+  VM_K_COUNT = 14
+};
+
 typedef struct vm_volume vm_volume;
 
 /* Bytes of device memory a volume with this configuration needs.
@@ -207,6 +243,13 @@ int vm_integrate_backward(vm_volume* vol, const float* depth,
                           const float* dL_dtsdf1, float* dL_dtsdf0,
                           float* dL_ddepth, hipStream_t stream);
 
+/* Pool indices of blocks by coordinate, one hash lookup each (the O(1)
+ * access of Sec. IV).  coords: device n*3 int32; idx: device n int32,
+ * receives the block's row in pool order (as in vm_export_blocks and the
+ * gradient arrays) or -1 when the block is not allocated. */
+int vm_lookup_blocks(vm_volume* vol, const int32_t* coords, int32_t* idx, int64_t n,
+                     hipStream_t stream);
+
 /* Synchronise `stream` and report counters and the sticky device error. */
 int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream);
 
@@ -230,6 +273,19 @@ int vm_export_vertices(vm_volume* vol, uint64_t* edge_keys, float* t,
  * extraction/refinement, 2 blocks touched since the last extraction. */
 int vm_export_block_list(vm_volume* vol, int which, int32_t* coords,
                          int64_t cap, int64_t* n, hipStream_t stream);
+
+/* Running totals (see VM_TOTAL_*): out[n] receives the first n of them.
+ * Synchronises `stream`. */
+int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream);
+
+/* Kernel timing for benchmarks.  While enabled, each kernel launch of the
+ * volume is bracketed by two HIP events recorded on its stream (events are
+ * created by the library on first use and reused).  vm_profile(vol, 1)
+ * clears previous records; vm_profile_read synchronises the recorded
+ * events and writes, per VM_K_* kernel, the launch count and the summed
+ * event-to-event milliseconds (arrays of VM_K_COUNT entries, host). */
+int vm_profile(vm_volume* vol, int enable);
+int vm_profile_read(vm_volume* vol, int64_t* launches, double* ms);
 
 #ifdef __cplusplus
 }

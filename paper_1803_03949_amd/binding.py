@@ -49,6 +49,12 @@ _STATUS_FIELDS = ["blocks", "frame_blocks", "pending_blocks", "dirty_blocks", "v
                   "refined_cubes"]
 
 
+TOTALS = ["frames", "frame_blocks", "dirty_blocks", "vertex_blocks", "new_vertices",
+          "updated_vertices", "changed_cubes", "gc_scanned", "freed_vertices", "refined_cubes"]
+KERNELS = ["collect", "assign", "link", "fuse", "import", "dirty", "classify", "refine",
+           "vertices", "triangles", "gc", "download", "backward", "counters"]
+
+
 class vm_status(ctypes.Structure):
     _fields_ = [("error", ctypes.c_int32), ("error_bits", ctypes.c_uint32)] + \
                [(n, ctypes.c_int64) for n in _STATUS_FIELDS]
@@ -85,6 +91,10 @@ def lib() -> ctypes.CDLL:
             "vm_export_blocks": [P, P, P, P, P, P, I64, PI64, P],
             "vm_export_vertices": [P, P, P, P, I64, PI64, P],
             "vm_export_block_list": [P, ctypes.c_int, P, I64, PI64, P],
+            "vm_get_totals": [P, P, ctypes.c_int, P],
+            "vm_lookup_blocks": [P, P, P, I64, P],
+            "vm_profile": [P, ctypes.c_int],
+            "vm_profile_read": [P, P, P],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -236,6 +246,30 @@ class Volume:
         _check(lib().vm_export_block_list(self.h, code, _ptr(out), n.value, ctypes.byref(n),
                                           _stream(stream)), "vm_export_block_list")
         return out[: n.value]
+
+    def lookup(self, coords: torch.Tensor, stream=None) -> torch.Tensor:
+        """Pool rows of the blocks at `coords` (device (n,3) int32), -1 if absent."""
+        assert coords.is_cuda and coords.dtype == torch.int32 and coords.is_contiguous()
+        out = torch.empty(coords.shape[0], dtype=torch.int32, device=self.device)
+        _check(lib().vm_lookup_blocks(self.h, _ptr(coords), _ptr(out), coords.shape[0],
+                                      _stream(stream)), "vm_lookup_blocks")
+        return out
+
+    # -- measurement ------------------------------------------------------------
+    def totals(self, stream=None) -> dict:
+        out = np.zeros(len(TOTALS), np.int64)
+        _check(lib().vm_get_totals(self.h, _ptr(out), len(TOTALS), _stream(stream)), "vm_get_totals")
+        return dict(zip(TOTALS, (int(x) for x in out)))
+
+    def profile(self, enable: bool):
+        _check(lib().vm_profile(self.h, 1 if enable else 0), "vm_profile")
+
+    def profile_read(self) -> dict:
+        """{kernel: (launches, total ms)} of the recorded launches."""
+        n = np.zeros(len(KERNELS), np.int64)
+        ms = np.zeros(len(KERNELS), np.float64)
+        _check(lib().vm_profile_read(self.h, _ptr(n), _ptr(ms)), "vm_profile_read")
+        return {k: (int(a), float(b)) for k, a, b in zip(KERNELS, n, ms) if a}
 
     # -- gradients -------------------------------------------------------------
     def extract_backward(self, dL_dverts: torch.Tensor, out: torch.Tensor | None = None,

@@ -2,6 +2,7 @@
 // inversion and the kernel sequence of each call.  No device allocation:
 // every byte lives in the caller's buffer.
 #include <math.h>
+#include <stddef.h>
 #include <string.h>
 
 #include <mutex>
@@ -18,6 +19,10 @@ void build_mc_tables(uint8_t* tri, uint8_t* uses);
 using namespace vm;
 
 struct vm_volume {
+  struct ProfRec {
+    int kid;
+    hipEvent_t a, b;
+  };
   vm_config cfg;
   char* mem;
   size_t bytes;
@@ -29,6 +34,10 @@ struct vm_volume {
   bool have_fp;
   int grid_blocks;  // workgroups of per-block kernels
   int grid_items;   // workgroups of per-item kernels
+  int grid_waves;   // workgroups of wave-per-block kernels (4 waves each)
+  bool prof;        // bracket launches with events
+  std::vector<hipEvent_t> ev_free;
+  std::vector<ProfRec> recs;
 };
 
 namespace {
@@ -57,13 +66,15 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   };
   const size_t H = (size_t)1 << c.hash_log2, B = (size_t)c.max_blocks,
                V = (size_t)c.max_vertices, T = (size_t)c.max_tri_cubes;
-  const size_t changed = T * 2 < 4096 ? 4096 : (T * 2 > 0x7FFFFFFF ? 0x7FFFFFFF : T * 2);
   const size_t scan = (V > T ? V : T) / 1024 + 2;
   v->cnt = (Counters*)take(sizeof(Counters));
+  v->vseg = (Seg*)take(sizeof(Seg) * kSegs);
+  v->cseg = (Seg*)take(sizeof(Seg) * kSegs);
   v->tri_table = (const uint8_t*)take(256 * 16);
   v->edge_uses = (const uint8_t*)take(256 * 12);
   v->slots = (unsigned long long*)take(8 * H);
   v->slot_stamp = (uint32_t*)take(4 * H);
+  v->slot_src = (uint32_t*)take(4 * H);
   v->block_key = (uint64_t*)take(8 * B);
   v->nbr = (int32_t*)take(4 * 27 * B);
   v->d = (float*)take(4 * kVox * B);
@@ -72,17 +83,17 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->tcur = (uint8_t*)take(kVox * B);
   v->evtx = (int32_t*)take(4 * 3 * kVox * B);
   v->cchunk = (int32_t*)take(4 * kVox * B);
+  v->chg = (uint64_t*)take(8 * 8 * B);
   v->st_pending = (uint32_t*)take(4 * B);
   v->st_dirty = (uint32_t*)take(4 * B);
   v->st_vtx = (uint32_t*)take(4 * B);
   v->st_frame = (uint32_t*)take(4 * B);
-  v->frame_slots = (uint32_t*)take(4 * B);
-  v->frame_src = (uint32_t*)take(4 * B);
   v->frame_list = (uint32_t*)take(4 * B);
+  v->frame_src = (uint32_t*)take(4 * B);
   v->pending = (uint32_t*)take(4 * B);
   v->dirty = (uint32_t*)take(4 * B);
+  v->vcand = (uint32_t*)take(4 * 8 * B);
   v->vblocks = (uint32_t*)take(4 * B);
-  v->changed = (uint32_t*)take(4 * changed);
   v->vt = (float*)take(4 * V);
   v->vowner = (uint32_t*)take(4 * V);
   v->vref = (int32_t*)take(4 * V);
@@ -95,7 +106,8 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->max_blocks = (uint32_t)B;
   v->max_vertices = (uint32_t)V;
   v->max_chunks = (uint32_t)T;
-  v->max_changed = (uint32_t)changed;
+  v->vseg_cap = (uint32_t)((V + kSegs - 1) / kSegs);
+  v->cseg_cap = (uint32_t)((T + kSegs - 1) / kSegs);
   v->hash_mask = (uint32_t)(H - 1);
   v->hash_mode = c.hash_mode;
   return off;
@@ -105,26 +117,31 @@ int hip_status(hipError_t e) { return e == hipSuccess ? VM_OK : VM_ERR_HIP; }
 
 int launched() { return hip_status(hipGetLastError()); }
 
-int clear_state(vm_volume* vol, hipStream_t stream) {
+// Empty the volume.  full = true (creation) also clears the running totals
+// and uploads the marching-cubes tables.
+int clear_state(vm_volume* vol, hipStream_t stream, bool full) {
   const VolDev& v = vol->dev;
   const size_t H = (size_t)v.hash_mask + 1, B = v.max_blocks;
   hipError_t e = hipSuccess;
   auto set = [&](void* p, int val, size_t n) {
     if (e == hipSuccess) e = hipMemsetAsync(p, val, n, stream);
   };
-  set(v.cnt, 0, sizeof(Counters));
+  set(v.cnt, 0, full ? sizeof(Counters) : offsetof(Counters, acc));
+  set(v.vseg, 0, sizeof(Seg) * kSegs);
+  set(v.cseg, 0, sizeof(Seg) * kSegs);
   set(v.slots, 0xFF, 8 * H);
   set(v.slot_stamp, 0, 4 * H);
   set(v.st_pending, 0, 4 * B);
   set(v.st_dirty, 0, 4 * B);
   set(v.st_vtx, 0, 4 * B);
   set(v.st_frame, 0, 4 * B);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync((void*)v.tri_table, g_tri, sizeof(g_tri), hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync((void*)v.edge_uses, g_uses, sizeof(g_uses), hipMemcpyHostToDevice, stream);
-  // host copies of the tables must stay valid until the copies ran
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (full) {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)v.tri_table, g_tri, sizeof(g_tri), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)v.edge_uses, g_uses, sizeof(g_uses), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  }
   vol->frame = 0;
   vol->epoch = 1;
   vol->pass = 0;
@@ -144,8 +161,69 @@ int error_code(uint32_t bits) {
   return VM_OK;
 }
 
-void counters_op(vm_volume* vol, int op, hipStream_t s) {
-  hipLaunchKernelGGL(k_counters, dim3(1), dim3(1), 0, s, vol->dev, op, 0u);
+hipEvent_t prof_event(vm_volume* vol, hipStream_t s) {
+  hipEvent_t e = nullptr;
+  if (!vol->ev_free.empty()) {
+    e = vol->ev_free.back();
+    vol->ev_free.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  if (hipEventRecord(e, s) != hipSuccess) {
+    vol->ev_free.push_back(e);
+    return nullptr;
+  }
+  return e;
+}
+
+hipEvent_t prof_begin(vm_volume* vol, hipStream_t s) {
+  return vol->prof ? prof_event(vol, s) : nullptr;
+}
+
+void prof_end(vm_volume* vol, int kid, hipEvent_t a, hipStream_t s) {
+  if (!vol->prof || !a) return;
+  hipEvent_t b = prof_event(vol, s);
+  if (!b) {
+    vol->ev_free.push_back(a);
+    return;
+  }
+  vol->recs.push_back({kid, a, b});
+}
+
+// Launch a kernel, bracketed by timing events while profiling is enabled.
+#define VM_LAUNCH(vol, kid, kernel, grid, block, stream, ...)       \
+  do {                                                              \
+    hipEvent_t vm_ev_ = prof_begin((vol), (stream));                \
+    hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__); \
+    prof_end((vol), (kid), vm_ev_, (stream));                       \
+  } while (0)
+
+void prep(vm_volume* vol, int op, hipStream_t s) {
+  VM_LAUNCH(vol, VM_K_COUNTERS, k_prep, dim3(1), dim3(kSegs), s, vol->dev, op, 0u);
+}
+
+// Hash slots scanned per workgroup by the frame compaction: at most 256
+// workgroups, at least 4096 slots each.
+uint32_t compact_per_wg(const VolDev& v) {
+  const uint32_t H = v.hash_mask + 1;
+  uint32_t per = (H + 255) / 256;
+  return per < 4096 ? 4096 : per;
+}
+
+// Host copy of the counters and both segment tables.
+struct Snapshot {
+  Counters c;
+  Seg vseg[kSegs], cseg[kSegs];
+};
+
+int read_snapshot(vm_volume* vol, Snapshot* s, hipStream_t stream) {
+  hipError_t e = hipMemcpyAsync(&s->c, vol->dev.cnt, sizeof(Counters), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->vseg, vol->dev.vseg, sizeof(s->vseg), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->cseg, vol->dev.cseg, sizeof(s->cseg), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return hip_status(e);
 }
 
 }  // namespace
@@ -187,7 +265,9 @@ int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes, hipStrea
   }
   vol->grid_blocks = cus * 4;
   vol->grid_items = cus * 8;
-  int r = clear_state(vol, stream);
+  vol->grid_waves = cus * 8;
+  vol->prof = false;
+  int r = clear_state(vol, stream, true);
   if (r != VM_OK) {
     delete vol;
     return r;
@@ -198,13 +278,18 @@ int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes, hipStrea
 
 int vm_destroy_volume(vm_volume* vol) {
   if (!vol) return VM_ERR_ARG;
+  for (auto& r : vol->recs) vol->ev_free.push_back(r.a), vol->ev_free.push_back(r.b);
+  for (hipEvent_t e : vol->ev_free) (void)hipEventDestroy(e);
   delete vol;
   return VM_OK;
 }
 
 int vm_reset_volume(vm_volume* vol, hipStream_t stream) {
   if (!vol) return VM_ERR_ARG;
-  return clear_state(vol, stream);
+  prep(vol, VM_OP_RESET, stream);
+  int r = launched();
+  if (r != VM_OK) return r;
+  return clear_state(vol, stream, false);
 }
 
 int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* K,
@@ -234,12 +319,12 @@ int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* 
   fp.frame = ++vol->frame;
   const VolDev& v = vol->dev;
   const int npix = K->width * K->height;
-  counters_op(vol, VM_OP_BEGIN_FRAME, stream);
-  hipLaunchKernelGGL(k_collect, dim3((npix + 255) / 256), dim3(256), 0, stream, v, fp, depth);
-  hipLaunchKernelGGL(k_assign, dim3(vol->grid_items), dim3(256), 0, stream, v, vol->epoch);
-  hipLaunchKernelGGL(k_link, dim3(vol->grid_items), dim3(256), 0, stream, v);
-  hipLaunchKernelGGL(k_fuse, dim3(vol->grid_blocks), dim3(512), 0, stream, v, fp, depth);
-  counters_op(vol, VM_OP_END_FRAME, stream);
+  const uint32_t per = compact_per_wg(v);
+  const uint32_t ncompact = (v.hash_mask + per) / per;
+  VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3((npix + 255) / 256), dim3(256), stream, v, fp, depth);
+  VM_LAUNCH(vol, VM_K_ASSIGN, k_frame_compact, dim3(ncompact), dim3(256), stream, v, fp.frame,
+            vol->epoch, per);
+  VM_LAUNCH(vol, VM_K_FUSE, k_fuse, dim3(vol->grid_blocks), dim3(512), stream, v, fp, depth);
   vol->last_fp = fp;
   vol->have_fp = true;
   return launched();
@@ -252,14 +337,14 @@ int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
   if (n == 0) return VM_OK;
   const VolDev& v = vol->dev;
   const uint32_t frame = ++vol->frame;
-  counters_op(vol, VM_OP_BEGIN_FRAME, stream);
-  hipLaunchKernelGGL(k_import_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, v,
-                     coords, (uint32_t)n, frame);
-  hipLaunchKernelGGL(k_assign, dim3(vol->grid_items), dim3(256), 0, stream, v, vol->epoch);
-  hipLaunchKernelGGL(k_link, dim3(vol->grid_items), dim3(256), 0, stream, v);
-  hipLaunchKernelGGL(k_import_copy, dim3(vol->grid_blocks), dim3(512), 0, stream, v, tsdf, weight,
-                     frame);
-  counters_op(vol, VM_OP_END_FRAME, stream);
+  const uint32_t per = compact_per_wg(v);
+  const uint32_t ncompact = (v.hash_mask + per) / per;
+  VM_LAUNCH(vol, VM_K_IMPORT, k_import_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), stream,
+            v, coords, (uint32_t)n, frame);
+  VM_LAUNCH(vol, VM_K_ASSIGN, k_frame_compact, dim3(ncompact), dim3(256), stream, v, frame,
+            vol->epoch, per);
+  VM_LAUNCH(vol, VM_K_IMPORT, k_import_copy, dim3(vol->grid_blocks), dim3(512), stream, v, tsdf,
+            weight, frame);
   vol->have_fp = false;
   return launched();
 }
@@ -268,18 +353,17 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
   if (!vol || (scope != VM_SCOPE_DIRTY && scope != VM_SCOPE_ALL)) return VM_ERR_ARG;
   const VolDev& v = vol->dev;
   const uint32_t pass = ++vol->pass;
-  counters_op(vol, VM_OP_BEGIN_EXTRACT, stream);
+  prep(vol, VM_OP_EXTRACT, stream);
   if (scope == VM_SCOPE_ALL)
-    hipLaunchKernelGGL(k_dirty_all, dim3(vol->grid_items), dim3(256), 0, stream, v, pass);
+    VM_LAUNCH(vol, VM_K_DIRTY, k_dirty_all, dim3(vol->grid_items), dim3(256), stream, v, pass);
   else
-    hipLaunchKernelGGL(k_dirty, dim3(vol->grid_items), dim3(256), 0, stream, v, pass);
-  counters_op(vol, VM_OP_END_PENDING, stream);
+    VM_LAUNCH(vol, VM_K_DIRTY, k_dirty, dim3(vol->grid_items), dim3(256), stream, v, pass,
+              vol->epoch);
   ++vol->epoch;
-  hipLaunchKernelGGL(k_classify, dim3(vol->grid_blocks), dim3(512), 0, stream, v, pass, 0);
-  hipLaunchKernelGGL(k_vertices, dim3(vol->grid_blocks), dim3(512), 0, stream, v);
-  counters_op(vol, VM_OP_FIN_VERTICES, stream);
-  hipLaunchKernelGGL(k_triangles, dim3(vol->grid_items), dim3(256), 0, stream, v);
-  counters_op(vol, VM_OP_FIN_TRIANGLES, stream);
+  VM_LAUNCH(vol, VM_K_CLASSIFY, k_classify, dim3(vol->grid_waves), dim3(256), stream, v, pass, 0);
+  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
+  VM_LAUNCH(vol, VM_K_VERTICES, k_vertices, dim3(vol->grid_waves), dim3(256), stream, v);
+  VM_LAUNCH(vol, VM_K_TRIANGLES, k_triangles, dim3(vol->grid_waves), dim3(256), stream, v);
   return launched();
 }
 
@@ -287,20 +371,20 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   if (!vol) return VM_ERR_ARG;
   const VolDev& v = vol->dev;
   const uint32_t pass = ++vol->pass;
-  counters_op(vol, VM_OP_BEGIN_REFINE, stream);
-  hipLaunchKernelGGL(k_classify, dim3(vol->grid_blocks), dim3(512), 0, stream, v, pass, 1);
-  hipLaunchKernelGGL(k_vertices, dim3(vol->grid_blocks), dim3(512), 0, stream, v);
-  counters_op(vol, VM_OP_FIN_VERTICES, stream);
-  hipLaunchKernelGGL(k_triangles, dim3(vol->grid_items), dim3(256), 0, stream, v);
-  counters_op(vol, VM_OP_FIN_TRIANGLES, stream);
+  prep(vol, VM_OP_REFINE, stream);
+  VM_LAUNCH(vol, VM_K_REFINE, k_classify, dim3(vol->grid_waves), dim3(256), stream, v, pass, 1);
+  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
+  VM_LAUNCH(vol, VM_K_VERTICES, k_vertices, dim3(vol->grid_waves), dim3(256), stream, v);
+  VM_LAUNCH(vol, VM_K_TRIANGLES, k_triangles, dim3(vol->grid_waves), dim3(256), stream, v);
   return launched();
 }
 
 int vm_gc(vm_volume* vol, hipStream_t stream) {
   if (!vol) return VM_ERR_ARG;
-  counters_op(vol, VM_OP_BEGIN_GC, stream);
-  hipLaunchKernelGGL(k_gc, dim3(vol->grid_items), dim3(256), 0, stream, vol->dev);
-  counters_op(vol, VM_OP_FIN_GC, stream);
+  uint32_t parts = vol->dev.vseg_cap / 4096;
+  parts = parts < 1 ? 1 : (parts > 64 ? 64 : parts);
+  prep(vol, VM_OP_GC, stream);
+  VM_LAUNCH(vol, VM_K_GC, k_gc, dim3(kSegs * parts), dim3(256), stream, vol->dev, parts);
   return launched();
 }
 
@@ -308,19 +392,21 @@ int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys, int32_t*
                      int64_t vcap, int64_t tcap, int64_t* nv, int64_t* nt, hipStream_t stream) {
   if (!vol || !nv || !nt || vcap < 0 || tcap < 0 || (vcap > 0 && !verts) || (tcap > 0 && !tris))
     return VM_ERR_ARG;
-  Counters c;
-  int r = read_counters(vol, &c, stream);
-  if (r != VM_OK) return r;
   const VolDev& v = vol->dev;
-  const uint32_t pv = c.vtx_hwm / 1024 + 1, pt = c.chk_hwm / 1024 + 1;
+  prep(vol, VM_OP_FINALISE, stream);
+  int r = launched();
+  if (r != VM_OK) return r;
+  Counters c;
+  const uint32_t pv = (v.max_vertices + 1023) / 1024, pt = (v.max_chunks + 1023) / 1024;
   const uint32_t vc = (uint32_t)(vcap > 0xFFFFFFFFll ? 0xFFFFFFFFll : vcap);
   const uint32_t tc = (uint32_t)(tcap > 0xFFFFFFFFll ? 0xFFFFFFFFll : tcap);
-  hipLaunchKernelGGL(k_dl_count, dim3(pv), dim3(256), 0, stream, v, 0);
-  hipLaunchKernelGGL(k_dl_scan, dim3(1), dim3(1024), 0, stream, v, 0, pv);
-  hipLaunchKernelGGL(k_dl_write_vertices, dim3(pv), dim3(256), 0, stream, v, verts, edge_keys, vc);
-  hipLaunchKernelGGL(k_dl_count, dim3(pt), dim3(256), 0, stream, v, 1);
-  hipLaunchKernelGGL(k_dl_scan, dim3(1), dim3(1024), 0, stream, v, 1, pt);
-  hipLaunchKernelGGL(k_dl_write_triangles, dim3(pt), dim3(256), 0, stream, v, tris, tc);
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_count, dim3(pv), dim3(256), stream, v, 0);
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_scan, dim3(1), dim3(1024), stream, v, 0, pv);
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_write_vertices, dim3(pv), dim3(256), stream, v, verts, edge_keys,
+            vc);
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_count, dim3(pt), dim3(256), stream, v, 1);
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_scan, dim3(1), dim3(1024), stream, v, 1, pt);
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_write_triangles, dim3(pt), dim3(256), stream, v, tris, tc);
   r = launched();
   if (r != VM_OK) return r;
   r = read_counters(vol, &c, stream);
@@ -335,8 +421,8 @@ int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys, int32_t*
 int vm_extract_backward(vm_volume* vol, const float* dL_dverts, float* dL_dtsdf,
                         hipStream_t stream) {
   if (!vol || !dL_dtsdf) return VM_ERR_ARG;
-  hipLaunchKernelGGL(k_bwd_tsdf, dim3(vol->grid_blocks), dim3(512), 0, stream, vol->dev,
-                     dL_dverts, dL_dtsdf);
+  VM_LAUNCH(vol, VM_K_BACKWARD, k_bwd_tsdf, dim3(vol->grid_blocks), dim3(512), stream, vol->dev,
+            dL_dverts, dL_dtsdf);
   return launched();
 }
 
@@ -344,36 +430,48 @@ int vm_integrate_backward(vm_volume* vol, const float* depth, const float* dL_dt
                           float* dL_dtsdf0, float* dL_ddepth, hipStream_t stream) {
   if (!vol || !depth || !dL_dtsdf1 || !dL_dtsdf0 || !dL_ddepth || !vol->have_fp) return VM_ERR_ARG;
   const FrameParams& fp = vol->last_fp;
-  hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, stream, dL_ddepth,
-                     (uint64_t)fp.W * (uint64_t)fp.H);
-  hipLaunchKernelGGL(k_bwd_fusion, dim3(vol->grid_blocks), dim3(512), 0, stream, vol->dev, fp,
-                     depth, dL_dtsdf1, dL_dtsdf0, dL_ddepth);
+  VM_LAUNCH(vol, VM_K_BACKWARD, k_zero_f32, dim3(256), dim3(256), stream, dL_ddepth,
+            (uint64_t)fp.W * (uint64_t)fp.H);
+  VM_LAUNCH(vol, VM_K_BACKWARD, k_bwd_fusion, dim3(vol->grid_blocks), dim3(512), stream, vol->dev,
+            fp, depth, dL_dtsdf1, dL_dtsdf0, dL_ddepth);
   return launched();
 }
 
 int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   if (!vol || !out) return VM_ERR_ARG;
-  Counters c;
-  int r = read_counters(vol, &c, stream);
+  prep(vol, VM_OP_FINALISE, stream);
+  int r = launched();
   if (r != VM_OK) return r;
+  Snapshot sn;
+  r = read_snapshot(vol, &sn, stream);
+  if (r != VM_OK) return r;
+  const Counters& c = sn.c;
   const uint32_t B = vol->dev.max_blocks;
+  uint32_t st_new = 0, st_upd = 0, st_freed = 0, st_chg = 0, st_ref = 0;
+  int64_t vh = 0, vf = 0, ch = 0, cf = 0;
+  for (int k = 0; k < kSegs; ++k) {
+    st_new += sn.vseg[k].st_new, st_upd += sn.vseg[k].st_upd, st_freed += sn.vseg[k].st_freed;
+    st_chg += sn.cseg[k].st_chg, st_ref += sn.cseg[k].st_ref;
+    vh += sn.vseg[k].hwm, vf += sn.vseg[k].tail - sn.vseg[k].head;
+    ch += sn.cseg[k].hwm, cf += sn.cseg[k].tail - sn.cseg[k].head;
+  }
   memset(out, 0, sizeof(*out));
   out->error = error_code(c.error);
   out->error_bits = c.error;
   out->blocks = c.n_blocks < B ? c.n_blocks : B;
-  out->frame_blocks = c.last_frame_list;
-  out->pending_blocks = c.n_pending;
+  out->frame_blocks = c.n_frame < B ? c.n_frame : B;
+  out->pending_blocks = c.n_pending[vol->epoch & 1];
   out->dirty_blocks = c.n_dirty;
   out->vertex_blocks = c.n_vblocks;
-  out->changed_cubes = c.n_changed;
-  out->vertex_slots = c.vtx_hwm;
-  out->free_vertex_slots = c.vtx_tail - c.vtx_head;
-  out->tri_cube_slots = c.chk_hwm;
-  out->free_tri_cube_slots = c.chk_tail - c.chk_head;
-  out->new_vertices = c.st_new_vtx;
-  out->updated_vertices = c.st_upd_vtx;
-  out->freed_vertices = c.st_freed;
-  out->refined_cubes = c.st_refined;
+  out->changed_cubes = st_chg - c.base_chg;
+  out->vertex_slots = vh;
+  out->free_vertex_slots = vf;
+  out->tri_cube_slots = ch;
+  out->free_tri_cube_slots = cf;
+  out->new_vertices = st_new - c.base_new;
+  out->updated_vertices = st_upd - c.base_upd;
+  out->freed_vertices = st_freed - c.base_freed;
+  out->refined_cubes = st_ref - c.base_ref;
   return out->error;
 }
 
@@ -408,12 +506,12 @@ int vm_export_blocks(vm_volume* vol, int32_t* coords, float* tsdf, float* weight
 int vm_export_vertices(vm_volume* vol, uint64_t* edge_keys, float* t, int32_t* refcount,
                        int64_t cap, int64_t* n, hipStream_t stream) {
   if (!vol || !n || cap < 0 || (cap > 0 && (!edge_keys || !t || !refcount))) return VM_ERR_ARG;
-  Counters c;
-  int r = read_counters(vol, &c, stream);
+  prep(vol, VM_OP_FINALISE, stream);
+  int r = launched();
   if (r != VM_OK) return r;
-  *n = c.vtx_hwm;
-  const uint32_t m = (uint32_t)((int64_t)c.vtx_hwm < cap ? c.vtx_hwm : cap);
-  if (m == 0) return VM_OK;
+  *n = vol->dev.max_vertices;
+  const uint32_t m = (uint32_t)((int64_t)vol->dev.max_vertices < cap ? vol->dev.max_vertices : cap);
+  if (m == 0) return hip_status(hipStreamSynchronize(stream));
   hipLaunchKernelGGL(k_export_vertices, dim3((m + 255) / 256), dim3(256), 0, stream, vol->dev,
                      edge_keys, t, refcount, m);
   r = launched();
@@ -428,7 +526,7 @@ int vm_export_block_list(vm_volume* vol, int which, int32_t* coords, int64_t cap
   int r = read_counters(vol, &c, stream);
   if (r != VM_OK) return r;
   const VolDev& v = vol->dev;
-  const uint32_t len = which == 0 ? c.last_frame_list : which == 1 ? c.n_dirty : c.n_pending;
+  const uint32_t len = which == 0 ? c.n_frame : which == 1 ? c.n_dirty : c.n_pending[vol->epoch & 1];
   const size_t cnt = len < v.max_blocks ? len : v.max_blocks;
   *n = (int64_t)cnt;
   const size_t m = (size_t)cap < cnt ? (size_t)cap : cnt;
@@ -451,6 +549,57 @@ int vm_export_block_list(vm_volume* vol, int which, int32_t* coords, int64_t cap
     ++k;
   }
   *n = (int64_t)k;
+  return VM_OK;
+}
+
+int vm_lookup_blocks(vm_volume* vol, const int32_t* coords, int32_t* idx, int64_t n,
+                     hipStream_t stream) {
+  if (!vol || n < 0 || n > 0x7FFFFFFF || (n > 0 && (!coords || !idx))) return VM_ERR_ARG;
+  if (n == 0) return VM_OK;
+  const uint32_t m = (uint32_t)n;
+  hipLaunchKernelGGL(k_lookup, dim3((m + 255) / 256 < 65535 ? (m + 255) / 256 : 65535), dim3(256), 0,
+                     stream, vol->dev, coords, idx, m);
+  return launched();
+}
+
+int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream) {
+  if (!vol || !out || n < 0 || n > VM_TOTAL_COUNT) return VM_ERR_ARG;
+  Snapshot sn;
+  int r = read_snapshot(vol, &sn, stream);
+  if (r != VM_OK) return r;
+  unsigned long long t[VM_TOTAL_COUNT];
+  for (int i = 0; i < VM_TOTAL_COUNT; ++i) t[i] = sn.c.acc[i];
+  for (int k = 0; k < kSegs; ++k) {
+    t[VM_TOTAL_NEW_VERTICES] += sn.vseg[k].st_new;
+    t[VM_TOTAL_UPDATED_VERTICES] += sn.vseg[k].st_upd;
+    t[VM_TOTAL_FREED_VERTICES] += sn.vseg[k].st_freed;
+    t[VM_TOTAL_CHANGED_CUBES] += sn.cseg[k].st_chg;
+    t[VM_TOTAL_REFINED_CUBES] += sn.cseg[k].st_ref;
+  }
+  for (int i = 0; i < n; ++i) out[i] = (int64_t)t[i];
+  return VM_OK;
+}
+
+int vm_profile(vm_volume* vol, int enable) {
+  if (!vol) return VM_ERR_ARG;
+  if (enable) {
+    for (auto& r : vol->recs) vol->ev_free.push_back(r.a), vol->ev_free.push_back(r.b);
+    vol->recs.clear();
+  }
+  vol->prof = enable != 0;
+  return VM_OK;
+}
+
+int vm_profile_read(vm_volume* vol, int64_t* launches, double* ms) {
+  if (!vol || !launches || !ms) return VM_ERR_ARG;
+  for (int k = 0; k < VM_K_COUNT; ++k) launches[k] = 0, ms[k] = 0.0;
+  if (!vol->recs.empty() && hipEventSynchronize(vol->recs.back().b) != hipSuccess) return VM_ERR_HIP;
+  for (auto& r : vol->recs) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return VM_ERR_HIP;
+    launches[r.kid] += 1;
+    ms[r.kid] += (double)t;
+  }
   return VM_OK;
 }
 

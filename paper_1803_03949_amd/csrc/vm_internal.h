@@ -6,15 +6,23 @@
 // 2 KiB rows:
 //   hash      u64 slot = (42-bit block key << 22) | 22-bit pool index,
 //             all-ones = empty; open addressing with linear probing and
-//             64-bit compare-and-swap inserts, no deletion.
+//             64-bit compare-and-swap inserts, no deletion; a per-slot frame
+//             stamp marks the blocks a frame collected.
 //   blocks    key u64, 27-neighbour index table, TSDF f32[512],
 //             weight f32[512], previous/current cube type u8[512],
 //             edge->vertex slot i32[3][512] (the three edges every voxel
-//             owns), cube->triangle chunk i32[512], pass stamps.
+//             owns), cube->triangle chunk i32[512], changed-cube bitmask
+//             u64[8], pass stamps.
 //   vertices  t f32, owner edge (index into the edge->vertex array) u32,
 //             reference count i32 (-1 = free), recycle ring, download row.
 //   triangles one 64-byte chunk per cube that holds triangles: owner cube,
 //             then up to 5 triangles as 3 vertex slots each.
+//
+// Contention on single counters is what limits a GPU here, not bytes: every
+// list is built with at most one atomic per workgroup, and the vertex and
+// triangle pools are split into kSegs independent segments (a block's
+// allocations go to segment block % kSegs), each with its own 128-byte
+// counter line, bump pointer and recycle ring.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,6 +43,8 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kNewFlag = 0x80000000u;   // frame-list entry: block is new
 constexpr int kChunkWords = 16;              // owner + 5 triangles * 3 slots
 constexpr int kMaxBlocks = 1 << 21;
+constexpr int kSegs = 64;                    // pool segments
+constexpr int kTile = 1024;                  // list items per compaction workgroup
 
 // Error bits (bit k <-> VM error code -(k+2)).
 constexpr uint32_t kErrHash = 1u << 0;
@@ -43,21 +53,40 @@ constexpr uint32_t kErrVertices = 1u << 2;
 constexpr uint32_t kErrTris = 1u << 3;
 constexpr uint32_t kErrRange = 1u << 6;
 
+// One pool segment: slots [base, base + size) of the pool, with its own
+// bump pointer, recycle ring (same index range of the ring array) and
+// running statistics.  128 bytes, so that segments never share a line.
+struct Seg {
+  uint32_t hwm;      // slots handed out by bumping, relative to base
+  uint32_t head;     // ring read position (free slots = tail - head)
+  uint32_t tail;     // ring write position
+  uint32_t ticket;   // allocations taken since the last finalise
+  uint32_t push;     // frees pushed since the last finalise
+  uint32_t st_new;   // running count of allocations
+  uint32_t st_upd;   // running count of rewritten vertices
+  uint32_t st_freed; // running count of frees
+  uint32_t st_chg;   // running count of cubes whose triangles changed
+  uint32_t st_ref;   // running count of cubes re-typed by refinement
+  uint32_t pad[22];
+};
+static_assert(sizeof(Seg) == 128, "segment record size");
+
 // Device counters (one 256-byte record at the start of the workspace).
 struct Counters {
   uint32_t n_blocks;       // pool high-water mark (may exceed capacity on error)
   uint32_t n_frame;        // entries of the current frame list
-  uint32_t n_pending;      // blocks touched since the last extraction
+  uint32_t n_pending[2];   // blocks touched since the last extraction (by epoch parity)
   uint32_t n_dirty;        // blocks of the last extraction / refinement
   uint32_t n_vblocks;      // blocks whose owned edges get recomputed
-  uint32_t n_changed;      // cubes whose triangles get rewritten
-  uint32_t vtx_hwm, vtx_head, vtx_tail, vtx_ticket, vtx_push;
-  uint32_t chk_hwm, chk_head, chk_tail, chk_ticket, chk_push;
   uint32_t error;
-  uint32_t st_new_vtx, st_upd_vtx, st_freed, st_refined;
   uint32_t dl_nv, dl_nt;
-  uint32_t last_frame_list;  // entries of the last frame list (for backward)
-  uint32_t pad[40];
+  uint32_t n_refined;      // cubes re-typed by the last refinement
+  // segment totals when the last extract / refine / gc started
+  uint32_t base_new, base_upd, base_freed, base_chg, base_ref;
+  uint32_t pad[17];
+  // running totals since the volume was created (not cleared by a reset)
+  unsigned long long acc[10];
+  unsigned long long pad2[6];
 };
 static_assert(sizeof(Counters) == 256, "counter record size");
 
@@ -66,12 +95,16 @@ struct VolDev {
   float s, inv_s, inv_block, mu_m, mu_v, eps;
   uint32_t hash_mask;
   int32_t hash_mode;
-  uint32_t max_blocks, max_vertices, max_chunks, max_changed;
+  uint32_t max_blocks, max_vertices, max_chunks;
+  uint32_t vseg_cap, cseg_cap;  // slots per segment
   Counters* cnt;
+  Seg* vseg;                  // [kSegs] vertex pool segments
+  Seg* cseg;                  // [kSegs] triangle chunk pool segments
   const uint8_t* tri_table;   // [256][16]: count, then 15 cube-edge ids
   const uint8_t* edge_uses;   // [256][12]: triangles of the type using the edge
   unsigned long long* slots;  // [hash]
   uint32_t* slot_stamp;       // [hash] frame that last collected the slot
+  uint32_t* slot_src;         // [hash] import: source row of the slot's block
   uint64_t* block_key;        // [B]
   int32_t* nbr;               // [B][27]
   float* d;                   // [B][512]
@@ -80,17 +113,17 @@ struct VolDev {
   uint8_t* tcur;              // [B][512]
   int32_t* evtx;              // [B][3][512]
   int32_t* cchunk;            // [B][512]
+  uint64_t* chg;              // [B][8] cubes whose triangles changed, per wave
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
   uint32_t* st_vtx;           // [B] pass that listed the block for vertices
   uint32_t* st_frame;         // [B] last frame that fused the block
-  uint32_t* frame_slots;      // [B] hash slots collected by the frame
+  uint32_t* frame_list;       // [B] pool index | kNewFlag
   uint32_t* frame_src;        // [B] import: source row of each entry
-  uint32_t* frame_list;       // [B] pool index | kNewFlag, or kNone
   uint32_t* pending;          // [B]
   uint32_t* dirty;            // [B]
+  uint32_t* vcand;            // [8B] vertex-block candidates of each dirty block
   uint32_t* vblocks;          // [B]
-  uint32_t* changed;          // [max_changed] (block << 9) | cube
   float* vt;                  // [V]
   uint32_t* vowner;           // [V] index into evtx
   int32_t* vref;              // [V]
@@ -144,21 +177,19 @@ __device__ inline unsigned long long load_slot(const unsigned long long* p) {
 }
 
 // Find-or-insert a block key.  Returns the slot, or -1 when the table is
-// full.  *inserted tells whether this call created the entry (its pool index
-// is then kPending until the assignment pass).
-__device__ inline int64_t hash_insert(const VolDev& v, uint64_t key, bool* inserted) {
+// full.  A new entry's pool index is kPending until the compaction pass.
+// Probes use plain (cacheable) loads: a slot's key never changes once set,
+// so a stale read can only show an empty slot, and the compare-and-swap
+// that follows returns the slot's true content.
+__device__ inline int64_t hash_insert(const VolDev& v, uint64_t key) {
   uint32_t h = hash_home(key, v.hash_mask, v.hash_mode);
-  *inserted = false;
   for (uint32_t probe = 0; probe <= v.hash_mask; ++probe) {
     uint32_t s = (h + probe) & v.hash_mask;
-    unsigned long long cur = load_slot(&v.slots[s]);
+    unsigned long long cur = v.slots[s];
     if (cur == kEmpty) {
       unsigned long long want = ((unsigned long long)key << kIdxBits) | kPending;
       unsigned long long prev = atomicCAS(&v.slots[s], (unsigned long long)kEmpty, want);
-      if (prev == kEmpty) {
-        *inserted = true;
-        return s;
-      }
+      if (prev == kEmpty) return s;
       cur = prev;
     }
     if ((cur >> kIdxBits) == key) return s;
@@ -166,12 +197,13 @@ __device__ inline int64_t hash_insert(const VolDev& v, uint64_t key, bool* inser
   return -1;
 }
 
-// Pool index of a key, or -1 if absent (or not yet assigned).
+// Pool index of a key, or -1 if absent (or not yet assigned).  For use
+// after the kernel that assigned the indices has completed.
 __device__ inline int32_t hash_find(const VolDev& v, uint64_t key) {
   uint32_t h = hash_home(key, v.hash_mask, v.hash_mode);
   for (uint32_t probe = 0; probe <= v.hash_mask; ++probe) {
     uint32_t s = (h + probe) & v.hash_mask;
-    unsigned long long cur = load_slot(&v.slots[s]);
+    unsigned long long cur = v.slots[s];
     if (cur == kEmpty) return -1;
     if ((cur >> kIdxBits) == key) {
       uint32_t idx = (uint32_t)(cur & kIdxMask);
@@ -187,32 +219,79 @@ __host__ __device__ inline int nbr_dir(int dx, int dy, int dz) {
 }
 constexpr int kSelf = 13;
 
-// ---- wave helpers (wave64) -------------------------------------------------
+// ---- wave and workgroup helpers (wave64) ------------------------------------
 __device__ inline uint64_t lanes_below() {
   return (1ull << __lane_id()) - 1ull;
 }
 
-// Wave-aggregated ticket: one atomic per wave.  Every active lane must call.
-__device__ inline uint32_t wave_ticket(uint32_t* counter, bool want) {
-  uint64_t m = __ballot(want);
-  uint32_t base = 0;
-  if (m) {
-    int leader = __ffsll((unsigned long long)m) - 1;
-    if ((int)__lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-  }
-  return base + (uint32_t)__popcll(m & lanes_below());
+// Make a wave's LDS writes visible to the other lanes of the same wave (no
+// workgroup barrier: waves that own separate LDS regions run independently).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Slot number of allocation ticket k from a recycle ring + bump pool, or
-// kNone when the pool is exhausted.  head/tail/hwm are fixed for the
-// duration of the allocating kernel.
-__device__ inline uint32_t ticket_slot(uint32_t k, const uint32_t* ring, uint32_t head,
-                                       uint32_t tail, uint32_t hwm, uint32_t cap) {
-  uint32_t avail = tail - head;
-  if (k < avail) return ring[(uint32_t)(((uint64_t)head + k) % cap)];
-  uint64_t s = (uint64_t)hwm + (k - avail);
-  return s < cap ? (uint32_t)s : kNone;
+// Exclusive prefix of x over the wave and the wave's total.
+__device__ inline uint32_t wave_scan(uint32_t x, uint32_t* total) {
+  const int lane = __lane_id();
+  uint32_t incl = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  *total = __shfl(incl, 63);
+  return incl - x;
+}
+
+__device__ inline uint32_t wave_sum(uint32_t x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+__device__ inline uint64_t shfl64(uint64_t x, int src) {
+  const uint32_t lo = __shfl((uint32_t)x, src), hi = __shfl((uint32_t)(x >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Exclusive prefix of x over the workgroup and its total, for workgroups of
+// up to 16 waves.  Every lane must call; swave holds 16 words of LDS.
+__device__ inline uint32_t wg_scan(uint32_t x, uint32_t* swave, uint32_t* total) {
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  const int nwave = (blockDim.x + 63) >> 6;
+  uint32_t incl = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) swave[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < nwave; ++w) {
+    const uint32_t c = swave[w];
+    if (w < wave) before += c;
+    all += c;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - x;
+}
+
+// Segment bounds.
+__device__ inline uint32_t seg_size(uint32_t s, uint32_t cap, uint32_t total) {
+  const uint64_t b = (uint64_t)s * cap;
+  return b >= total ? 0u : (uint32_t)((total - b) < cap ? (total - b) : cap);
+}
+
+// Slot of allocation ticket k of a segment: from its recycle ring first,
+// then by bumping; kNone when the segment is exhausted.  The segment's
+// head/tail/hwm are fixed for the duration of the allocating kernel.
+__device__ inline uint32_t seg_slot(uint32_t head, uint32_t tail, uint32_t hwm, uint32_t k,
+                                    const uint32_t* ring, uint32_t base, uint32_t size) {
+  const uint32_t avail = tail - head;
+  if (k < avail) return ring[base + (uint32_t)(((uint64_t)head + k) % size)];
+  const uint64_t s = (uint64_t)hwm + (k - avail);
+  return s < size ? base + (uint32_t)s : kNone;
 }
 
 __device__ inline bool depth_ok(float D, float dmin, float dmax) {
@@ -269,21 +348,21 @@ __device__ inline float edge_param(float da, float db) {
 
 // ---- kernels (defined in vm_kernels.hip, launched from vm_api.hip) ----------
 namespace vm {
-__global__ void k_counters(VolDev v, int op, uint32_t arg);
+__global__ void k_prep(VolDev v, int op, uint32_t arg);
 __global__ void k_collect(VolDev v, FrameParams fp, const float* __restrict__ depth);
 __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ coords, uint32_t n,
                                 uint32_t frame);
-__global__ void k_assign(VolDev v, uint32_t epoch);
-__global__ void k_link(VolDev v);
+__global__ void k_frame_compact(VolDev v, uint32_t frame, uint32_t epoch, uint32_t per_wg);
 __global__ void k_fuse(VolDev v, FrameParams fp, const float* __restrict__ depth);
 __global__ void k_import_copy(VolDev v, const float* __restrict__ tsdf,
                               const float* __restrict__ weight, uint32_t frame);
-__global__ void k_dirty(VolDev v, uint32_t pass);
+__global__ void k_dirty(VolDev v, uint32_t pass, uint32_t epoch);
 __global__ void k_dirty_all(VolDev v, uint32_t pass);
 __global__ void k_classify(VolDev v, uint32_t pass, int refine);
+__global__ void k_vblock_compact(VolDev v);
 __global__ void k_vertices(VolDev v);
 __global__ void k_triangles(VolDev v);
-__global__ void k_gc(VolDev v);
+__global__ void k_gc(VolDev v, uint32_t parts);
 __global__ void k_dl_count(VolDev v, int what);
 __global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
 __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,
@@ -295,17 +374,17 @@ __global__ void k_bwd_fusion(VolDev v, FrameParams fp, const float* __restrict__
                              float* __restrict__ gD);
 __global__ void k_zero_f32(float* p, uint64_t n);
 __global__ void k_export_vertices(VolDev v, uint64_t* keys, float* t, int32_t* ref, uint32_t n);
+__global__ void k_lookup(VolDev v, const int32_t* __restrict__ coords, int32_t* __restrict__ idx,
+                         uint32_t n);
 }  // namespace vm
 
-// Counter operations of k_counters.
+// Bookkeeping operations of k_prep.  Every one of them first finalises the
+// pool segments (recycled slots consumed, bump pointers advanced, frees
+// made available), which is idempotent.
 enum {
-  VM_OP_BEGIN_FRAME = 0,   // n_frame = 0
-  VM_OP_BEGIN_EXTRACT = 1, // n_dirty = n_vblocks = n_changed = 0, stats = 0
-  VM_OP_END_PENDING = 2,   // n_pending = 0
-  VM_OP_FIN_VERTICES = 3,  // consume vertex tickets
-  VM_OP_FIN_TRIANGLES = 4, // consume chunk tickets and pushes
-  VM_OP_BEGIN_GC = 5,
-  VM_OP_FIN_GC = 6,
-  VM_OP_BEGIN_REFINE = 7,  // n_vblocks = n_changed = 0
-  VM_OP_END_FRAME = 8      // last_frame_list = n_frame
+  VM_OP_EXTRACT = 1,    // before an extraction: account and reset dirty/vertex lists
+  VM_OP_REFINE = 2,     // before a refinement: reset the vertex list
+  VM_OP_GC = 3,         // before a garbage collection
+  VM_OP_FINALISE = 4,   // segments only
+  VM_OP_RESET = 5       // before a reset: fold segment statistics into the totals
 };

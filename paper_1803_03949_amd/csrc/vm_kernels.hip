@@ -1,75 +1,69 @@
 // HIP kernels of the voxmesh library for gfx950 (wave64).
 //
-// Work that is per block (fusion, classification, vertex update, backward)
-// runs one 512-lane workgroup per 8^3 block, one lane per voxel/cube, with
-// the block and its one-voxel halo staged in LDS.  Work lists live on the
-// device, so every kernel loops over its list with a grid stride and the
-// host never waits for a count.  Allocation in the pools uses one atomic
-// per wave (ballot + popcount ranks) or per workgroup.
+// Work that is per block (fusion, classification, vertex update, triangle
+// rewrite, backward) runs one 512-lane workgroup per 8^3 block, one lane per
+// voxel/cube, with the block and its one-voxel halo staged in LDS.  Work
+// lists live on the device and every kernel loops over its list with a grid
+// stride, so the host never waits for a count.  Lists are compacted with one
+// atomic per workgroup; pool allocations take one atomic per block on the
+// block's pool segment.
+#include "voxmesh.h"
 #include "vm_internal.h"
 
 namespace vm {
 
 // ============================================================================
-// counters
+// bookkeeping
 // ============================================================================
-__global__ void k_counters(VolDev v, int op, uint32_t arg) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ inline void finalise_seg(Seg& g, uint32_t size) {
+  const uint32_t avail = g.tail - g.head;
+  const uint32_t from_ring = min(g.ticket, avail);
+  g.head += from_ring;
+  const uint64_t hwm = (uint64_t)g.hwm + (g.ticket - from_ring);
+  g.hwm = hwm > size ? size : (uint32_t)hwm;
+  g.tail += g.push;
+  g.ticket = 0;
+  g.push = 0;
+}
+
+// One wave: lane s finalises segment s of both pools, the lanes sum the
+// segment statistics, then lane 0 does the operation's resets and snapshots.
+__global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
+  const int s = threadIdx.x;
+  Seg& vs = v.vseg[s];
+  Seg& cs = v.cseg[s];
+  finalise_seg(vs, seg_size(s, v.vseg_cap, v.max_vertices));
+  finalise_seg(cs, seg_size(s, v.cseg_cap, v.max_chunks));
+  const uint32_t sum_new = wave_sum(vs.st_new), sum_upd = wave_sum(vs.st_upd);
+  const uint32_t sum_freed = wave_sum(vs.st_freed), hwm = wave_sum(vs.hwm);
+  const uint32_t sum_chg = wave_sum(cs.st_chg), sum_ref = wave_sum(cs.st_ref);
+  if (s != 0) return;
   Counters* c = v.cnt;
   switch (op) {
-    case VM_OP_BEGIN_FRAME:
-      c->n_frame = 0;
-      break;
-    case VM_OP_END_FRAME:
-      c->last_frame_list = min(c->n_frame, v.max_blocks);
-      break;
-    case VM_OP_BEGIN_EXTRACT:
+    case VM_OP_EXTRACT:
       c->n_dirty = 0;
       c->n_vblocks = 0;
-      c->n_changed = 0;
-      c->st_new_vtx = 0;
-      c->st_upd_vtx = 0;
-      c->st_refined = 0;
+      c->base_new = sum_new;
+      c->base_upd = sum_upd;
+      c->base_chg = sum_chg;
       break;
-    case VM_OP_BEGIN_REFINE:
+    case VM_OP_REFINE:
       c->n_vblocks = 0;
-      c->n_changed = 0;
-      c->st_new_vtx = 0;
-      c->st_upd_vtx = 0;
-      c->st_refined = 0;
+      c->base_new = sum_new;
+      c->base_upd = sum_upd;
+      c->base_chg = sum_chg;
+      c->base_ref = sum_ref;
       break;
-    case VM_OP_END_PENDING:
-      c->n_pending = 0;
+    case VM_OP_GC:
+      c->base_freed = sum_freed;
+      c->acc[VM_TOTAL_GC_SCANNED] += hwm;
       break;
-    case VM_OP_FIN_VERTICES: {
-      uint32_t avail = c->vtx_tail - c->vtx_head;
-      uint32_t used = c->vtx_ticket;
-      uint32_t from_ring = min(used, avail);
-      c->vtx_head += from_ring;
-      uint64_t hwm = (uint64_t)c->vtx_hwm + (used - from_ring);
-      c->vtx_hwm = hwm > v.max_vertices ? v.max_vertices : (uint32_t)hwm;
-      c->vtx_ticket = 0;
-      break;
-    }
-    case VM_OP_FIN_TRIANGLES: {
-      uint32_t avail = c->chk_tail - c->chk_head;
-      uint32_t used = c->chk_ticket;
-      uint32_t from_ring = min(used, avail);
-      c->chk_head += from_ring;
-      uint64_t hwm = (uint64_t)c->chk_hwm + (used - from_ring);
-      c->chk_hwm = hwm > v.max_chunks ? v.max_chunks : (uint32_t)hwm;
-      c->chk_tail += c->chk_push;
-      c->chk_ticket = 0;
-      c->chk_push = 0;
-      break;
-    }
-    case VM_OP_BEGIN_GC:
-      c->vtx_push = 0;
-      break;
-    case VM_OP_FIN_GC:
-      c->vtx_tail += c->vtx_push;
-      c->st_freed = c->vtx_push;
-      c->vtx_push = 0;
+    case VM_OP_RESET:
+      c->acc[VM_TOTAL_NEW_VERTICES] += sum_new;
+      c->acc[VM_TOTAL_UPDATED_VERTICES] += sum_upd;
+      c->acc[VM_TOTAL_FREED_VERTICES] += sum_freed;
+      c->acc[VM_TOTAL_CHANGED_CUBES] += sum_chg;
+      c->acc[VM_TOTAL_REFINED_CUBES] += sum_ref;
       break;
     default:
       break;
@@ -81,34 +75,30 @@ __global__ void k_counters(VolDev v, int op, uint32_t arg) {
 // block collection (Eq. 1)
 // ============================================================================
 
-// Mark one block key as collected by this frame: insert it if absent and
-// list its hash slot once per frame.
-__device__ static void collect_key(const VolDev& v, uint64_t key, uint32_t frame, uint32_t src) {
-  bool inserted;
-  int64_t s = hash_insert(v, key, &inserted);
+// Insert a block key (if absent) and stamp its slot with the frame.  Racing
+// lanes store the same stamp, so no atomic is needed for it.
+__device__ static void collect_key(const VolDev& v, uint64_t key, uint32_t frame) {
+  const int64_t s = hash_insert(v, key);
   if (s < 0) {
     atomicOr(&v.cnt->error, kErrHash);
     return;
   }
-  uint32_t* st = &v.slot_stamp[s];
-  if (__hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == frame) return;
-  if (atomicMax(st, frame) >= frame) return;
-  uint32_t pos = atomicAdd(&v.cnt->n_frame, 1u);
-  if (pos < v.max_blocks) {
-    v.frame_slots[pos] = (uint32_t)s;
-    v.frame_src[pos] = src;
-  } else {
-    atomicOr(&v.cnt->error, kErrBlocks);
-  }
+  if (v.slot_stamp[s] != frame) v.slot_stamp[s] = frame;
 }
 
 // One lane per pixel.  Each valid pixel spans the integer box of blocks
-// between its ray points at camera depth D - mu and D + mu; lanes of a wave
-// that name the same block are merged before touching the hash.
+// between its ray points at camera depth D - mu and D + mu.  Per box cell,
+// the lanes of a wave first agree on the distinct keys (ballot/shuffle), then
+// the lanes holding distinct keys probe the hash in parallel.
 __global__ __launch_bounds__(256) void k_collect(VolDev v, FrameParams fp,
                                                  const float* __restrict__ depth) {
   const int npix = fp.W * fp.H;
   const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pix == 0) {
+    // the frame list is rebuilt by the compaction that follows
+    v.cnt->n_frame = 0;
+    v.cnt->acc[VM_TOTAL_FRAMES] += 1;
+  }
   int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
   int nbox = 0;
   if (pix < npix) {
@@ -152,6 +142,7 @@ __global__ __launch_bounds__(256) void k_collect(VolDev v, FrameParams fp,
       const int cx = j % ext[0], cy = (j / ext[0]) % ext[1], cz = j / (ext[0] * ext[1]);
       key = pack_key(lo[0] + cx, lo[1] + cy, lo[2] + cz);
     }
+    bool mine = false;  // this lane holds the first copy of its key
     uint64_t todo = __ballot(has);
     while (todo) {
       const int leader = __ffsll((unsigned long long)todo) - 1;
@@ -160,93 +151,146 @@ __global__ __launch_bounds__(256) void k_collect(VolDev v, FrameParams fp,
       const uint64_t lk = ((uint64_t)khi << 32) | klo;
       const bool same = has && key == lk;
       todo &= ~__ballot(same);
+      if ((int)__lane_id() == leader) mine = true;
       if (same) has = false;
-      if ((int)__lane_id() == leader) collect_key(v, lk, fp.frame, 0);
     }
+    if (mine) collect_key(v, key, fp.frame);
   }
 }
 
 __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ coords, uint32_t n,
                                 uint32_t frame) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    v.cnt->n_frame = 0;
+    v.cnt->acc[VM_TOTAL_FRAMES] += 1;
+  }
   if (i >= n) return;
   const int x = coords[3 * i], y = coords[3 * i + 1], z = coords[3 * i + 2];
   if (!key_in_range(x, y, z)) {
     atomicOr(&v.cnt->error, kErrRange);
     return;
   }
-  collect_key(v, pack_key(x, y, z), frame, i);
+  const int64_t s = hash_insert(v, pack_key(x, y, z));
+  if (s < 0) {
+    atomicOr(&v.cnt->error, kErrHash);
+    return;
+  }
+  v.slot_stamp[s] = frame;
+  v.slot_src[s] = i;
 }
 
-// Give every newly inserted key of the frame a pool index (one atomic per
-// wave), publish it in the hash slot and list the block as pending for the
-// next extraction.
-__global__ __launch_bounds__(256) void k_assign(VolDev v, uint32_t epoch) {
-  const uint32_t n = min(v.cnt->n_frame, v.max_blocks);
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-    const uint32_t i = base + threadIdx.x;
-    const bool act = i < n;
-    uint32_t s = 0, idx = kNone;
-    uint64_t key = 0;
-    if (act) {
-      s = v.frame_slots[i];
-      const unsigned long long val = load_slot(&v.slots[s]);
-      key = val >> kIdxBits;
-      idx = (uint32_t)(val & kIdxMask);
+// Scan a contiguous range of hash slots per workgroup for the slots this
+// frame stamped: give new keys a pool index, publish it, and append the
+// blocks to the frame list and (once per extraction epoch) to the pending
+// list.  Two passes over the range: count, one atomic per list, write.
+__global__ __launch_bounds__(256) void k_frame_compact(VolDev v, uint32_t frame, uint32_t epoch,
+                                                       uint32_t per_wg) {
+  __shared__ uint32_t swave[16];
+  __shared__ uint32_t sbase[3];
+  const uint32_t H = v.hash_mask + 1;
+  const uint32_t b0 = blockIdx.x * per_wg;
+  if (b0 >= H) return;
+  const uint32_t b1 = min(H, b0 + per_wg);
+  // stamps of 16 slots per lane per round, loaded before they are examined
+  constexpr int kR = 16;
+  uint32_t nhit = 0, nnew = 0, npend = 0;
+  for (uint32_t r0 = b0; r0 < b1; r0 += kR * blockDim.x) {
+    uint32_t stamp[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const uint32_t s = r0 + r * blockDim.x + threadIdx.x;
+      stamp[r] = s < b1 ? v.slot_stamp[s] : 0u;
     }
-    const bool isnew = act && idx == kPending;
-    const uint32_t t = wave_ticket(&v.cnt->n_blocks, isnew);
-    if (isnew) {
-      if (t < v.max_blocks) {
-        idx = t;
-        v.slots[s] = ((unsigned long long)key << kIdxBits) | idx;
-        v.block_key[idx] = key;
-        int32_t* nb = v.nbr + (size_t)idx * 27;
-        for (int d = 0; d < 27; ++d) nb[d] = d == kSelf ? (int32_t)idx : -1;
-        v.frame_list[i] = idx | kNewFlag;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      if (stamp[r] != frame) continue;
+      const uint32_t s = r0 + r * blockDim.x + threadIdx.x;
+      ++nhit;
+      const uint32_t idx = (uint32_t)(v.slots[s] & kIdxMask);
+      if (idx == kPending) ++nnew, ++npend;
+      else npend += v.st_pending[idx] != epoch;
+    }
+  }
+  uint32_t t_hit, t_new, t_pend;
+  uint32_t r_hit = wg_scan(nhit, swave, &t_hit);
+  uint32_t r_new = wg_scan(nnew, swave, &t_new);
+  uint32_t r_pend = wg_scan(npend, swave, &t_pend);
+  if (t_hit == 0) return;
+  if (threadIdx.x == 0) {
+    sbase[0] = atomicAdd(&v.cnt->n_frame, t_hit);
+    sbase[1] = t_new ? atomicAdd(&v.cnt->n_blocks, t_new) : 0u;
+    sbase[2] = t_pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], t_pend) : 0u;
+  }
+  __syncthreads();
+  r_hit += sbase[0];
+  r_new += sbase[1];
+  r_pend += sbase[2];
+  for (uint32_t r0 = b0; r0 < b1; r0 += kR * blockDim.x) {
+    uint32_t stamp[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const uint32_t s = r0 + r * blockDim.x + threadIdx.x;
+      stamp[r] = s < b1 ? v.slot_stamp[s] : 0u;
+    }
+    for (int r = 0; r < kR; ++r) {
+      if (stamp[r] != frame) continue;
+      const uint32_t s = r0 + r * blockDim.x + threadIdx.x;
+      const unsigned long long val = v.slots[s];
+      uint32_t idx = (uint32_t)(val & kIdxMask);
+      uint32_t entry;
+      bool pend;
+      if (idx == kPending) {
+        const uint32_t t = r_new++;
+        pend = true;
+        if (t < v.max_blocks) {
+          idx = t;
+          const uint64_t key = val >> kIdxBits;
+          v.slots[s] = (key << kIdxBits) | idx;
+          v.block_key[idx] = key;
+          int32_t* nb = v.nbr + (size_t)idx * 27;
+          for (int d = 0; d < 27; ++d) nb[d] = d == kSelf ? (int32_t)idx : -1;
+          entry = idx | kNewFlag;
+        } else {
+          atomicOr(&v.cnt->error, kErrBlocks);
+          idx = kNone;
+          entry = kNone;
+        }
+      } else {
+        entry = idx;
+        pend = v.st_pending[idx] != epoch;
+      }
+      const uint32_t pos = r_hit++;
+      if (pos < v.max_blocks) {
+        v.frame_list[pos] = entry;
+        v.frame_src[pos] = v.slot_src[s];
       } else {
         atomicOr(&v.cnt->error, kErrBlocks);
-        v.frame_list[i] = kNone;
-        idx = kNone;
       }
-    } else if (act) {
-      v.frame_list[i] = idx;
-    }
-    const bool pend = act && idx != kNone && v.st_pending[idx] != epoch;
-    if (pend) v.st_pending[idx] = epoch;
-    const uint32_t p = wave_ticket(&v.cnt->n_pending, pend);
-    if (pend) {
-      if (p < v.max_blocks) v.pending[p] = idx;
-      else atomicOr(&v.cnt->error, kErrBlocks);
+      if (pend) {
+        const uint32_t p = r_pend++;
+        if (idx != kNone) v.st_pending[idx] = epoch;
+        if (p < v.max_blocks) v.pending[p] = idx;
+        else atomicOr(&v.cnt->error, kErrBlocks);
+      }
     }
   }
 }
 
-// Link each new block with its 26 neighbours in both directions.
-__global__ __launch_bounds__(256) void k_link(VolDev v) {
-  const uint32_t n = min(v.cnt->n_frame, v.max_blocks);
-  const uint32_t total = n * 27u;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
-    const uint32_t i = t / 27u, dir = t % 27u;
-    if (dir == (uint32_t)kSelf) continue;
-    const uint32_t e = v.frame_list[i];
-    if (e == kNone || !(e & kNewFlag)) continue;
-    const uint32_t idx = e & ~kNewFlag;
-    int x, y, z;
-    unpack_key(v.block_key[idx], x, y, z);
-    const int nx = x + (int)(dir % 3) - 1, ny = y + (int)((dir / 3) % 3) - 1, nz = z + (int)(dir / 9) - 1;
-    if (!key_in_range(nx, ny, nz)) continue;
-    const int32_t nb = hash_find(v, pack_key(nx, ny, nz));
-    if (nb < 0) continue;
-    v.nbr[(size_t)idx * 27 + dir] = nb;
-    v.nbr[(size_t)nb * 27 + (26 - dir)] = (int32_t)idx;
-  }
+// Link a new block with its 26 neighbours in both directions (lanes 0..26
+// of the workgroup handling it).
+__device__ inline void link_block(const VolDev& v, uint32_t idx, int l) {
+  if (l >= 27 || l == kSelf) return;
+  int x, y, z;
+  unpack_key(v.block_key[idx], x, y, z);
+  const int nx = x + l % 3 - 1, ny = y + (l / 3) % 3 - 1, nz = z + l / 9 - 1;
+  if (!key_in_range(nx, ny, nz)) return;
+  const int32_t nb = hash_find(v, pack_key(nx, ny, nz));
+  if (nb < 0) return;
+  v.nbr[(size_t)idx * 27 + l] = nb;
+  v.nbr[(size_t)nb * 27 + (26 - l)] = (int32_t)idx;
 }
 
-// ============================================================================
-// fusion (Eq. 2) and import
-// ============================================================================
 __device__ inline void init_cube(const VolDev& v, uint32_t idx, int l) {
   const size_t o = (size_t)idx * kVox + l;
   v.tprev[o] = 0;
@@ -257,10 +301,14 @@ __device__ inline void init_cube(const VolDev& v, uint32_t idx, int l) {
   v.evtx[((size_t)idx * 3 + 2) * kVox + l] = -1;
 }
 
+// ============================================================================
+// fusion (Eq. 2) and import
+// ============================================================================
 __global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
                                               const float* __restrict__ depth) {
   const uint32_t n = min(v.cnt->n_frame, v.max_blocks);
   const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
+  if (blockIdx.x == 0 && l == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
   for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
     const uint32_t e = v.frame_list[i];
     if (e == kNone) continue;
@@ -270,8 +318,12 @@ __global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
     unpack_key(v.block_key[idx], bx, by, bz);
     const size_t o = (size_t)idx * kVox + l;
     float d = 0.f, w = 0.f;
-    if (isnew) init_cube(v, idx, l);
-    else d = v.d[o], w = v.w[o];
+    if (isnew) {
+      init_cube(v, idx, l);
+      link_block(v, idx, l);
+    } else {
+      d = v.d[o], w = v.w[o];
+    }
     const FuseSample fs = fuse_sample(v, fp, depth, 8 * bx + lx, 8 * by + ly, 8 * bz + lz);
     if (fs.upd) {
       float num = d * w;
@@ -293,11 +345,15 @@ __global__ __launch_bounds__(512) void k_import_copy(VolDev v, const float* __re
                                                      uint32_t frame) {
   const uint32_t n = min(v.cnt->n_frame, v.max_blocks);
   const int l = threadIdx.x;
+  if (blockIdx.x == 0 && l == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
   for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
     const uint32_t e = v.frame_list[i];
     if (e == kNone) continue;
     const uint32_t idx = e & ~kNewFlag;
-    if (e & kNewFlag) init_cube(v, idx, l);
+    if (e & kNewFlag) {
+      init_cube(v, idx, l);
+      link_block(v, idx, l);
+    }
     const size_t src = (size_t)v.frame_src[i] * kVox + l;
     const size_t o = (size_t)idx * kVox + l;
     v.d[o] = tsdf[src];
@@ -311,21 +367,41 @@ __global__ __launch_bounds__(512) void k_import_copy(VolDev v, const float* __re
 // ============================================================================
 
 // Dirty = pending blocks and their allocated neighbours at offsets {-1,0}^3.
-__global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass) {
-  const uint32_t n = min(v.cnt->n_pending, v.max_blocks);
-  const uint32_t total = n * 8u;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < total; base += stride) {
-    const uint32_t t = base + threadIdx.x;
-    bool claim = false;
-    int32_t nb = -1;
-    if (t < total) {
+// Candidates (8 per pending block) are claimed through a per-block pass
+// stamp and compacted tile by tile, one atomic per tile.
+__global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t epoch) {
+  __shared__ uint32_t swave[16];
+  __shared__ uint32_t sbase;
+  const uint32_t np = min(v.cnt->n_pending[epoch & 1], v.max_blocks);
+  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->n_pending[(epoch + 1) & 1] = 0;
+  const uint32_t total = np * 8u;
+  for (uint32_t t0 = blockIdx.x * kTile; t0 < total; t0 += gridDim.x * kTile) {
+    int32_t got[4];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t t = t0 + threadIdx.x * 4 + k;
+      got[k] = -1;
+      if (t >= total) continue;
       const uint32_t idx = v.pending[t >> 3], o = t & 7u;
-      nb = v.nbr[(size_t)idx * 27 + nbr_dir(-(int)(o & 1), -(int)((o >> 1) & 1), -(int)(o >> 2))];
-      if (nb >= 0 && v.st_dirty[nb] != pass) claim = atomicMax(&v.st_dirty[nb], pass) < pass;
+      if (idx == kNone) continue;
+      const int32_t nb =
+          v.nbr[(size_t)idx * 27 + nbr_dir(-(int)(o & 1), -(int)((o >> 1) & 1), -(int)(o >> 2))];
+      if (nb >= 0 && v.st_dirty[nb] != pass && atomicMax(&v.st_dirty[nb], pass) < pass) {
+        got[k] = nb;
+        ++cnt;
+      }
     }
-    const uint32_t p = wave_ticket(&v.cnt->n_dirty, claim);
-    if (claim) v.dirty[p] = (uint32_t)nb;
+    uint32_t tot;
+    uint32_t r = wg_scan(cnt, swave, &tot);
+    if (tot == 0) continue;
+    if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_dirty, tot);
+    __syncthreads();
+    r += sbase;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (got[k] >= 0) v.dirty[r++] = (uint32_t)got[k];
+    __syncthreads();
   }
 }
 
@@ -335,7 +411,11 @@ __global__ __launch_bounds__(256) void k_dirty_all(VolDev v, uint32_t pass) {
     v.dirty[i] = i;
     v.st_dirty[i] = pass;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->n_dirty = n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    v.cnt->n_dirty = n;
+    v.cnt->n_pending[0] = 0;
+    v.cnt->n_pending[1] = 0;
+  }
 }
 
 __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc[8], float eps) {
@@ -361,196 +441,267 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
   return keep_prev ? prev : kRegular[best];
 }
 
-// One workgroup per dirty block, one lane per cube.  The block's 8^3 corners
-// plus the +x/+y/+z halo layer (9^3) are staged in LDS.  refine = 0: new
-// cube types from the signs (Sec. V-B), previous type saved.  refine = 1:
-// Eqs. (3)-(5) applied to the current types (Sec. V-F).
-__global__ __launch_bounds__(512) void k_classify(VolDev v, uint32_t pass, int refine) {
-  __shared__ float sd[729];
-  __shared__ uint8_t sok[729];
-  __shared__ int32_t snb[8];
-  __shared__ uint32_t sflags, srefined;
+// One wave per dirty block, four blocks per workgroup, no workgroup
+// barriers: per-block work is a chain of dependent memory round trips, and
+// many independent waves hide it better than one wide workgroup.  Lane q
+// owns the column (q & 7, q >> 3) of cubes, z = 0..7.  The block's corners
+// plus the +x/+y/+z halo layer (9^3) are staged in the wave's LDS.
+// refine = 0: new cube types from the signs (Sec. V-B), previous type
+// saved.  refine = 1: Eqs. (3)-(5) applied to the current types (Sec. V-F).
+// Cubes whose triangles change are recorded in the block's bitmask (one
+// 64-bit word per z layer); the blocks owning their edges (this one and, on
+// its +x/+y/+z faces, neighbours) become vertex-block candidates at fixed
+// positions 8i..8i+7.
+__global__ __launch_bounds__(256) void k_classify(VolDev v, uint32_t pass, int refine) {
+  __shared__ float sd_all[4][729];
+  __shared__ uint8_t sok_all[4][732];
+  __shared__ int32_t snb_all[4][8];
+  const int wave = threadIdx.x >> 6, q = __lane_id(), lx = q & 7, ly = q >> 3;
+  float* sd = sd_all[wave];
+  uint8_t* sok = sok_all[wave];
+  int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
-  const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
   const int coff[8] = {0, 1, 1 + 9, 9, 81, 1 + 81, 1 + 9 + 81, 9 + 81};
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+  for (uint32_t i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
     const uint32_t idx = v.dirty[i];
-    if (l < 8) snb[l] = v.nbr[(size_t)idx * 27 + nbr_dir(l & 1, (l >> 1) & 1, l >> 2)];
-    if (l == 0) sflags = 0, srefined = 0;
-    __syncthreads();
-    for (int j = l; j < 729; j += 512) {
-      const int x = j % 9, y = (j / 9) % 9, z = j / 81;
-      const int nb = snb[(x >> 3) | ((y >> 3) << 1) | ((z >> 3) << 2)];
-      float dv = 0.f;
-      uint8_t ok = 0;
-      if (nb >= 0) {
-        const size_t o = (size_t)nb * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7);
-        dv = v.d[o];
-        ok = v.w[o] > 0.f;
-      }
-      sd[j] = dv;
-      sok[j] = ok;
-    }
-    __syncthreads();
-    const int base = lx + 9 * ly + 81 * lz;
-    bool valid = true;
-    uint32_t t = 0;
-    float dc[8];
+    const int32_t mynb = q < 8 ? v.nbr[(size_t)idx * 27 + nbr_dir(q & 1, (q >> 1) & 1, q >> 2)] : -1;
+    if (q < 8) snb[q] = mynb;
+    wave_sync();
+    {
+      // all loads of the 9^3 halo first, then the LDS stores
+      float dv[12], wv[12];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      valid = valid && sok[base + coff[k]];
-      dc[k] = sd[base + coff[k]];
-      t |= (uint32_t)(dc[k] < 0.f) << k;
+      for (int it = 0; it < 12; ++it) {
+        const int j = q + 64 * it;
+        dv[it] = 0.f, wv[it] = 0.f;
+        if (j < 729) {
+          const int x = j % 9, y = (j / 9) % 9, z = j / 81;
+          const int nb = snb[(x >> 3) | ((y >> 3) << 1) | ((z >> 3) << 2)];
+          if (nb >= 0) {
+            const size_t o = (size_t)nb * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7);
+            dv[it] = v.d[o];
+            wv[it] = v.w[o];
+          }
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < 12; ++it) {
+        const int j = q + 64 * it;
+        if (j < 729) {
+          sd[j] = dv[it];
+          sok[j] = wv[it] > 0.f;
+        }
+      }
     }
-    if (!valid) t = 0;
-    const size_t o = (size_t)idx * kVox + l;
-    const uint32_t old = v.tcur[o];
-    uint32_t nt;
-    if (!refine) {
-      v.tprev[o] = (uint8_t)old;
-      nt = t;
-    } else {
-      nt = valid ? refine_type(old, v.tprev[o], dc, v.eps) : old;
+    wave_sync();
+    uint32_t flags = 0, nchanged = 0;
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      const int base = lx + 9 * ly + 81 * lz;
+      bool valid = true;
+      uint32_t t = 0;
+      float dc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        valid = valid && sok[base + coff[k]];
+        dc[k] = sd[base + coff[k]];
+        t |= (uint32_t)(dc[k] < 0.f) << k;
+      }
+      if (!valid) t = 0;
+      const size_t o = (size_t)idx * kVox + q + 64 * lz;
+      const uint32_t old = v.tcur[o];
+      uint32_t nt;
+      if (!refine) {
+        v.tprev[o] = (uint8_t)old;
+        nt = t;
+      } else {
+        nt = valid ? refine_type(old, v.tprev[o], dc, v.eps) : old;
+      }
+      if (nt != old) v.tcur[o] = (uint8_t)nt;
+      const bool tri_change = nt != old && (v.tri_table[old * 16] || v.tri_table[nt * 16]);
+      const uint64_t m = __ballot(tri_change);
+      if (q == 0) v.chg[(size_t)idx * 8 + lz] = m;
+      nchanged += (uint32_t)__popcll(m);
+      if (tri_change) {
+        // owners of this cube's edges: this block and, on its +x/+y/+z
+        // faces, the neighbours (never the +x+y+z corner one)
+        const bool ex = lx == 7, ey = ly == 7, ez = lz == 7;
+        flags |= 1u | (ex ? 2u : 0u) | (ey ? 4u : 0u) | (ez ? 16u : 0u) | (ex && ey ? 8u : 0u) |
+                 (ex && ez ? 32u : 0u) | (ey && ez ? 64u : 0u);
+      }
     }
-    if (nt != old) v.tcur[o] = (uint8_t)nt;
-    const bool tri_change = nt != old && (v.tri_table[old * 16] || v.tri_table[nt * 16]);
-    const uint32_t p = wave_ticket(&v.cnt->n_changed, tri_change);
-    if (tri_change) {
-      if (p < v.max_changed) v.changed[p] = (idx << 9) | (uint32_t)l;
-      else atomicOr(&v.cnt->error, kErrTris);
-      // owners of this cube's edges: this block and, on its +x/+y/+z
-      // faces, the neighbours (never the +x+y+z corner one)
-      const bool ex = lx == 7, ey = ly == 7, ez = lz == 7;
-      uint32_t f = 1u | (ex ? 2u : 0u) | (ey ? 4u : 0u) | (ez ? 16u : 0u) | (ex && ey ? 8u : 0u) |
-                   (ex && ez ? 32u : 0u) | (ey && ez ? 64u : 0u);
-      atomicOr(&sflags, f);
-      if (refine) atomicAdd(&srefined, 1u);
-    }
-    __syncthreads();
-    if (l < 64) {
+    // wave-wide OR of the owner flags
+    uint32_t wflags = refine ? 0u : 1u;
+    for (int b = 0; b < 7; ++b)
+      if (__ballot((flags >> b) & 1u)) wflags |= 1u << b;
+    if (q < 8) {
       // extraction recomputes every dirty block's vertices (their end
       // points may have moved); refinement only blocks with changed cubes
-      const uint32_t flags = sflags | (refine ? 0u : 1u);
-      int32_t nb = -1;
-      bool claim = false;
-      if (l < 8 && ((flags >> l) & 1u)) {
-        nb = l == 0 ? (int32_t)idx : snb[l];
-        if (nb >= 0 && v.st_vtx[nb] != pass) claim = atomicMax(&v.st_vtx[nb], pass) < pass;
+      uint32_t out = kNone;
+      if ((wflags >> q) & 1u) {
+        const int32_t nb = q == 0 ? (int32_t)idx : mynb;
+        if (nb >= 0 && v.st_vtx[nb] != pass && atomicMax(&v.st_vtx[nb], pass) < pass)
+          out = (uint32_t)nb;
       }
-      const uint32_t q = wave_ticket(&v.cnt->n_vblocks, claim);
-      if (claim) v.vblocks[q] = (uint32_t)nb;
-      if (l == 0 && srefined) atomicAdd(&v.cnt->st_refined, srefined);
+      v.vcand[(size_t)i * 8 + q] = out;
     }
+    if (refine && q == 0 && nchanged) atomicAdd(&v.cseg[idx % kSegs].st_ref, nchanged);
+    wave_sync();
+  }
+}
+
+// Compact the vertex-block candidates (8 per dirty block), one atomic per tile.
+__global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
+  __shared__ uint32_t swave[16];
+  __shared__ uint32_t sbase;
+  const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
+  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_DIRTY_BLOCKS] += n;
+  const uint32_t total = n * 8u;
+  for (uint32_t t0 = blockIdx.x * kTile; t0 < total; t0 += gridDim.x * kTile) {
+    uint32_t got[4], cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t t = t0 + threadIdx.x * 4 + k;
+      got[k] = t < total ? v.vcand[t] : kNone;
+      cnt += got[k] != kNone;
+    }
+    uint32_t tot;
+    uint32_t r = wg_scan(cnt, swave, &tot);
+    if (tot == 0) continue;
+    if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_vblocks, tot);
+    __syncthreads();
+    r += sbase;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (got[k] != kNone) v.vblocks[r++] = got[k];
     __syncthreads();
   }
 }
 
-// One workgroup per listed block, one lane per voxel.  Each voxel owns the
-// edges from it along +x, +y, +z.  The reference count of an edge is the
-// number of triangles, over the four cubes around it, that use it; a
-// positive count needs a vertex (created here on first use), whose
-// parameter t is rewritten from the end point TSDF values.  The counts come
-// from cube types staged in LDS with the -x/-y/-z halo, so no atomics and no
-// per-triangle increments are needed.
-__global__ __launch_bounds__(512) void k_vertices(VolDev v) {
+// One wave per listed block.  Each voxel owns the edges from it along +x,
+// +y, +z.  The reference count of an edge is the number of triangles, over
+// the four cubes around it, that use it; a positive count needs a vertex
+// (created here on first use, Sec. V-C), whose parameter t is rewritten
+// from the end point TSDF values.  The counts come from cube types staged
+// in LDS with the -x/-y/-z halo, so no per-triangle increments are needed.
+// New vertices take slots from the block's pool segment, one atomic per
+// block.
+__global__ __launch_bounds__(256) void k_vertices(VolDev v) {
   __shared__ uint8_t suses[256 * 12];
-  __shared__ uint8_t st[729];   // cube types at local -1..7
-  __shared__ float sd[729];     // TSDF at local 0..8
-  __shared__ int32_t snb[27];
-  __shared__ uint32_t swave[8];
-  __shared__ uint32_t sbase, snew, supd;
-  const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
+  __shared__ uint8_t st_all[4][732];   // cube types at local -1..7
+  __shared__ float sd_all[4][729];     // TSDF at local 0..8
+  __shared__ int32_t snb_all[4][27];
+  const int wave = threadIdx.x >> 6, q = __lane_id(), lx = q & 7, ly = q >> 3;
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(v.edge_uses);
     uint32_t* dst = reinterpret_cast<uint32_t*>(suses);
-    for (int j = l; j < 256 * 12 / 4; j += 512) dst[j] = src[j];
+    for (int j = threadIdx.x; j < 256 * 12 / 4; j += blockDim.x) dst[j] = src[j];
   }
+  __syncthreads();
+  uint8_t* st = st_all[wave];
+  float* sd = sd_all[wave];
+  int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_vblocks, v.max_blocks);
-  const uint32_t head = v.cnt->vtx_head, tail = v.cnt->vtx_tail, hwm = v.cnt->vtx_hwm;
-  const int wave = l >> 6;
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
+  for (uint32_t i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
     const uint32_t idx = v.vblocks[i];
-    if (l < 27) snb[l] = v.nbr[(size_t)idx * 27 + l];
-    if (l == 0) snew = 0, supd = 0;
-    __syncthreads();
-    for (int j = l; j < 729; j += 512) {
-      const int x = j % 9, y = (j / 9) % 9, z = j / 81;
-      const int cx = x - 1, cy = y - 1, cz = z - 1;
-      const int nb = snb[nbr_dir(cx < 0 ? -1 : 0, cy < 0 ? -1 : 0, cz < 0 ? -1 : 0)];
-      st[j] = nb >= 0 ? v.tcur[(size_t)nb * kVox + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7)] : 0;
-      const int nb2 = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
-      sd[j] = nb2 >= 0 ? v.d[(size_t)nb2 * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)] : 0.f;
-    }
-    __syncthreads();
-    const int tb = (lx + 1) + 9 * (ly + 1) + 81 * (lz + 1);
-#define USES(c, e) ((uint32_t)suses[(uint32_t)st[c] * 12 + (e)])
-    uint32_t ref[3];
-    ref[0] = USES(tb, 0) + USES(tb - 9, 2) + USES(tb - 81, 4) + USES(tb - 90, 6);
-    ref[1] = USES(tb, 3) + USES(tb - 1, 1) + USES(tb - 81, 7) + USES(tb - 82, 5);
-    ref[2] = USES(tb, 8) + USES(tb - 1, 9) + USES(tb - 10, 10) + USES(tb - 9, 11);
-#undef USES
-    size_t eo[3];
-    int32_t slot[3];
-    bool need[3];
+    const uint32_t sg = idx % kSegs;
+    if (q < 27) snb[q] = v.nbr[(size_t)idx * 27 + q];
+    wave_sync();
+    {
+      // all loads of the two halos first, then the LDS stores
+      uint32_t tv[12];
+      float dv[12];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      eo[a] = ((size_t)idx * 3 + a) * kVox + l;
-      slot[a] = v.evtx[eo[a]];
-      need[a] = ref[a] > 0 && slot[a] < 0;
-    }
-    const uint64_t m0 = __ballot(need[0]), m1 = __ballot(need[1]), m2 = __ballot(need[2]);
-    const uint32_t c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2);
-    const uint64_t lt = lanes_below();
-    uint32_t rank[3];
-    rank[0] = __popcll(m0 & lt);
-    rank[1] = c0 + __popcll(m1 & lt);
-    rank[2] = c0 + c1 + __popcll(m2 & lt);
-    if (__lane_id() == 0) swave[wave] = c0 + c1 + c2;
-    __syncthreads();
-    if (l == 0) {
-      uint32_t acc = 0;
-      for (int w = 0; w < 8; ++w) {
-        const uint32_t c = swave[w];
-        swave[w] = acc;
-        acc += c;
+      for (int it = 0; it < 12; ++it) {
+        const int j = q + 64 * it;
+        tv[it] = 0, dv[it] = 0.f;
+        if (j < 729) {
+          const int x = j % 9, y = (j / 9) % 9, z = j / 81;
+          const int cx = x - 1, cy = y - 1, cz = z - 1;
+          const int nb = snb[nbr_dir(cx < 0 ? -1 : 0, cy < 0 ? -1 : 0, cz < 0 ? -1 : 0)];
+          const int nb2 = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
+          if (nb >= 0) tv[it] = v.tcur[(size_t)nb * kVox + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7)];
+          if (nb2 >= 0) dv[it] = v.d[(size_t)nb2 * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+        }
       }
-      sbase = acc ? atomicAdd(&v.cnt->vtx_ticket, acc) : 0u;
+#pragma unroll
+      for (int it = 0; it < 12; ++it) {
+        const int j = q + 64 * it;
+        if (j < 729) {
+          st[j] = (uint8_t)tv[it];
+          sd[j] = dv[it];
+        }
+      }
     }
-    __syncthreads();
-    const uint32_t tk = sbase + swave[wave];
-    const int sdb = lx + 9 * ly + 81 * lz;
+    wave_sync();
+    int32_t slot[8][3];
+    uint32_t refs[3] = {0, 0, 0};  // 8 counts of 4 bits per axis
+    uint32_t nneed = 0;
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      const int tb = (lx + 1) + 9 * (ly + 1) + 81 * (lz + 1);
+#define USES(c, e) ((uint32_t)suses[(uint32_t)st[c] * 12 + (e)])
+      const uint32_t r0 = USES(tb, 0) + USES(tb - 9, 2) + USES(tb - 81, 4) + USES(tb - 90, 6);
+      const uint32_t r1 = USES(tb, 3) + USES(tb - 1, 1) + USES(tb - 81, 7) + USES(tb - 82, 5);
+      const uint32_t r2 = USES(tb, 8) + USES(tb - 1, 9) + USES(tb - 10, 10) + USES(tb - 9, 11);
+#undef USES
+      refs[0] |= r0 << (4 * lz);
+      refs[1] |= r1 << (4 * lz);
+      refs[2] |= r2 << (4 * lz);
+      const uint32_t r[3] = {r0, r1, r2};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        slot[lz][a] = v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
+        nneed += r[a] > 0 && slot[lz][a] < 0;
+      }
+    }
+    uint32_t total;
+    uint32_t rank = wave_scan(nneed, &total);
+    uint32_t base = 0;
+    if (q == 0 && total) base = atomicAdd(&v.vseg[sg].ticket, total);
+    rank += __shfl(base, 0);
+    const Seg& g = v.vseg[sg];
+    const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
+    const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
     const int step[3] = {1, 9, 81};
     uint32_t nnew = 0, nupd = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (ref[a] > 0) {
-        int32_t s = slot[a];
-        if (s < 0) {
-          const uint32_t ns = ticket_slot(tk + rank[a], v.vring, head, tail, hwm, v.max_vertices);
-          if (ns == kNone) {
-            atomicOr(&v.cnt->error, kErrVertices);
-            continue;
+    for (int lz = 0; lz < 8; ++lz) {
+      const int sdb = lx + 9 * ly + 81 * lz;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const uint32_t ref = (refs[a] >> (4 * lz)) & 15u;
+        int32_t s = slot[lz][a];
+        if (ref > 0) {
+          if (s < 0) {
+            const uint32_t ns = seg_slot(head, tail, hwm, rank++, v.vring, gbase, gsize);
+            if (ns == kNone) {
+              atomicOr(&v.cnt->error, kErrVertices);
+              continue;
+            }
+            s = (int32_t)ns;
+            const size_t eo = ((size_t)idx * 3 + a) * kVox + q + 64 * lz;
+            v.evtx[eo] = s;
+            v.vowner[s] = (uint32_t)eo;
+            ++nnew;
+          } else {
+            ++nupd;
           }
-          s = (int32_t)ns;
-          v.evtx[eo[a]] = s;
-          v.vowner[s] = (uint32_t)eo[a];
-          ++nnew;
-        } else {
-          ++nupd;
+          v.vt[s] = edge_param(sd[sdb], sd[sdb + step[a]]);
+          v.vref[s] = (int32_t)ref;
+        } else if (s >= 0) {
+          v.vref[s] = 0;
         }
-        v.vt[s] = edge_param(sd[sdb], sd[sdb + step[a]]);
-        v.vref[s] = (int32_t)ref[a];
-      } else if (slot[a] >= 0) {
-        v.vref[slot[a]] = 0;
       }
     }
-    if (nnew) atomicAdd(&snew, nnew);
-    if (nupd) atomicAdd(&supd, nupd);
-    __syncthreads();
-    if (l == 0) {
-      if (snew) atomicAdd(&v.cnt->st_new_vtx, snew);
-      if (supd) atomicAdd(&v.cnt->st_upd_vtx, supd);
+    nnew = wave_sum(nnew);
+    nupd = wave_sum(nupd);
+    if (q == 0) {
+      if (nnew) atomicAdd(&v.vseg[sg].st_new, nnew);
+      if (nupd) atomicAdd(&v.vseg[sg].st_upd, nupd);
     }
+    wave_sync();
   }
 }
 
@@ -567,83 +718,164 @@ __device__ inline void edge_owner(int e, int& ox, int& oy, int& oz, int& axis) {
   axis = (int)(p >> 3);
 }
 
-// One lane per cube whose triangles changed: (re)write its triangle chunk
-// as vertex slots of the owning edges, or recycle the chunk when the cube's
-// new type has no triangles (Sec. V-D).  Unchanged cubes keep theirs.
+// One wave per dirty block: every cube whose triangles changed (re)writes
+// its triangle chunk as vertex slots of the owning edges, or recycles the
+// chunk when its new type has no triangles (Sec. V-D).  Unchanged cubes
+// keep theirs.  The changed cubes are listed in LDS; allocation and frees
+// take one atomic each per block on the block's chunk segment; each chunk
+// (64 bytes) is then written by 16 lanes.
 __global__ __launch_bounds__(256) void k_triangles(VolDev v) {
-  const uint32_t n = min(v.cnt->n_changed, v.max_changed);
-  const uint32_t head = v.cnt->chk_head, tail = v.cnt->chk_tail, hwm = v.cnt->chk_hwm;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-    const uint32_t i = base + threadIdx.x;
-    const bool act = i < n;
-    uint32_t idx = 0, l = 0, type = 0, ntri = 0;
-    int32_t chunk = -1;
-    if (act) {
-      const uint32_t e = v.changed[i];
-      idx = e >> 9;
-      l = e & 511u;
-      type = v.tcur[(size_t)idx * kVox + l];
-      ntri = v.tri_table[type * 16];
-      chunk = v.cchunk[(size_t)idx * kVox + l];
+  __shared__ uint8_t stri[256 * 16];
+  __shared__ uint16_t slist_all[4][512];
+  __shared__ int32_t schunk_all[4][512];
+  __shared__ uint8_t stype_all[4][512];
+  __shared__ int32_t snb_all[4][27];
+  const int wave = threadIdx.x >> 6, q = __lane_id();
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(v.tri_table);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(stri);
+    for (int j = threadIdx.x; j < 256 * 16 / 4; j += blockDim.x) dst[j] = src[j];
+  }
+  __syncthreads();
+  uint16_t* slist = slist_all[wave];
+  int32_t* schunk = schunk_all[wave];
+  uint8_t* stype = stype_all[wave];
+  int32_t* snb = snb_all[wave];
+  const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
+  for (uint32_t i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
+    const uint32_t idx = v.dirty[i];
+    const uint64_t mymask = q < 8 ? v.chg[(size_t)idx * 8 + q] : 0ull;
+    if (!__ballot(mymask != 0ull)) continue;
+    if (q < 27) snb[q] = v.nbr[(size_t)idx * 27 + q];
+    const uint32_t sg = idx % kSegs;
+    // list the changed cubes, z layer by z layer
+    uint32_t nchg = 0;
+    for (int lz = 0; lz < 8; ++lz) {
+      const uint64_t m = shfl64(mymask, lz);
+      if ((m >> q) & 1ull) slist[nchg + __popcll(m & lanes_below())] = (uint16_t)(q + 64 * lz);
+      nchg += (uint32_t)__popcll(m);
     }
-    const bool want_alloc = act && ntri > 0 && chunk < 0;
-    const bool want_free = act && ntri == 0 && chunk >= 0;
-    const uint32_t ta = wave_ticket(&v.cnt->chk_ticket, want_alloc);
-    const uint32_t tf = wave_ticket(&v.cnt->chk_push, want_free);
-    if (want_free) {
-      v.chunks[(size_t)chunk * kChunkWords] = kNone;
-      v.cring[(uint32_t)(((uint64_t)tail + tf) % v.max_chunks)] = (uint32_t)chunk;
-      v.cchunk[(size_t)idx * kVox + l] = -1;
+    wave_sync();
+    // pass 1: types, chunks and the allocations / frees they need
+    uint32_t nalloc = 0, nfree = 0;
+    for (uint32_t c = q; c < nchg; c += 64) {
+      const size_t o = (size_t)idx * kVox + slist[c];
+      const uint32_t type = v.tcur[o];
+      const int32_t chunk = v.cchunk[o];
+      const uint32_t ntri = stri[type * 16];
+      stype[c] = (uint8_t)type;
+      schunk[c] = chunk;
+      nalloc += ntri > 0 && chunk < 0;
+      nfree += ntri == 0 && chunk >= 0;
     }
-    if (!act || ntri == 0) continue;
-    if (chunk < 0) {
-      const uint32_t ns = ticket_slot(ta, v.cring, head, tail, hwm, v.max_chunks);
-      if (ns == kNone) {
-        atomicOr(&v.cnt->error, kErrTris);
-        continue;
-      }
-      chunk = (int32_t)ns;
-      v.cchunk[(size_t)idx * kVox + l] = chunk;
+    uint32_t ta, tf;
+    uint32_t ra = wave_scan(nalloc, &ta), rf = wave_scan(nfree, &tf);
+    uint32_t ba = 0, bf = 0;
+    if (q == 0) {
+      if (ta) ba = atomicAdd(&v.cseg[sg].ticket, ta);
+      if (tf) bf = atomicAdd(&v.cseg[sg].push, tf);
+      atomicAdd(&v.cseg[sg].st_chg, nchg);
     }
-    uint32_t* c = v.chunks + (size_t)chunk * kChunkWords;
-    c[0] = (idx << 9) | l;
-    const int lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
-    const uint8_t* tt = v.tri_table + type * 16 + 1;
-    for (int k = 0; k < 15; ++k) {
-      uint32_t slot = kNone;
-      if (k < (int)(3 * ntri)) {
-        int ox, oy, oz, axis;
-        edge_owner(tt[k], ox, oy, oz, axis);
-        const int x = lx + ox, y = ly + oy, z = lz + oz;
-        const int dir = nbr_dir(x >> 3, y >> 3, z >> 3);
-        const int32_t nb = dir == kSelf ? (int32_t)idx : v.nbr[(size_t)idx * 27 + dir];
-        if (nb >= 0) {
-          const int32_t s = v.evtx[((size_t)nb * 3 + axis) * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
-          slot = s >= 0 ? (uint32_t)s : kNone;
+    ra += __shfl(ba, 0);
+    rf += __shfl(bf, 0);
+    const Seg& g = v.cseg[sg];
+    const uint32_t gbase = sg * v.cseg_cap, gsize = seg_size(sg, v.cseg_cap, v.max_chunks);
+    // pass 2: take or recycle the chunks
+    for (uint32_t c = q; c < nchg; c += 64) {
+      const size_t o = (size_t)idx * kVox + slist[c];
+      const uint32_t ntri = stri[stype[c] * 16];
+      int32_t chunk = schunk[c];
+      if (ntri == 0) {
+        if (chunk >= 0) {
+          v.chunks[(size_t)chunk * kChunkWords] = kNone;
+          v.cring[gbase + (uint32_t)(((uint64_t)g.tail + rf++) % gsize)] = (uint32_t)chunk;
+          v.cchunk[o] = -1;
+        }
+        chunk = -1;
+      } else if (chunk < 0) {
+        const uint32_t ns = seg_slot(g.head, g.tail, g.hwm, ra++, v.cring, gbase, gsize);
+        if (ns == kNone) {
+          atomicOr(&v.cnt->error, kErrTris);
+        } else {
+          chunk = (int32_t)ns;
+          v.cchunk[o] = chunk;
         }
       }
-      c[1 + k] = slot;
+      schunk[c] = chunk;
     }
+    wave_sync();
+    // pass 3: write the chunks, 16 lanes (64 bytes) per cube; up to 32
+    // cubes per round, all edge-slot gathers issued before the stores
+    const int k = q & 15;
+    for (uint32_t c0 = 0; c0 < nchg; c0 += 32) {
+      uint32_t word[8];
+      int32_t dst[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const uint32_t c = c0 + 4 * r + (q >> 4);
+        dst[r] = -1;
+        word[r] = kNone;
+        if (c >= nchg) continue;
+        const int32_t chunk = schunk[c];
+        if (chunk < 0) continue;
+        dst[r] = chunk;
+        const uint32_t l = slist[c], type = stype[c];
+        const uint32_t ntri = stri[type * 16];
+        if (k == 0) {
+          word[r] = (idx << 9) | l;
+        } else if (k - 1 < (int)(3 * ntri)) {
+          int ox, oy, oz, axis;
+          edge_owner(stri[type * 16 + k], ox, oy, oz, axis);
+          const int x = (int)(l & 7) + ox, y = (int)((l >> 3) & 7) + oy, z = (int)(l >> 6) + oz;
+          const int32_t nb = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
+          if (nb >= 0) {
+            const int32_t s =
+                v.evtx[((size_t)nb * 3 + axis) * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+            word[r] = s >= 0 ? (uint32_t)s : kNone;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        if (dst[r] >= 0) v.chunks[(size_t)dst[r] * kChunkWords + k] = word[r];
+    }
+    wave_sync();
   }
 }
 
 // ============================================================================
 // garbage collection (Sec. V-E)
 // ============================================================================
-__global__ __launch_bounds__(256) void k_gc(VolDev v) {
-  const uint32_t n = v.cnt->vtx_hwm;
-  const uint32_t tail = v.cnt->vtx_tail;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-    const uint32_t i = base + threadIdx.x;
-    const bool dead = i < n && v.vref[i] == 0;
-    const uint32_t p = wave_ticket(&v.cnt->vtx_push, dead);
-    if (dead) {
-      v.evtx[v.vowner[i]] = -1;
-      v.vref[i] = -1;
-      v.vring[(uint32_t)(((uint64_t)tail + p) % v.max_vertices)] = i;
-    }
+
+// Workgroup w scans part w / kSegs of vertex segment w % kSegs up to its
+// high-water mark and recycles the slots no triangle references.
+__global__ __launch_bounds__(256) void k_gc(VolDev v, uint32_t parts) {
+  __shared__ uint32_t swave[16];
+  __shared__ uint32_t sbase;
+  const uint32_t sg = blockIdx.x % kSegs, part = blockIdx.x / kSegs;
+  const Seg& g = v.vseg[sg];
+  const uint32_t hwm = g.hwm, tail = g.tail;
+  const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
+  const uint32_t per = (hwm + parts - 1) / parts;
+  const uint32_t r0 = part * per, r1 = min(hwm, r0 + per);
+  if (r0 >= r1) return;
+  uint32_t cnt = 0;
+  for (uint32_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) cnt += v.vref[gbase + k] == 0;
+  uint32_t tot;
+  uint32_t r = wg_scan(cnt, swave, &tot);
+  if (tot == 0) return;
+  if (threadIdx.x == 0) {
+    sbase = atomicAdd(&v.vseg[sg].push, tot);
+    atomicAdd(&v.vseg[sg].st_freed, tot);
+  }
+  __syncthreads();
+  r += sbase;
+  for (uint32_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) {
+    const uint32_t s = gbase + k;
+    if (v.vref[s] != 0) continue;
+    v.evtx[v.vowner[s]] = -1;
+    v.vref[s] = -1;
+    v.vring[gbase + (uint32_t)(((uint64_t)tail + r++) % gsize)] = s;
   }
 }
 
@@ -652,9 +884,17 @@ __global__ __launch_bounds__(256) void k_gc(VolDev v) {
 // ============================================================================
 constexpr int kScanItems = 1024;  // items per workgroup (256 lanes x 4)
 
-__device__ inline uint32_t item_count(const VolDev& v, int what, uint32_t i, uint32_t n) {
-  if (i >= n) return 0;
-  if (what == 0) return v.vref[i] > 0 ? 1u : 0u;
+__device__ inline bool slot_in_use(const Seg* seg, uint32_t cap, uint32_t i) {
+  const uint32_t s = i / cap;
+  return i - s * cap < seg[s].hwm;
+}
+
+__device__ inline uint32_t item_count(const VolDev& v, int what, uint32_t i) {
+  if (what == 0) {
+    if (i >= v.max_vertices || !slot_in_use(v.vseg, v.vseg_cap, i)) return 0;
+    return v.vref[i] > 0 ? 1u : 0u;
+  }
+  if (i >= v.max_chunks || !slot_in_use(v.cseg, v.cseg_cap, i)) return 0;
   const uint32_t* c = v.chunks + (size_t)i * kChunkWords;
   if (c[0] == kNone) return 0;
   uint32_t k = 0;
@@ -662,59 +902,27 @@ __device__ inline uint32_t item_count(const VolDev& v, int what, uint32_t i, uin
   return k;
 }
 
-// Exclusive scan of one value per lane across a 256-lane workgroup.
-__device__ inline uint32_t wg_exclusive_scan(uint32_t x, uint32_t* swave, uint32_t* total) {
-  const int lane = __lane_id(), wave = threadIdx.x >> 6;
-  uint32_t incl = x;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(incl, off);
-    if (lane >= off) incl += y;
-  }
-  if (lane == 63) swave[wave] = incl;
-  __syncthreads();
-  uint32_t before = 0, all = 0;
-  for (int w = 0; w < 4; ++w) {
-    if (w < wave) before += swave[w];
-    all += swave[w];
-  }
-  __syncthreads();
-  *total = all;
-  return before + incl - x;
-}
-
 __global__ __launch_bounds__(256) void k_dl_count(VolDev v, int what) {
-  __shared__ uint32_t swave[4];
-  const uint32_t n = what == 0 ? v.cnt->vtx_hwm : v.cnt->chk_hwm;
+  __shared__ uint32_t swave[16];
   const uint32_t i0 = blockIdx.x * kScanItems + threadIdx.x * 4;
   uint32_t c = 0;
-  for (int k = 0; k < 4; ++k) c += item_count(v, what, i0 + k, n);
+  for (int k = 0; k < 4; ++k) c += item_count(v, what, i0 + k);
   uint32_t total;
-  wg_exclusive_scan(c, swave, &total);
+  wg_scan(c, swave, &total);
   if (threadIdx.x == 0) v.scan[blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(1024) void k_dl_scan(VolDev v, int what, uint32_t nparts) {
-  __shared__ uint32_t sw[16];
+  __shared__ uint32_t swave[16];
   __shared__ uint32_t carry;
-  const int lane = __lane_id(), wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (uint32_t base = 0; base < nparts; base += 1024) {
     const uint32_t i = base + threadIdx.x;
     const uint32_t x = i < nparts ? v.scan[i] : 0u;
-    uint32_t incl = x;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(incl, off);
-      if (lane >= off) incl += y;
-    }
-    if (lane == 63) sw[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-    for (int w = 0; w < 16; ++w) {
-      if (w < wave) before += sw[w];
-      all += sw[w];
-    }
-    if (i < nparts) v.scan[i] = carry + before + incl - x;
+    uint32_t all;
+    const uint32_t before = wg_scan(x, swave, &all);
+    if (i < nparts) v.scan[i] = carry + before;
     __syncthreads();
     if (threadIdx.x == 0) carry += all;
     __syncthreads();
@@ -728,16 +936,15 @@ __global__ __launch_bounds__(1024) void k_dl_scan(VolDev v, int what, uint32_t n
 __global__ __launch_bounds__(256) void k_dl_write_vertices(VolDev v, float* __restrict__ verts,
                                                            uint64_t* __restrict__ keys,
                                                            uint32_t vcap) {
-  __shared__ uint32_t swave[4];
-  const uint32_t n = v.cnt->vtx_hwm;
+  __shared__ uint32_t swave[16];
   const uint32_t i0 = blockIdx.x * kScanItems + threadIdx.x * 4;
   uint32_t live[4], c = 0;
-  for (int k = 0; k < 4; ++k) c += (live[k] = item_count(v, 0, i0 + k, n));
+  for (int k = 0; k < 4; ++k) c += (live[k] = item_count(v, 0, i0 + k));
   uint32_t total;
-  uint32_t j = v.scan[blockIdx.x] + wg_exclusive_scan(c, swave, &total);
+  uint32_t j = v.scan[blockIdx.x] + wg_scan(c, swave, &total);
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = i0 + k;
-    if (i >= n) break;
+    if (i >= v.max_vertices) break;
     if (!live[k]) {
       v.vdl[i] = -1;
       continue;
@@ -765,18 +972,16 @@ __global__ __launch_bounds__(256) void k_dl_write_vertices(VolDev v, float* __re
 
 __global__ __launch_bounds__(256) void k_dl_write_triangles(VolDev v, int32_t* __restrict__ tris,
                                                             uint32_t tcap) {
-  __shared__ uint32_t swave[4];
-  const uint32_t n = v.cnt->chk_hwm;
+  __shared__ uint32_t swave[16];
   const uint32_t i0 = blockIdx.x * kScanItems + threadIdx.x * 4;
   uint32_t c = 0;
-  for (int k = 0; k < 4; ++k) c += item_count(v, 1, i0 + k, n);
+  for (int k = 0; k < 4; ++k) c += item_count(v, 1, i0 + k);
   uint32_t total;
-  uint32_t j = v.scan[blockIdx.x] + wg_exclusive_scan(c, swave, &total);
+  uint32_t j = v.scan[blockIdx.x] + wg_scan(c, swave, &total);
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = i0 + k;
-    if (i >= n) break;
+    if (item_count(v, 1, i) == 0) continue;
     const uint32_t* ch = v.chunks + (size_t)i * kChunkWords;
-    if (ch[0] == kNone) continue;
     for (int t = 0; t < 5; ++t) {
       if (ch[1 + 3 * t] == kNone) continue;
       if (j < tcap) {
@@ -900,9 +1105,10 @@ __global__ void k_zero_f32(float* p, uint64_t n) {
 // ============================================================================
 __global__ void k_export_vertices(VolDev v, uint64_t* keys, float* t, int32_t* ref, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int32_t r = v.vref[i];
+    const bool used = slot_in_use(v.vseg, v.vseg_cap, i);
+    const int32_t r = used ? v.vref[i] : -1;
     ref[i] = r;
-    t[i] = v.vt[i];
+    t[i] = used ? v.vt[i] : 0.f;
     uint64_t k = ~0ull;
     if (r >= 0) {
       const uint32_t owner = v.vowner[i];
@@ -910,6 +1116,14 @@ __global__ void k_export_vertices(VolDev v, uint64_t* keys, float* t, int32_t* r
       k = edge_key(v.block_key[blk], (int)(rem % kVox), (int)(rem / kVox));
     }
     keys[i] = k;
+  }
+}
+
+__global__ void k_lookup(VolDev v, const int32_t* __restrict__ coords, int32_t* __restrict__ idx,
+                         uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int x = coords[3 * i], y = coords[3 * i + 1], z = coords[3 * i + 2];
+    idx[i] = key_in_range(x, y, z) ? hash_find(v, pack_key(x, y, z)) : -1;
   }
 }
 

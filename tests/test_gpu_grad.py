@@ -1,0 +1,162 @@
+"""GPU backward passes vs the oracle's FP64 gradients (themselves pinned to
+FP64 central finite differences), through the C ABI and through the
+torch.autograd.Function wrappers.
+
+Bar: every component within 1e-4 relative, with a floor of 1e-4 times the
+largest magnitude (FP32 kernels against an FP64 reference)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from paper_1803_03949_amd import Volume, key_to_edge
+from paper_1803_03949_amd.autograd import FusedMesh
+from tests.gpu_compare import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def close(got, want, rel=1e-4):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    floor = rel * max(np.abs(want).max(), 1e-30)
+    err = np.abs(got - want)
+    bad = err > rel * np.abs(want) + floor
+    assert not bad.any(), (int(bad.sum()), float(err.max()), float(floor))
+    return float((err / (np.abs(want) + floor)).max())
+
+
+def sphere_case():
+    S = 0.01
+    sv = scenes.sphere_volume(seed=11, dims_blocks=(2, 2, 2), voxel_m=S, radius=0.05,
+                              center=np.full(3, 0.08), jitter=0.005)
+    c = sv.meta["center"]
+    pose = scenes.look_at(c + np.array([0.02, -0.30, 0.12]), c).astype(np.float32)
+    sc = scenes.Scene([(c + np.array([0.0, 0.0, 0.002]), 0.0505)], [], None)
+    depth = sc.render(pose.astype(np.float64), scenes.pixel_rays(), None, 0.1, 5.0)
+    target = scenes.Scene([(c, sv.meta["radius"] + 0.003)], [], None)
+    return sv, depth, pose, target, (0.1, 5.0)
+
+
+def grad_case():
+    gs = scenes.grad_scene(seed=4)
+    return gs.volume, gs.depth, gs.pose, gs.target, (0.1, 10.0)
+
+
+def sdf_grad(scene, pos):
+    """Loss sum of squared target distances and its gradient (FP64, torch CPU)."""
+    p = torch.tensor(pos, dtype=torch.float64, requires_grad=True)
+    x, y, z = p[:, 0], p[:, 1], p[:, 2]
+    parts = []
+    for c, r in scene.spheres:
+        parts.append(torch.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) - r)
+    for c, h, yaw in scene.boxes:
+        cs, sn = np.cos(yaw), np.sin(yaw)
+        px, py, pz = x - c[0], y - c[1], z - c[2]
+        lx, ly = cs * px + sn * py, -sn * px + cs * py
+        q = torch.stack([lx.abs() - h[0], ly.abs() - h[1], pz.abs() - h[2]], 1)
+        parts.append(torch.linalg.norm(q.clamp(min=0), dim=1) + q.max(1).values.clamp(max=0))
+    sdf = torch.stack(parts, 0).min(0).values
+    L = (sdf * sdf).sum()
+    L.backward()
+    return float(L), p.grad.numpy()
+
+
+def build_pair(case, with_frame):
+    sv, depth, pose, target, (dmin, dmax) = case
+    coords, d, w = sv.blocks()
+    o = oracle.OracleVolume(sv.voxel_m)
+    o.import_blocks(coords, d, w)
+    g = Volume(sv.voxel_m, hash_log2=16, max_blocks=1 << 14, max_vertices=1 << 20,
+               max_tri_cubes=1 << 20)
+    g.import_blocks(*to_dev(coords, d, w))
+    if with_frame:
+        o.integrate(depth, scenes.K, pose, dmin, dmax)
+        g.integrate(to_dev(depth)[0], scenes.K, pose, dmin, dmax)
+    o.extract(scope_all=True)
+    g.extract(scope_all=True)
+    o.gc()
+    g.gc()
+    return o, g
+
+
+def gpu_rows_for_oracle(g, o):
+    """For each oracle block (its export order), the GPU pool row."""
+    gc = g.export_blocks()["coords"]
+    idx = {tuple(c): i for i, c in enumerate(gc.tolist())}
+    oc = o.blocks()["coords"]
+    assert len(gc) == len(oc)
+    return np.array([idx[tuple(c)] for c in oc.tolist()])
+
+
+def dLdv_in_gpu_order(g, o, target):
+    pos = o.positions64()
+    _, dLdv = sdf_grad(target, pos)
+    okeys = o.vertices()["keys"]
+    verts, tris, keys = g.download()
+    gk = key_to_edge(keys)
+    index = {tuple(k): i for i, k in enumerate(okeys.tolist())}
+    perm = np.array([index[tuple(k)] for k in gk.tolist()])
+    return dLdv, torch.from_numpy(dLdv[perm].astype(np.float32)).cuda()
+
+
+@pytest.mark.parametrize("case", ["sphere", "scene"])
+def test_extract_and_fusion_backward_match_oracle(case):
+    c = sphere_case() if case == "sphere" else grad_case()
+    print(f"[grad] {case}", flush=True)
+    o, g = build_pair(c, with_frame=True)
+    target = c[3]
+    dLdv, dLdv_gpu = dLdv_in_gpu_order(g, o, target)
+    rows = gpu_rows_for_oracle(g, o)
+    g1 = g.extract_backward(dLdv_gpu)
+    ref1 = o.grad_tsdf64(dLdv)
+    close(g1.cpu().numpy()[rows], ref1)
+    # fusion backward on the same (FP32) upstream gradient
+    depth = to_dev(c[1])[0]
+    g0, gD = g.integrate_backward(depth, g1)
+    ref0, refD = o.grad_fusion64(g1.cpu().numpy()[rows].astype(np.float64), *c[1].shape)
+    close(g0.cpu().numpy()[rows], ref0)
+    close(gD.cpu().numpy(), refD, rel=1e-4)
+    assert np.count_nonzero(refD) > 50
+
+
+def test_autograd_function_end_to_end():
+    sv, depth, pose, target, (dmin, dmax) = sphere_case()
+    coords, d, w = sv.blocks()
+    vol = Volume(sv.voxel_m, hash_log2=12, max_blocks=4096, max_vertices=1 << 16,
+                 max_tri_cubes=1 << 16)
+    dt = to_dev(depth)[0].requires_grad_(True)
+    cd, td, wd = to_dev(coords, d, w)
+    td.requires_grad_(True)
+    verts, tris, keys = FusedMesh.apply(dt, td, wd, cd, vol, scenes.K, pose, dmin, dmax)
+    c0 = torch.tensor(target.spheres[0][0], device=verts.device, dtype=torch.float64)
+    r0 = target.spheres[0][1]
+    L = ((torch.linalg.norm(verts.double() - c0, dim=1) - r0) ** 2).sum()
+    L.backward()
+    # reference: oracle chain on the same vertex gradient
+    o, _ = build_pair((sv, depth, pose, target, (dmin, dmax)), with_frame=True)
+    okeys = o.vertices()["keys"]
+    gk = key_to_edge(keys)
+    index = {tuple(k): i for i, k in enumerate(gk.tolist())}
+    perm = np.array([index[tuple(k)] for k in okeys.tolist()])
+    vg = verts.detach().double().cpu().numpy()[perm]
+    dLdv = 2 * ((np.linalg.norm(vg - target.spheres[0][0], axis=1) - r0) /
+                np.linalg.norm(vg - target.spheres[0][0], axis=1))[:, None] * (vg - target.spheres[0][0])
+    ref1 = o.grad_tsdf64(dLdv)
+    ref0, refD = o.grad_fusion64(ref1, *depth.shape)
+    close(dt.grad.cpu().numpy(), refD, rel=1e-3)
+    # tsdf0 gradient rows follow the input coords; oracle rows follow its order
+    oc = o.blocks()["coords"]
+    oidx = {tuple(c): i for i, c in enumerate(oc.tolist())}
+    sel = np.array([oidx[tuple(c)] for c in coords.tolist()])
+    close(td.grad.cpu().numpy(), ref0[sel], rel=1e-3)
+
+
+def test_backward_is_deterministic():
+    c = grad_case()
+    o, g = build_pair(c, with_frame=True)
+    _, dLdv_gpu = dLdv_in_gpu_order(g, o, c[3])
+    a = g.extract_backward(dLdv_gpu).clone()
+    b = g.extract_backward(dLdv_gpu).clone()
+    assert torch.equal(a, b)
