@@ -6,9 +6,15 @@ slots) fused and meshed frame by frame (integrate + extract + gc) into a
 volume that starts empty.  The reported value is fused frames per second
 over the timed steps, with every depth frame already resident in HBM.
 
-Prints one JSON line.  The single-sphere extraction (blocks meshed per
-second) and the CPU oracle timed on a bounded sample of the same sequence
-are reported beside it.
+Prints one JSON line.  Beside the headline value it reports:
+  - the roofline of the dominant kernel, timed with HIP events around that
+    kernel's launches inside the timed region;
+  - the single-sphere extraction (512 blocks, blocks meshed per second);
+  - the 4 mm sequence with holes and refinement (frames per second);
+  - differentiable extraction of the 128^3 scene (forward + backward time);
+  - batched forward + backward over 64 sphere volumes in one graph launch
+    (blocks per second) against the same steps volume by volume;
+  - the CPU oracle timed on a bounded sample of the headline sequence.
 """
 from __future__ import annotations
 
@@ -23,6 +29,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
 
 def render_frames(seq, ks, workers):
     if workers <= 1:
@@ -32,33 +44,50 @@ def render_frames(seq, ks, workers):
         return list(ex.map(seq.frame, ks))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--frames", type=int, default=100)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: the method has no multi-GPU path here "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
+def algorithmic_bytes(tot, npix):
+    """Bytes each kernel must move for the work in `tot` (running totals):
+    halo re-reads and hash-probe misses excluded; per-unit figures as
+    derived in the design notes."""
+    return {
+        "collect": 4 * npix * tot["frames"],
+        "fuse": 4 * npix * tot["frames"] + 8192 * tot["frame_blocks"],
+        "classify": 5632 * tot["dirty_blocks"],
+        "vertices": 8704 * tot["vertex_blocks"] + 8 * tot["updated_vertices"]
+        + 16 * tot["new_vertices"],
+        "triangles": 96 * tot["changed_cubes"],
+        "gc": 4 * tot["gc_scanned"] + 16 * tot["freed_vertices"],
+    }
 
+
+def median_ms(fn, reps, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return float(np.median(out))
+
+
+def room_fusion(args, dev):
+    """Headline workload; returns (fields of the JSON line, frames, seq)."""
     import torch
 
     import scenes
     from paper_1803_03949_amd import Volume
 
-    assert torch.cuda.is_available(), "no GPU"
-    dev = torch.device("cuda:0")
     seq = scenes.room_sequence(seed=2, n_frames=args.frames, voxel_m=0.008)
     t0 = time.time()
     frames = render_frames(seq, range(args.frames), args.workers)
-    print(f"[bench] rendered {args.frames} frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    log(f"rendered {args.frames} frames in {time.time() - t0:.1f}s")
     depth = torch.from_numpy(np.stack(frames)).to(dev)
-    poses = [p for p in seq.poses]
+    poses = list(seq.poses)
     vol = Volume(seq.voxel_m, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23,
                  max_tri_cubes=1 << 23, device=dev)
 
@@ -72,42 +101,18 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    npix = depth.shape[1] * depth.shape[2]
 
-    # timed region, every kernel bracketed by HIP events on its stream
+    # profiling pass: every kernel bracketed by events, to find the dominant one
     tot0 = vol.totals()
     vol.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     vol.profile(False)
     prof = vol.profile_read()
-    tot1 = vol.totals()
-    st = vol.status()
-    ms_per_step = 1000.0 * dt / args.steps
-    fps = args.frames * args.steps / dt
-
-    # the same timed region without events, for the events' overhead
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    fps_noev = args.frames * args.steps / (time.perf_counter() - t0)
-
-    tot = {k: tot1[k] - tot0[k] for k in tot1}
-    npix = depth.shape[1] * depth.shape[2]
-    # algorithmic bytes each kernel must move (halo re-reads and hash probe
-    # misses excluded); per-unit figures are derived in the design notes
-    algo = {
-        "collect": 4 * npix * tot["frames"],
-        "fuse": 4 * npix * tot["frames"] + 8192 * tot["frame_blocks"],
-        "classify": 5632 * tot["dirty_blocks"],
-        "vertices": 8704 * tot["vertex_blocks"] + 8 * tot["updated_vertices"] + 16 * tot["new_vertices"],
-        "triangles": 96 * tot["changed_cubes"],
-        "gc": 4 * tot["gc_scanned"] + 16 * tot["freed_vertices"],
-    }
+    tot = {k: v - tot0[k] for k, v in vol.totals().items()}
+    algo = algorithmic_bytes(tot, npix)
     kernels = {}
     for k, (n, ms) in prof.items():
         e = {"launches": n, "ms_total": round(ms, 4), "us_per_launch": round(1000 * ms / n, 3)}
@@ -116,56 +121,291 @@ def main():
             e["GBps"] = round(algo[k] / (ms * 1e-3) / 1e9, 2)
         kernels[k] = e
     dom = max((k for k in kernels if k in algo), key=lambda k: kernels[k]["ms_total"])
-    achieved = kernels[dom]["GBps"]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": achieved / 8000.0, "traffic": None}
-    print(f"[bench] {fps:.1f} frames/s ({fps_noev:.1f} without events), blocks {st['blocks']}",
-          file=sys.stderr, flush=True)
-    for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_total"]):
-        print(f"[bench]   {k:10s} {e}", file=sys.stderr, flush=True)
 
-    # single-sphere extraction: 512 blocks, one extraction from a reset state
+    # timed region: K steps, events around the dominant kernel's launches only
+    tot0 = vol.totals()
+    vol.profile(True, kernels=[dom])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    vol.profile(False)
+    n_dom, ms_dom = vol.profile_read()[dom]
+    tot = {k: v - tot0[k] for k, v in vol.totals().items()}
+    bytes_dom = algorithmic_bytes(tot, npix)[dom]
+    achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": None, "bytes_per_launch": bytes_dom // max(n_dom, 1),
+                "us_per_launch": round(1000 * ms_dom / n_dom, 3)}
+    fps = args.frames * args.steps / dt
+
+    # the same steps without any event
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    fps_noev = args.frames * args.steps / (time.perf_counter() - t0)
+    st = vol.status()
+    log(f"{fps:.1f} frames/s ({fps_noev:.1f} without events), blocks {st['blocks']}")
+    for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_total"]):
+        log(f"  {k:10s} {e}")
+    fields = {"value": fps, "ms_per_step": 1000.0 * dt / args.steps, "roofline": roofline,
+              "value_without_events": fps_noev, "blocks": st["blocks"],
+              "totals_per_step": {k: v // args.steps for k, v in tot.items()},
+              "kernels": kernels}
+    del vol
+    return fields, frames, seq
+
+
+def sphere_extract(dev):
+    import torch
+
+    import scenes
+    from paper_1803_03949_amd import Volume
+
     sv = scenes.sphere_volume(seed=1)
     coords, d, w = sv.blocks()
     cdev = [torch.from_numpy(a).to(dev) for a in (coords, d, w)]
-    svol = Volume(sv.voxel_m, hash_log2=16, max_blocks=1024, max_vertices=1 << 20,
-                  max_tri_cubes=1 << 20, device=dev)
+    vol = Volume(sv.voxel_m, hash_log2=16, max_blocks=1024, max_vertices=1 << 20,
+                 max_tri_cubes=1 << 20, device=dev)
     times = []
     for rep in range(110):
-        svol.reset()
-        svol.import_blocks(*cdev)
-        s0 = torch.cuda.Event(enable_timing=True)
-        s1 = torch.cuda.Event(enable_timing=True)
-        s0.record()
-        svol.extract(scope_all=True)
-        s1.record()
+        vol.reset()
+        vol.import_blocks(*cdev)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        vol.extract(scope_all=True)
+        b.record()
         torch.cuda.synchronize()
         if rep >= 10:
-            times.append(s0.elapsed_time(s1))
-    sphere_ms = float(np.median(times))
+            times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    return {"blocks_per_s": 512 / (ms / 1000.0), "extract_ms": ms}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        n = 3
-        o = oracle.OracleVolume(seq.voxel_m)
-        c0 = time.perf_counter()
-        for k in range(n):
-            o.integrate(frames[k], scenes.K, poses[k], seq.min_depth, seq.max_depth)
-            o.extract()
-            o.gc()
-        cdt = time.perf_counter() - c0
-        cpu = {"value": n / cdt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {n} frames of the same sequence, integrate+extract+gc, single thread"}
+
+def room_fine(args, dev):
+    """4 mm, holes, refinement after every extraction."""
+    import torch
+
+    import scenes
+    from paper_1803_03949_amd import Volume
+
+    seq = scenes.room_sequence(seed=3, n_frames=args.fine_frames, voxel_m=0.004, holes=True)
+    t0 = time.time()
+    frames = render_frames(seq, range(args.fine_frames), args.workers)
+    log(f"rendered {args.fine_frames} 4 mm frames in {time.time() - t0:.1f}s")
+    depth = torch.from_numpy(np.stack(frames)).to(dev)
+    poses = list(seq.poses)
+    del frames
+    vol = Volume(seq.voxel_m, hash_log2=22, max_blocks=1 << 19, max_vertices=1 << 24,
+                 max_tri_cubes=1 << 24, device=dev)
+
+    def step():
+        vol.reset()
+        for k in range(args.fine_frames):
+            vol.integrate(depth[k], scenes.K, poses[k], seq.min_depth, seq.max_depth)
+            vol.extract()
+            vol.refine()
+            vol.gc()
+
+    step()
+    torch.cuda.synchronize()
+    tot0 = vol.totals()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tot = {k: v - tot0[k] for k, v in vol.totals().items()}
+    st = vol.status()
+    out = {"frames_per_s": args.fine_frames / dt, "ms_per_frame": 1000 * dt / args.fine_frames,
+           "frames": args.fine_frames, "blocks": st["blocks"],
+           "dirty_blocks_per_s": tot["dirty_blocks"] / dt, "refined_cubes": tot["refined_cubes"]}
+    log(f"4 mm + refine: {out['frames_per_s']:.1f} frames/s, blocks {st['blocks']}")
+    del vol, depth
+    torch.cuda.empty_cache()
+    return out
+
+
+def grad_scene_fwd_bwd(dev):
+    import torch
+
+    import scenes
+    from paper_1803_03949_amd import Volume
+    from paper_1803_03949_amd.autograd import FusedMesh
+
+    gs = scenes.grad_scene(seed=4)
+    coords, d, w = gs.volume.blocks()
+    vol = Volume(gs.volume.voxel_m, hash_log2=16, max_blocks=1 << 14, max_vertices=1 << 21,
+                 max_tri_cubes=1 << 21, device=dev)
+    cd, td, wd = (torch.from_numpy(a).to(dev) for a in (coords, d, w))
+    dd = torch.from_numpy(gs.depth).to(dev)
+    (c0, r0) = gs.target.spheres[0]
+    c0 = torch.tensor(c0, device=dev, dtype=torch.float32)
+
+    def fwd_bwd():
+        dt_ = dd.clone().requires_grad_(True)
+        t_ = td.clone().requires_grad_(True)
+        verts, tris, keys = FusedMesh.apply(dt_, t_, wd, cd, vol, scenes.K, gs.pose, 0.1, 10.0)
+        L = ((torch.linalg.norm(verts - c0, dim=1) - r0) ** 2).sum()
+        L.backward()
+        return verts.shape[0]
+
+    nv = fwd_bwd()
+    ms = median_ms(fwd_bwd, 20)
+    return {"fwd_bwd_ms": ms, "blocks": int(len(coords)), "vertices": int(nv),
+            "note": "includes the host synchronisation of the mesh download"}
+
+
+def batched(args, dev):
+    import torch
+
+    import scenes
+    from paper_1803_03949_amd.batch import (BatchMesher, PlainMesher, autotune,
+                                            default_space, sphere_loss_grad)
+
+    t0 = time.time()
+    vols = scenes.batch_volumes(seed=5, n=64, voxel_m=0.008)
+    coords, ds, ws = [], [], []
+    for v in vols:
+        c, d, w = v.blocks()
+        coords.append(c)
+        ds.append(d)
+        ws.append(w)
+    sizes = [len(c) for c in coords]
+    tsdf = torch.from_numpy(np.concatenate(ds)).to(dev)
+    weight = torch.from_numpy(np.concatenate(ws)).to(dev)
+    del ds, ws
+    centers = torch.tensor(np.stack([v.meta["center"] for v in vols]), dtype=torch.float32,
+                           device=dev)
+    radii = torch.tensor([v.meta["target_radius"] for v in vols], dtype=torch.float32,
+                         device=dev)
+    N = int(sum(sizes))
+    log(f"64 volumes, {N} blocks (sizes {min(sizes)}..{max(sizes)}), built in "
+        f"{time.time() - t0:.1f}s")
+
+    b = BatchMesher(0.008, coords, tsdf, weight, sphere_loss_grad(centers, radii))
+    space = default_space() if args.tune_full else \
+        [p for p in default_space() if p["block_groups_per_cu"] == 4]
+    tune = autotune(b, space=space, reps=5, log=log)
+    batch_ms = median_ms(b.replay, args.batch_reps)
+    default_launch = dict(wave_group_size=4, wave_groups_per_cu=8, block_groups_per_cu=4,
+                          item_groups_per_cu=8, block_order=0)
+    b.set_launch(**default_launch)
+    b.capture()
+    default_ms = median_ms(b.replay, args.batch_reps)
+    b.set_launch(**tune["launch"])
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    grad_b = b.grad.clone()
+
+    p = PlainMesher(0.008, coords, tsdf, weight,
+                    [sphere_loss_grad(centers[i:i + 1], radii[i:i + 1]) for i in range(64)])
+    plain_ms = median_ms(p.run, args.batch_reps)
+    identical = bool(torch.equal(p.grad(), grad_b))
+    # the per-volume sequence captured in one graph too (launch overhead removed)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        p.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        p.run()
+    plain_graph_ms = median_ms(g.replay, args.batch_reps)
+    out = {
+        "volumes": 64, "blocks": N, "sizes": sizes,
+        "batched_blocks_per_s": N / (batch_ms / 1000), "batched_ms": batch_ms,
+        "batched_default_mapping_ms": default_ms,
+        "plain_blocks_per_s": N / (plain_ms / 1000), "plain_ms": plain_ms,
+        "plain_graph_ms": plain_graph_ms,
+        "speedup_vs_plain": plain_ms / batch_ms,
+        "speedup_vs_plain_graph": plain_graph_ms / batch_ms,
+        "identical_to_plain": identical,
+        "tuned_launch": tune["launch"], "tune_points": tune.get("points"),
+        "tune_cached": tune.get("cached"),
+    }
+    log(f"batched fwd+bwd {batch_ms:.3f} ms ({out['batched_blocks_per_s']:.3e} blocks/s), "
+        f"plain {plain_ms:.3f} ms, plain graph {plain_graph_ms:.3f} ms, identical {identical}")
+    del b, p, g
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(frames, seq, n=3):
+    import oracle
+    import scenes
+
+    o = oracle.OracleVolume(seq.voxel_m)
+    c0 = time.perf_counter()
+    for k in range(n):
+        o.integrate(frames[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        o.extract()
+        o.gc()
+    cdt = time.perf_counter() - c0
+    return {"value": n / cdt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} frames of the same sequence, integrate+extract+gc, "
+                      "single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--fine-frames", type=int, default=500)
+    ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only (for profiling runs)")
+    ap.add_argument("--tune-full", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic, to calibrate hardware byte counters)")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method has no multi-GPU path here "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "no GPU"
+    dev = torch.device("cuda:0")
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib << 18
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + written")
+        del a, b
+    head, frames, seq = room_fusion(args, dev)
+    extras = {}
+    if not args.no_extras:
+        extras["sphere_512_blocks"] = sphere_extract(dev)
+        log(f"sphere: {extras['sphere_512_blocks']}")
+        extras["grad_scene_128"] = grad_scene_fwd_bwd(dev)
+        log(f"grad scene: {extras['grad_scene_128']}")
+        extras["batched_64_volumes"] = batched(args, dev)
+        extras["room_4mm_holes_refine"] = room_fine(args, dev)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(frames, seq)
 
     out = {
         "metric": "fused frames/s @8mm (integrate + extract + gc per frame)",
-        "value": fps,
+        "value": head["value"],
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -173,13 +413,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"room sequence, {args.frames} frames 640x480, 8 mm voxels, "
                                "8^3 blocks, 2^20 hash slots, integrate+extract+gc per frame"},
-        "roofline": roofline,
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "value_without_events": fps_noev,
-        "sphere_blocks_per_s": 512 / (sphere_ms / 1000.0),
-        "sphere_extract_ms": sphere_ms,
-        "totals_per_step": {k: v // args.steps for k, v in tot.items()},
-        "kernels": kernels,
+        "value_without_events": head["value_without_events"],
+        "blocks": head["blocks"],
+        "totals_per_step": head["totals_per_step"],
+        "kernels": head["kernels"],
+        "extras": extras,
     }
     print(json.dumps(out))
 

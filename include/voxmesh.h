@@ -35,6 +35,17 @@
  *   at voxel g = 8b + l and runs one step along axis a (0 x, 1 y, 2 z) has
  *   key ((b.x+8192) << 39) | ((b.y+8192) << 25) | ((b.z+8192) << 11)
  *     | ((l.x + 8 l.y + 64 l.z) << 2) | a.
+ * - Batches: a volume created with batch_volumes = m > 0 holds m independent
+ *   volumes ("slots") in one hash table and one set of pools, so that every
+ *   call processes all of them in the same kernel launches.  Block (x, y, z)
+ *   of slot k, with 0 <= x <= 62, is stored at block coordinate
+ *   (64k - 8192 + x, y, z): slots lie 64 blocks apart along x with at least
+ *   one empty block between them, so no cube, edge or vertex spans two
+ *   slots and each slot's mesh and gradients are exactly those of a plain
+ *   volume holding only its blocks.  Edge keys carry the stored coordinate
+ *   (key bits 39.. hold 64k + x); vertex positions are in the slot's frame.
+ *   Blocks enter through vm_import_batch; vm_integrate_depth and
+ *   vm_import_blocks reject a batch.
  * - Floating point: FP32 everywhere on the hot path, without contraction of
  *   products into fused multiply-adds and with correctly rounded division, so
  *   fusion and cube signs are reproducible bit for bit.
@@ -76,6 +87,8 @@ typedef struct vm_config {
   int32_t max_tri_cubes;/* cubes holding triangles at one time, 1 .. 2^30 */
   int32_t hash_mode;    /* 0: mixing hash; 1: every key starts probing at
                            slot 0 (long probe chains, for testing only) */
+  int32_t batch_volumes;/* 0: a plain volume; m in 1..256: a batch of m
+                           independent volumes (see "Batches" below) */
 } vm_config;
 
 /* Pinhole camera, pixel (u, v) at column u, row v; depth in metres. */
@@ -243,6 +256,57 @@ int vm_integrate_backward(vm_volume* vol, const float* depth,
                           const float* dL_dtsdf1, float* dL_dtsdf0,
                           float* dL_ddepth, hipStream_t stream);
 
+/* Import with explicit slots and output rows.  slots: device int32 n, the
+ * slot of each block (must be NULL for a plain volume, non-NULL for a
+ * batch); coords: device n*3 int32 in the slot's frame; tsdf, weight as for
+ * vm_import_blocks; rows: device int32 n or NULL, receives each block's
+ * row in pool order (for vm_extract_backward_slots).  A slot outside
+ * 0..m-1 or x outside 0..62 sets VM_ERR_RANGE and skips the block. */
+int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
+                    const float* tsdf, const float* weight, int64_t n,
+                    int32_t* rows, hipStream_t stream);
+
+/* Positions of every vertex pool entry, uncompacted and without
+ * synchronising (for graph capture): pos (device, cap*3 FP32 metres, slot
+ * frame) and slot_of (device int32 cap, may be NULL) get, for each entry
+ * holding a live vertex, its position and slot (0 for a plain volume), and
+ * 0 / -1 for every other entry.  cap must be at least max_vertices
+ * (VM_ERR_CAPACITY otherwise); entries from max_vertices on are not
+ * written. */
+int vm_export_positions(vm_volume* vol, float* pos, int32_t* slot_of,
+                        int64_t cap, hipStream_t stream);
+
+/* vm_extract_backward with the upstream gradient per vertex pool entry
+ * (dL_dpos: device max_vertices*3 FP32, rows as vm_export_positions; rows
+ * of entries without a live vertex are ignored) and the output in the
+ * caller's block order: with rows (device int32 n_rows, pool rows e.g. from
+ * vm_import_batch; -1 gives a zero row), dL_dtsdf (device n_rows*512 FP32)
+ * row i is the gradient of block rows[i]; with rows == NULL it holds every
+ * block in pool order.  Deterministic, as vm_extract_backward. */
+int vm_extract_backward_slots(vm_volume* vol, const float* dL_dpos,
+                              const int32_t* rows, int64_t n_rows,
+                              float* dL_dtsdf, hipStream_t stream);
+
+/* Workgroup mapping of the volume's kernels; results do not depend on it
+ * (bit for bit), only speed does.  Defaults: {4, 8, 4, 8, 0}. */
+typedef struct vm_launch {
+  int32_t wave_group_size;    /* waves per workgroup of the kernels that give
+                                 each block one wave (classification,
+                                 vertices, triangles): 2, 4 or 8 */
+  int32_t wave_groups_per_cu; /* their workgroups per compute unit, 1..32 */
+  int32_t block_groups_per_cu;/* workgroups per compute unit of the kernels
+                                 that give each block a 512-lane workgroup
+                                 (fusion, import, backward), 1..16 */
+  int32_t item_groups_per_cu; /* workgroups per compute unit of the list
+                                 kernels (256 lanes), 1..32 */
+  int32_t block_order;        /* 0: block i goes to workgroup i mod grid;
+                                 1: each workgroup takes a contiguous run */
+} vm_launch;
+
+/* Set / read the mapping.  VM_ERR_ARG for values outside the ranges. */
+int vm_set_launch(vm_volume* vol, const vm_launch* launch);
+int vm_get_launch(vm_volume* vol, vm_launch* launch);
+
 /* Pool indices of blocks by coordinate, one hash lookup each (the O(1)
  * access of Sec. IV).  coords: device n*3 int32; idx: device n int32,
  * receives the block's row in pool order (as in vm_export_blocks and the
@@ -283,8 +347,12 @@ int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream);
  * created by the library on first use and reused).  vm_profile(vol, 1)
  * clears previous records; vm_profile_read synchronises the recorded
  * events and writes, per VM_K_* kernel, the launch count and the summed
- * event-to-event milliseconds (arrays of VM_K_COUNT entries, host). */
+ * event-to-event milliseconds (arrays of VM_K_COUNT entries, host).
+ * vm_profile_mask records only the kernels whose bit (1 << VM_K_*) is set
+ * in mask (0 stops recording), so that timing one kernel adds events
+ * around that kernel alone. */
 int vm_profile(vm_volume* vol, int enable);
+int vm_profile_mask(vm_volume* vol, uint32_t mask);
 int vm_profile_read(vm_volume* vol, int64_t* launches, double* ms);
 
 #ifdef __cplusplus

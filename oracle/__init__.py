@@ -48,6 +48,7 @@ def lib():
             "orc_create": (vp, [f, f, f]),
             "orc_destroy": (None, [vp]),
             "orc_integrate": (i, [vp, P, i, i, f, f, f, f, f, f, P]),
+            "orc_restrict_blocks": (None, [vp, P, i]),
             "orc_import_blocks": (i, [vp, P, P, P, i]),
             "orc_extract": (i, [vp, i]),
             "orc_refine": (i, [vp]),
@@ -166,6 +167,13 @@ class OracleVolume:
         fx, fy, cx, cy = (float(np.float32(x)) for x in K)
         return lib().orc_integrate(self._h, _ptr(depth), W, H, fx, fy, cx, cy,
                                    float(min_depth), float(max_depth), _ptr(T))
+
+    def restrict(self, coords) -> None:
+        """Collect only these blocks in later integrations (None: all).  The
+        collected blocks' TSDF and weights are exactly those of a full run."""
+        c = np.ascontiguousarray(np.zeros((0, 3)) if coords is None else coords,
+                                 dtype=np.int32).reshape(-1, 3)
+        lib().orc_restrict_blocks(self._h, _ptr(c), c.shape[0])
 
     def import_blocks(self, coords: np.ndarray, d: np.ndarray, w: np.ndarray) -> int:
         coords = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 3)

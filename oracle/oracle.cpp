@@ -293,6 +293,13 @@ struct Volume {
   std::set<I3> pending_touched;  // blocks touched since the last extraction
   std::set<I3> last_dirty;       // blocks processed by the last extraction
 
+  // Optional restriction of collection to a fixed set of blocks (empty: no
+  // restriction).  A block's collection and fusion depend only on the depth
+  // frame and on the block's own voxels, so a restricted run computes
+  // exactly what a full run computes for those blocks, at a fraction of the
+  // cost: used to check sampled blocks of long sequences.
+  std::set<I3> only;
+
   // Kept from the last integration for the backward pass.
   std::map<I3, FuseRec> fuse;
   std::vector<float> last_depth;
@@ -502,7 +509,10 @@ int orc_integrate(void* h, const float* depth, int W, int H, float fx, float fy,
       if (!in_range) continue;
       for (int bz = bmin[2]; bz <= bmax[2]; ++bz)
         for (int by = bmin[1]; by <= bmax[1]; ++by)
-          for (int bx = bmin[0]; bx <= bmax[0]; ++bx) touched.insert(I3{bx, by, bz});
+          for (int bx = bmin[0]; bx <= bmax[0]; ++bx) {
+            const I3 b{bx, by, bz};
+            if (v.only.empty() || v.only.count(b)) touched.insert(b);
+          }
     }
   }
   for (const I3& b : touched)
@@ -547,6 +557,14 @@ int orc_integrate(void* h, const float* depth, int W, int H, float fx, float fy,
   v.frame_touched = touched;
   v.pending_touched.insert(touched.begin(), touched.end());
   return (int)touched.size();
+}
+
+// Restrict block collection of later integrations to the n given blocks
+// (n = 0 lifts the restriction).
+void orc_restrict_blocks(void* h, const int* coords, int n) {
+  Volume& v = *(Volume*)h;
+  v.only.clear();
+  for (int i = 0; i < n; ++i) v.only.insert(I3{coords[3 * i], coords[3 * i + 1], coords[3 * i + 2]});
 }
 
 // Allocate blocks and set their TSDF/weights directly (used for synthetic

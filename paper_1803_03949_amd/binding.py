@@ -34,7 +34,18 @@ class vm_config(ctypes.Structure):
     _fields_ = [("voxel_m", ctypes.c_float), ("trunc_vox", ctypes.c_float),
                 ("refine_eps_vox", ctypes.c_float), ("hash_log2", ctypes.c_int32),
                 ("max_blocks", ctypes.c_int32), ("max_vertices", ctypes.c_int32),
-                ("max_tri_cubes", ctypes.c_int32), ("hash_mode", ctypes.c_int32)]
+                ("max_tri_cubes", ctypes.c_int32), ("hash_mode", ctypes.c_int32),
+                ("batch_volumes", ctypes.c_int32)]
+
+
+class vm_launch(ctypes.Structure):
+    _fields_ = [("wave_group_size", ctypes.c_int32), ("wave_groups_per_cu", ctypes.c_int32),
+                ("block_groups_per_cu", ctypes.c_int32), ("item_groups_per_cu", ctypes.c_int32),
+                ("block_order", ctypes.c_int32)]
+
+
+LAUNCH_FIELDS = [f for f, _ in vm_launch._fields_]
+SLOT_SPAN = 64  # stored block x of slot k, local x: 64k - 8192 + x
 
 
 class vm_intrinsics(ctypes.Structure):
@@ -93,7 +104,13 @@ def lib() -> ctypes.CDLL:
             "vm_export_block_list": [P, ctypes.c_int, P, I64, PI64, P],
             "vm_get_totals": [P, P, ctypes.c_int, P],
             "vm_lookup_blocks": [P, P, P, I64, P],
+            "vm_import_batch": [P, P, P, P, P, I64, P, P],
+            "vm_export_positions": [P, P, P, I64, P],
+            "vm_extract_backward_slots": [P, P, P, I64, P, P],
+            "vm_set_launch": [P, ctypes.POINTER(vm_launch)],
+            "vm_get_launch": [P, ctypes.POINTER(vm_launch)],
             "vm_profile": [P, ctypes.c_int],
+            "vm_profile_mask": [P, ctypes.c_uint32],
             "vm_profile_read": [P, P, P],
         }
         for name, args in sigs.items():
@@ -128,13 +145,14 @@ class Volume:
 
     def __init__(self, voxel_m: float, trunc_vox: float = 4.0, refine_eps_vox: float = 0.5,
                  hash_log2: int = 20, max_blocks: int = 1 << 16, max_vertices: int = 1 << 22,
-                 max_tri_cubes: int = 1 << 22, hash_mode: int = 0, device=None):
+                 max_tri_cubes: int = 1 << 22, hash_mode: int = 0, batch_volumes: int = 0,
+                 device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("voxmesh needs a ROCm GPU (torch.cuda.is_available() is False)")
         L = lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.cfg = vm_config(voxel_m, trunc_vox, refine_eps_vox, hash_log2, max_blocks,
-                             max_vertices, max_tri_cubes, hash_mode)
+                             max_vertices, max_tri_cubes, hash_mode, batch_volumes)
         nbytes = ctypes.c_size_t()
         _check(L.vm_volume_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)), "vm_volume_bytes")
         self.nbytes = nbytes.value
@@ -172,6 +190,21 @@ class Volume:
         assert tsdf.numel() == 512 * n and weight.numel() == 512 * n
         _check(lib().vm_import_blocks(self.h, _ptr(coords), _ptr(tsdf), _ptr(weight), n,
                                       _stream(stream)), "vm_import_blocks")
+
+    def import_batch(self, slots: torch.Tensor | None, coords: torch.Tensor, tsdf: torch.Tensor,
+                     weight: torch.Tensor, rows: torch.Tensor | None = None, stream=None):
+        """Import blocks into slots of a batch (slots None for a plain volume);
+        rows, if given ((n,) int32 device), receives each block's pool row."""
+        n = coords.shape[0]
+        assert coords.is_cuda and coords.dtype == torch.int32 and coords.is_contiguous()
+        assert tsdf.dtype == torch.float32 and weight.dtype == torch.float32
+        assert tsdf.numel() == 512 * n and weight.numel() == 512 * n
+        if slots is not None:
+            assert slots.is_cuda and slots.dtype == torch.int32 and slots.numel() == n
+        if rows is not None:
+            assert rows.is_cuda and rows.dtype == torch.int32 and rows.numel() == n
+        _check(lib().vm_import_batch(self.h, _ptr(slots), _ptr(coords), _ptr(tsdf), _ptr(weight),
+                                     n, _ptr(rows), _stream(stream)), "vm_import_batch")
 
     def extract(self, scope_all: bool = False, stream=None):
         _check(lib().vm_extract_mesh(self.h, VM_SCOPE_ALL if scope_all else VM_SCOPE_DIRTY,
@@ -261,8 +294,16 @@ class Volume:
         _check(lib().vm_get_totals(self.h, _ptr(out), len(TOTALS), _stream(stream)), "vm_get_totals")
         return dict(zip(TOTALS, (int(x) for x in out)))
 
-    def profile(self, enable: bool):
-        _check(lib().vm_profile(self.h, 1 if enable else 0), "vm_profile")
+    def profile(self, enable: bool, kernels=None):
+        """Bracket kernel launches with events: all kernels, or only those
+        named in `kernels` (names as in KERNELS)."""
+        if kernels is None or not enable:
+            _check(lib().vm_profile(self.h, 1 if enable else 0), "vm_profile")
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << KERNELS.index(k)
+            _check(lib().vm_profile_mask(self.h, mask), "vm_profile_mask")
 
     def profile_read(self) -> dict:
         """{kernel: (launches, total ms)} of the recorded launches."""
@@ -282,6 +323,47 @@ class Volume:
         _check(lib().vm_extract_backward(self.h, _ptr(dL), _ptr(out), _stream(stream)),
                "vm_extract_backward")
         return out[:nb]
+
+    def positions(self, pos: torch.Tensor | None = None, slot_of: torch.Tensor | None = None,
+                  stream=None):
+        """Every vertex pool entry's position ((max_vertices, 3) metres, slot
+        frame) and slot ((max_vertices,) int32, -1 without a live vertex);
+        no synchronisation."""
+        V = self.cfg.max_vertices
+        if pos is None:
+            pos = torch.empty((V, 3), dtype=torch.float32, device=self.device)
+        if slot_of is None:
+            slot_of = torch.empty(V, dtype=torch.int32, device=self.device)
+        _check(lib().vm_export_positions(self.h, _ptr(pos), _ptr(slot_of), pos.shape[0],
+                                         _stream(stream)), "vm_export_positions")
+        return pos, slot_of
+
+    def extract_backward_slots(self, dL_dpos: torch.Tensor, rows: torch.Tensor | None,
+                               out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """dL/d(TSDF) from per-pool-entry vertex gradients, for the blocks at
+        pool rows `rows` ((n,) int32 device) in that order."""
+        assert dL_dpos.is_contiguous() and dL_dpos.shape[0] >= self.cfg.max_vertices
+        if rows is None:
+            nb = self.status(stream)["blocks"]
+            n = nb
+        else:
+            n = rows.shape[0]
+        if out is None:
+            out = torch.empty((max(n, 1), 512), dtype=torch.float32, device=self.device)
+        _check(lib().vm_extract_backward_slots(self.h, _ptr(dL_dpos), _ptr(rows), n, _ptr(out),
+                                               _stream(stream)), "vm_extract_backward_slots")
+        return out[:n]
+
+    def set_launch(self, **kw):
+        cur = self.get_launch()
+        cur.update(kw)
+        l = vm_launch(*(int(cur[f]) for f in LAUNCH_FIELDS))
+        _check(lib().vm_set_launch(self.h, ctypes.byref(l)), "vm_set_launch")
+
+    def get_launch(self) -> dict:
+        l = vm_launch()
+        _check(lib().vm_get_launch(self.h, ctypes.byref(l)), "vm_get_launch")
+        return {f: int(getattr(l, f)) for f in LAUNCH_FIELDS}
 
     def integrate_backward(self, depth: torch.Tensor, dL_dtsdf1: torch.Tensor, stream=None):
         """(dL/d(TSDF before the last fusion), dL/d(depth)) for the last frame."""

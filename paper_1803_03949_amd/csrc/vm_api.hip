@@ -32,10 +32,12 @@ struct vm_volume {
   uint32_t pass;    // dirty / vertex-list stamps
   FrameParams last_fp;
   bool have_fp;
+  int cus;          // compute units of the device
+  vm_launch launch; // workgroup mapping (see vm_set_launch)
   int grid_blocks;  // workgroups of per-block kernels
   int grid_items;   // workgroups of per-item kernels
-  int grid_waves;   // workgroups of wave-per-block kernels (4 waves each)
-  bool prof;        // bracket launches with events
+  int grid_waves;   // workgroups of wave-per-block kernels
+  uint32_t prof;    // bit k: bracket launches of kernel k with events
   std::vector<hipEvent_t> ev_free;
   std::vector<ProfRec> recs;
 };
@@ -53,7 +55,24 @@ bool config_ok(const vm_config* c) {
          isfinite(c->trunc_vox) && c->refine_eps_vox >= 0.f && c->hash_log2 >= 10 &&
          c->hash_log2 <= 28 && c->max_blocks >= 1 && c->max_blocks <= kMaxBlocks &&
          c->max_vertices >= 1 && c->max_vertices <= (1 << 30) && c->max_tri_cubes >= 1 &&
-         c->max_tri_cubes <= (1 << 30) && (c->hash_mode == 0 || c->hash_mode == 1);
+         c->max_tri_cubes <= (1 << 30) && (c->hash_mode == 0 || c->hash_mode == 1) &&
+         c->batch_volumes >= 0 && c->batch_volumes <= kMaxSlots;
+}
+
+bool launch_ok(const vm_launch* l) {
+  return l && (l->wave_group_size == 2 || l->wave_group_size == 4 || l->wave_group_size == 8) &&
+         l->wave_groups_per_cu >= 1 && l->wave_groups_per_cu <= 32 &&
+         l->block_groups_per_cu >= 1 && l->block_groups_per_cu <= 16 &&
+         l->item_groups_per_cu >= 1 && l->item_groups_per_cu <= 32 &&
+         (l->block_order == 0 || l->block_order == 1);
+}
+
+void apply_launch(vm_volume* vol, const vm_launch& l) {
+  vol->launch = l;
+  vol->grid_blocks = vol->cus * l.block_groups_per_cu;
+  vol->grid_items = vol->cus * l.item_groups_per_cu;
+  vol->grid_waves = vol->cus * l.wave_groups_per_cu;
+  vol->dev.order = (uint32_t)l.block_order;
 }
 
 // Carve the workspace; with base == nullptr only the size is computed.
@@ -84,6 +103,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->evtx = (int32_t*)take(4 * 3 * kVox * B);
   v->cchunk = (int32_t*)take(4 * kVox * B);
   v->chg = (uint64_t*)take(8 * 8 * B);
+  v->surf = (uint8_t*)take(B);
   v->st_pending = (uint32_t*)take(4 * B);
   v->st_dirty = (uint32_t*)take(4 * B);
   v->st_vtx = (uint32_t*)take(4 * B);
@@ -106,8 +126,11 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->max_blocks = (uint32_t)B;
   v->max_vertices = (uint32_t)V;
   v->max_chunks = (uint32_t)T;
-  v->vseg_cap = (uint32_t)((V + kSegs - 1) / kSegs);
-  v->cseg_cap = (uint32_t)((T + kSegs - 1) / kSegs);
+  // one segment per 256 blocks of capacity, at most kSegs
+  const size_t nseg = B / 256 < 1 ? 1 : (B / 256 > (size_t)kSegs ? (size_t)kSegs : B / 256);
+  v->nseg = (uint32_t)nseg;
+  v->vseg_cap = (uint32_t)((V + nseg - 1) / nseg);
+  v->cseg_cap = (uint32_t)((T + nseg - 1) / nseg);
   v->hash_mask = (uint32_t)(H - 1);
   v->hash_mode = c.hash_mode;
   return off;
@@ -117,24 +140,30 @@ int hip_status(hipError_t e) { return e == hipSuccess ? VM_OK : VM_ERR_HIP; }
 
 int launched() { return hip_status(hipGetLastError()); }
 
+// Fill n 32-bit words with a value: a kernel rather than a memset node, so
+// that a reset can sit inside a captured graph.
+void fill(void* p, uint32_t value, size_t bytes, hipStream_t stream) {
+  const uint64_t n = bytes / 4;
+  uint64_t g = (n + 255) / 256;
+  g = g < 1 ? 1 : (g > 2048 ? 2048 : g);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(256), 0, stream, (uint32_t*)p, value, n);
+}
+
 // Empty the volume.  full = true (creation) also clears the running totals
 // and uploads the marching-cubes tables.
 int clear_state(vm_volume* vol, hipStream_t stream, bool full) {
   const VolDev& v = vol->dev;
   const size_t H = (size_t)v.hash_mask + 1, B = v.max_blocks;
-  hipError_t e = hipSuccess;
-  auto set = [&](void* p, int val, size_t n) {
-    if (e == hipSuccess) e = hipMemsetAsync(p, val, n, stream);
-  };
-  set(v.cnt, 0, full ? sizeof(Counters) : offsetof(Counters, acc));
-  set(v.vseg, 0, sizeof(Seg) * kSegs);
-  set(v.cseg, 0, sizeof(Seg) * kSegs);
-  set(v.slots, 0xFF, 8 * H);
-  set(v.slot_stamp, 0, 4 * H);
-  set(v.st_pending, 0, 4 * B);
-  set(v.st_dirty, 0, 4 * B);
-  set(v.st_vtx, 0, 4 * B);
-  set(v.st_frame, 0, 4 * B);
+  fill(v.cnt, 0, full ? sizeof(Counters) : offsetof(Counters, acc), stream);
+  fill(v.vseg, 0, sizeof(Seg) * kSegs, stream);
+  fill(v.cseg, 0, sizeof(Seg) * kSegs, stream);
+  fill(v.slots, 0xFFFFFFFFu, 8 * H, stream);
+  fill(v.slot_stamp, 0, 4 * H, stream);
+  fill(v.st_pending, 0, 4 * B, stream);
+  fill(v.st_dirty, 0, 4 * B, stream);
+  fill(v.st_vtx, 0, 4 * B, stream);
+  fill(v.st_frame, 0, 4 * B, stream);
+  hipError_t e = hipGetLastError();
   if (full) {
     if (e == hipSuccess)
       e = hipMemcpyAsync((void*)v.tri_table, g_tri, sizeof(g_tri), hipMemcpyHostToDevice, stream);
@@ -176,12 +205,12 @@ hipEvent_t prof_event(vm_volume* vol, hipStream_t s) {
   return e;
 }
 
-hipEvent_t prof_begin(vm_volume* vol, hipStream_t s) {
-  return vol->prof ? prof_event(vol, s) : nullptr;
+hipEvent_t prof_begin(vm_volume* vol, int kid, hipStream_t s) {
+  return (vol->prof >> kid) & 1u ? prof_event(vol, s) : nullptr;
 }
 
 void prof_end(vm_volume* vol, int kid, hipEvent_t a, hipStream_t s) {
-  if (!vol->prof || !a) return;
+  if (!a) return;
   hipEvent_t b = prof_event(vol, s);
   if (!b) {
     vol->ev_free.push_back(a);
@@ -193,9 +222,20 @@ void prof_end(vm_volume* vol, int kid, hipEvent_t a, hipStream_t s) {
 // Launch a kernel, bracketed by timing events while profiling is enabled.
 #define VM_LAUNCH(vol, kid, kernel, grid, block, stream, ...)       \
   do {                                                              \
-    hipEvent_t vm_ev_ = prof_begin((vol), (stream));                \
+    hipEvent_t vm_ev_ = prof_begin((vol), (kid), (stream));         \
     hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__); \
     prof_end((vol), (kid), vm_ev_, (stream));                       \
+  } while (0)
+
+// Launch a wave-per-block kernel instantiated for the volume's group size.
+#define VM_LAUNCH_W(vol, kid, kernel, stream, ...)                                          \
+  do {                                                                                  \
+    const dim3 vm_g_((vol)->grid_waves);                                                \
+    switch ((vol)->launch.wave_group_size) {                                            \
+      case 2: VM_LAUNCH(vol, kid, kernel<2>, vm_g_, dim3(128), stream, __VA_ARGS__); break; \
+      case 8: VM_LAUNCH(vol, kid, kernel<8>, vm_g_, dim3(512), stream, __VA_ARGS__); break; \
+      default: VM_LAUNCH(vol, kid, kernel<4>, vm_g_, dim3(256), stream, __VA_ARGS__); break; \
+    }                                                                                   \
   } while (0)
 
 void prep(vm_volume* vol, int op, hipStream_t s) {
@@ -263,10 +303,10 @@ int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes, hipStrea
     delete vol;
     return VM_ERR_HIP;
   }
-  vol->grid_blocks = cus * 4;
-  vol->grid_items = cus * 8;
-  vol->grid_waves = cus * 8;
-  vol->prof = false;
+  v.batch = (uint32_t)cfg->batch_volumes;
+  vol->cus = cus;
+  apply_launch(vol, vm_launch{4, 8, 4, 8, 0});
+  vol->prof = 0;
   int r = clear_state(vol, stream, true);
   if (r != VM_OK) {
     delete vol;
@@ -295,7 +335,8 @@ int vm_reset_volume(vm_volume* vol, hipStream_t stream) {
 int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* K,
                        const float cam_to_world[16], hipStream_t stream) {
   if (!vol || !depth || !K || !cam_to_world || K->width <= 0 || K->height <= 0 ||
-      (int64_t)K->width * K->height > (1 << 28) || !(K->fx != 0.f) || !(K->fy != 0.f))
+      (int64_t)K->width * K->height > (1 << 28) || !(K->fx != 0.f) || !(K->fy != 0.f) ||
+      vol->dev.batch)
     return VM_ERR_ARG;
   FrameParams fp;
   const float* T = cam_to_world;
@@ -332,7 +373,15 @@ int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* 
 
 int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
                      const float* weight, int64_t n, hipStream_t stream) {
-  if (!vol || n < 0 || n > (int64_t)vol->dev.max_blocks || (n > 0 && (!coords || !tsdf || !weight)))
+  if (!vol || vol->dev.batch) return VM_ERR_ARG;
+  return vm_import_batch(vol, nullptr, coords, tsdf, weight, n, nullptr, stream);
+}
+
+int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
+                    const float* tsdf, const float* weight, int64_t n, int32_t* rows,
+                    hipStream_t stream) {
+  if (!vol || n < 0 || n > (int64_t)vol->dev.max_blocks ||
+      (n > 0 && (!coords || !tsdf || !weight)) || (vol->dev.batch != 0) != (slots != nullptr))
     return VM_ERR_ARG;
   if (n == 0) return VM_OK;
   const VolDev& v = vol->dev;
@@ -340,11 +389,11 @@ int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
   const uint32_t per = compact_per_wg(v);
   const uint32_t ncompact = (v.hash_mask + per) / per;
   VM_LAUNCH(vol, VM_K_IMPORT, k_import_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), stream,
-            v, coords, (uint32_t)n, frame);
+            v, slots, coords, (uint32_t)n, frame);
   VM_LAUNCH(vol, VM_K_ASSIGN, k_frame_compact, dim3(ncompact), dim3(256), stream, v, frame,
             vol->epoch, per);
   VM_LAUNCH(vol, VM_K_IMPORT, k_import_copy, dim3(vol->grid_blocks), dim3(512), stream, v, tsdf,
-            weight, frame);
+            weight, frame, rows);
   vol->have_fp = false;
   return launched();
 }
@@ -360,10 +409,11 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
     VM_LAUNCH(vol, VM_K_DIRTY, k_dirty, dim3(vol->grid_items), dim3(256), stream, v, pass,
               vol->epoch);
   ++vol->epoch;
-  VM_LAUNCH(vol, VM_K_CLASSIFY, k_classify, dim3(vol->grid_waves), dim3(256), stream, v, pass, 0);
-  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
-  VM_LAUNCH(vol, VM_K_VERTICES, k_vertices, dim3(vol->grid_waves), dim3(256), stream, v);
-  VM_LAUNCH(vol, VM_K_TRIANGLES, k_triangles, dim3(vol->grid_waves), dim3(256), stream, v);
+  VM_LAUNCH_W(vol, VM_K_CLASSIFY, k_classify, stream, v, pass, 0);
+  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v,
+            pass);
+  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
+  VM_LAUNCH_W(vol, VM_K_TRIANGLES, k_triangles, stream, v);
   return launched();
 }
 
@@ -372,10 +422,11 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   const VolDev& v = vol->dev;
   const uint32_t pass = ++vol->pass;
   prep(vol, VM_OP_REFINE, stream);
-  VM_LAUNCH(vol, VM_K_REFINE, k_classify, dim3(vol->grid_waves), dim3(256), stream, v, pass, 1);
-  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
-  VM_LAUNCH(vol, VM_K_VERTICES, k_vertices, dim3(vol->grid_waves), dim3(256), stream, v);
-  VM_LAUNCH(vol, VM_K_TRIANGLES, k_triangles, dim3(vol->grid_waves), dim3(256), stream, v);
+  VM_LAUNCH_W(vol, VM_K_REFINE, k_classify, stream, v, pass, 1);
+  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v,
+            pass);
+  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
+  VM_LAUNCH_W(vol, VM_K_TRIANGLES, k_triangles, stream, v);
   return launched();
 }
 
@@ -384,7 +435,8 @@ int vm_gc(vm_volume* vol, hipStream_t stream) {
   uint32_t parts = vol->dev.vseg_cap / 4096;
   parts = parts < 1 ? 1 : (parts > 64 ? 64 : parts);
   prep(vol, VM_OP_GC, stream);
-  VM_LAUNCH(vol, VM_K_GC, k_gc, dim3(kSegs * parts), dim3(256), stream, vol->dev, parts);
+  VM_LAUNCH(vol, VM_K_GC, k_gc, dim3(vol->dev.nseg * parts), dim3(256), stream, vol->dev,
+            parts);
   return launched();
 }
 
@@ -422,8 +474,39 @@ int vm_extract_backward(vm_volume* vol, const float* dL_dverts, float* dL_dtsdf,
                         hipStream_t stream) {
   if (!vol || !dL_dtsdf) return VM_ERR_ARG;
   VM_LAUNCH(vol, VM_K_BACKWARD, k_bwd_tsdf, dim3(vol->grid_blocks), dim3(512), stream, vol->dev,
-            dL_dverts, dL_dtsdf);
+            dL_dverts, 0, nullptr, 0u, dL_dtsdf);
   return launched();
+}
+
+int vm_extract_backward_slots(vm_volume* vol, const float* dL_dpos, const int32_t* rows,
+                              int64_t n_rows, float* dL_dtsdf, hipStream_t stream) {
+  if (!vol || !dL_dpos || !dL_dtsdf || (rows && (n_rows < 0 || n_rows > (int64_t)kMaxBlocks)))
+    return VM_ERR_ARG;
+  VM_LAUNCH(vol, VM_K_BACKWARD, k_bwd_tsdf, dim3(vol->grid_blocks), dim3(512), stream, vol->dev,
+            dL_dpos, 1, rows, (uint32_t)(rows ? n_rows : 0), dL_dtsdf);
+  return launched();
+}
+
+int vm_export_positions(vm_volume* vol, float* pos, int32_t* slot_of, int64_t cap,
+                        hipStream_t stream) {
+  if (!vol || !pos) return VM_ERR_ARG;
+  if (cap < (int64_t)vol->dev.max_vertices) return VM_ERR_CAPACITY;
+  prep(vol, VM_OP_FINALISE, stream);
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_positions, dim3(vol->grid_items), dim3(256), stream, vol->dev,
+            pos, slot_of);
+  return launched();
+}
+
+int vm_set_launch(vm_volume* vol, const vm_launch* launch) {
+  if (!vol || !launch_ok(launch)) return VM_ERR_ARG;
+  apply_launch(vol, *launch);
+  return VM_OK;
+}
+
+int vm_get_launch(vm_volume* vol, vm_launch* launch) {
+  if (!vol || !launch) return VM_ERR_ARG;
+  *launch = vol->launch;
+  return VM_OK;
 }
 
 int vm_integrate_backward(vm_volume* vol, const float* depth, const float* dL_dtsdf1,
@@ -580,14 +663,18 @@ int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream) {
   return VM_OK;
 }
 
-int vm_profile(vm_volume* vol, int enable) {
-  if (!vol) return VM_ERR_ARG;
-  if (enable) {
+int vm_profile_mask(vm_volume* vol, uint32_t mask) {
+  if (!vol || (mask >> VM_K_COUNT)) return VM_ERR_ARG;
+  if (mask) {
     for (auto& r : vol->recs) vol->ev_free.push_back(r.a), vol->ev_free.push_back(r.b);
     vol->recs.clear();
   }
-  vol->prof = enable != 0;
+  vol->prof = mask;
   return VM_OK;
+}
+
+int vm_profile(vm_volume* vol, int enable) {
+  return vm_profile_mask(vol, enable ? (1u << VM_K_COUNT) - 1u : 0u);
 }
 
 int vm_profile_read(vm_volume* vol, int64_t* launches, double* ms) {

@@ -20,8 +20,9 @@
 //
 // Contention on single counters is what limits a GPU here, not bytes: every
 // list is built with at most one atomic per workgroup, and the vertex and
-// triangle pools are split into kSegs independent segments (a block's
-// allocations go to segment block % kSegs), each with its own 128-byte
+// triangle pools are split into up to kSegs independent segments (a block's
+// allocations go to segment block % nseg; small volumes use fewer segments
+// so that each still averages over many blocks), each with its own 128-byte
 // counter line, bump pointer and recycle ring.
 #pragma once
 
@@ -96,6 +97,7 @@ struct VolDev {
   uint32_t hash_mask;
   int32_t hash_mode;
   uint32_t max_blocks, max_vertices, max_chunks;
+  uint32_t nseg;              // pool segments in use (1..kSegs)
   uint32_t vseg_cap, cseg_cap;  // slots per segment
   Counters* cnt;
   Seg* vseg;                  // [kSegs] vertex pool segments
@@ -114,6 +116,7 @@ struct VolDev {
   int32_t* evtx;              // [B][3][512]
   int32_t* cchunk;            // [B][512]
   uint64_t* chg;              // [B][8] cubes whose triangles changed, per wave
+  uint8_t* surf;              // [B] 1 when some cube of the block has triangles
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
   uint32_t* st_vtx;           // [B] pass that listed the block for vertices
@@ -133,7 +136,37 @@ struct VolDev {
   uint32_t* cring;            // [T]
   uint32_t* scan;             // [scan_cap] download partial sums
   uint32_t scan_cap;
+  uint32_t batch;             // number of volume slots, 0 for a plain volume
+  uint32_t order;             // 0: strided block-to-workgroup mapping, 1: runs
 };
+
+// Batched volumes: slot k's block x lies in [0, kSlotSpan - 2] and is stored
+// at x + kSlotSpan * k - kKeyBias, so slots never touch.
+constexpr int kSlotSpan = 64;
+constexpr int kMaxSlots = 16384 / kSlotSpan;
+
+// Block position in the frame its positions are reported in: the world for a
+// plain volume, the slot's own frame (and the slot index) for a batch.
+__device__ inline void block_frame(const VolDev& v, int& bx, int& slot) {
+  slot = 0;
+  if (v.batch) {
+    slot = (bx + kKeyBias) / kSlotSpan;
+    bx = (bx + kKeyBias) % kSlotSpan;
+  }
+}
+
+// Items of a loop shared by `lanes` workers per workgroup (waves or whole
+// workgroups, lanes = 1): strided (item i to workgroup i / lanes mod grid)
+// or contiguous runs of about n / grid items per workgroup.
+struct ItemLoop {
+  uint32_t i, end, step;
+};
+__device__ inline ItemLoop item_loop(const VolDev& v, uint32_t n, uint32_t lanes, uint32_t lane) {
+  if (v.order == 0) return {blockIdx.x * lanes + lane, n, gridDim.x * lanes};
+  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t b = min(n, blockIdx.x * per);
+  return {b + lane, min(n, b + per), lanes};
+}
 
 // Per-frame camera parameters, passed by value.
 struct FrameParams {
@@ -294,6 +327,21 @@ __device__ inline uint32_t seg_slot(uint32_t head, uint32_t tail, uint32_t hwm, 
   return s < size ? base + (uint32_t)s : kNone;
 }
 
+// The 217 cells of a 9^3 halo region that are not in the 8^3 block: those
+// with some coordinate at the outer layer `edge` (8 for the +x/+y/+z halo,
+// -1 for the -x/-y/-z one).  Faces x, y, z (64 each), then the three
+// edges (8 each), then the corner.  Writes the cell's coordinates.
+__device__ inline void halo_cell(int h, int edge, int& x, int& y, int& z) {
+  const int a = h & 7, b = (h >> 3) & 7;
+  if (h < 64) x = edge, y = a, z = b;
+  else if (h < 128) x = a, y = edge, z = b;
+  else if (h < 192) x = a, y = b, z = edge;
+  else if (h < 200) x = edge, y = edge, z = a;
+  else if (h < 208) x = edge, y = a, z = edge;
+  else if (h < 216) x = a, y = edge, z = edge;
+  else x = edge, y = edge, z = edge;
+}
+
 __device__ inline bool depth_ok(float D, float dmin, float dmax) {
   return isfinite(D) && D > 0.f && D >= dmin && D <= dmax;
 }
@@ -350,17 +398,22 @@ __device__ inline float edge_param(float da, float db) {
 namespace vm {
 __global__ void k_prep(VolDev v, int op, uint32_t arg);
 __global__ void k_collect(VolDev v, FrameParams fp, const float* __restrict__ depth);
-__global__ void k_import_insert(VolDev v, const int32_t* __restrict__ coords, uint32_t n,
+__global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
+                                const int32_t* __restrict__ coords, uint32_t n,
                                 uint32_t frame);
 __global__ void k_frame_compact(VolDev v, uint32_t frame, uint32_t epoch, uint32_t per_wg);
 __global__ void k_fuse(VolDev v, FrameParams fp, const float* __restrict__ depth);
 __global__ void k_import_copy(VolDev v, const float* __restrict__ tsdf,
-                              const float* __restrict__ weight, uint32_t frame);
+                              const float* __restrict__ weight, uint32_t frame,
+                              int32_t* __restrict__ rows);
 __global__ void k_dirty(VolDev v, uint32_t pass, uint32_t epoch);
 __global__ void k_dirty_all(VolDev v, uint32_t pass);
+template <int W>
 __global__ void k_classify(VolDev v, uint32_t pass, int refine);
-__global__ void k_vblock_compact(VolDev v);
+__global__ void k_vblock_compact(VolDev v, uint32_t pass);
+template <int W>
 __global__ void k_vertices(VolDev v);
+template <int W>
 __global__ void k_triangles(VolDev v);
 __global__ void k_gc(VolDev v, uint32_t parts);
 __global__ void k_dl_count(VolDev v, int what);
@@ -368,7 +421,11 @@ __global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
 __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,
                                     uint64_t* __restrict__ keys, uint32_t vcap);
 __global__ void k_dl_write_triangles(VolDev v, int32_t* __restrict__ tris, uint32_t tcap);
-__global__ void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv, float* __restrict__ out);
+__global__ void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv, int by_slot,
+                           const int32_t* __restrict__ rows, uint32_t n_rows,
+                           float* __restrict__ out);
+__global__ void k_positions(VolDev v, float* __restrict__ pos, int32_t* __restrict__ slot_of);
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, uint64_t n);
 __global__ void k_bwd_fusion(VolDev v, FrameParams fp, const float* __restrict__ depth,
                              const float* __restrict__ g1, float* __restrict__ g0,
                              float* __restrict__ gD);

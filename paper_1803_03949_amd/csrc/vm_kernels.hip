@@ -158,15 +158,24 @@ __global__ __launch_bounds__(256) void k_collect(VolDev v, FrameParams fp,
   }
 }
 
-__global__ void k_import_insert(VolDev v, const int32_t* __restrict__ coords, uint32_t n,
-                                uint32_t frame) {
+__global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
+                                const int32_t* __restrict__ coords, uint32_t n, uint32_t frame) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     v.cnt->n_frame = 0;
     v.cnt->acc[VM_TOTAL_FRAMES] += 1;
   }
   if (i >= n) return;
-  const int x = coords[3 * i], y = coords[3 * i + 1], z = coords[3 * i + 2];
+  int x = coords[3 * i];
+  const int y = coords[3 * i + 1], z = coords[3 * i + 2];
+  if (slots) {
+    const int k = slots[i];
+    if (k < 0 || (uint32_t)k >= v.batch || x < 0 || x > kSlotSpan - 2) {
+      atomicOr(&v.cnt->error, kErrRange);
+      return;
+    }
+    x += kSlotSpan * k - kKeyBias;
+  }
   if (!key_in_range(x, y, z)) {
     atomicOr(&v.cnt->error, kErrRange);
     return;
@@ -309,7 +318,8 @@ __global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
   const uint32_t n = min(v.cnt->n_frame, v.max_blocks);
   const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
   if (blockIdx.x == 0 && l == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+  for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
+    const uint32_t i = it.i;
     const uint32_t e = v.frame_list[i];
     if (e == kNone) continue;
     const uint32_t idx = e & ~kNewFlag;
@@ -321,6 +331,7 @@ __global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
     if (isnew) {
       init_cube(v, idx, l);
       link_block(v, idx, l);
+      if (l == 0) v.surf[idx] = 0;
     } else {
       d = v.d[o], w = v.w[o];
     }
@@ -342,23 +353,29 @@ __global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
 
 __global__ __launch_bounds__(512) void k_import_copy(VolDev v, const float* __restrict__ tsdf,
                                                      const float* __restrict__ weight,
-                                                     uint32_t frame) {
+                                                     uint32_t frame, int32_t* __restrict__ rows) {
   const uint32_t n = min(v.cnt->n_frame, v.max_blocks);
   const int l = threadIdx.x;
   if (blockIdx.x == 0 && l == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+  for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
+    const uint32_t i = it.i;
     const uint32_t e = v.frame_list[i];
     if (e == kNone) continue;
     const uint32_t idx = e & ~kNewFlag;
     if (e & kNewFlag) {
       init_cube(v, idx, l);
       link_block(v, idx, l);
+      if (l == 0) v.surf[idx] = 0;
     }
-    const size_t src = (size_t)v.frame_src[i] * kVox + l;
+    const uint32_t row = v.frame_src[i];
+    const size_t src = (size_t)row * kVox + l;
     const size_t o = (size_t)idx * kVox + l;
     v.d[o] = tsdf[src];
     v.w[o] = weight[src];
-    if (l == 0) v.st_frame[idx] = frame;
+    if (l == 0) {
+      v.st_frame[idx] = frame;
+      if (rows) rows[row] = (int32_t)idx;
+    }
   }
 }
 
@@ -449,22 +466,34 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
 // refine = 0: new cube types from the signs (Sec. V-B), previous type
 // saved.  refine = 1: Eqs. (3)-(5) applied to the current types (Sec. V-F).
 // Cubes whose triangles change are recorded in the block's bitmask (one
-// 64-bit word per z layer); the blocks owning their edges (this one and, on
-// its +x/+y/+z faces, neighbours) become vertex-block candidates at fixed
-// positions 8i..8i+7.
-__global__ __launch_bounds__(256) void k_classify(VolDev v, uint32_t pass, int refine) {
-  __shared__ float sd_all[4][729];
-  __shared__ uint8_t sok_all[4][732];
-  __shared__ int32_t snb_all[4][8];
+// 64-bit word per z layer); their triangle chunks are taken or recycled
+// here (one atomic each per block on the block's chunk segment) and filled
+// by k_triangles once the vertices exist.  The blocks owning edges of the
+// block's cubes become vertex-block candidates at fixed positions 8i..8i+7:
+// this block (marked kNewFlag when only a surface nearby makes it needed)
+// and, for cubes on its +x/+y/+z faces that changed, neighbours.
+template <int W>
+__global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass, int refine) {
+  __shared__ float sd_all[W][729];
+  __shared__ uint8_t sok_all[W][732];
+  __shared__ int32_t snb_all[W][8];
   const int wave = threadIdx.x >> 6, q = __lane_id(), lx = q & 7, ly = q >> 3;
   float* sd = sd_all[wave];
   uint8_t* sok = sok_all[wave];
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
   const int coff[8] = {0, 1, 1 + 9, 9, 81, 1 + 81, 1 + 9 + 81, 9 + 81};
-  for (uint32_t i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
+  for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
+    const uint32_t i = it.i;
     const uint32_t idx = v.dirty[i];
     const int32_t mynb = q < 8 ? v.nbr[(size_t)idx * 27 + nbr_dir(q & 1, (q >> 1) & 1, q >> 2)] : -1;
+    // the block's own types, independent of the halo: load them now
+    uint32_t old[8], prev[8];
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      old[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
+      prev[lz] = v.tprev[(size_t)idx * kVox + q + 64 * lz];
+    }
     if (q < 8) snb[q] = mynb;
     wave_sync();
     {
@@ -494,7 +523,8 @@ __global__ __launch_bounds__(256) void k_classify(VolDev v, uint32_t pass, int r
       }
     }
     wave_sync();
-    uint32_t flags = 0, nchanged = 0;
+    uint32_t flags = 0, nchanged = 0, chmask = 0, surf = 0;
+    uint32_t ntype[8];
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
       const int base = lx + 9 * ly + 81 * lz;
@@ -509,20 +539,22 @@ __global__ __launch_bounds__(256) void k_classify(VolDev v, uint32_t pass, int r
       }
       if (!valid) t = 0;
       const size_t o = (size_t)idx * kVox + q + 64 * lz;
-      const uint32_t old = v.tcur[o];
       uint32_t nt;
       if (!refine) {
-        v.tprev[o] = (uint8_t)old;
+        v.tprev[o] = (uint8_t)old[lz];
         nt = t;
       } else {
-        nt = valid ? refine_type(old, v.tprev[o], dc, v.eps) : old;
+        nt = valid ? refine_type(old[lz], prev[lz], dc, v.eps) : old[lz];
       }
-      if (nt != old) v.tcur[o] = (uint8_t)nt;
-      const bool tri_change = nt != old && (v.tri_table[old * 16] || v.tri_table[nt * 16]);
+      ntype[lz] = nt;
+      if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
+      surf |= v.tri_table[nt * 16];
+      const bool tri_change = nt != old[lz] && (v.tri_table[old[lz] * 16] || v.tri_table[nt * 16]);
       const uint64_t m = __ballot(tri_change);
       if (q == 0) v.chg[(size_t)idx * 8 + lz] = m;
       nchanged += (uint32_t)__popcll(m);
       if (tri_change) {
+        chmask |= 1u << lz;
         // owners of this cube's edges: this block and, on its +x/+y/+z
         // faces, the neighbours (never the +x+y+z corner one)
         const bool ex = lx == 7, ey = ly == 7, ez = lz == 7;
@@ -530,28 +562,78 @@ __global__ __launch_bounds__(256) void k_classify(VolDev v, uint32_t pass, int r
                  (ex && ez ? 32u : 0u) | (ey && ez ? 64u : 0u);
       }
     }
-    // wave-wide OR of the owner flags
-    uint32_t wflags = refine ? 0u : 1u;
+    // triangle chunks of the changed cubes: take one for a cube that gains
+    // triangles, recycle it for a cube that loses them
+    const uint32_t sg = idx % v.nseg;
+    int32_t chunk[8];
+    uint32_t nalloc = 0, nfree = 0;
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      chunk[lz] = -1;
+      if (!((chmask >> lz) & 1u)) continue;
+      chunk[lz] = v.cchunk[(size_t)idx * kVox + q + 64 * lz];
+      const bool has = v.tri_table[ntype[lz] * 16] != 0;
+      nalloc += has && chunk[lz] < 0;
+      nfree += !has && chunk[lz] >= 0;
+    }
+    uint32_t ta, tf;
+    uint32_t ra = wave_scan(nalloc, &ta), rf = wave_scan(nfree, &tf);
+    if (ta | tf) {
+      uint32_t ba = 0, bf = 0;
+      if (q == 0) {
+        if (ta) ba = atomicAdd(&v.cseg[sg].ticket, ta);
+        if (tf) bf = atomicAdd(&v.cseg[sg].push, tf);
+      }
+      ra += __shfl(ba, 0);
+      rf += __shfl(bf, 0);
+      const Seg& g = v.cseg[sg];
+      const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
+      const uint32_t gbase = sg * v.cseg_cap, gsize = seg_size(sg, v.cseg_cap, v.max_chunks);
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) {
+        if (!((chmask >> lz) & 1u)) continue;
+        const size_t o = (size_t)idx * kVox + q + 64 * lz;
+        const bool has = v.tri_table[ntype[lz] * 16] != 0;
+        if (!has && chunk[lz] >= 0) {
+          v.chunks[(size_t)chunk[lz] * kChunkWords] = kNone;
+          v.cring[gbase + (uint32_t)(((uint64_t)tail + rf++) % gsize)] = (uint32_t)chunk[lz];
+          v.cchunk[o] = -1;
+        } else if (has && chunk[lz] < 0) {
+          const uint32_t ns = seg_slot(head, tail, hwm, ra++, v.cring, gbase, gsize);
+          if (ns == kNone) atomicOr(&v.cnt->error, kErrTris);
+          else v.cchunk[o] = (int32_t)ns;
+        }
+      }
+    }
+    // wave-wide OR of the owner flags and of "some cube has triangles"
+    uint32_t wflags = 0;
     for (int b = 0; b < 7; ++b)
       if (__ballot((flags >> b) & 1u)) wflags |= 1u << b;
+    const bool any_surf = __ballot(surf != 0) != 0;
     if (q < 8) {
-      // extraction recomputes every dirty block's vertices (their end
-      // points may have moved); refinement only blocks with changed cubes
+      // extraction recomputes the vertices of every dirty block whose edges
+      // some surface uses (their end points may have moved); refinement
+      // only those of blocks with changed cubes
       uint32_t out = kNone;
-      if ((wflags >> q) & 1u) {
-        const int32_t nb = q == 0 ? (int32_t)idx : mynb;
-        if (nb >= 0 && v.st_vtx[nb] != pass && atomicMax(&v.st_vtx[nb], pass) < pass)
-          out = (uint32_t)nb;
-      }
+      if ((wflags >> q) & 1u) out = q == 0 ? idx : (mynb >= 0 ? (uint32_t)mynb : kNone);
+      else if (q == 0 && !refine) out = idx | kNewFlag;
       v.vcand[(size_t)i * 8 + q] = out;
     }
-    if (refine && q == 0 && nchanged) atomicAdd(&v.cseg[idx % kSegs].st_ref, nchanged);
+    if (q == 0) {
+      v.surf[idx] = any_surf ? 1 : 0;
+      if (nchanged) atomicAdd(&v.cseg[sg].st_chg, nchanged);
+      if (refine && nchanged) atomicAdd(&v.cseg[sg].st_ref, nchanged);
+    }
     wave_sync();
   }
 }
 
-// Compact the vertex-block candidates (8 per dirty block), one atomic per tile.
-__global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
+// Compact the vertex-block candidates (8 per dirty block) and claim each
+// block once per pass, one atomic per tile for the list.  A candidate
+// marked kNewFlag (a dirty block whose cubes did not change) is kept only
+// when it or one of its -x/-y/-z neighbours has a cube with triangles, i.e.
+// when some vertex on its edges can exist.
+__global__ __launch_bounds__(256) void k_vblock_compact(VolDev v, uint32_t pass) {
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase;
   const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
@@ -562,8 +644,20 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t t = t0 + threadIdx.x * 4 + k;
-      got[k] = t < total ? v.vcand[t] : kNone;
-      cnt += got[k] != kNone;
+      uint32_t c = t < total ? v.vcand[t] : kNone;
+      if (c != kNone && (c & kNewFlag)) {
+        c &= ~kNewFlag;
+        bool near = v.surf[c] != 0;
+        for (int o = 1; o < 8 && !near; ++o) {
+          const int32_t nb =
+              v.nbr[(size_t)c * 27 + nbr_dir(-(o & 1), -((o >> 1) & 1), -(o >> 2))];
+          near = nb >= 0 && v.surf[nb] != 0;
+        }
+        if (!near) c = kNone;
+      }
+      if (c != kNone && !(v.st_vtx[c] != pass && atomicMax(&v.st_vtx[c], pass) < pass)) c = kNone;
+      got[k] = c;
+      cnt += c != kNone;
     }
     uint32_t tot;
     uint32_t r = wg_scan(cnt, swave, &tot);
@@ -586,11 +680,12 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
 // in LDS with the -x/-y/-z halo, so no per-triangle increments are needed.
 // New vertices take slots from the block's pool segment, one atomic per
 // block.
-__global__ __launch_bounds__(256) void k_vertices(VolDev v) {
+template <int W>
+__global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
   __shared__ uint8_t suses[256 * 12];
-  __shared__ uint8_t st_all[4][732];   // cube types at local -1..7
-  __shared__ float sd_all[4][729];     // TSDF at local 0..8
-  __shared__ int32_t snb_all[4][27];
+  __shared__ uint8_t st_all[W][732];   // cube types at local -1..7
+  __shared__ float sd_all[W][729];     // TSDF at local 0..8
+  __shared__ int32_t snb_all[W][27];
   const int wave = threadIdx.x >> 6, q = __lane_id(), lx = q & 7, ly = q >> 3;
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(v.edge_uses);
@@ -603,42 +698,69 @@ __global__ __launch_bounds__(256) void k_vertices(VolDev v) {
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_vblocks, v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
-  for (uint32_t i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
+  for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
+    const uint32_t i = it.i;
     const uint32_t idx = v.vblocks[i];
-    const uint32_t sg = idx % kSegs;
+    const uint32_t sg = idx % v.nseg;
+    // which of the block's own edges hold a vertex (independent of the halo:
+    // loaded now, the slots themselves are read again after the allocation)
+    uint32_t has_slot = 0;  // bit 3*lz + a
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        has_slot |= (uint32_t)(v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz] >= 0) << (3 * lz + a);
     if (q < 27) snb[q] = v.nbr[(size_t)idx * 27 + q];
     wave_sync();
     {
-      // all loads of the two halos first, then the LDS stores
-      uint32_t tv[12];
-      float dv[12];
+      // own block: cube types at local 0..7 and TSDF at local 0..8, lane q
+      // holding column (lx, ly); loads first, then the LDS stores
+      uint32_t tv[8];
+      float dv[8];
 #pragma unroll
-      for (int it = 0; it < 12; ++it) {
-        const int j = q + 64 * it;
-        tv[it] = 0, dv[it] = 0.f;
-        if (j < 729) {
-          const int x = j % 9, y = (j / 9) % 9, z = j / 81;
-          const int cx = x - 1, cy = y - 1, cz = z - 1;
-          const int nb = snb[nbr_dir(cx < 0 ? -1 : 0, cy < 0 ? -1 : 0, cz < 0 ? -1 : 0)];
+      for (int lz = 0; lz < 8; ++lz) {
+        tv[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
+        dv[lz] = v.d[(size_t)idx * kVox + q + 64 * lz];
+      }
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) {
+        st[(lx + 1) + 9 * (ly + 1) + 81 * (lz + 1)] = (uint8_t)tv[lz];
+        sd[lx + 9 * ly + 81 * lz] = dv[lz];
+      }
+      // halos: cube types of the -x/-y/-z neighbours (local -1) and TSDF of
+      // the +x/+y/+z neighbours (local 8), 217 cells each
+      uint32_t th[4];
+      float dh[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int h = q + 64 * r;
+        th[r] = 0, dh[r] = 0.f;
+        if (h < 217) {
+          int x, y, z;
+          halo_cell(h, -1, x, y, z);
+          const int nb = snb[nbr_dir(x < 0 ? -1 : 0, y < 0 ? -1 : 0, z < 0 ? -1 : 0)];
+          if (nb >= 0) th[r] = v.tcur[(size_t)nb * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+          halo_cell(h, 8, x, y, z);
           const int nb2 = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
-          if (nb >= 0) tv[it] = v.tcur[(size_t)nb * kVox + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7)];
-          if (nb2 >= 0) dv[it] = v.d[(size_t)nb2 * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+          if (nb2 >= 0) dh[r] = v.d[(size_t)nb2 * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
         }
       }
 #pragma unroll
-      for (int it = 0; it < 12; ++it) {
-        const int j = q + 64 * it;
-        if (j < 729) {
-          st[j] = (uint8_t)tv[it];
-          sd[j] = dv[it];
+      for (int r = 0; r < 4; ++r) {
+        const int h = q + 64 * r;
+        if (h < 217) {
+          int x, y, z;
+          halo_cell(h, -1, x, y, z);
+          st[(x + 1) + 9 * (y + 1) + 81 * (z + 1)] = (uint8_t)th[r];
+          halo_cell(h, 8, x, y, z);
+          sd[x + 9 * y + 81 * z] = dh[r];
         }
       }
     }
     wave_sync();
-    int32_t slot[8][3];
     uint32_t refs[3] = {0, 0, 0};  // 8 counts of 4 bits per axis
     uint32_t nneed = 0;
-#pragma unroll
+#pragma unroll 2
     for (int lz = 0; lz < 8; ++lz) {
       const int tb = (lx + 1) + 9 * (ly + 1) + 81 * (lz + 1);
 #define USES(c, e) ((uint32_t)suses[(uint32_t)st[c] * 12 + (e)])
@@ -649,12 +771,8 @@ __global__ __launch_bounds__(256) void k_vertices(VolDev v) {
       refs[0] |= r0 << (4 * lz);
       refs[1] |= r1 << (4 * lz);
       refs[2] |= r2 << (4 * lz);
-      const uint32_t r[3] = {r0, r1, r2};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        slot[lz][a] = v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
-        nneed += r[a] > 0 && slot[lz][a] < 0;
-      }
+      const uint32_t hs = has_slot >> (3 * lz);
+      nneed += (r0 > 0 && !(hs & 1u)) + (r1 > 0 && !(hs & 2u)) + (r2 > 0 && !(hs & 4u));
     }
     uint32_t total;
     uint32_t rank = wave_scan(nneed, &total);
@@ -666,13 +784,14 @@ __global__ __launch_bounds__(256) void k_vertices(VolDev v) {
     const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
     const int step[3] = {1, 9, 81};
     uint32_t nnew = 0, nupd = 0;
-#pragma unroll
+#pragma unroll 2
     for (int lz = 0; lz < 8; ++lz) {
       const int sdb = lx + 9 * ly + 81 * lz;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const uint32_t ref = (refs[a] >> (4 * lz)) & 15u;
-        int32_t s = slot[lz][a];
+        if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
+        int32_t s = v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
         if (ref > 0) {
           if (s < 0) {
             const uint32_t ns = seg_slot(head, tail, hwm, rank++, v.vring, gbase, gsize);
@@ -718,18 +837,18 @@ __device__ inline void edge_owner(int e, int& ox, int& oy, int& oz, int& axis) {
   axis = (int)(p >> 3);
 }
 
-// One wave per dirty block: every cube whose triangles changed (re)writes
-// its triangle chunk as vertex slots of the owning edges, or recycles the
-// chunk when its new type has no triangles (Sec. V-D).  Unchanged cubes
-// keep theirs.  The changed cubes are listed in LDS; allocation and frees
-// take one atomic each per block on the block's chunk segment; each chunk
-// (64 bytes) is then written by 16 lanes.
-__global__ __launch_bounds__(256) void k_triangles(VolDev v) {
+// One wave per dirty block: every cube whose triangles changed and whose
+// new type has triangles writes its chunk (taken in k_classify) as vertex
+// slots of the owning edges (Sec. V-D); unchanged cubes keep theirs.  The
+// changed cubes are listed in LDS; each chunk (64 bytes) is written by 16
+// lanes, all edge-slot gathers of up to 32 cubes issued before the stores.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
   __shared__ uint8_t stri[256 * 16];
-  __shared__ uint16_t slist_all[4][512];
-  __shared__ int32_t schunk_all[4][512];
-  __shared__ uint8_t stype_all[4][512];
-  __shared__ int32_t snb_all[4][27];
+  __shared__ uint16_t slist_all[W][512];
+  __shared__ int32_t schunk_all[W][512];
+  __shared__ uint8_t stype_all[W][512];
+  __shared__ int32_t snb_all[W][27];
   const int wave = threadIdx.x >> 6, q = __lane_id();
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(v.tri_table);
@@ -742,12 +861,13 @@ __global__ __launch_bounds__(256) void k_triangles(VolDev v) {
   uint8_t* stype = stype_all[wave];
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
-  for (uint32_t i = blockIdx.x * 4 + wave; i < n; i += gridDim.x * 4) {
+  for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
+    const uint32_t i = it.i;
     const uint32_t idx = v.dirty[i];
     const uint64_t mymask = q < 8 ? v.chg[(size_t)idx * 8 + q] : 0ull;
+    const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
     if (!__ballot(mymask != 0ull)) continue;
-    if (q < 27) snb[q] = v.nbr[(size_t)idx * 27 + q];
-    const uint32_t sg = idx % kSegs;
+    if (q < 27) snb[q] = mynb;
     // list the changed cubes, z layer by z layer
     uint32_t nchg = 0;
     for (int lz = 0; lz < 8; ++lz) {
@@ -756,56 +876,12 @@ __global__ __launch_bounds__(256) void k_triangles(VolDev v) {
       nchg += (uint32_t)__popcll(m);
     }
     wave_sync();
-    // pass 1: types, chunks and the allocations / frees they need
-    uint32_t nalloc = 0, nfree = 0;
     for (uint32_t c = q; c < nchg; c += 64) {
       const size_t o = (size_t)idx * kVox + slist[c];
-      const uint32_t type = v.tcur[o];
-      const int32_t chunk = v.cchunk[o];
-      const uint32_t ntri = stri[type * 16];
-      stype[c] = (uint8_t)type;
-      schunk[c] = chunk;
-      nalloc += ntri > 0 && chunk < 0;
-      nfree += ntri == 0 && chunk >= 0;
-    }
-    uint32_t ta, tf;
-    uint32_t ra = wave_scan(nalloc, &ta), rf = wave_scan(nfree, &tf);
-    uint32_t ba = 0, bf = 0;
-    if (q == 0) {
-      if (ta) ba = atomicAdd(&v.cseg[sg].ticket, ta);
-      if (tf) bf = atomicAdd(&v.cseg[sg].push, tf);
-      atomicAdd(&v.cseg[sg].st_chg, nchg);
-    }
-    ra += __shfl(ba, 0);
-    rf += __shfl(bf, 0);
-    const Seg& g = v.cseg[sg];
-    const uint32_t gbase = sg * v.cseg_cap, gsize = seg_size(sg, v.cseg_cap, v.max_chunks);
-    // pass 2: take or recycle the chunks
-    for (uint32_t c = q; c < nchg; c += 64) {
-      const size_t o = (size_t)idx * kVox + slist[c];
-      const uint32_t ntri = stri[stype[c] * 16];
-      int32_t chunk = schunk[c];
-      if (ntri == 0) {
-        if (chunk >= 0) {
-          v.chunks[(size_t)chunk * kChunkWords] = kNone;
-          v.cring[gbase + (uint32_t)(((uint64_t)g.tail + rf++) % gsize)] = (uint32_t)chunk;
-          v.cchunk[o] = -1;
-        }
-        chunk = -1;
-      } else if (chunk < 0) {
-        const uint32_t ns = seg_slot(g.head, g.tail, g.hwm, ra++, v.cring, gbase, gsize);
-        if (ns == kNone) {
-          atomicOr(&v.cnt->error, kErrTris);
-        } else {
-          chunk = (int32_t)ns;
-          v.cchunk[o] = chunk;
-        }
-      }
-      schunk[c] = chunk;
+      stype[c] = v.tcur[o];
+      schunk[c] = v.cchunk[o];
     }
     wave_sync();
-    // pass 3: write the chunks, 16 lanes (64 bytes) per cube; up to 32
-    // cubes per round, all edge-slot gathers issued before the stores
     const int k = q & 15;
     for (uint32_t c0 = 0; c0 < nchg; c0 += 32) {
       uint32_t word[8];
@@ -816,11 +892,12 @@ __global__ __launch_bounds__(256) void k_triangles(VolDev v) {
         dst[r] = -1;
         word[r] = kNone;
         if (c >= nchg) continue;
-        const int32_t chunk = schunk[c];
-        if (chunk < 0) continue;
-        dst[r] = chunk;
-        const uint32_t l = slist[c], type = stype[c];
+        const uint32_t type = stype[c];
         const uint32_t ntri = stri[type * 16];
+        const int32_t chunk = schunk[c];
+        if (chunk < 0 || ntri == 0) continue;
+        dst[r] = chunk;
+        const uint32_t l = slist[c];
         if (k == 0) {
           word[r] = (idx << 9) | l;
         } else if (k - 1 < (int)(3 * ntri)) {
@@ -847,12 +924,12 @@ __global__ __launch_bounds__(256) void k_triangles(VolDev v) {
 // garbage collection (Sec. V-E)
 // ============================================================================
 
-// Workgroup w scans part w / kSegs of vertex segment w % kSegs up to its
+// Workgroup w scans part w / nseg of vertex segment w % nseg up to its
 // high-water mark and recycles the slots no triangle references.
 __global__ __launch_bounds__(256) void k_gc(VolDev v, uint32_t parts) {
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase;
-  const uint32_t sg = blockIdx.x % kSegs, part = blockIdx.x / kSegs;
+  const uint32_t sg = blockIdx.x % v.nseg, part = blockIdx.x / v.nseg;
   const Seg& g = v.vseg[sg];
   const uint32_t hwm = g.hwm, tail = g.tail;
   const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
@@ -900,6 +977,28 @@ __device__ inline uint32_t item_count(const VolDev& v, int what, uint32_t i) {
   uint32_t k = 0;
   for (int t = 0; t < 5; ++t) k += c[1 + 3 * t] != kNone;
   return k;
+}
+
+// Position in metres of the vertex in pool entry i, in the frame of its
+// volume (the slot's own frame in a batch): owner voxel g, plus t along the
+// edge's axis.  Returns the slot; *key receives the edge key when non-NULL.
+__device__ inline int vertex_position(const VolDev& v, uint32_t i, float p[3], uint64_t* key) {
+  const uint32_t owner = v.vowner[i];
+  const uint32_t blk = owner / (3 * kVox), rem = owner % (3 * kVox);
+  const int axis = (int)(rem / kVox), local = (int)(rem % kVox);
+  const uint64_t bkey = v.block_key[blk];
+  int bx, by, bz, slot;
+  unpack_key(bkey, bx, by, bz);
+  block_frame(v, bx, slot);
+  const int g[3] = {8 * bx + (local & 7), 8 * by + ((local >> 3) & 7), 8 * bz + (local >> 6)};
+  const float t = v.vt[i];
+  for (int a = 0; a < 3; ++a) {
+    float c = (float)g[a];
+    if (a == axis) c = c + t;
+    p[a] = c * v.s;
+  }
+  if (key) *key = edge_key(bkey, local, axis);
+  return slot;
 }
 
 __global__ __launch_bounds__(256) void k_dl_count(VolDev v, int what) {
@@ -951,22 +1050,29 @@ __global__ __launch_bounds__(256) void k_dl_write_vertices(VolDev v, float* __re
     }
     v.vdl[i] = (int32_t)j;
     if (j < vcap) {
-      const uint32_t owner = v.vowner[i];
-      const uint32_t blk = owner / (3 * kVox), rem = owner % (3 * kVox);
-      const int axis = (int)(rem / kVox), local = (int)(rem % kVox);
-      const uint64_t bkey = v.block_key[blk];
-      int bx, by, bz;
-      unpack_key(bkey, bx, by, bz);
-      const int g[3] = {8 * bx + (local & 7), 8 * by + ((local >> 3) & 7), 8 * bz + (local >> 6)};
-      const float t = v.vt[i];
-      for (int a = 0; a < 3; ++a) {
-        float p = (float)g[a];
-        if (a == axis) p = p + t;
-        verts[3 * (size_t)j + a] = p * v.s;
-      }
-      if (keys) keys[j] = edge_key(bkey, local, axis);
+      float p[3];
+      uint64_t key;
+      vertex_position(v, i, p, &key);
+      for (int a = 0; a < 3; ++a) verts[3 * (size_t)j + a] = p[a];
+      if (keys) keys[j] = key;
     }
     ++j;
+  }
+}
+
+// Every vertex pool entry's position (0 and slot -1 for entries without a
+// live vertex): no compaction, so no host round trip.
+__global__ __launch_bounds__(256) void k_positions(VolDev v, float* __restrict__ pos,
+                                                   int32_t* __restrict__ slot_of) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < v.max_vertices;
+       i += gridDim.x * blockDim.x) {
+    float p[3] = {0.f, 0.f, 0.f};
+    int slot = -1;
+    if (item_count(v, 0, i)) slot = vertex_position(v, i, p, nullptr);
+    pos[3 * (size_t)i] = p[0];
+    pos[3 * (size_t)i + 1] = p[1];
+    pos[3 * (size_t)i + 2] = p[2];
+    if (slot_of) slot_of[i] = slot;
   }
 }
 
@@ -1003,14 +1109,28 @@ __global__ __launch_bounds__(256) void k_dl_write_triangles(VolDev v, int32_t* _
 // edges incident to the voxel (its own three, and the three owned by its
 // -x/-y/-z neighbours), in a fixed order.
 __global__ __launch_bounds__(512) void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv,
-                                                  float* __restrict__ out) {
+                                                  int by_slot, const int32_t* __restrict__ rows,
+                                                  uint32_t n_rows, float* __restrict__ out) {
   __shared__ float sd[1000];  // TSDF at local -1..8
   __shared__ int32_t snb[27];
-  const uint32_t n = min(v.cnt->n_blocks, v.max_blocks);
+  const uint32_t nb_all = min(v.cnt->n_blocks, v.max_blocks);
+  const uint32_t n = rows ? n_rows : nb_all;
   const uint32_t nv = v.cnt->dl_nv;
   const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
   const int lc[3] = {lx, ly, lz};
-  for (uint32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
+  // upstream gradient row of the vertex in pool entry s, -1 if none
+  auto grad_row = [&](int32_t s) -> int32_t {
+    if (s < 0 || v.vref[s] <= 0) return -1;
+    if (by_slot) return s;
+    const int32_t r = v.vdl[s];
+    return r >= 0 && (uint32_t)r < nv ? r : -1;
+  };
+  for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
+    const int32_t idx = rows ? rows[it.i] : (int32_t)it.i;
+    if (idx < 0 || (uint32_t)idx >= nb_all) {
+      out[(size_t)it.i * kVox + l] = 0.f;
+      continue;
+    }
     if (l < 27) snb[l] = v.nbr[(size_t)idx * 27 + l];
     __syncthreads();
     for (int j = l; j < 1000; j += 512) {
@@ -1026,16 +1146,13 @@ __global__ __launch_bounds__(512) void k_bwd_tsdf(VolDev v, const float* __restr
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       // the edge this voxel owns: it is the first end point
-      int32_t s = v.evtx[((size_t)idx * 3 + a) * kVox + l];
-      if (s >= 0 && v.vref[s] > 0) {
-        const int32_t r = v.vdl[s];
-        if (r >= 0 && (uint32_t)r < nv) {
-          const float da = sd[c], db = sd[c + step[a]];
-          if (da != db) {
-            const float g = dL_dv[3 * (size_t)r + a] * v.s;
-            const float den = (da - db) * (da - db);
-            acc = acc + g * (-db / den);
-          }
+      int32_t r = grad_row(v.evtx[((size_t)idx * 3 + a) * kVox + l]);
+      if (r >= 0) {
+        const float da = sd[c], db = sd[c + step[a]];
+        if (da != db) {
+          const float g = dL_dv[3 * (size_t)r + a] * v.s;
+          const float den = (da - db) * (da - db);
+          acc = acc + g * (-db / den);
         }
       }
       // the edge its -a neighbour owns: it is the second end point
@@ -1048,21 +1165,18 @@ __global__ __launch_bounds__(512) void k_bwd_tsdf(VolDev v, const float* __restr
         // the -a neighbour block when this voxel is on the block's face
         const int lstep = a == 0 ? 1 : a == 1 ? 8 : 64;
         const int ol = back < 0 ? l + 7 * lstep : l - lstep;
-        s = v.evtx[((size_t)nb * 3 + a) * kVox + ol];
-        if (s >= 0 && v.vref[s] > 0) {
-          const int32_t r = v.vdl[s];
-          if (r >= 0 && (uint32_t)r < nv) {
-            const float da = sd[c - step[a]], db = sd[c];
-            if (da != db) {
-              const float g = dL_dv[3 * (size_t)r + a] * v.s;
-              const float den = (da - db) * (da - db);
-              acc = acc + g * (da / den);
-            }
+        r = grad_row(v.evtx[((size_t)nb * 3 + a) * kVox + ol]);
+        if (r >= 0) {
+          const float da = sd[c - step[a]], db = sd[c];
+          if (da != db) {
+            const float g = dL_dv[3 * (size_t)r + a] * v.s;
+            const float den = (da - db) * (da - db);
+            acc = acc + g * (da / den);
           }
         }
       }
     }
-    out[(size_t)idx * kVox + l] = acc;
+    out[(size_t)it.i * kVox + l] = acc;
     __syncthreads();
   }
 }
@@ -1075,7 +1189,8 @@ __global__ __launch_bounds__(512) void k_bwd_fusion(VolDev v, FrameParams fp,
                                                     float* __restrict__ gD) {
   const uint32_t n = min(v.cnt->n_blocks, v.max_blocks);
   const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
-  for (uint32_t idx = blockIdx.x; idx < n; idx += gridDim.x) {
+  for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
+    const uint32_t idx = it.i;
     const size_t o = (size_t)idx * kVox + l;
     const float g = g1[o];
     float out = g;
@@ -1092,6 +1207,12 @@ __global__ __launch_bounds__(512) void k_bwd_fusion(VolDev v, FrameParams fp,
     }
     g0[o] = out;
   }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = value;
 }
 
 __global__ void k_zero_f32(float* p, uint64_t n) {
@@ -1126,5 +1247,15 @@ __global__ void k_lookup(VolDev v, const int32_t* __restrict__ coords, int32_t* 
     idx[i] = key_in_range(x, y, z) ? hash_find(v, pack_key(x, y, z)) : -1;
   }
 }
+
+template __global__ void k_classify<2>(VolDev, uint32_t, int);
+template __global__ void k_classify<4>(VolDev, uint32_t, int);
+template __global__ void k_classify<8>(VolDev, uint32_t, int);
+template __global__ void k_vertices<2>(VolDev);
+template __global__ void k_vertices<4>(VolDev);
+template __global__ void k_vertices<8>(VolDev);
+template __global__ void k_triangles<2>(VolDev);
+template __global__ void k_triangles<4>(VolDev);
+template __global__ void k_triangles<8>(VolDev);
 
 }  // namespace vm

@@ -1,0 +1,135 @@
+"""The C-ABI library without a GPU: it loads, exports every function the
+header declares, its structs have the layout the Python binding assumes,
+and the host-only entry point (workspace sizing and configuration checks)
+behaves as documented."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1803_03949_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "voxmesh.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\bint\s+(vm_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_method_calls():
+    names = declared_functions()
+    for required in ["vm_create_volume", "vm_integrate_depth", "vm_extract_mesh",
+                     "vm_refine_mesh", "vm_gc", "vm_download_mesh", "vm_extract_backward",
+                     "vm_integrate_backward", "vm_import_batch", "vm_export_positions",
+                     "vm_extract_backward_slots", "vm_set_launch"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_function():
+    L = binding.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_signatures_for_every_function():
+    L = binding.lib()
+    for n in declared_functions():
+        assert getattr(L, n).argtypes is not None, n
+
+
+LAYOUT_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "voxmesh.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+int main() {
+  printf("vm_config %zu\n", sizeof(vm_config));
+  F(vm_config, hash_mode) F(vm_config, batch_volumes)
+  printf("vm_status %zu\n", sizeof(vm_status));
+  F(vm_status, blocks) F(vm_status, refined_cubes)
+  printf("vm_intrinsics %zu\n", sizeof(vm_intrinsics));
+  F(vm_intrinsics, max_depth_m)
+  printf("vm_launch %zu\n", sizeof(vm_launch));
+  F(vm_launch, block_order)
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    src = tmp_path / "probe.cpp"
+    src.write_text(LAYOUT_PROBE)
+    exe = tmp_path / "probe"
+    r = subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                        "-I", "/opt/rocm/include", str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True,
+                                                       text=True).stdout.splitlines())
+    want = {
+        "vm_config": ctypes.sizeof(binding.vm_config),
+        "vm_config.hash_mode": binding.vm_config.hash_mode.offset,
+        "vm_config.batch_volumes": binding.vm_config.batch_volumes.offset,
+        "vm_status": ctypes.sizeof(binding.vm_status),
+        "vm_status.blocks": binding.vm_status.blocks.offset,
+        "vm_status.refined_cubes": binding.vm_status.refined_cubes.offset,
+        "vm_intrinsics": ctypes.sizeof(binding.vm_intrinsics),
+        "vm_intrinsics.max_depth_m": binding.vm_intrinsics.max_depth_m.offset,
+        "vm_launch": ctypes.sizeof(binding.vm_launch),
+        "vm_launch.block_order": binding.vm_launch.block_order.offset,
+    }
+    assert {k: int(v) for k, v in got.items()} == want
+
+
+def cfg(**kw):
+    base = dict(voxel_m=0.008, trunc_vox=4.0, refine_eps_vox=0.5, hash_log2=16, max_blocks=4096,
+                max_vertices=1 << 18, max_tri_cubes=1 << 18, hash_mode=0, batch_volumes=0)
+    base.update(kw)
+    return binding.vm_config(**base)
+
+
+def volume_bytes(c):
+    n = ctypes.c_size_t()
+    r = binding.lib().vm_volume_bytes(ctypes.byref(c), ctypes.byref(n))
+    return r, n.value
+
+
+def test_volume_bytes_grows_with_every_capacity():
+    r, base = volume_bytes(cfg())
+    assert r == binding.VM_OK and base > 0
+    # the block pool holds at least TSDF + weight + types + edge slots per voxel
+    r, more = volume_bytes(cfg(max_blocks=8192))
+    assert r == 0 and more - base >= 4096 * 512 * (4 + 4 + 1 + 1 + 12)
+    r, more = volume_bytes(cfg(max_vertices=1 << 19))
+    assert r == 0 and more > base
+    r, more = volume_bytes(cfg(max_tri_cubes=1 << 19))
+    assert r == 0 and more > base
+    r, more = volume_bytes(cfg(hash_log2=17))
+    assert r == 0 and more - base >= 8 * (1 << 16)
+    # a batch needs no extra memory
+    assert volume_bytes(cfg(batch_volumes=64)) == (0, base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(voxel_m=0.0), dict(voxel_m=float("nan")), dict(trunc_vox=0.0), dict(refine_eps_vox=-1.0),
+    dict(hash_log2=9), dict(hash_log2=29), dict(max_blocks=0), dict(max_blocks=(1 << 21) + 1),
+    dict(max_vertices=0), dict(max_tri_cubes=0), dict(hash_mode=2), dict(batch_volumes=-1),
+    dict(batch_volumes=257),
+])
+def test_invalid_configurations_are_rejected(bad):
+    assert volume_bytes(cfg(**bad))[0] == -1
+
+
+def test_null_arguments_are_rejected():
+    L = binding.lib()
+    assert L.vm_volume_bytes(None, None) == -1
+    assert L.vm_destroy_volume(None) == -1
+    assert L.vm_extract_mesh(None, 0, None) == -1
+    assert L.vm_import_batch(None, None, None, None, None, 0, None, None) == -1
+    assert L.vm_export_positions(None, None, None, 0, None) == -1
+    assert L.vm_set_launch(None, None) == -1

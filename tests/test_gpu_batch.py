@@ -1,0 +1,170 @@
+"""Batched forward + backward over independent volumes (one slot each) vs the
+same steps volume by volume, vs the oracle, under HIP graph replay and under
+every workgroup mapping.
+
+Bar: the batch is an exact re-arrangement of the per-volume work, so the
+vertex set (positions) and the TSDF gradient must agree bit for bit with
+the plain per-volume path; against the oracle's FP64 gradient the FP32
+kernels are held to 1e-4 relative (floor 1e-4 of the largest magnitude)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from paper_1803_03949_amd import Volume, VmError, key_to_edge
+from paper_1803_03949_amd.binding import SLOT_SPAN
+from paper_1803_03949_amd.batch import (BatchMesher, PlainMesher, canonical_vertices,
+                                        sphere_loss_grad)
+
+pytestmark = pytest.mark.gpu
+
+S = 0.008
+
+
+def workload(n=6, lo=8, hi=400, seed=7):
+    vols = scenes.batch_volumes(seed=seed, n=n, voxel_m=S, lo=lo, hi=hi)
+    coords, ds, ws = [], [], []
+    for v in vols:
+        c, d, w = v.blocks()
+        coords.append(c)
+        ds.append(d)
+        ws.append(w)
+    tsdf = torch.from_numpy(np.concatenate(ds).reshape(-1, 512)).cuda()
+    weight = torch.from_numpy(np.concatenate(ws).reshape(-1, 512)).cuda()
+    centers = torch.tensor(np.stack([v.meta["center"] for v in vols]), dtype=torch.float32).cuda()
+    radii = torch.tensor([v.meta["target_radius"] for v in vols], dtype=torch.float32).cuda()
+    return vols, coords, tsdf, weight, centers, radii
+
+
+def plain_for(coords, tsdf, weight, centers, radii):
+    grads = [sphere_loss_grad(centers[i:i + 1], radii[i:i + 1]) for i in range(len(coords))]
+    return PlainMesher(S, coords, tsdf, weight, grads)
+
+
+def per_slot_vertices(m: BatchMesher):
+    rows = canonical_vertices(m.pos, m.slot)
+    return [rows[rows[:, 0] == k][:, 1:] for k in range(m.n_vol)]
+
+
+def test_batch_matches_per_volume_path_bit_for_bit():
+    vols, coords, tsdf, weight, centers, radii = workload()
+    print(f"[batch] sizes {[len(c) for c in coords]}", flush=True)
+    b = BatchMesher(S, coords, tsdf, weight, sphere_loss_grad(centers, radii))
+    b.run()
+    p = plain_for(coords, tsdf, weight, centers, radii)
+    p.run()
+    torch.cuda.synchronize()
+    assert b.vol.status()["error"] == 0
+    assert torch.equal(b.grad, p.grad())
+    got = per_slot_vertices(b)
+    for k, it in enumerate(p.items):
+        want = canonical_vertices(it["pos"], it["slot"])[:, 1:]
+        assert got[k].shape == want.shape and np.array_equal(got[k], want), k
+    assert float(b.grad.abs().max()) > 0
+
+
+def test_batch_gradient_matches_oracle():
+    vols, coords, tsdf, weight, centers, radii = workload(n=3, lo=20, hi=150, seed=8)
+    b = BatchMesher(S, coords, tsdf, weight, sphere_loss_grad(centers, radii))
+    b.run()
+    torch.cuda.synchronize()
+    g = b.grad.cpu().numpy()
+    verts, _, vkeys = b.vol.download()
+    verts = verts.cpu().numpy().astype(np.float64)
+    edges = key_to_edge(vkeys)
+    # stored block x of slot k is 64k - 8192 + local x
+    slot = (edges[:, 0] // 8 + 8192) // SLOT_SPAN
+    edges[:, 0] -= 8 * (SLOT_SPAN * slot - 8192)
+    off = 0
+    for k, v in enumerate(vols):
+        c, d, w = v.blocks()
+        o = oracle.OracleVolume(S)
+        o.import_blocks(c, d, w)
+        o.extract(scope_all=True)
+        pos = o.positions64()
+        ctr, r = v.meta["center"], v.meta["target_radius"]
+        dist = np.linalg.norm(pos - ctr, axis=1)
+        dLdv = (2 * (dist - r) / dist)[:, None] * (pos - ctr)
+        ref = o.grad_tsdf64(dLdv)
+        oc = o.blocks()["coords"]
+        idx = {tuple(x): i for i, x in enumerate(oc.tolist())}
+        sel = np.array([idx[tuple(x)] for x in c.tolist()])
+        want = ref[sel]
+        got = g[off:off + len(c)]
+        floor = 1e-4 * np.abs(want).max()
+        assert np.all(np.abs(got - want) <= 1e-4 * np.abs(want) + floor), k
+        # the vertex set itself: oracle edges and positions vs the slot frame
+        keys = o.vertices()["keys"]
+        want_pos = {tuple(e): p for e, p in zip(keys.tolist(), pos)}
+        mine = slot == k
+        assert int(mine.sum()) == len(want_pos)
+        for e, p in zip(edges[mine].tolist(), verts[mine]):
+            assert np.abs(p - want_pos[tuple(e)]).max() <= 1e-5 * S + 2e-7
+        off += len(c)
+
+
+def test_graph_replays_match_eager():
+    vols, coords, tsdf, weight, centers, radii = workload(n=5, seed=9)
+    b = BatchMesher(S, coords, tsdf, weight, sphere_loss_grad(centers, radii))
+    b.run()
+    torch.cuda.synchronize()
+    eager = b.grad.clone()
+    eager_v = canonical_vertices(b.pos, b.slot)
+    b.capture()
+    p = plain_for(coords, tsdf, weight, centers, radii)
+    for rep in range(3):
+        b.grad.fill_(float("nan"))
+        b.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(b.grad, eager), rep
+        assert np.array_equal(canonical_vertices(b.pos, b.slot), eager_v), rep
+        p.run()  # unrelated eager work between replays
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("w", [2, 4, 8])
+@pytest.mark.parametrize("order", [0, 1])
+def test_every_mapping_gives_identical_bits(w, order):
+    vols, coords, tsdf, weight, centers, radii = workload(n=4, seed=10)
+    b = BatchMesher(S, coords, tsdf, weight, sphere_loss_grad(centers, radii))
+    b.run()
+    torch.cuda.synchronize()
+    ref, ref_v = b.grad.clone(), canonical_vertices(b.pos, b.slot)
+    for groups, bg in [(1, 1), (4, 2), (16, 8)]:
+        b.set_launch(wave_group_size=w, wave_groups_per_cu=groups, block_groups_per_cu=bg,
+                     item_groups_per_cu=groups, block_order=order)
+        b.run()
+        torch.cuda.synchronize()
+        assert torch.equal(b.grad, ref), (groups, bg)
+        assert np.array_equal(canonical_vertices(b.pos, b.slot), ref_v), (groups, bg)
+
+
+def test_positions_are_the_downloaded_vertices():
+    sv = scenes.sphere_volume(seed=1)
+    c, d, w = sv.blocks()
+    v = Volume(S, hash_log2=12, max_blocks=1024, max_vertices=1 << 16, max_tri_cubes=1 << 16)
+    v.import_blocks(*(torch.from_numpy(x).cuda() for x in (c, d.reshape(-1, 512), w.reshape(-1, 512))))
+    v.extract(scope_all=True)
+    pos, slot = v.positions()
+    verts, _, _ = v.download(with_keys=False)
+    live = canonical_vertices(pos, slot)
+    assert np.all(live[:, 0] == 0)
+    dv = verts.cpu().numpy().astype(np.float64)
+    assert np.array_equal(live[:, 1:], dv[np.lexsort(dv.T[::-1])])
+
+
+def test_batch_range_errors():
+    b = Volume(S, hash_log2=12, max_blocks=64, max_vertices=1 << 12, max_tri_cubes=1 << 12,
+               batch_volumes=2)
+    z = torch.zeros((1, 512), dtype=torch.float32, device="cuda")
+    for slot, x in [(2, 0), (-1, 0), (0, 63), (0, -1)]:
+        b.reset()
+        b.import_batch(torch.tensor([slot], dtype=torch.int32, device="cuda"),
+                       torch.tensor([[x, 0, 0]], dtype=torch.int32, device="cuda"), z, z)
+        with pytest.raises(VmError, match="VM_ERR_RANGE"):
+            b.status()
+    # a batch takes no plain import and no depth frame
+    b.reset()
+    with pytest.raises(VmError, match="VM_ERR_ARG"):
+        b.import_blocks(torch.zeros((1, 3), dtype=torch.int32, device="cuda"), z, z)

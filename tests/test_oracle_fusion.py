@@ -119,3 +119,37 @@ def test_pose_translation_shifts_the_collected_blocks():
     vol.integrate(scenes.plane_depth(D1), scenes.K, T)
     b = {tuple(x) for x in vol.block_set("frame").tolist()}
     assert b == {(x + 3, y - 2, z + 5) for x, y, z in a}
+
+
+def test_restricted_collection_matches_full_run_on_the_kept_blocks():
+    """Collection and fusion of a block depend only on the depth frame and
+    the block itself, so restricting collection to a sample of blocks gives
+    those blocks bit for bit the TSDF and weights of the full run (and the
+    absent ones stay absent)."""
+    seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=0.008)
+    frames = [seq.frame(k) for k in (0, 1)]
+    full = oracle.OracleVolume(0.008)
+    for k, f in enumerate(frames):
+        full.integrate(f, scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+    fb = full.blocks()
+    rng = np.random.default_rng(0)
+    keep = fb["coords"][rng.choice(len(fb["coords"]), 24, replace=False)]
+    have = {tuple(c) for c in fb["coords"].tolist()}
+    absent = []
+    for c in fb["coords"][rng.permutation(len(fb["coords"]))].tolist():
+        for off in ((-2, 0, 0), (0, -2, 0), (0, 0, 2), (3, 3, 3)):
+            n = (c[0] + off[0], c[1] + off[1], c[2] + off[2])
+            if n not in have and len(absent) < 8:
+                absent.append(n)
+    sample = np.concatenate([keep, np.array(absent, np.int32)])
+    part = oracle.OracleVolume(0.008)
+    part.restrict(sample)
+    for k, f in enumerate(frames):
+        part.integrate(f, scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+    pb = part.blocks()
+    assert {tuple(c) for c in pb["coords"].tolist()} == {tuple(c) for c in keep.tolist()}
+    row = {tuple(c): i for i, c in enumerate(fb["coords"].tolist())}
+    for i, c in enumerate(pb["coords"].tolist()):
+        j = row[tuple(c)]
+        assert np.array_equal(pb["d"][i].view(np.uint32), fb["d"][j].view(np.uint32))
+        assert np.array_equal(pb["w"][i], fb["w"][j])
