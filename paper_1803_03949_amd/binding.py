@@ -13,7 +13,10 @@ import os
 import numpy as np
 import torch
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvoxmesh.so")
+# The library built in this package directory; VOXMESH_LIBRARY names another
+# build of the same sources (e.g. to compare two builds side by side).
+LIB_PATH = os.environ.get("VOXMESH_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libvoxmesh.so")
 
 VM_OK = 0
 VM_SCOPE_DIRTY, VM_SCOPE_ALL = 0, 1

@@ -103,7 +103,6 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->evtx = (int32_t*)take(4 * 3 * kVox * B);
   v->cchunk = (int32_t*)take(4 * kVox * B);
   v->chg = (uint64_t*)take(8 * 8 * B);
-  v->surf = (uint8_t*)take(B);
   v->st_pending = (uint32_t*)take(4 * B);
   v->st_dirty = (uint32_t*)take(4 * B);
   v->st_vtx = (uint32_t*)take(4 * B);
@@ -410,8 +409,7 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
               vol->epoch);
   ++vol->epoch;
   VM_LAUNCH_W(vol, VM_K_CLASSIFY, k_classify, stream, v, pass, 0);
-  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v,
-            pass);
+  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
   VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
   VM_LAUNCH_W(vol, VM_K_TRIANGLES, k_triangles, stream, v);
   return launched();
@@ -423,8 +421,7 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   const uint32_t pass = ++vol->pass;
   prep(vol, VM_OP_REFINE, stream);
   VM_LAUNCH_W(vol, VM_K_REFINE, k_classify, stream, v, pass, 1);
-  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v,
-            pass);
+  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
   VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
   VM_LAUNCH_W(vol, VM_K_TRIANGLES, k_triangles, stream, v);
   return launched();

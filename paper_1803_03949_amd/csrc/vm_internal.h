@@ -116,7 +116,6 @@ struct VolDev {
   int32_t* evtx;              // [B][3][512]
   int32_t* cchunk;            // [B][512]
   uint64_t* chg;              // [B][8] cubes whose triangles changed, per wave
-  uint8_t* surf;              // [B] 1 when some cube of the block has triangles
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
   uint32_t* st_vtx;           // [B] pass that listed the block for vertices
@@ -410,7 +409,7 @@ __global__ void k_dirty(VolDev v, uint32_t pass, uint32_t epoch);
 __global__ void k_dirty_all(VolDev v, uint32_t pass);
 template <int W>
 __global__ void k_classify(VolDev v, uint32_t pass, int refine);
-__global__ void k_vblock_compact(VolDev v, uint32_t pass);
+__global__ void k_vblock_compact(VolDev v);
 template <int W>
 __global__ void k_vertices(VolDev v);
 template <int W>

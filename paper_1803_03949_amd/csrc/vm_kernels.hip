@@ -331,7 +331,6 @@ __global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
     if (isnew) {
       init_cube(v, idx, l);
       link_block(v, idx, l);
-      if (l == 0) v.surf[idx] = 0;
     } else {
       d = v.d[o], w = v.w[o];
     }
@@ -365,7 +364,6 @@ __global__ __launch_bounds__(512) void k_import_copy(VolDev v, const float* __re
     if (e & kNewFlag) {
       init_cube(v, idx, l);
       link_block(v, idx, l);
-      if (l == 0) v.surf[idx] = 0;
     }
     const uint32_t row = v.frame_src[i];
     const size_t src = (size_t)row * kVox + l;
@@ -466,18 +464,17 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
 // refine = 0: new cube types from the signs (Sec. V-B), previous type
 // saved.  refine = 1: Eqs. (3)-(5) applied to the current types (Sec. V-F).
 // Cubes whose triangles change are recorded in the block's bitmask (one
-// 64-bit word per z layer); their triangle chunks are taken or recycled
-// here (one atomic each per block on the block's chunk segment) and filled
-// by k_triangles once the vertices exist.  The blocks owning edges of the
-// block's cubes become vertex-block candidates at fixed positions 8i..8i+7:
-// this block (marked kNewFlag when only a surface nearby makes it needed)
-// and, for cubes on its +x/+y/+z faces that changed, neighbours.
+// 64-bit word per z layer) for k_triangles.  The blocks whose vertices must
+// be recomputed are claimed (once per pass) and written as candidates at
+// fixed positions 8i..8i+7: on extraction this block (its edges' end points
+// may have moved), and the owners of the edges of changed cubes (this block
+// and, for cubes on its +x/+y/+z faces, neighbours).
 template <int W>
 __global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass, int refine) {
   __shared__ float sd_all[W][729];
   __shared__ uint8_t sok_all[W][732];
   __shared__ int32_t snb_all[W][8];
-  const int wave = threadIdx.x >> 6, q = __lane_id(), lx = q & 7, ly = q >> 3;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id(), lx = q & 7, ly = q >> 3;
   float* sd = sd_all[wave];
   uint8_t* sok = sok_all[wave];
   int32_t* snb = snb_all[wave];
@@ -523,8 +520,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass,
       }
     }
     wave_sync();
-    uint32_t flags = 0, nchanged = 0, chmask = 0, surf = 0;
-    uint32_t ntype[8];
+    uint32_t flags = 0, nchanged = 0;
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
       const int base = lx + 9 * ly + 81 * lz;
@@ -546,15 +542,12 @@ __global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass,
       } else {
         nt = valid ? refine_type(old[lz], prev[lz], dc, v.eps) : old[lz];
       }
-      ntype[lz] = nt;
       if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
-      surf |= v.tri_table[nt * 16];
       const bool tri_change = nt != old[lz] && (v.tri_table[old[lz] * 16] || v.tri_table[nt * 16]);
       const uint64_t m = __ballot(tri_change);
       if (q == 0) v.chg[(size_t)idx * 8 + lz] = m;
       nchanged += (uint32_t)__popcll(m);
       if (tri_change) {
-        chmask |= 1u << lz;
         // owners of this cube's edges: this block and, on its +x/+y/+z
         // faces, the neighbours (never the +x+y+z corner one)
         const bool ex = lx == 7, ey = ly == 7, ez = lz == 7;
@@ -562,78 +555,31 @@ __global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass,
                  (ex && ez ? 32u : 0u) | (ey && ez ? 64u : 0u);
       }
     }
-    // triangle chunks of the changed cubes: take one for a cube that gains
-    // triangles, recycle it for a cube that loses them
-    const uint32_t sg = idx % v.nseg;
-    int32_t chunk[8];
-    uint32_t nalloc = 0, nfree = 0;
-#pragma unroll
-    for (int lz = 0; lz < 8; ++lz) {
-      chunk[lz] = -1;
-      if (!((chmask >> lz) & 1u)) continue;
-      chunk[lz] = v.cchunk[(size_t)idx * kVox + q + 64 * lz];
-      const bool has = v.tri_table[ntype[lz] * 16] != 0;
-      nalloc += has && chunk[lz] < 0;
-      nfree += !has && chunk[lz] >= 0;
-    }
-    uint32_t ta, tf;
-    uint32_t ra = wave_scan(nalloc, &ta), rf = wave_scan(nfree, &tf);
-    if (ta | tf) {
-      uint32_t ba = 0, bf = 0;
-      if (q == 0) {
-        if (ta) ba = atomicAdd(&v.cseg[sg].ticket, ta);
-        if (tf) bf = atomicAdd(&v.cseg[sg].push, tf);
-      }
-      ra += __shfl(ba, 0);
-      rf += __shfl(bf, 0);
-      const Seg& g = v.cseg[sg];
-      const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
-      const uint32_t gbase = sg * v.cseg_cap, gsize = seg_size(sg, v.cseg_cap, v.max_chunks);
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz) {
-        if (!((chmask >> lz) & 1u)) continue;
-        const size_t o = (size_t)idx * kVox + q + 64 * lz;
-        const bool has = v.tri_table[ntype[lz] * 16] != 0;
-        if (!has && chunk[lz] >= 0) {
-          v.chunks[(size_t)chunk[lz] * kChunkWords] = kNone;
-          v.cring[gbase + (uint32_t)(((uint64_t)tail + rf++) % gsize)] = (uint32_t)chunk[lz];
-          v.cchunk[o] = -1;
-        } else if (has && chunk[lz] < 0) {
-          const uint32_t ns = seg_slot(head, tail, hwm, ra++, v.cring, gbase, gsize);
-          if (ns == kNone) atomicOr(&v.cnt->error, kErrTris);
-          else v.cchunk[o] = (int32_t)ns;
-        }
-      }
-    }
-    // wave-wide OR of the owner flags and of "some cube has triangles"
-    uint32_t wflags = 0;
+    // wave-wide OR of the owner flags
+    uint32_t wflags = refine ? 0u : 1u;
     for (int b = 0; b < 7; ++b)
       if (__ballot((flags >> b) & 1u)) wflags |= 1u << b;
-    const bool any_surf = __ballot(surf != 0) != 0;
     if (q < 8) {
-      // extraction recomputes the vertices of every dirty block whose edges
-      // some surface uses (their end points may have moved); refinement
-      // only those of blocks with changed cubes
       uint32_t out = kNone;
-      if ((wflags >> q) & 1u) out = q == 0 ? idx : (mynb >= 0 ? (uint32_t)mynb : kNone);
-      else if (q == 0 && !refine) out = idx | kNewFlag;
+      if ((wflags >> q) & 1u) {
+        const int32_t nb = q == 0 ? (int32_t)idx : mynb;
+        if (nb >= 0 && v.st_vtx[nb] != pass && atomicMax(&v.st_vtx[nb], pass) < pass)
+          out = (uint32_t)nb;
+      }
       v.vcand[(size_t)i * 8 + q] = out;
     }
-    if (q == 0) {
-      v.surf[idx] = any_surf ? 1 : 0;
-      if (nchanged) atomicAdd(&v.cseg[sg].st_chg, nchanged);
-      if (refine && nchanged) atomicAdd(&v.cseg[sg].st_ref, nchanged);
+    if (q == 0 && nchanged) {
+      const uint32_t sg = idx % v.nseg;
+      atomicAdd(&v.cseg[sg].st_chg, nchanged);
+      if (refine) atomicAdd(&v.cseg[sg].st_ref, nchanged);
     }
     wave_sync();
   }
 }
 
-// Compact the vertex-block candidates (8 per dirty block) and claim each
-// block once per pass, one atomic per tile for the list.  A candidate
-// marked kNewFlag (a dirty block whose cubes did not change) is kept only
-// when it or one of its -x/-y/-z neighbours has a cube with triangles, i.e.
-// when some vertex on its edges can exist.
-__global__ __launch_bounds__(256) void k_vblock_compact(VolDev v, uint32_t pass) {
+// Compact the vertex-block candidates (8 per dirty block, already claimed),
+// one atomic per tile.
+__global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase;
   const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
@@ -644,20 +590,8 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v, uint32_t pass)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t t = t0 + threadIdx.x * 4 + k;
-      uint32_t c = t < total ? v.vcand[t] : kNone;
-      if (c != kNone && (c & kNewFlag)) {
-        c &= ~kNewFlag;
-        bool near = v.surf[c] != 0;
-        for (int o = 1; o < 8 && !near; ++o) {
-          const int32_t nb =
-              v.nbr[(size_t)c * 27 + nbr_dir(-(o & 1), -((o >> 1) & 1), -(o >> 2))];
-          near = nb >= 0 && v.surf[nb] != 0;
-        }
-        if (!near) c = kNone;
-      }
-      if (c != kNone && !(v.st_vtx[c] != pass && atomicMax(&v.st_vtx[c], pass) < pass)) c = kNone;
-      got[k] = c;
-      cnt += c != kNone;
+      got[k] = t < total ? v.vcand[t] : kNone;
+      cnt += got[k] != kNone;
     }
     uint32_t tot;
     uint32_t r = wg_scan(cnt, swave, &tot);
@@ -686,7 +620,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
   __shared__ uint8_t st_all[W][732];   // cube types at local -1..7
   __shared__ float sd_all[W][729];     // TSDF at local 0..8
   __shared__ int32_t snb_all[W][27];
-  const int wave = threadIdx.x >> 6, q = __lane_id(), lx = q & 7, ly = q >> 3;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id(), lx = q & 7, ly = q >> 3;
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(v.edge_uses);
     uint32_t* dst = reinterpret_cast<uint32_t*>(suses);
@@ -702,19 +636,22 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
     const uint32_t i = it.i;
     const uint32_t idx = v.vblocks[i];
     const uint32_t sg = idx % v.nseg;
-    // which of the block's own edges hold a vertex (independent of the halo:
-    // loaded now, the slots themselves are read again after the allocation)
+    // requested at once: the neighbour table, which of the block's edges
+    // hold a vertex (the slots themselves are read again after the
+    // allocation) and its pool segment (fixed during this kernel)
+    const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
+    const Seg& g = v.vseg[sg];
+    const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
     uint32_t has_slot = 0;  // bit 3*lz + a
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz)
 #pragma unroll
       for (int a = 0; a < 3; ++a)
         has_slot |= (uint32_t)(v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz] >= 0) << (3 * lz + a);
-    if (q < 27) snb[q] = v.nbr[(size_t)idx * 27 + q];
+    if (q < 27) snb[q] = mynb;
     wave_sync();
     {
-      // own block: cube types at local 0..7 and TSDF at local 0..8, lane q
-      // holding column (lx, ly); loads first, then the LDS stores
+      // own block into LDS: cube types at local 0..7, TSDF at local 0..7
       uint32_t tv[8];
       float dv[8];
 #pragma unroll
@@ -758,7 +695,9 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
       }
     }
     wave_sync();
-    uint32_t refs[3] = {0, 0, 0};  // 8 counts of 4 bits per axis
+    // 8 counts of 8 bits per axis: an edge can carry up to 16 triangles (four
+    // in each of its four cubes)
+    uint64_t refs[3] = {0, 0, 0};
     uint32_t nneed = 0;
 #pragma unroll 2
     for (int lz = 0; lz < 8; ++lz) {
@@ -768,9 +707,9 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
       const uint32_t r1 = USES(tb, 3) + USES(tb - 1, 1) + USES(tb - 81, 7) + USES(tb - 82, 5);
       const uint32_t r2 = USES(tb, 8) + USES(tb - 1, 9) + USES(tb - 10, 10) + USES(tb - 9, 11);
 #undef USES
-      refs[0] |= r0 << (4 * lz);
-      refs[1] |= r1 << (4 * lz);
-      refs[2] |= r2 << (4 * lz);
+      refs[0] |= (uint64_t)r0 << (8 * lz);
+      refs[1] |= (uint64_t)r1 << (8 * lz);
+      refs[2] |= (uint64_t)r2 << (8 * lz);
       const uint32_t hs = has_slot >> (3 * lz);
       nneed += (r0 > 0 && !(hs & 1u)) + (r1 > 0 && !(hs & 2u)) + (r2 > 0 && !(hs & 4u));
     }
@@ -779,8 +718,6 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
     uint32_t base = 0;
     if (q == 0 && total) base = atomicAdd(&v.vseg[sg].ticket, total);
     rank += __shfl(base, 0);
-    const Seg& g = v.vseg[sg];
-    const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
     const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
     const int step[3] = {1, 9, 81};
     uint32_t nnew = 0, nupd = 0;
@@ -789,7 +726,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
       const int sdb = lx + 9 * ly + 81 * lz;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const uint32_t ref = (refs[a] >> (4 * lz)) & 15u;
+        const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u;
         if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
         int32_t s = v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
         if (ref > 0) {
@@ -837,11 +774,13 @@ __device__ inline void edge_owner(int e, int& ox, int& oy, int& oz, int& axis) {
   axis = (int)(p >> 3);
 }
 
-// One wave per dirty block: every cube whose triangles changed and whose
-// new type has triangles writes its chunk (taken in k_classify) as vertex
-// slots of the owning edges (Sec. V-D); unchanged cubes keep theirs.  The
-// changed cubes are listed in LDS; each chunk (64 bytes) is written by 16
-// lanes, all edge-slot gathers of up to 32 cubes issued before the stores.
+// One wave per dirty block: every cube whose triangles changed gets its
+// triangles rewritten (Sec. V-D) as vertex slots of the owning edges; a cube
+// that gains triangles takes a 64-byte chunk, one that loses them recycles
+// it (one atomic each per block on the block's chunk segment); unchanged
+// cubes keep theirs.  The changed cubes are listed in LDS; each chunk is
+// written by 16 lanes, all edge-slot gathers of up to 32 cubes issued
+// before the stores.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
   __shared__ uint8_t stri[256 * 16];
@@ -849,7 +788,7 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
   __shared__ int32_t schunk_all[W][512];
   __shared__ uint8_t stype_all[W][512];
   __shared__ int32_t snb_all[W][27];
-  const int wave = threadIdx.x >> 6, q = __lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id();
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(v.tri_table);
     uint32_t* dst = reinterpret_cast<uint32_t*>(stri);
@@ -861,11 +800,49 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
   uint8_t* stype = stype_all[wave];
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
+  const int k = q & 15;
+  // the chunk words lane q writes for the 32 cubes c0 + 4r + q/16 (r < 8):
+  // word 0 the owner cube, then the vertex slots of the triangles' edges
+  auto gather = [&](uint32_t idx, uint32_t c0, uint32_t nchg, uint32_t word[8]) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t c = c0 + 4 * r + (q >> 4);
+      word[r] = kNone;
+      if (c >= nchg) continue;
+      const uint32_t l = slist[c], type = stype[c];
+      const uint32_t ntri = stri[type * 16];
+      if (k == 0) {
+        word[r] = (idx << 9) | l;
+      } else if (k - 1 < (int)(3 * ntri)) {
+        int ox, oy, oz, axis;
+        edge_owner(stri[type * 16 + k], ox, oy, oz, axis);
+        const int x = (int)(l & 7) + ox, y = (int)((l >> 3) & 7) + oy, z = (int)(l >> 6) + oz;
+        const int32_t nb = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
+        if (nb >= 0) {
+          const int32_t s =
+              v.evtx[((size_t)nb * 3 + axis) * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+          word[r] = s >= 0 ? (uint32_t)s : kNone;
+        }
+      }
+    }
+  };
+  auto store = [&](uint32_t c0, uint32_t nchg, const uint32_t word[8]) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t c = c0 + 4 * r + (q >> 4);
+      if (c >= nchg) continue;
+      const int32_t chunk = schunk[c];
+      if (chunk >= 0) v.chunks[(size_t)chunk * kChunkWords + k] = word[r];
+    }
+  };
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
-    const uint32_t i = it.i;
-    const uint32_t idx = v.dirty[i];
+    const uint32_t idx = v.dirty[it.i];
+    const uint32_t sg = idx % v.nseg;
     const uint64_t mymask = q < 8 ? v.chg[(size_t)idx * 8 + q] : 0ull;
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
+    // the block's chunk segment does not change during this kernel
+    const Seg& g = v.cseg[sg];
+    const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
     if (!__ballot(mymask != 0ull)) continue;
     if (q < 27) snb[q] = mynb;
     // list the changed cubes, z layer by z layer
@@ -876,45 +853,62 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
       nchg += (uint32_t)__popcll(m);
     }
     wave_sync();
+    // types, chunks and the allocations / frees they need
+    uint32_t nalloc = 0, nfree = 0;
     for (uint32_t c = q; c < nchg; c += 64) {
       const size_t o = (size_t)idx * kVox + slist[c];
-      stype[c] = v.tcur[o];
-      schunk[c] = v.cchunk[o];
+      const uint32_t type = v.tcur[o];
+      const int32_t chunk = v.cchunk[o];
+      const uint32_t ntri = stri[type * 16];
+      stype[c] = (uint8_t)type;
+      schunk[c] = chunk;
+      nalloc += ntri > 0 && chunk < 0;
+      nfree += ntri == 0 && chunk >= 0;
+    }
+    uint32_t ta, tf;
+    uint32_t ra = wave_scan(nalloc, &ta), rf = wave_scan(nfree, &tf);
+    uint32_t ba = 0, bf = 0;
+    if (q == 0) {
+      if (ta) ba = atomicAdd(&v.cseg[sg].ticket, ta);
+      if (tf) bf = atomicAdd(&v.cseg[sg].push, tf);
     }
     wave_sync();
-    const int k = q & 15;
-    for (uint32_t c0 = 0; c0 < nchg; c0 += 32) {
-      uint32_t word[8];
-      int32_t dst[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const uint32_t c = c0 + 4 * r + (q >> 4);
-        dst[r] = -1;
-        word[r] = kNone;
-        if (c >= nchg) continue;
-        const uint32_t type = stype[c];
-        const uint32_t ntri = stri[type * 16];
-        const int32_t chunk = schunk[c];
-        if (chunk < 0 || ntri == 0) continue;
-        dst[r] = chunk;
-        const uint32_t l = slist[c];
-        if (k == 0) {
-          word[r] = (idx << 9) | l;
-        } else if (k - 1 < (int)(3 * ntri)) {
-          int ox, oy, oz, axis;
-          edge_owner(stri[type * 16 + k], ox, oy, oz, axis);
-          const int x = (int)(l & 7) + ox, y = (int)((l >> 3) & 7) + oy, z = (int)(l >> 6) + oz;
-          const int32_t nb = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
-          if (nb >= 0) {
-            const int32_t s =
-                v.evtx[((size_t)nb * 3 + axis) * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
-            word[r] = s >= 0 ? (uint32_t)s : kNone;
+    // the first 32 cubes' edge-slot gathers overlap the pool atomics
+    uint32_t word[8];
+    gather(idx, 0, nchg, word);
+    if (ta | tf) {
+      ra += __shfl(ba, 0);
+      rf += __shfl(bf, 0);
+      const uint32_t gbase = sg * v.cseg_cap, gsize = seg_size(sg, v.cseg_cap, v.max_chunks);
+      for (uint32_t c = q; c < nchg; c += 64) {
+        const size_t o = (size_t)idx * kVox + slist[c];
+        const uint32_t ntri = stri[stype[c] * 16];
+        int32_t chunk = schunk[c];
+        if (ntri == 0) {
+          if (chunk >= 0) {
+            v.chunks[(size_t)chunk * kChunkWords] = kNone;
+            v.cring[gbase + (uint32_t)(((uint64_t)tail + rf++) % gsize)] = (uint32_t)chunk;
+            v.cchunk[o] = -1;
+          }
+          chunk = -1;
+        } else if (chunk < 0) {
+          const uint32_t ns = seg_slot(head, tail, hwm, ra++, v.cring, gbase, gsize);
+          if (ns == kNone) {
+            atomicOr(&v.cnt->error, kErrTris);
+          } else {
+            chunk = (int32_t)ns;
+            v.cchunk[o] = chunk;
           }
         }
+        schunk[c] = chunk;
       }
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (dst[r] >= 0) v.chunks[(size_t)dst[r] * kChunkWords + k] = word[r];
+      wave_sync();
+    }
+    // write the chunks, 16 lanes (64 bytes) per cube, 32 cubes per round
+    store(0, nchg, word);
+    for (uint32_t c0 = 32; c0 < nchg; c0 += 32) {
+      gather(idx, c0, nchg, word);
+      store(c0, nchg, word);
     }
     wave_sync();
   }

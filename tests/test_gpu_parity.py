@@ -199,3 +199,26 @@ def test_capacity_errors_are_reported(which):
     assert st["error"] == want, st
     with pytest.raises(VmError):
         g.status()
+
+
+@pytest.mark.parametrize("origin", [(3, 3, 3), (7, 8, 8), (7, 7, 7), (8, 8, 8)])
+def test_most_loaded_edges(origin):
+    """Edges carrying 16 triangles (the most any edge can), inside a block
+    and across block faces, edges and corners: counts, vertices and
+    triangles as the oracle's."""
+    from tests.edge_load import POINTS, edge_loads
+    load, pats = edge_loads()
+    best = pats[load == load.max()]
+    tsdf = np.full((16, 16, 16), 2.0, np.float32)  # (z, y, x)
+    for j, pat in enumerate(best[:3]):
+        gx, gy, gz = origin[0], origin[1], origin[2]
+        shift = 0 if j == 0 else (j * 5) % 6
+        for i, (x, y, z) in enumerate(POINTS):
+            inside = (int(pat) >> i) & 1
+            tsdf[gz + z, gy + y, (gx + x + shift) % 16] = -0.5 if inside else 0.5
+    dense = scenes.DenseVolume(0.01, (2, 2, 2), tsdf, np.ones_like(tsdf))
+    g, o = import_both(dense, 0.01)
+    g.extract(scope_all=True)
+    o.extract(scope_all=True)
+    compare_all(g, o)
+    assert int(o.vertices()["ref"].max()) == 16

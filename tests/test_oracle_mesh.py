@@ -232,3 +232,15 @@ def test_gc_frees_exactly_the_unreferenced_vertices():
     # every remaining vertex is used by a triangle and vice versa
     used = {tuple(k) for tri in vol.triangles().tolist() for k in tri}
     assert used == {tuple(k) for k in after["keys"].tolist()}
+
+
+def test_an_edge_can_carry_more_than_fifteen_triangles():
+    """Reference counts need more than four bits: the four cubes around an
+    edge can each use it in four triangles (brute force over all 2^18 sign
+    patterns of their corners).  A crossing edge is used by every one of the
+    four cubes, so a count is 0 or at least 4."""
+    from tests.edge_load import edge_loads
+    load, pats = edge_loads()
+    assert load.max() == 16
+    counts = set(np.unique(load).tolist())
+    assert counts == {0} | set(range(4, 17))
