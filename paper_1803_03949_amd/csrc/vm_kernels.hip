@@ -613,13 +613,18 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
 // from the end point TSDF values.  The counts come from cube types staged
 // in LDS with the -x/-y/-z halo, so no per-triangle increments are needed.
 // New vertices take slots from the block's pool segment, one atomic per
-// block.
+// block; the block's edge slots are kept in LDS and the recycled slots it
+// takes are fetched in one batch, so the write pass waits on no memory.
+constexpr int kRingBatch = 256;  // recycled slots fetched per block at once
+
 template <int W>
-__global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
+__global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
   __shared__ uint8_t suses[256 * 12];
-  __shared__ uint8_t st_all[W][732];   // cube types at local -1..7
-  __shared__ float sd_all[W][729];     // TSDF at local 0..8
+  __shared__ uint32_t st_all[W][kRingBatch];  // cube types at local -1..7, then slots
+  __shared__ float sd_all[W][729];            // TSDF at local 0..8
+  __shared__ int32_t ses_all[W][3 * kVox];    // slot of edge (a, l) at a * 512 + l
   __shared__ int32_t snb_all[W][27];
+  static_assert(kRingBatch * 4 >= 732, "type staging fits the slot batch");
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id(), lx = q & 7, ly = q >> 3;
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(v.edge_uses);
@@ -627,27 +632,36 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
     for (int j = threadIdx.x; j < 256 * 12 / 4; j += blockDim.x) dst[j] = src[j];
   }
   __syncthreads();
-  uint8_t* st = st_all[wave];
+  uint8_t* st = reinterpret_cast<uint8_t*>(st_all[wave]);
+  uint32_t* sring = st_all[wave];
   float* sd = sd_all[wave];
+  int32_t* ses = ses_all[wave];
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_vblocks, v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
-    const uint32_t i = it.i;
-    const uint32_t idx = v.vblocks[i];
+    const uint32_t idx = v.vblocks[it.i];
     const uint32_t sg = idx % v.nseg;
-    // requested at once: the neighbour table, which of the block's edges
-    // hold a vertex (the slots themselves are read again after the
-    // allocation) and its pool segment (fixed during this kernel)
+    // requested at once: the neighbour table, the block's edge slots and
+    // its pool segment (fixed during this kernel)
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
     const Seg& g = v.vseg[sg];
     const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
     uint32_t has_slot = 0;  // bit 3*lz + a
+    {
+      int32_t es[24];
 #pragma unroll
-    for (int lz = 0; lz < 8; ++lz)
+      for (int lz = 0; lz < 8; ++lz)
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        has_slot |= (uint32_t)(v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz] >= 0) << (3 * lz + a);
+        for (int a = 0; a < 3; ++a) es[3 * lz + a] = v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          ses[a * kVox + q + 64 * lz] = es[3 * lz + a];
+          has_slot |= (uint32_t)(es[3 * lz + a] >= 0) << (3 * lz + a);
+        }
+    }
     if (q < 27) snb[q] = mynb;
     wave_sync();
     {
@@ -717,8 +731,15 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
     uint32_t rank = wave_scan(nneed, &total);
     uint32_t base = 0;
     if (q == 0 && total) base = atomicAdd(&v.vseg[sg].ticket, total);
-    rank += __shfl(base, 0);
+    base = __shfl(base, 0);
     const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
+    // the slots of the first kRingBatch allocations, fetched together (the
+    // type staging is no longer needed: the batch reuses its LDS)
+    wave_sync();
+    const uint32_t batch = min(total, (uint32_t)kRingBatch);
+    for (uint32_t k = q; k < batch; k += 64)
+      sring[k] = seg_slot(head, tail, hwm, base + k, v.vring, gbase, gsize);
+    wave_sync();
     const int step[3] = {1, 9, 81};
     uint32_t nnew = 0, nupd = 0;
 #pragma unroll 2
@@ -728,10 +749,13 @@ __global__ __launch_bounds__(64 * W, 4) void k_vertices(VolDev v) {
       for (int a = 0; a < 3; ++a) {
         const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u;
         if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
-        int32_t s = v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
+        int32_t s = ses[a * kVox + q + 64 * lz];
         if (ref > 0) {
           if (s < 0) {
-            const uint32_t ns = seg_slot(head, tail, hwm, rank++, v.vring, gbase, gsize);
+            const uint32_t ns = rank < batch ? sring[rank]
+                                             : seg_slot(head, tail, hwm, base + rank, v.vring,
+                                                        gbase, gsize);
+            ++rank;
             if (ns == kNone) {
               atomicOr(&v.cnt->error, kErrVertices);
               continue;
