@@ -222,3 +222,21 @@ def test_most_loaded_edges(origin):
     o.extract(scope_all=True)
     compare_all(g, o)
     assert int(o.vertices()["ref"].max()) == 16
+
+
+def test_wide_truncation_band():
+    """A truncation band several blocks deep: pixel boxes of up to 5^3
+    blocks (beyond the per-lane batch of the collection kernel)."""
+    seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=0.03)
+    g = new_volume(seq.voxel_m, trunc_vox=14.0)
+    o = oracle.OracleVolume(seq.voxel_m, 14.0, 0.5)
+    for k in (0, 7):
+        depth = seq.frame(k)
+        g.integrate(to_dev(depth)[0], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        o.integrate(depth, scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        gf = {tuple(x) for x in g.block_list("frame").tolist()}
+        of = {tuple(x) for x in o.block_set("frame").tolist()}
+        assert gf == of
+        g.extract()
+        o.extract()
+    compare_all(g, o)
