@@ -128,8 +128,7 @@ def room_fusion(args, dev):
     log(f"rendered {args.frames} frames in {time.time() - t0:.1f}s")
     depth = torch.from_numpy(np.stack(frames)).to(dev)
     poses = list(seq.poses)
-    vol = Volume(seq.voxel_m, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23,
-                 max_tri_cubes=1 << 23, device=dev)
+    vol = Volume(seq.voxel_m, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23, device=dev)
 
     def step():
         vol.reset()
@@ -210,8 +209,7 @@ def sphere_extract(dev):
     sv = scenes.sphere_volume(seed=1)
     coords, d, w = sv.blocks()
     cdev = [torch.from_numpy(a).to(dev) for a in (coords, d, w)]
-    vol = Volume(sv.voxel_m, hash_log2=16, max_blocks=1024, max_vertices=1 << 20,
-                 max_tri_cubes=1 << 20, device=dev)
+    vol = Volume(sv.voxel_m, hash_log2=16, max_blocks=1024, max_vertices=1 << 20, device=dev)
     times = []
     for rep in range(110):
         vol.reset()
@@ -241,8 +239,7 @@ def room_fine(args, dev):
     depth = torch.from_numpy(np.stack(frames)).to(dev)
     poses = list(seq.poses)
     del frames
-    vol = Volume(seq.voxel_m, hash_log2=22, max_blocks=1 << 19, max_vertices=1 << 24,
-                 max_tri_cubes=1 << 24, device=dev)
+    vol = Volume(seq.voxel_m, hash_log2=22, max_blocks=1 << 19, max_vertices=1 << 24, device=dev)
 
     def step():
         vol.reset()
@@ -279,8 +276,7 @@ def grad_scene_fwd_bwd(dev):
 
     gs = scenes.grad_scene(seed=4)
     coords, d, w = gs.volume.blocks()
-    vol = Volume(gs.volume.voxel_m, hash_log2=16, max_blocks=1 << 14, max_vertices=1 << 21,
-                 max_tri_cubes=1 << 21, device=dev)
+    vol = Volume(gs.volume.voxel_m, hash_log2=16, max_blocks=1 << 14, max_vertices=1 << 21, device=dev)
     cd, td, wd = (torch.from_numpy(a).to(dev) for a in (coords, d, w))
     dd = torch.from_numpy(gs.depth).to(dev)
     (c0, r0) = gs.target.spheres[0]

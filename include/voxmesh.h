@@ -68,7 +68,7 @@ enum {
   VM_ERR_HASH_FULL = -2,       /* hash table probe sequence exhausted */
   VM_ERR_BLOCK_POOL_FULL = -3, /* more blocks than max_blocks */
   VM_ERR_VERTEX_POOL_FULL = -4,/* more live vertices than max_vertices */
-  VM_ERR_TRI_POOL_FULL = -5,   /* more triangle-holding cubes than max_tri_cubes */
+  VM_ERR_TRI_POOL_FULL = -5,   /* reserved (triangles are stored per cube) */
   VM_ERR_CAPACITY = -6,        /* caller output buffer too small */
   VM_ERR_HIP = -7,             /* a HIP runtime call failed */
   VM_ERR_RANGE = -8            /* a block coordinate outside [-8192, 8191] */
@@ -76,7 +76,10 @@ enum {
 
 enum { VM_SCOPE_DIRTY = 0, VM_SCOPE_ALL = 1 };
 
-/* Volume configuration.  Sizes are capacities of the caller buffer. */
+/* Volume configuration.  Sizes are capacities of the caller buffer: per
+ * block of max_blocks about 45 KiB (TSDF and weight 4 KiB, types 1 KiB,
+ * edge-to-vertex slots 6 KiB, the triangles of its 512 cubes 32 KiB) and per
+ * vertex of max_vertices 20 bytes, plus 12 bytes per hash slot. */
 typedef struct vm_config {
   float voxel_m;        /* cube edge length s in metres (e.g. 0.008) */
   float trunc_vox;      /* truncation mu in voxel units (e.g. 4) */
@@ -84,7 +87,6 @@ typedef struct vm_config {
   int32_t hash_log2;    /* hash table holds 2^hash_log2 slots, 10..28 */
   int32_t max_blocks;   /* block pool capacity, 1 .. 2^21 */
   int32_t max_vertices; /* vertex pool capacity, 1 .. 2^30 */
-  int32_t max_tri_cubes;/* cubes holding triangles at one time, 1 .. 2^30 */
   int32_t hash_mode;    /* 0: mixing hash; 1: every key starts probing at
                            slot 0 (long probe chains, for testing only) */
   int32_t batch_volumes;/* 0: a plain volume; m in 1..256: a batch of m
@@ -110,8 +112,8 @@ typedef struct vm_status {
   int64_t changed_cubes;    /* cubes whose triangles changed */
   int64_t vertex_slots;     /* vertex pool high-water mark */
   int64_t free_vertex_slots;/* recycled vertex slots awaiting reuse */
-  int64_t tri_cube_slots;   /* triangle pool high-water mark (cubes) */
-  int64_t free_tri_cube_slots;
+  int64_t triangles;        /* triangles of the current mesh */
+  int64_t tri_cubes;        /* cubes holding triangles */
   int64_t new_vertices;     /* vertices created by the last extract/refine */
   int64_t updated_vertices; /* vertices whose position was rewritten */
   int64_t freed_vertices;   /* vertices recycled by the last vm_gc */

@@ -60,12 +60,12 @@ def sphere_loss(pos: torch.Tensor, slot: torch.Tensor, centers, radii) -> float:
     return float((d * d).sum())
 
 
-def capacities(n_blocks: int) -> tuple[int, int]:
-    """Vertex and triangle-cube pool sizes for a volume of n_blocks blocks
-    holding a sphere-like surface: 64 per block plus 8192 (the 64 workload
-    volumes hold 15 vertices per block on average, at most 102 per block in
-    volumes of a few blocks, which the constant covers)."""
-    return 64 * n_blocks + 8192, 64 * n_blocks + 8192
+def vertex_capacity(n_blocks: int) -> int:
+    """Vertex pool size for a volume of n_blocks blocks holding a
+    sphere-like surface: 64 per block plus 8192 (the 64 workload volumes
+    hold 15 vertices per block on average, at most 102 per block in volumes
+    of a few blocks, which the constant covers)."""
+    return 64 * n_blocks + 8192
 
 
 class BatchMesher:
@@ -84,10 +84,10 @@ class BatchMesher:
         self.sizes = sizes
         N = sum(sizes)
         self.n_blocks = N
-        V, T = capacities(N)
+        V = vertex_capacity(N)
         hash_log2 = max(12, int(math.ceil(math.log2(max(2 * N, 2)))))
         self.vol = Volume(voxel_m, trunc_vox=trunc_vox, hash_log2=hash_log2, max_blocks=N,
-                          max_vertices=V, max_tri_cubes=T, batch_volumes=self.n_vol)
+                          max_vertices=V, batch_volumes=self.n_vol)
         dev = self.vol.device
         c = np.concatenate([np.asarray(x, np.int32).reshape(-1, 3) for x in coords])
         assert c[:, 0].min() >= 0 and c[:, 0].max() <= SLOT_SPAN - 2
@@ -147,10 +147,10 @@ class PlainMesher:
         off = 0
         for i, c in enumerate(coords):
             n = int(len(c))
-            V, T = capacities(n)
+            V = vertex_capacity(n)
             hash_log2 = max(12, int(math.ceil(math.log2(max(2 * n, 2)))))
             vol = Volume(voxel_m, trunc_vox=trunc_vox, hash_log2=hash_log2, max_blocks=n,
-                         max_vertices=V, max_tri_cubes=T)
+                         max_vertices=V)
             dev = vol.device
             self.items.append(dict(
                 coords=torch.from_numpy(np.asarray(c, np.int32).reshape(-1, 3)).to(dev),

@@ -37,7 +37,7 @@ class vm_config(ctypes.Structure):
     _fields_ = [("voxel_m", ctypes.c_float), ("trunc_vox", ctypes.c_float),
                 ("refine_eps_vox", ctypes.c_float), ("hash_log2", ctypes.c_int32),
                 ("max_blocks", ctypes.c_int32), ("max_vertices", ctypes.c_int32),
-                ("max_tri_cubes", ctypes.c_int32), ("hash_mode", ctypes.c_int32),
+                ("hash_mode", ctypes.c_int32),
                 ("batch_volumes", ctypes.c_int32)]
 
 
@@ -58,8 +58,8 @@ class vm_intrinsics(ctypes.Structure):
 
 
 _STATUS_FIELDS = ["blocks", "frame_blocks", "pending_blocks", "dirty_blocks", "vertex_blocks",
-                  "changed_cubes", "vertex_slots", "free_vertex_slots", "tri_cube_slots",
-                  "free_tri_cube_slots", "new_vertices", "updated_vertices", "freed_vertices",
+                  "changed_cubes", "vertex_slots", "free_vertex_slots", "triangles",
+                  "tri_cubes", "new_vertices", "updated_vertices", "freed_vertices",
                   "refined_cubes"]
 
 
@@ -148,14 +148,14 @@ class Volume:
 
     def __init__(self, voxel_m: float, trunc_vox: float = 4.0, refine_eps_vox: float = 0.5,
                  hash_log2: int = 20, max_blocks: int = 1 << 16, max_vertices: int = 1 << 22,
-                 max_tri_cubes: int = 1 << 22, hash_mode: int = 0, batch_volumes: int = 0,
+                 hash_mode: int = 0, batch_volumes: int = 0,
                  device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("voxmesh needs a ROCm GPU (torch.cuda.is_available() is False)")
         L = lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.cfg = vm_config(voxel_m, trunc_vox, refine_eps_vox, hash_log2, max_blocks,
-                             max_vertices, max_tri_cubes, hash_mode, batch_volumes)
+                             max_vertices, hash_mode, batch_volumes)
         nbytes = ctypes.c_size_t()
         _check(L.vm_volume_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)), "vm_volume_bytes")
         self.nbytes = nbytes.value
@@ -235,7 +235,7 @@ class Volume:
         """(verts (V,3) f32 metres, tris (F,3) i32, keys (V,) int64 or None)."""
         st = self.status(stream)
         vcap = max(1, st["vertex_slots"])
-        tcap = max(1, 5 * st["tri_cube_slots"])
+        tcap = max(1, st["triangles"])
         verts = torch.empty((vcap, 3), dtype=torch.float32, device=self.device)
         tris = torch.empty((tcap, 3), dtype=torch.int32, device=self.device)
         keys = torch.empty(vcap, dtype=torch.int64, device=self.device) if with_keys else None

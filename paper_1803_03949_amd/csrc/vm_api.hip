@@ -54,8 +54,8 @@ bool config_ok(const vm_config* c) {
   return c && c->voxel_m > 0.f && isfinite(c->voxel_m) && c->trunc_vox > 0.f &&
          isfinite(c->trunc_vox) && c->refine_eps_vox >= 0.f && c->hash_log2 >= 10 &&
          c->hash_log2 <= 28 && c->max_blocks >= 1 && c->max_blocks <= kMaxBlocks &&
-         c->max_vertices >= 1 && c->max_vertices <= (1 << 30) && c->max_tri_cubes >= 1 &&
-         c->max_tri_cubes <= (1 << 30) && (c->hash_mode == 0 || c->hash_mode == 1) &&
+         c->max_vertices >= 1 && c->max_vertices <= (1 << 30) &&
+         (c->hash_mode == 0 || c->hash_mode == 1) &&
          c->batch_volumes >= 0 && c->batch_volumes <= kMaxSlots;
 }
 
@@ -84,8 +84,8 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
     return p;
   };
   const size_t H = (size_t)1 << c.hash_log2, B = (size_t)c.max_blocks,
-               V = (size_t)c.max_vertices, T = (size_t)c.max_tri_cubes;
-  const size_t scan = (V > T ? V : T) / 1024 + 2;
+               V = (size_t)c.max_vertices, C = B * kVox;
+  const size_t scan = (V > C ? V : C) / 1024 + 2;
   v->cnt = (Counters*)take(sizeof(Counters));
   v->vseg = (Seg*)take(sizeof(Seg) * kSegs);
   v->cseg = (Seg*)take(sizeof(Seg) * kSegs);
@@ -101,7 +101,6 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->tprev = (uint8_t*)take(kVox * B);
   v->tcur = (uint8_t*)take(kVox * B);
   v->evtx = (int32_t*)take(4 * 3 * kVox * B);
-  v->cchunk = (int32_t*)take(4 * kVox * B);
   v->chg = (uint64_t*)take(8 * 8 * B);
   v->st_pending = (uint32_t*)take(4 * B);
   v->st_dirty = (uint32_t*)take(4 * B);
@@ -118,18 +117,15 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->vref = (int32_t*)take(4 * V);
   v->vring = (uint32_t*)take(4 * V);
   v->vdl = (int32_t*)take(4 * V);
-  v->chunks = (uint32_t*)take(4 * kChunkWords * T);
-  v->cring = (uint32_t*)take(4 * T);
+  v->chunks = (uint32_t*)take(4 * kChunkWords * C);
   v->scan = (uint32_t*)take(4 * scan);
   v->scan_cap = (uint32_t)scan;
   v->max_blocks = (uint32_t)B;
   v->max_vertices = (uint32_t)V;
-  v->max_chunks = (uint32_t)T;
   // one segment per 256 blocks of capacity, at most kSegs
   const size_t nseg = B / 256 < 1 ? 1 : (B / 256 > (size_t)kSegs ? (size_t)kSegs : B / 256);
   v->nseg = (uint32_t)nseg;
   v->vseg_cap = (uint32_t)((V + nseg - 1) / nseg);
-  v->cseg_cap = (uint32_t)((T + nseg - 1) / nseg);
   v->hash_mask = (uint32_t)(H - 1);
   v->hash_mode = c.hash_mode;
   return off;
@@ -446,7 +442,8 @@ int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys, int32_t*
   int r = launched();
   if (r != VM_OK) return r;
   Counters c;
-  const uint32_t pv = (v.max_vertices + 1023) / 1024, pt = (v.max_chunks + 1023) / 1024;
+  const uint32_t pv = (v.max_vertices + 1023) / 1024,
+                 pt = (uint32_t)(((uint64_t)v.max_blocks * kVox + 1023) / 1024);
   const uint32_t vc = (uint32_t)(vcap > 0xFFFFFFFFll ? 0xFFFFFFFFll : vcap);
   const uint32_t tc = (uint32_t)(tcap > 0xFFFFFFFFll ? 0xFFFFFFFFll : tcap);
   VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_count, dim3(pv), dim3(256), stream, v, 0);
@@ -528,12 +525,12 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   const Counters& c = sn.c;
   const uint32_t B = vol->dev.max_blocks;
   uint32_t st_new = 0, st_upd = 0, st_freed = 0, st_chg = 0, st_ref = 0;
-  int64_t vh = 0, vf = 0, ch = 0, cf = 0;
+  int64_t vh = 0, vf = 0, tris = 0, tcubes = 0;
   for (int k = 0; k < kSegs; ++k) {
     st_new += sn.vseg[k].st_new, st_upd += sn.vseg[k].st_upd, st_freed += sn.vseg[k].st_freed;
     st_chg += sn.cseg[k].st_chg, st_ref += sn.cseg[k].st_ref;
     vh += sn.vseg[k].hwm, vf += sn.vseg[k].tail - sn.vseg[k].head;
-    ch += sn.cseg[k].hwm, cf += sn.cseg[k].tail - sn.cseg[k].head;
+    tris += sn.cseg[k].st_tri, tcubes += sn.cseg[k].st_tcube;
   }
   memset(out, 0, sizeof(*out));
   out->error = error_code(c.error);
@@ -546,8 +543,8 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   out->changed_cubes = st_chg - c.base_chg;
   out->vertex_slots = vh;
   out->free_vertex_slots = vf;
-  out->tri_cube_slots = ch;
-  out->free_tri_cube_slots = cf;
+  out->triangles = tris;
+  out->tri_cubes = tcubes;
   out->new_vertices = st_new - c.base_new;
   out->updated_vertices = st_upd - c.base_upd;
   out->freed_vertices = st_freed - c.base_freed;

@@ -15,12 +15,13 @@
 //             u64[8], pass stamps.
 //   vertices  t f32, owner edge (index into the edge->vertex array) u32,
 //             reference count i32 (-1 = free), recycle ring, download row.
-//   triangles one 64-byte chunk per cube that holds triangles: owner cube,
-//             then up to 5 triangles as 3 vertex slots each.
+//   triangles one 64-byte record per cube, at a fixed place in its block's
+//             region: up to 5 triangles as 3 vertex slots each (the cube's
+//             type says how many are valid).
 //
 // Contention on single counters is what limits a GPU here, not bytes: every
-// list is built with at most one atomic per workgroup, and the vertex and
-// triangle pools are split into up to kSegs independent segments (a block's
+// list is built with at most one atomic per workgroup, and the vertex pool
+// is split into up to kSegs independent segments (a block's
 // allocations go to segment block % nseg; small volumes use fewer segments
 // so that each still averages over many blocks), each with its own 128-byte
 // counter line, bump pointer and recycle ring.
@@ -42,7 +43,7 @@ constexpr uint32_t kPending = kIdxMask - 1;
 constexpr int kKeyBias = 8192;               // block coords in [-8192, 8191]
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kNewFlag = 0x80000000u;   // frame-list entry: block is new
-constexpr int kChunkWords = 16;              // owner + 5 triangles * 3 slots
+constexpr int kChunkWords = 16;              // 5 triangles * 3 slots, 1 spare
 constexpr int kMaxBlocks = 1 << 21;
 constexpr int kSegs = 64;                    // pool segments
 constexpr int kTile = 1024;                  // list items per compaction workgroup
@@ -68,7 +69,9 @@ struct Seg {
   uint32_t st_freed; // running count of frees
   uint32_t st_chg;   // running count of cubes whose triangles changed
   uint32_t st_ref;   // running count of cubes re-typed by refinement
-  uint32_t pad[22];
+  int32_t st_tri;    // running change of the number of triangles
+  int32_t st_tcube;  // running change of the number of cubes with triangles
+  uint32_t pad[20];
 };
 static_assert(sizeof(Seg) == 128, "segment record size");
 
@@ -96,12 +99,12 @@ struct VolDev {
   float s, inv_s, inv_block, mu_m, mu_v, eps;
   uint32_t hash_mask;
   int32_t hash_mode;
-  uint32_t max_blocks, max_vertices, max_chunks;
+  uint32_t max_blocks, max_vertices;
   uint32_t nseg;              // pool segments in use (1..kSegs)
-  uint32_t vseg_cap, cseg_cap;  // slots per segment
+  uint32_t vseg_cap;            // vertex slots per segment
   Counters* cnt;
   Seg* vseg;                  // [kSegs] vertex pool segments
-  Seg* cseg;                  // [kSegs] triangle chunk pool segments
+  Seg* cseg;                  // [kSegs] cube statistics (changed, refined, triangles)
   const uint8_t* tri_table;   // [256][16]: count, then 15 cube-edge ids
   const uint8_t* edge_uses;   // [256][12]: triangles of the type using the edge
   unsigned long long* slots;  // [hash]
@@ -114,7 +117,6 @@ struct VolDev {
   uint8_t* tprev;             // [B][512]
   uint8_t* tcur;              // [B][512]
   int32_t* evtx;              // [B][3][512]
-  int32_t* cchunk;            // [B][512]
   uint64_t* chg;              // [B][8] cubes whose triangles changed, per wave
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
@@ -131,8 +133,7 @@ struct VolDev {
   int32_t* vref;              // [V]
   uint32_t* vring;            // [V]
   int32_t* vdl;               // [V] row in the last download, -1 if none
-  uint32_t* chunks;           // [T][16]
-  uint32_t* cring;            // [T]
+  uint32_t* chunks;           // [B][512][16] triangles of every cube
   uint32_t* scan;             // [scan_cap] download partial sums
   uint32_t scan_cap;
   uint32_t batch;             // number of volume slots, 0 for a plain volume

@@ -26,14 +26,13 @@ __device__ inline void finalise_seg(Seg& g, uint32_t size) {
   g.push = 0;
 }
 
-// One wave: lane s finalises segment s of both pools, the lanes sum the
+// One wave: lane s finalises vertex pool segment s, the lanes sum the
 // segment statistics, then lane 0 does the operation's resets and snapshots.
 __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
   const int s = threadIdx.x;
   Seg& vs = v.vseg[s];
   Seg& cs = v.cseg[s];
   finalise_seg(vs, seg_size(s, v.vseg_cap, v.max_vertices));
-  finalise_seg(cs, seg_size(s, v.cseg_cap, v.max_chunks));
   const uint32_t sum_new = wave_sum(vs.st_new), sum_upd = wave_sum(vs.st_upd);
   const uint32_t sum_freed = wave_sum(vs.st_freed), hwm = wave_sum(vs.hwm);
   const uint32_t sum_chg = wave_sum(cs.st_chg), sum_ref = wave_sum(cs.st_ref);
@@ -304,7 +303,6 @@ __device__ inline void init_cube(const VolDev& v, uint32_t idx, int l) {
   const size_t o = (size_t)idx * kVox + l;
   v.tprev[o] = 0;
   v.tcur[o] = 0;
-  v.cchunk[o] = -1;
   v.evtx[((size_t)idx * 3 + 0) * kVox + l] = -1;
   v.evtx[((size_t)idx * 3 + 1) * kVox + l] = -1;
   v.evtx[((size_t)idx * 3 + 2) * kVox + l] = -1;
@@ -521,6 +519,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass,
     }
     wave_sync();
     uint32_t flags = 0, nchanged = 0;
+    int dtri = 0, dtcube = 0;  // change of the triangle and triangle-cube counts
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
       const int base = lx + 9 * ly + 81 * lz;
@@ -543,7 +542,10 @@ __global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass,
         nt = valid ? refine_type(old[lz], prev[lz], dc, v.eps) : old[lz];
       }
       if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
-      const bool tri_change = nt != old[lz] && (v.tri_table[old[lz] * 16] || v.tri_table[nt * 16]);
+      const int ntri_old = v.tri_table[old[lz] * 16], ntri_new = v.tri_table[nt * 16];
+      const bool tri_change = nt != old[lz] && (ntri_old || ntri_new);
+      dtri += ntri_new - ntri_old;
+      dtcube += (ntri_new > 0) - (ntri_old > 0);
       const uint64_t m = __ballot(tri_change);
       if (q == 0) v.chg[(size_t)idx * 8 + lz] = m;
       nchanged += (uint32_t)__popcll(m);
@@ -568,10 +570,14 @@ __global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass,
       }
       v.vcand[(size_t)i * 8 + q] = out;
     }
+    dtri = wave_sum(dtri);
+    dtcube = wave_sum(dtcube);
     if (q == 0 && nchanged) {
       const uint32_t sg = idx % v.nseg;
       atomicAdd(&v.cseg[sg].st_chg, nchanged);
       if (refine) atomicAdd(&v.cseg[sg].st_ref, nchanged);
+      if (dtri) atomicAdd(&v.cseg[sg].st_tri, dtri);
+      if (dtcube) atomicAdd(&v.cseg[sg].st_tcube, dtcube);
     }
     wave_sync();
   }
@@ -798,19 +804,19 @@ __device__ inline void edge_owner(int e, int& ox, int& oy, int& oz, int& axis) {
   axis = (int)(p >> 3);
 }
 
-// One wave per dirty block: every cube whose triangles changed gets its
-// triangles rewritten (Sec. V-D) as vertex slots of the owning edges; a cube
-// that gains triangles takes a 64-byte chunk, one that loses them recycles
-// it (one atomic each per block on the block's chunk segment); unchanged
-// cubes keep theirs.  The changed cubes are listed in LDS; each chunk is
-// written by 16 lanes, all edge-slot gathers of up to 32 cubes issued
-// before the stores.
+// One wave per (dirty block, z layer): every cube of the layer whose
+// triangles changed and whose new type has triangles gets them rewritten
+// (Sec. V-D) as the vertex slots of the owning edges, into the cube's own
+// record; unchanged cubes keep theirs, and a cube without triangles needs no
+// write (its type says so).  Each record (64 bytes) is written by 16 lanes;
+// the edge-slot gathers of 32 cubes are issued before their stores.  Work
+// per wave is at most one layer of 64 cubes, so a block with many changed
+// cubes is spread over up to eight waves.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
   __shared__ uint8_t stri[256 * 16];
-  __shared__ uint16_t slist_all[W][512];
-  __shared__ int32_t schunk_all[W][512];
-  __shared__ uint8_t stype_all[W][512];
+  __shared__ uint8_t slist_all[W][64];  // changed cubes of the layer (x + 8y)
+  __shared__ uint8_t stype_all[W][64];  // their types
   __shared__ int32_t snb_all[W][27];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id();
   {
@@ -819,28 +825,44 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
     for (int j = threadIdx.x; j < 256 * 16 / 4; j += blockDim.x) dst[j] = src[j];
   }
   __syncthreads();
-  uint16_t* slist = slist_all[wave];
-  int32_t* schunk = schunk_all[wave];
+  uint8_t* slist = slist_all[wave];
   uint8_t* stype = stype_all[wave];
   int32_t* snb = snb_all[wave];
-  const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
+  const uint32_t n = min(v.cnt->n_dirty, v.max_blocks) * 8u;
   const int k = q & 15;
-  // the chunk words lane q writes for the 32 cubes c0 + 4r + q/16 (r < 8):
-  // word 0 the owner cube, then the vertex slots of the triangles' edges
-  auto gather = [&](uint32_t idx, uint32_t c0, uint32_t nchg, uint32_t word[8]) {
+  for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
+    const uint32_t idx = v.dirty[it.i >> 3];
+    const int lz = (int)(it.i & 7u);
+    const uint64_t m = v.chg[(size_t)idx * 8 + lz];
+    if (m == 0ull) continue;
+    const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
+    const uint32_t mytype = v.tcur[(size_t)idx * kVox + q + 64 * lz];
+    if (q < 27) snb[q] = mynb;
+    // changed cubes whose new type has triangles, in lane order
+    const uint64_t w = __ballot(((m >> q) & 1ull) && stri[mytype * 16] != 0);
+    if ((w >> q) & 1ull) {
+      const int pos = __popcll(w & lanes_below());
+      slist[pos] = (uint8_t)q;
+      stype[pos] = (uint8_t)mytype;
+    }
+    wave_sync();
+    const uint32_t nw = (uint32_t)__popcll(w);
+    for (uint32_t c0 = 0; c0 < nw; c0 += 32) {
+      uint32_t word[8];
+      int32_t dst[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const uint32_t c = c0 + 4 * r + (q >> 4);
-      word[r] = kNone;
-      if (c >= nchg) continue;
-      const uint32_t l = slist[c], type = stype[c];
-      const uint32_t ntri = stri[type * 16];
-      if (k == 0) {
-        word[r] = (idx << 9) | l;
-      } else if (k - 1 < (int)(3 * ntri)) {
+      for (int r = 0; r < 8; ++r) {
+        const uint32_t c = c0 + 4 * r + (q >> 4);
+        word[r] = kNone;
+        dst[r] = -1;
+        if (c >= nw) continue;
+        const uint32_t type = stype[c], ntri = stri[type * 16];
+        if (k >= (int)(3 * ntri)) continue;
+        const int l = slist[c] + 64 * lz;
+        dst[r] = l;
         int ox, oy, oz, axis;
-        edge_owner(stri[type * 16 + k], ox, oy, oz, axis);
-        const int x = (int)(l & 7) + ox, y = (int)((l >> 3) & 7) + oy, z = (int)(l >> 6) + oz;
+        edge_owner(stri[type * 16 + 1 + k], ox, oy, oz, axis);
+        const int x = (l & 7) + ox, y = ((l >> 3) & 7) + oy, z = (l >> 6) + oz;
         const int32_t nb = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
         if (nb >= 0) {
           const int32_t s =
@@ -848,91 +870,9 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
           word[r] = s >= 0 ? (uint32_t)s : kNone;
         }
       }
-    }
-  };
-  auto store = [&](uint32_t c0, uint32_t nchg, const uint32_t word[8]) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const uint32_t c = c0 + 4 * r + (q >> 4);
-      if (c >= nchg) continue;
-      const int32_t chunk = schunk[c];
-      if (chunk >= 0) v.chunks[(size_t)chunk * kChunkWords + k] = word[r];
-    }
-  };
-  for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
-    const uint32_t idx = v.dirty[it.i];
-    const uint32_t sg = idx % v.nseg;
-    const uint64_t mymask = q < 8 ? v.chg[(size_t)idx * 8 + q] : 0ull;
-    const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
-    // the block's chunk segment does not change during this kernel
-    const Seg& g = v.cseg[sg];
-    const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
-    if (!__ballot(mymask != 0ull)) continue;
-    if (q < 27) snb[q] = mynb;
-    // list the changed cubes, z layer by z layer
-    uint32_t nchg = 0;
-    for (int lz = 0; lz < 8; ++lz) {
-      const uint64_t m = shfl64(mymask, lz);
-      if ((m >> q) & 1ull) slist[nchg + __popcll(m & lanes_below())] = (uint16_t)(q + 64 * lz);
-      nchg += (uint32_t)__popcll(m);
-    }
-    wave_sync();
-    // types, chunks and the allocations / frees they need
-    uint32_t nalloc = 0, nfree = 0;
-    for (uint32_t c = q; c < nchg; c += 64) {
-      const size_t o = (size_t)idx * kVox + slist[c];
-      const uint32_t type = v.tcur[o];
-      const int32_t chunk = v.cchunk[o];
-      const uint32_t ntri = stri[type * 16];
-      stype[c] = (uint8_t)type;
-      schunk[c] = chunk;
-      nalloc += ntri > 0 && chunk < 0;
-      nfree += ntri == 0 && chunk >= 0;
-    }
-    uint32_t ta, tf;
-    uint32_t ra = wave_scan(nalloc, &ta), rf = wave_scan(nfree, &tf);
-    uint32_t ba = 0, bf = 0;
-    if (q == 0) {
-      if (ta) ba = atomicAdd(&v.cseg[sg].ticket, ta);
-      if (tf) bf = atomicAdd(&v.cseg[sg].push, tf);
-    }
-    wave_sync();
-    // the first 32 cubes' edge-slot gathers overlap the pool atomics
-    uint32_t word[8];
-    gather(idx, 0, nchg, word);
-    if (ta | tf) {
-      ra += __shfl(ba, 0);
-      rf += __shfl(bf, 0);
-      const uint32_t gbase = sg * v.cseg_cap, gsize = seg_size(sg, v.cseg_cap, v.max_chunks);
-      for (uint32_t c = q; c < nchg; c += 64) {
-        const size_t o = (size_t)idx * kVox + slist[c];
-        const uint32_t ntri = stri[stype[c] * 16];
-        int32_t chunk = schunk[c];
-        if (ntri == 0) {
-          if (chunk >= 0) {
-            v.chunks[(size_t)chunk * kChunkWords] = kNone;
-            v.cring[gbase + (uint32_t)(((uint64_t)tail + rf++) % gsize)] = (uint32_t)chunk;
-            v.cchunk[o] = -1;
-          }
-          chunk = -1;
-        } else if (chunk < 0) {
-          const uint32_t ns = seg_slot(head, tail, hwm, ra++, v.cring, gbase, gsize);
-          if (ns == kNone) {
-            atomicOr(&v.cnt->error, kErrTris);
-          } else {
-            chunk = (int32_t)ns;
-            v.cchunk[o] = chunk;
-          }
-        }
-        schunk[c] = chunk;
-      }
-      wave_sync();
-    }
-    // write the chunks, 16 lanes (64 bytes) per cube, 32 cubes per round
-    store(0, nchg, word);
-    for (uint32_t c0 = 32; c0 < nchg; c0 += 32) {
-      gather(idx, c0, nchg, word);
-      store(c0, nchg, word);
+      for (int r = 0; r < 8; ++r)
+        if (dst[r] >= 0) v.chunks[((size_t)idx * kVox + dst[r]) * kChunkWords + k] = word[r];
     }
     wave_sync();
   }
@@ -989,12 +929,9 @@ __device__ inline uint32_t item_count(const VolDev& v, int what, uint32_t i) {
     if (i >= v.max_vertices || !slot_in_use(v.vseg, v.vseg_cap, i)) return 0;
     return v.vref[i] > 0 ? 1u : 0u;
   }
-  if (i >= v.max_chunks || !slot_in_use(v.cseg, v.cseg_cap, i)) return 0;
-  const uint32_t* c = v.chunks + (size_t)i * kChunkWords;
-  if (c[0] == kNone) return 0;
-  uint32_t k = 0;
-  for (int t = 0; t < 5; ++t) k += c[1 + 3 * t] != kNone;
-  return k;
+  // cube i of the block pool: its type's triangles
+  if (i / kVox >= min(v.cnt->n_blocks, v.max_blocks)) return 0;
+  return v.tri_table[(uint32_t)v.tcur[i] * 16];
 }
 
 // Position in metres of the vertex in pool entry i, in the frame of its
@@ -1104,17 +1041,14 @@ __global__ __launch_bounds__(256) void k_dl_write_triangles(VolDev v, int32_t* _
   uint32_t j = v.scan[blockIdx.x] + wg_scan(c, swave, &total);
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = i0 + k;
-    if (item_count(v, 1, i) == 0) continue;
+    const uint32_t ntri = item_count(v, 1, i);
     const uint32_t* ch = v.chunks + (size_t)i * kChunkWords;
-    for (int t = 0; t < 5; ++t) {
-      if (ch[1 + 3 * t] == kNone) continue;
-      if (j < tcap) {
-        for (int q = 0; q < 3; ++q) {
-          const uint32_t s = ch[1 + 3 * t + q];
-          tris[3 * (size_t)j + q] = s == kNone ? -1 : v.vdl[s];
-        }
+    for (uint32_t t = 0; t < ntri; ++t, ++j) {
+      if (j >= tcap) continue;
+      for (int q = 0; q < 3; ++q) {
+        const uint32_t s = ch[3 * t + q];
+        tris[3 * (size_t)j + q] = s == kNone ? -1 : v.vdl[s];
       }
-      ++j;
     }
   }
 }

@@ -88,7 +88,7 @@ def test_struct_layouts_match_the_binding(tmp_path):
 
 def cfg(**kw):
     base = dict(voxel_m=0.008, trunc_vox=4.0, refine_eps_vox=0.5, hash_log2=16, max_blocks=4096,
-                max_vertices=1 << 18, max_tri_cubes=1 << 18, hash_mode=0, batch_volumes=0)
+                max_vertices=1 << 18, hash_mode=0, batch_volumes=0)
     base.update(kw)
     return binding.vm_config(**base)
 
@@ -102,12 +102,11 @@ def volume_bytes(c):
 def test_volume_bytes_grows_with_every_capacity():
     r, base = volume_bytes(cfg())
     assert r == binding.VM_OK and base > 0
-    # the block pool holds at least TSDF + weight + types + edge slots per voxel
+    # the block pool holds at least TSDF + weight + types + edge slots and
+    # the 64-byte triangle record of every cube
     r, more = volume_bytes(cfg(max_blocks=8192))
-    assert r == 0 and more - base >= 4096 * 512 * (4 + 4 + 1 + 1 + 12)
+    assert r == 0 and more - base >= 4096 * 512 * (4 + 4 + 1 + 1 + 12 + 64)
     r, more = volume_bytes(cfg(max_vertices=1 << 19))
-    assert r == 0 and more > base
-    r, more = volume_bytes(cfg(max_tri_cubes=1 << 19))
     assert r == 0 and more > base
     r, more = volume_bytes(cfg(hash_log2=17))
     assert r == 0 and more - base >= 8 * (1 << 16)
@@ -118,7 +117,7 @@ def test_volume_bytes_grows_with_every_capacity():
 @pytest.mark.parametrize("bad", [
     dict(voxel_m=0.0), dict(voxel_m=float("nan")), dict(trunc_vox=0.0), dict(refine_eps_vox=-1.0),
     dict(hash_log2=9), dict(hash_log2=29), dict(max_blocks=0), dict(max_blocks=(1 << 21) + 1),
-    dict(max_vertices=0), dict(max_tri_cubes=0), dict(hash_mode=2), dict(batch_volumes=-1),
+    dict(max_vertices=0), dict(hash_mode=2), dict(batch_volumes=-1),
     dict(batch_volumes=257),
 ])
 def test_invalid_configurations_are_rejected(bad):

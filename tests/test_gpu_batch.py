@@ -143,7 +143,7 @@ def test_every_mapping_gives_identical_bits(w, order):
 def test_positions_are_the_downloaded_vertices():
     sv = scenes.sphere_volume(seed=1)
     c, d, w = sv.blocks()
-    v = Volume(S, hash_log2=12, max_blocks=1024, max_vertices=1 << 16, max_tri_cubes=1 << 16)
+    v = Volume(S, hash_log2=12, max_blocks=1024, max_vertices=1 << 16)
     v.import_blocks(*(torch.from_numpy(x).cuda() for x in (c, d.reshape(-1, 512), w.reshape(-1, 512))))
     v.extract(scope_all=True)
     pos, slot = v.positions()
@@ -155,7 +155,7 @@ def test_positions_are_the_downloaded_vertices():
 
 
 def test_batch_range_errors():
-    b = Volume(S, hash_log2=12, max_blocks=64, max_vertices=1 << 12, max_tri_cubes=1 << 12,
+    b = Volume(S, hash_log2=12, max_blocks=64, max_vertices=1 << 12,
                batch_volumes=2)
     z = torch.zeros((1, 512), dtype=torch.float32, device="cuda")
     for slot, x in [(2, 0), (-1, 0), (0, 63), (0, -1)]:

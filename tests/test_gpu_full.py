@@ -53,8 +53,7 @@ def test_room_sequence_8mm_full_size():
     seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=0.008)
     frames = render(seq, 100)
     print("[full] room 8 mm: GPU", flush=True)
-    g = Volume(0.008, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23,
-               max_tri_cubes=1 << 23)
+    g = Volume(0.008, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23)
     depth = to_dev(np.stack(frames))[0]
     for k in range(100):
         g.integrate(depth[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
@@ -79,8 +78,7 @@ def test_room_sequence_4mm_refine_full_size():
     seq = scenes.room_sequence(seed=3, n_frames=500, voxel_m=0.004, holes=True)
     frames = render(seq, 500)
     print("[full] room 4 mm + refine: GPU", flush=True)
-    g = Volume(0.004, hash_log2=22, max_blocks=1 << 19, max_vertices=1 << 24,
-               max_tri_cubes=1 << 24)
+    g = Volume(0.004, hash_log2=22, max_blocks=1 << 19, max_vertices=1 << 24)
     depth = to_dev(np.stack(frames))[0]
     for k in range(500):
         g.integrate(depth[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)

@@ -68,8 +68,7 @@ def build_pair(case, with_frame):
     coords, d, w = sv.blocks()
     o = oracle.OracleVolume(sv.voxel_m)
     o.import_blocks(coords, d, w)
-    g = Volume(sv.voxel_m, hash_log2=16, max_blocks=1 << 14, max_vertices=1 << 20,
-               max_tri_cubes=1 << 20)
+    g = Volume(sv.voxel_m, hash_log2=16, max_blocks=1 << 14, max_vertices=1 << 20)
     g.import_blocks(*to_dev(coords, d, w))
     if with_frame:
         o.integrate(depth, scenes.K, pose, dmin, dmax)
@@ -124,8 +123,7 @@ def test_extract_and_fusion_backward_match_oracle(case):
 def test_autograd_function_end_to_end():
     sv, depth, pose, target, (dmin, dmax) = sphere_case()
     coords, d, w = sv.blocks()
-    vol = Volume(sv.voxel_m, hash_log2=12, max_blocks=4096, max_vertices=1 << 16,
-                 max_tri_cubes=1 << 16)
+    vol = Volume(sv.voxel_m, hash_log2=12, max_blocks=4096, max_vertices=1 << 16)
     dt = to_dev(depth)[0].requires_grad_(True)
     cd, td, wd = to_dev(coords, d, w)
     td.requires_grad_(True)

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 def new_volume(voxel_m, **kw):
     from paper_1803_03949_amd import Volume
-    args = dict(hash_log2=16, max_blocks=1 << 14, max_vertices=1 << 20, max_tri_cubes=1 << 20)
+    args = dict(hash_log2=16, max_blocks=1 << 14, max_vertices=1 << 20)
     args.update(kw)
     return Volume(voxel_m, **args)
 
@@ -116,8 +116,7 @@ def test_room_sequence_coarse():
 
 def test_room_sequence_8mm_two_frames():
     seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=0.008)
-    g, o = run_sequence(seq, [0, 1], dict(hash_log2=20, max_blocks=1 << 16, max_vertices=1 << 22,
-                                          max_tri_cubes=1 << 22), check_every=False)
+    g, o = run_sequence(seq, [0, 1], dict(hash_log2=20, max_blocks=1 << 16, max_vertices=1 << 22), check_every=False)
     info = compare_all(g, o)
     assert info["nv"] > 100000
 
@@ -168,17 +167,15 @@ def test_mesh_is_closed_and_oriented_on_gpu():
     assert meshutil.signed_volume(v, t) > 0
 
 
-@pytest.mark.parametrize("which", ["blocks", "vertices", "tris", "hash"])
+@pytest.mark.parametrize("which", ["blocks", "vertices", "hash"])
 def test_capacity_errors_are_reported(which):
     from paper_1803_03949_amd import VmError
     sv = scenes.sphere_volume(seed=1, dims_blocks=(4, 4, 4), radius=0.12, center=np.full(3, 0.128))
-    kw = dict(hash_log2=16, max_blocks=1 << 10, max_vertices=1 << 16, max_tri_cubes=1 << 16)
+    kw = dict(hash_log2=16, max_blocks=1 << 10, max_vertices=1 << 16)
     if which == "blocks":
         kw["max_blocks"] = 40
     elif which == "vertices":
         kw["max_vertices"] = 100
-    elif which == "tris":
-        kw["max_tri_cubes"] = 100
     else:
         kw["hash_log2"] = 10  # 1024 slots, but the integration below collects more blocks
     g = new_volume(sv.voxel_m, **kw)
@@ -195,7 +192,7 @@ def test_capacity_errors_are_reported(which):
         g.import_blocks(*to_dev(coords, d, w))
         g.extract(scope_all=True)
     st = g.status(check=False)
-    want = {"blocks": -3, "vertices": -4, "tris": -5, "hash": -2}[which]
+    want = {"blocks": -3, "vertices": -4, "hash": -2}[which]
     assert st["error"] == want, st
     with pytest.raises(VmError):
         g.status()
