@@ -92,10 +92,9 @@ def algorithmic_bytes(tot, npix):
         "collect": 4 * npix * tot["frames"],
         "fuse": 4 * npix * tot["frames"] + 8192 * tot["frame_blocks"],
         "classify": 5632 * tot["dirty_blocks"],
-        "vertices": 8704 * tot["vertex_blocks"] + 8 * tot["updated_vertices"]
-        + 16 * tot["new_vertices"],
+        "vertices": 8704 * tot["vertex_blocks"] + 5 * tot["updated_vertices"]
+        + 13 * tot["new_vertices"] + 12 * tot["freed_vertices"],
         "triangles": 96 * tot["changed_cubes"],
-        "gc": 4 * tot["gc_scanned"] + 16 * tot["freed_vertices"],
     }
 
 

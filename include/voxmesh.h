@@ -116,7 +116,7 @@ typedef struct vm_status {
   int64_t tri_cubes;        /* cubes holding triangles */
   int64_t new_vertices;     /* vertices created by the last extract/refine */
   int64_t updated_vertices; /* vertices whose position was rewritten */
-  int64_t freed_vertices;   /* vertices recycled by the last vm_gc */
+  int64_t freed_vertices;   /* vertices recycled by the last extract/refine */
   int64_t refined_cubes;    /* cubes re-typed by the last vm_refine_mesh */
 } vm_status;
 
@@ -131,7 +131,7 @@ enum {
   VM_TOTAL_NEW_VERTICES = 4,
   VM_TOTAL_UPDATED_VERTICES = 5,
   VM_TOTAL_CHANGED_CUBES = 6,   /* cubes whose triangles were rewritten */
-  VM_TOTAL_GC_SCANNED = 7,      /* vertex slots examined by vm_gc */
+  VM_TOTAL_GC_SCANNED = 7,      /* vertex slots in use at each vm_gc */
   VM_TOTAL_FREED_VERTICES = 8,
   VM_TOTAL_REFINED_CUBES = 9,
   VM_TOTAL_COUNT = 10
@@ -149,7 +149,7 @@ enum {
   VM_K_REFINE = 7,       /* cube types, refinement pass */
   VM_K_VERTICES = 8,     /* edge-owned vertices and reference counts */
   VM_K_TRIANGLES = 9,    /* triangle chunks of changed cubes */
-  VM_K_GC = 10,          /* garbage collection */
+  VM_K_GC = 10,          /* (reserved: recycling runs in the vertex pass) */
   VM_K_DOWNLOAD = 11,    /* download compaction (all its kernels) */
   VM_K_BACKWARD = 12,    /* backward passes */
   VM_K_COUNTERS = 13,    /* single-lane bookkeeping kernels */
@@ -222,7 +222,10 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream);
  * regular type puts a vertex on an edge without a sign change. */
 int vm_refine_mesh(vm_volume* vol, hipStream_t stream);
 
-/* Garbage collection (Sec. V-E): recycle every vertex no triangle uses. */
+/* Garbage collection (Sec. V-E).  A vertex no triangle uses any more is
+ * returned to its pool segment's recycle ring by the extraction (or
+ * refinement) that drops its count to zero, and its edge forgets it at
+ * once; vm_gc closes the rings so that those slots can be taken again. */
 int vm_gc(vm_volume* vol, hipStream_t stream);
 
 /* Compact the mesh into caller buffers (device): verts[vcap][3] FP32

@@ -101,6 +101,8 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->tprev = (uint8_t*)take(kVox * B);
   v->tcur = (uint8_t*)take(kVox * B);
   v->evtx = (int32_t*)take(4 * 3 * kVox * B);
+  v->et = (float*)take(4 * 3 * kVox * B);
+  v->eref = (uint8_t*)take(3 * kVox * B);
   v->chg = (uint64_t*)take(8 * 8 * B);
   v->st_pending = (uint32_t*)take(4 * B);
   v->st_dirty = (uint32_t*)take(4 * B);
@@ -112,9 +114,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->dirty = (uint32_t*)take(4 * B);
   v->vcand = (uint32_t*)take(4 * 8 * B);
   v->vblocks = (uint32_t*)take(4 * B);
-  v->vt = (float*)take(4 * V);
   v->vowner = (uint32_t*)take(4 * V);
-  v->vref = (int32_t*)take(4 * V);
   v->vring = (uint32_t*)take(4 * V);
   v->vdl = (int32_t*)take(4 * V);
   v->chunks = (uint32_t*)take(4 * kChunkWords * C);
@@ -425,11 +425,10 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
 
 int vm_gc(vm_volume* vol, hipStream_t stream) {
   if (!vol) return VM_ERR_ARG;
-  uint32_t parts = vol->dev.vseg_cap / 4096;
-  parts = parts < 1 ? 1 : (parts > 64 ? 64 : parts);
+  // the vertex pass already returned every vertex whose count dropped to
+  // zero to its segment's recycle ring; here the rings are closed so that
+  // the slots can be taken again
   prep(vol, VM_OP_GC, stream);
-  VM_LAUNCH(vol, VM_K_GC, k_gc, dim3(vol->dev.nseg * parts), dim3(256), stream, vol->dev,
-            parts);
   return launched();
 }
 

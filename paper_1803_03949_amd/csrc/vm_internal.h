@@ -13,8 +13,10 @@
 //             edge->vertex slot i32[3][512] (the three edges every voxel
 //             owns), cube->triangle chunk i32[512], changed-cube bitmask
 //             u64[8], pass stamps.
-//   vertices  t f32, owner edge (index into the edge->vertex array) u32,
-//             reference count i32 (-1 = free), recycle ring, download row.
+//   vertices  per edge (block-local, next to the edge->vertex slot): the
+//             vertex's t f32 and reference count u8; per pool slot: owner
+//             edge (index into the edge arrays, kNone when free), recycle
+//             ring, download row.
 //   triangles one 64-byte record per cube, at a fixed place in its block's
 //             region: up to 5 triangles as 3 vertex slots each (the cube's
 //             type says how many are valid).
@@ -116,7 +118,9 @@ struct VolDev {
   float* w;                   // [B][512]
   uint8_t* tprev;             // [B][512]
   uint8_t* tcur;              // [B][512]
-  int32_t* evtx;              // [B][3][512]
+  int32_t* evtx;              // [B][3][512] vertex slot of the edge, -1 if none
+  float* et;                  // [B][3][512] t of the edge's vertex
+  uint8_t* eref;              // [B][3][512] reference count of the edge's vertex
   uint64_t* chg;              // [B][8] cubes whose triangles changed, per wave
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
@@ -128,9 +132,7 @@ struct VolDev {
   uint32_t* dirty;            // [B]
   uint32_t* vcand;            // [8B] vertex-block candidates of each dirty block
   uint32_t* vblocks;          // [B]
-  float* vt;                  // [V]
-  uint32_t* vowner;           // [V] index into evtx
-  int32_t* vref;              // [V]
+  uint32_t* vowner;           // [V] index into the edge arrays, kNone if free
   uint32_t* vring;            // [V]
   int32_t* vdl;               // [V] row in the last download, -1 if none
   uint32_t* chunks;           // [B][512][16] triangles of every cube
@@ -415,7 +417,6 @@ template <int W>
 __global__ void k_vertices(VolDev v);
 template <int W>
 __global__ void k_triangles(VolDev v);
-__global__ void k_gc(VolDev v, uint32_t parts);
 __global__ void k_dl_count(VolDev v, int what);
 __global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
 __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,

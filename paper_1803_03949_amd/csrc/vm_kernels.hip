@@ -44,17 +44,18 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
       c->n_vblocks = 0;
       c->base_new = sum_new;
       c->base_upd = sum_upd;
+      c->base_freed = sum_freed;
       c->base_chg = sum_chg;
       break;
     case VM_OP_REFINE:
       c->n_vblocks = 0;
       c->base_new = sum_new;
       c->base_upd = sum_upd;
+      c->base_freed = sum_freed;
       c->base_chg = sum_chg;
       c->base_ref = sum_ref;
       break;
     case VM_OP_GC:
-      c->base_freed = sum_freed;
       c->acc[VM_TOTAL_GC_SCANNED] += hwm;
       break;
     case VM_OP_RESET:
@@ -303,9 +304,10 @@ __device__ inline void init_cube(const VolDev& v, uint32_t idx, int l) {
   const size_t o = (size_t)idx * kVox + l;
   v.tprev[o] = 0;
   v.tcur[o] = 0;
-  v.evtx[((size_t)idx * 3 + 0) * kVox + l] = -1;
-  v.evtx[((size_t)idx * 3 + 1) * kVox + l] = -1;
-  v.evtx[((size_t)idx * 3 + 2) * kVox + l] = -1;
+  for (int a = 0; a < 3; ++a) {
+    v.evtx[((size_t)idx * 3 + a) * kVox + l] = -1;
+    v.eref[((size_t)idx * 3 + a) * kVox + l] = 0;
+  }
 }
 
 // ============================================================================
@@ -718,7 +720,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     // 8 counts of 8 bits per axis: an edge can carry up to 16 triangles (four
     // in each of its four cubes)
     uint64_t refs[3] = {0, 0, 0};
-    uint32_t nneed = 0;
+    uint32_t nneed = 0, nfree = 0;
 #pragma unroll 2
     for (int lz = 0; lz < 8; ++lz) {
       const int tb = (lx + 1) + 9 * (ly + 1) + 81 * (lz + 1);
@@ -732,12 +734,21 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
       refs[2] |= (uint64_t)r2 << (8 * lz);
       const uint32_t hs = has_slot >> (3 * lz);
       nneed += (r0 > 0 && !(hs & 1u)) + (r1 > 0 && !(hs & 2u)) + (r2 > 0 && !(hs & 4u));
+      nfree += (r0 == 0 && (hs & 1u)) + (r1 == 0 && (hs & 2u)) + (r2 == 0 && (hs & 4u));
     }
-    uint32_t total;
-    uint32_t rank = wave_scan(nneed, &total);
-    uint32_t base = 0;
-    if (q == 0 && total) base = atomicAdd(&v.vseg[sg].ticket, total);
+    // one allocation and one recycling atomic per block, issued together;
+    // a vertex whose count dropped to zero goes back to the segment's ring
+    // at once (Sec. V-E), where it can be taken again once the ring is
+    // closed, never by this pass
+    uint32_t total, tfree;
+    uint32_t rank = wave_scan(nneed, &total), frank = wave_scan(nfree, &tfree);
+    uint32_t base = 0, fbase = 0;
+    if (q == 0) {
+      if (total) base = atomicAdd(&v.vseg[sg].ticket, total);
+      if (tfree) fbase = atomicAdd(&v.vseg[sg].push, tfree);
+    }
     base = __shfl(base, 0);
+    frank += __shfl(fbase, 0);
     const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
     // the slots of the first kRingBatch allocations, fetched together (the
     // type staging is no longer needed: the batch reuses its LDS)
@@ -755,6 +766,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
       for (int a = 0; a < 3; ++a) {
         const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u;
         if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
+        const size_t eo = ((size_t)idx * 3 + a) * kVox + q + 64 * lz;
         int32_t s = ses[a * kVox + q + 64 * lz];
         if (ref > 0) {
           if (s < 0) {
@@ -767,17 +779,20 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
               continue;
             }
             s = (int32_t)ns;
-            const size_t eo = ((size_t)idx * 3 + a) * kVox + q + 64 * lz;
             v.evtx[eo] = s;
             v.vowner[s] = (uint32_t)eo;
             ++nnew;
           } else {
             ++nupd;
           }
-          v.vt[s] = edge_param(sd[sdb], sd[sdb + step[a]]);
-          v.vref[s] = (int32_t)ref;
-        } else if (s >= 0) {
-          v.vref[s] = 0;
+          v.et[eo] = edge_param(sd[sdb], sd[sdb + step[a]]);
+          v.eref[eo] = (uint8_t)ref;
+        } else {
+          // s >= 0: the edge's vertex is no longer used
+          v.vring[gbase + (uint32_t)(((uint64_t)tail + frank++) % gsize)] = (uint32_t)s;
+          v.vowner[s] = kNone;
+          v.evtx[eo] = -1;
+          v.eref[eo] = 0;
         }
       }
     }
@@ -786,6 +801,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     if (q == 0) {
       if (nnew) atomicAdd(&v.vseg[sg].st_new, nnew);
       if (nupd) atomicAdd(&v.vseg[sg].st_upd, nupd);
+      if (tfree) atomicAdd(&v.vseg[sg].st_freed, tfree);
     }
     wave_sync();
   }
@@ -879,42 +895,6 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
 }
 
 // ============================================================================
-// garbage collection (Sec. V-E)
-// ============================================================================
-
-// Workgroup w scans part w / nseg of vertex segment w % nseg up to its
-// high-water mark and recycles the slots no triangle references.
-__global__ __launch_bounds__(256) void k_gc(VolDev v, uint32_t parts) {
-  __shared__ uint32_t swave[16];
-  __shared__ uint32_t sbase;
-  const uint32_t sg = blockIdx.x % v.nseg, part = blockIdx.x / v.nseg;
-  const Seg& g = v.vseg[sg];
-  const uint32_t hwm = g.hwm, tail = g.tail;
-  const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
-  const uint32_t per = (hwm + parts - 1) / parts;
-  const uint32_t r0 = part * per, r1 = min(hwm, r0 + per);
-  if (r0 >= r1) return;
-  uint32_t cnt = 0;
-  for (uint32_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) cnt += v.vref[gbase + k] == 0;
-  uint32_t tot;
-  uint32_t r = wg_scan(cnt, swave, &tot);
-  if (tot == 0) return;
-  if (threadIdx.x == 0) {
-    sbase = atomicAdd(&v.vseg[sg].push, tot);
-    atomicAdd(&v.vseg[sg].st_freed, tot);
-  }
-  __syncthreads();
-  r += sbase;
-  for (uint32_t k = r0 + threadIdx.x; k < r1; k += blockDim.x) {
-    const uint32_t s = gbase + k;
-    if (v.vref[s] != 0) continue;
-    v.evtx[v.vowner[s]] = -1;
-    v.vref[s] = -1;
-    v.vring[gbase + (uint32_t)(((uint64_t)tail + r++) % gsize)] = s;
-  }
-}
-
-// ============================================================================
 // download: two-level exclusive scans over the vertex and triangle pools
 // ============================================================================
 constexpr int kScanItems = 1024;  // items per workgroup (256 lanes x 4)
@@ -927,7 +907,7 @@ __device__ inline bool slot_in_use(const Seg* seg, uint32_t cap, uint32_t i) {
 __device__ inline uint32_t item_count(const VolDev& v, int what, uint32_t i) {
   if (what == 0) {
     if (i >= v.max_vertices || !slot_in_use(v.vseg, v.vseg_cap, i)) return 0;
-    return v.vref[i] > 0 ? 1u : 0u;
+    return v.vowner[i] != kNone ? 1u : 0u;
   }
   // cube i of the block pool: its type's triangles
   if (i / kVox >= min(v.cnt->n_blocks, v.max_blocks)) return 0;
@@ -946,7 +926,7 @@ __device__ inline int vertex_position(const VolDev& v, uint32_t i, float p[3], u
   unpack_key(bkey, bx, by, bz);
   block_frame(v, bx, slot);
   const int g[3] = {8 * bx + (local & 7), 8 * by + ((local >> 3) & 7), 8 * bz + (local >> 6)};
-  const float t = v.vt[i];
+  const float t = v.et[owner];
   for (int a = 0; a < 3; ++a) {
     float c = (float)g[a];
     if (a == axis) c = c + t;
@@ -1070,9 +1050,10 @@ __global__ __launch_bounds__(512) void k_bwd_tsdf(VolDev v, const float* __restr
   const uint32_t nv = v.cnt->dl_nv;
   const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
   const int lc[3] = {lx, ly, lz};
-  // upstream gradient row of the vertex in pool entry s, -1 if none
-  auto grad_row = [&](int32_t s) -> int32_t {
-    if (s < 0 || v.vref[s] <= 0) return -1;
+  // upstream gradient row of the vertex on edge e (slot s), -1 if none
+  auto grad_row = [&](size_t e) -> int32_t {
+    const int32_t s = v.evtx[e];
+    if (s < 0 || v.eref[e] == 0) return -1;
     if (by_slot) return s;
     const int32_t r = v.vdl[s];
     return r >= 0 && (uint32_t)r < nv ? r : -1;
@@ -1098,7 +1079,7 @@ __global__ __launch_bounds__(512) void k_bwd_tsdf(VolDev v, const float* __restr
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       // the edge this voxel owns: it is the first end point
-      int32_t r = grad_row(v.evtx[((size_t)idx * 3 + a) * kVox + l]);
+      int32_t r = grad_row(((size_t)idx * 3 + a) * kVox + l);
       if (r >= 0) {
         const float da = sd[c], db = sd[c + step[a]];
         if (da != db) {
@@ -1117,7 +1098,7 @@ __global__ __launch_bounds__(512) void k_bwd_tsdf(VolDev v, const float* __restr
         // the -a neighbour block when this voxel is on the block's face
         const int lstep = a == 0 ? 1 : a == 1 ? 8 : 64;
         const int ol = back < 0 ? l + 7 * lstep : l - lstep;
-        r = grad_row(v.evtx[((size_t)nb * 3 + a) * kVox + ol]);
+        r = grad_row(((size_t)nb * 3 + a) * kVox + ol);
         if (r >= 0) {
           const float da = sd[c - step[a]], db = sd[c];
           if (da != db) {
@@ -1178,17 +1159,15 @@ __global__ void k_zero_f32(float* p, uint64_t n) {
 // ============================================================================
 __global__ void k_export_vertices(VolDev v, uint64_t* keys, float* t, int32_t* ref, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const bool used = slot_in_use(v.vseg, v.vseg_cap, i);
-    const int32_t r = used ? v.vref[i] : -1;
-    ref[i] = r;
-    t[i] = used ? v.vt[i] : 0.f;
+    const uint32_t owner = slot_in_use(v.vseg, v.vseg_cap, i) ? v.vowner[i] : kNone;
     uint64_t k = ~0ull;
-    if (r >= 0) {
-      const uint32_t owner = v.vowner[i];
+    if (owner != kNone) {
       const uint32_t blk = owner / (3 * kVox), rem = owner % (3 * kVox);
       k = edge_key(v.block_key[blk], (int)(rem % kVox), (int)(rem / kVox));
     }
     keys[i] = k;
+    ref[i] = owner != kNone ? (int32_t)v.eref[owner] : -1;
+    t[i] = owner != kNone ? v.et[owner] : 0.f;
   }
 }
 
