@@ -355,11 +355,8 @@ int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* 
   fp.frame = ++vol->frame;
   const VolDev& v = vol->dev;
   const int npix = K->width * K->height;
-  const uint32_t per = compact_per_wg(v);
-  const uint32_t ncompact = (v.hash_mask + per) / per;
-  VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3((npix + 255) / 256), dim3(256), stream, v, fp, depth);
-  VM_LAUNCH(vol, VM_K_ASSIGN, k_frame_compact, dim3(ncompact), dim3(256), stream, v, fp.frame,
-            vol->epoch, per);
+  VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3((npix + 255) / 256), dim3(256), stream, v, fp, depth,
+            vol->epoch);
   VM_LAUNCH(vol, VM_K_FUSE, k_fuse, dim3(vol->grid_blocks), dim3(512), stream, v, fp, depth);
   vol->last_fp = fp;
   vol->have_fp = true;
@@ -535,7 +532,8 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   out->error = error_code(c.error);
   out->error_bits = c.error;
   out->blocks = c.n_blocks < B ? c.n_blocks : B;
-  out->frame_blocks = c.n_frame < B ? c.n_frame : B;
+  const uint32_t nf = c.n_frame[vol->frame & 1];
+  out->frame_blocks = nf < B ? nf : B;
   out->pending_blocks = c.n_pending[vol->epoch & 1];
   out->dirty_blocks = c.n_dirty;
   out->vertex_blocks = c.n_vblocks;
@@ -602,7 +600,7 @@ int vm_export_block_list(vm_volume* vol, int which, int32_t* coords, int64_t cap
   int r = read_counters(vol, &c, stream);
   if (r != VM_OK) return r;
   const VolDev& v = vol->dev;
-  const uint32_t len = which == 0 ? c.n_frame : which == 1 ? c.n_dirty : c.n_pending[vol->epoch & 1];
+  const uint32_t len = which == 0 ? c.n_frame[vol->frame & 1] : which == 1 ? c.n_dirty : c.n_pending[vol->epoch & 1];
   const size_t cnt = len < v.max_blocks ? len : v.max_blocks;
   *n = (int64_t)cnt;
   const size_t m = (size_t)cap < cnt ? (size_t)cap : cnt;

@@ -80,7 +80,7 @@ static_assert(sizeof(Seg) == 128, "segment record size");
 // Device counters (one 256-byte record at the start of the workspace).
 struct Counters {
   uint32_t n_blocks;       // pool high-water mark (may exceed capacity on error)
-  uint32_t n_frame;        // entries of the current frame list
+  uint32_t n_frame[2];     // entries of the frame list of frames of each parity
   uint32_t n_pending[2];   // blocks touched since the last extraction (by epoch parity)
   uint32_t n_dirty;        // blocks of the last extraction / refinement
   uint32_t n_vblocks;      // blocks whose owned edges get recomputed
@@ -89,7 +89,7 @@ struct Counters {
   uint32_t n_refined;      // cubes re-typed by the last refinement
   // segment totals when the last extract / refine / gc started
   uint32_t base_new, base_upd, base_freed, base_chg, base_ref;
-  uint32_t pad[17];
+  uint32_t pad[16];
   // running totals since the volume was created (not cleared by a reset)
   unsigned long long acc[10];
   unsigned long long pad2[6];
@@ -216,6 +216,32 @@ __device__ inline unsigned long long load_slot(const unsigned long long* p) {
 // Probes use plain (cacheable) loads: a slot's key never changes once set,
 // so a stale read can only show an empty slot, and the compare-and-swap
 // that follows returns the slot's true content.
+// Insert (if absent) and also return the slot's contents as this lane saw
+// them with the key in place: key | kPending for a key new to the table in
+// the current kernel, key | pool index otherwise.
+__device__ inline int64_t hash_insert_seen(const VolDev& v, uint64_t key,
+                                           unsigned long long* seen) {
+  uint32_t h = hash_home(key, v.hash_mask, v.hash_mode);
+  for (uint32_t probe = 0; probe <= v.hash_mask; ++probe) {
+    uint32_t s = (h + probe) & v.hash_mask;
+    unsigned long long cur = v.slots[s];
+    if (cur == kEmpty) {
+      unsigned long long want = ((unsigned long long)key << kIdxBits) | kPending;
+      unsigned long long prev = atomicCAS(&v.slots[s], (unsigned long long)kEmpty, want);
+      if (prev == kEmpty) {
+        *seen = want;
+        return s;
+      }
+      cur = prev;
+    }
+    if ((cur >> kIdxBits) == key) {
+      *seen = cur;
+      return s;
+    }
+  }
+  return -1;
+}
+
 __device__ inline int64_t hash_insert(const VolDev& v, uint64_t key) {
   uint32_t h = hash_home(key, v.hash_mask, v.hash_mode);
   for (uint32_t probe = 0; probe <= v.hash_mask; ++probe) {
@@ -399,7 +425,8 @@ __device__ inline float edge_param(float da, float db) {
 // ---- kernels (defined in vm_kernels.hip, launched from vm_api.hip) ----------
 namespace vm {
 __global__ void k_prep(VolDev v, int op, uint32_t arg);
-__global__ void k_collect(VolDev v, FrameParams fp, const float* __restrict__ depth);
+__global__ void k_collect(VolDev v, FrameParams fp, const float* __restrict__ depth,
+                          uint32_t epoch);
 __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
                                 const int32_t* __restrict__ coords, uint32_t n,
                                 uint32_t frame);

@@ -75,30 +75,65 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
 // block collection (Eq. 1)
 // ============================================================================
 
-// Insert a block key (if absent) and stamp its slot with the frame.  Racing
-// lanes store the same stamp, so no atomic is needed for it.
-__device__ static void collect_key(const VolDev& v, uint64_t key, uint32_t frame) {
-  const int64_t s = hash_insert(v, key);
-  if (s < 0) {
-    atomicOr(&v.cnt->error, kErrHash);
-    return;
-  }
-  if (v.slot_stamp[s] != frame) v.slot_stamp[s] = frame;
-}
-
 // One lane per pixel.  Each valid pixel spans the integer box of blocks
 // between its ray points at camera depth D - mu and D + mu.  Per box cell,
-// the lanes of a wave first agree on the distinct keys (ballot/shuffle), then
-// the lanes holding distinct keys probe the hash in parallel.
+// the lanes of a wave first agree on the distinct keys (ballot/shuffle),
+// then the lanes holding distinct keys insert them into the hash and claim
+// the slot for this frame (exchange of the slot's frame stamp): the one
+// claim that wins lists the block.  The workgroup gathers its claims in LDS
+// and appends them with one atomic per list: the frame list, the pending
+// list (blocks touched since the last extraction) and, for blocks new to
+// the hash, pool indices, given here with their neighbour tables cleared.
+constexpr int kClaimCap = 512;  // claims per workgroup gathered in LDS
+
+// List a claimed block: frame list entry, pending list entry (once per
+// extraction epoch) and, for a block new to the hash, its pool index (slot
+// value and key record updated, neighbour table cleared).  fpos, ppos and
+// bidx are the positions the caller reserved.
+__device__ inline void list_claim(const VolDev& v, uint32_t s, unsigned long long seen,
+                                  bool pend, uint32_t fpos, uint32_t ppos, uint32_t bidx,
+                                  uint32_t epoch) {
+  uint32_t idx = (uint32_t)(seen & kIdxMask), entry = idx;
+  if (idx == kPending) {
+    if (bidx < v.max_blocks) {
+      idx = bidx;
+      const uint64_t key = seen >> kIdxBits;
+      v.slots[s] = (key << kIdxBits) | idx;
+      v.block_key[idx] = key;
+      int32_t* nb = v.nbr + (size_t)idx * 27;
+      for (int d = 0; d < 27; ++d) nb[d] = d == kSelf ? (int32_t)idx : -1;
+      entry = idx | kNewFlag;
+    } else {
+      atomicOr(&v.cnt->error, kErrBlocks);
+      idx = kNone;
+      entry = kNone;
+    }
+  }
+  if (fpos < v.max_blocks) v.frame_list[fpos] = entry;
+  else atomicOr(&v.cnt->error, kErrBlocks);
+  if (pend) {
+    if (idx != kNone) v.st_pending[idx] = epoch;
+    if (ppos < v.max_blocks) v.pending[ppos] = idx;
+    else atomicOr(&v.cnt->error, kErrBlocks);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_collect(VolDev v, FrameParams fp,
-                                                 const float* __restrict__ depth) {
+                                                 const float* __restrict__ depth, uint32_t epoch) {
+  __shared__ unsigned long long sseen[kClaimCap];  // slot contents seen by the claim
+  __shared__ uint32_t sslot[kClaimCap];
+  __shared__ uint32_t nclaim;
+  __shared__ uint32_t swave[16];
+  __shared__ uint32_t sbase[3];
   const int npix = fp.W * fp.H;
   const int pix = blockIdx.x * blockDim.x + threadIdx.x;
   if (pix == 0) {
-    // the frame list is rebuilt by the compaction that follows
-    v.cnt->n_frame = 0;
+    // the other parity's list is the next frame's
+    v.cnt->n_frame[(fp.frame + 1) & 1] = 0;
     v.cnt->acc[VM_TOTAL_FRAMES] += 1;
   }
+  if (threadIdx.x == 0) nclaim = 0;
+  __syncthreads();
   int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
   int nbox = 0;
   if (pix < npix) {
@@ -154,7 +189,54 @@ __global__ __launch_bounds__(256) void k_collect(VolDev v, FrameParams fp,
       if ((int)__lane_id() == leader) mine = true;
       if (same) has = false;
     }
-    if (mine) collect_key(v, key, fp.frame);
+    if (!mine) continue;
+    unsigned long long seen = 0;
+    const int64_t s = hash_insert_seen(v, key, &seen);
+    if (s < 0) {
+      atomicOr(&v.cnt->error, kErrHash);
+      continue;
+    }
+    // one claim per block and frame wins
+    if (v.slot_stamp[s] == fp.frame || atomicExch(&v.slot_stamp[s], fp.frame) == fp.frame)
+      continue;
+    const uint32_t c = atomicAdd(&nclaim, 1u);
+    if (c < kClaimCap) {
+      sslot[c] = (uint32_t)s;
+      sseen[c] = seen;
+    } else {
+      // more claims than the workgroup gathers: list this one alone
+      const bool isnew = (uint32_t)(seen & kIdxMask) == kPending;
+      const bool pend = isnew || v.st_pending[(uint32_t)(seen & kIdxMask)] != epoch;
+      list_claim(v, (uint32_t)s, seen, pend, atomicAdd(&v.cnt->n_frame[fp.frame & 1], 1u),
+                 pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], 1u) : 0u,
+                 isnew ? atomicAdd(&v.cnt->n_blocks, 1u) : 0u, epoch);
+    }
+  }
+  __syncthreads();
+  const uint32_t nc = min(nclaim, (uint32_t)kClaimCap);
+  for (uint32_t c0 = 0; c0 < nc; c0 += blockDim.x) {
+    const uint32_t c = c0 + threadIdx.x;
+    unsigned long long seen = 0;
+    bool isnew = false, pend = false;
+    if (c < nc) {
+      seen = sseen[c];
+      isnew = (uint32_t)(seen & kIdxMask) == kPending;
+      pend = isnew || v.st_pending[(uint32_t)(seen & kIdxMask)] != epoch;
+    }
+    uint32_t t_hit, t_new, t_pend;
+    const uint32_t r_hit = wg_scan(c < nc ? 1u : 0u, swave, &t_hit);
+    const uint32_t r_new = wg_scan(isnew ? 1u : 0u, swave, &t_new);
+    const uint32_t r_pend = wg_scan(pend ? 1u : 0u, swave, &t_pend);
+    if (threadIdx.x == 0) {
+      sbase[0] = atomicAdd(&v.cnt->n_frame[fp.frame & 1], t_hit);
+      sbase[1] = t_new ? atomicAdd(&v.cnt->n_blocks, t_new) : 0u;
+      sbase[2] = t_pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], t_pend) : 0u;
+    }
+    __syncthreads();
+    if (c < nc)
+      list_claim(v, sslot[c], seen, pend, sbase[0] + r_hit, sbase[2] + r_pend, sbase[1] + r_new,
+                 epoch);
+    __syncthreads();
   }
 }
 
@@ -162,7 +244,7 @@ __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
                                 const int32_t* __restrict__ coords, uint32_t n, uint32_t frame) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    v.cnt->n_frame = 0;
+    v.cnt->n_frame[frame & 1] = 0;
     v.cnt->acc[VM_TOTAL_FRAMES] += 1;
   }
   if (i >= n) return;
@@ -227,7 +309,7 @@ __global__ __launch_bounds__(256) void k_frame_compact(VolDev v, uint32_t frame,
   uint32_t r_pend = wg_scan(npend, swave, &t_pend);
   if (t_hit == 0) return;
   if (threadIdx.x == 0) {
-    sbase[0] = atomicAdd(&v.cnt->n_frame, t_hit);
+    sbase[0] = atomicAdd(&v.cnt->n_frame[frame & 1], t_hit);
     sbase[1] = t_new ? atomicAdd(&v.cnt->n_blocks, t_new) : 0u;
     sbase[2] = t_pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], t_pend) : 0u;
   }
@@ -315,7 +397,7 @@ __device__ inline void init_cube(const VolDev& v, uint32_t idx, int l) {
 // ============================================================================
 __global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
                                               const float* __restrict__ depth) {
-  const uint32_t n = min(v.cnt->n_frame, v.max_blocks);
+  const uint32_t n = min(v.cnt->n_frame[fp.frame & 1], v.max_blocks);
   const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
   if (blockIdx.x == 0 && l == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
   for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
@@ -353,7 +435,7 @@ __global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
 __global__ __launch_bounds__(512) void k_import_copy(VolDev v, const float* __restrict__ tsdf,
                                                      const float* __restrict__ weight,
                                                      uint32_t frame, int32_t* __restrict__ rows) {
-  const uint32_t n = min(v.cnt->n_frame, v.max_blocks);
+  const uint32_t n = min(v.cnt->n_frame[frame & 1], v.max_blocks);
   const int l = threadIdx.x;
   if (blockIdx.x == 0 && l == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
   for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
