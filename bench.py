@@ -39,12 +39,11 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 4488.8, "write_kib": 1052.2, "source_sha1": "fdabfc95ce72"},
-    "fuse": {"fetch_kib": 12240.2, "write_kib": 14861.2, "source_sha1": "d35dc5544b75"},
-    "classify": {"fetch_kib": 28584.8, "write_kib": 3728.8, "source_sha1": "7af597156ae7"},
-    "vertices": {"fetch_kib": 31321.4, "write_kib": 13442.9, "source_sha1": "57a5237ca4b1"},
-    "triangles": {"fetch_kib": 5936.3, "write_kib": 6487.6, "source_sha1": "125f1d17712b"},
-    "gc": {"fetch_kib": 2517.7, "write_kib": 2009.5, "source_sha1": "7c0b3bc3de02"},
+    "collect": {"fetch_kib": 5803.8, "write_kib": 710.3, "source_sha1": "6e1c151cc034"},
+    "fuse": {"fetch_kib": 12366.1, "write_kib": 14724.7, "source_sha1": "db66a28e5bab"},
+    "classify": {"fetch_kib": 26952.6, "write_kib": 3889.5, "source_sha1": "cdc7fa06f21a"},
+    "vertices": {"fetch_kib": 30692.0, "write_kib": 9920.0, "source_sha1": "661bdb0572f6"},
+    "triangles": {"fetch_kib": 5182.4, "write_kib": 3631.5, "source_sha1": "4b7e0e805794"},
 }
 
 
@@ -324,10 +323,10 @@ def batched(args, dev):
 
     b = BatchMesher(0.008, coords, tsdf, weight, sphere_loss_grad(centers, radii))
     space = default_space() if args.tune_full else \
-        [p for p in default_space() if p["block_groups_per_cu"] == 4]
+        [p for p in default_space() if p["block_groups_per_cu"] == 8]
     tune = autotune(b, space=space, reps=5, log=log)
     batch_ms = median_ms(b.replay, args.batch_reps)
-    default_launch = dict(wave_group_size=4, wave_groups_per_cu=8, block_groups_per_cu=4,
+    default_launch = dict(wave_group_size=4, wave_groups_per_cu=16, block_groups_per_cu=8,
                           item_groups_per_cu=8, block_order=0)
     b.set_launch(**default_launch)
     b.capture()

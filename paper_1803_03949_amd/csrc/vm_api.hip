@@ -300,7 +300,7 @@ int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes, hipStrea
   }
   v.batch = (uint32_t)cfg->batch_volumes;
   vol->cus = cus;
-  apply_launch(vol, vm_launch{4, 8, 4, 8, 0});
+  apply_launch(vol, vm_launch{4, 16, 8, 8, 0});
   vol->prof = 0;
   int r = clear_state(vol, stream, true);
   if (r != VM_OK) {
@@ -355,7 +355,7 @@ int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* 
   fp.frame = ++vol->frame;
   const VolDev& v = vol->dev;
   const int npix = K->width * K->height;
-  VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3((npix + 255) / 256), dim3(256), stream, v, fp, depth,
+  VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3((npix + 1023) / 1024), dim3(1024), stream, v, fp, depth,
             vol->epoch);
   VM_LAUNCH(vol, VM_K_FUSE, k_fuse, dim3(vol->grid_blocks), dim3(512), stream, v, fp, depth);
   vol->last_fp = fp;

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
 // and appends them with one atomic per list: the frame list, the pending
 // list (blocks touched since the last extraction) and, for blocks new to
 // the hash, pool indices, given here with their neighbour tables cleared.
-constexpr int kClaimCap = 512;  // claims per workgroup gathered in LDS
+constexpr int kClaimCap = 1024;  // claims per workgroup gathered in LDS
 
 // List a claimed block: frame list entry, pending list entry (once per
 // extraction epoch) and, for a block new to the hash, its pool index (slot
@@ -118,7 +118,7 @@ __device__ inline void list_claim(const VolDev& v, uint32_t s, unsigned long lon
   }
 }
 
-__global__ __launch_bounds__(256) void k_collect(VolDev v, FrameParams fp,
+__global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
                                                  const float* __restrict__ depth, uint32_t epoch) {
   __shared__ unsigned long long sseen[kClaimCap];  // slot contents seen by the claim
   __shared__ uint32_t sslot[kClaimCap];
