@@ -102,14 +102,16 @@ def volume_bytes(c):
 def test_volume_bytes_grows_with_every_capacity():
     r, base = volume_bytes(cfg())
     assert r == binding.VM_OK and base > 0
-    # the block pool holds at least TSDF + weight + types + edge slots and
-    # the 64-byte triangle record of every cube
+    # per block: TSDF + weight + two types per voxel, vertex slot, t and
+    # count of its three edges, the 64-byte triangle record of every cube
+    # (the header's figure of about 51 KiB)
     r, more = volume_bytes(cfg(max_blocks=8192))
-    assert r == 0 and more - base >= 4096 * 512 * (4 + 4 + 1 + 1 + 12 + 64)
+    per_block = (more - base) / 4096
+    assert r == 0 and 512 * (4 + 4 + 1 + 1 + 3 * (4 + 4 + 1) + 64) <= per_block < 52 * 1024
     r, more = volume_bytes(cfg(max_vertices=1 << 19))
-    assert r == 0 and more > base
+    assert r == 0 and 12 * (1 << 18) <= more - base < 13 * (1 << 18)
     r, more = volume_bytes(cfg(hash_log2=17))
-    assert r == 0 and more - base >= 8 * (1 << 16)
+    assert r == 0 and 16 * (1 << 16) <= more - base < 17 * (1 << 16)
     # a batch needs no extra memory
     assert volume_bytes(cfg(batch_volumes=64)) == (0, base)
 
