@@ -525,7 +525,7 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   for (int k = 0; k < kSegs; ++k) {
     st_new += sn.vseg[k].st_new, st_upd += sn.vseg[k].st_upd, st_freed += sn.vseg[k].st_freed;
     st_chg += sn.cseg[k].st_chg, st_ref += sn.cseg[k].st_ref;
-    vh += sn.vseg[k].hwm, vf += sn.vseg[k].tail - sn.vseg[k].head;
+    vh += sn.vseg[k].hwm, vf += sn.vseg[k].count;
     tris += sn.cseg[k].st_tri, tcubes += sn.cseg[k].st_tcube;
   }
   memset(out, 0, sizeof(*out));

@@ -62,8 +62,8 @@ constexpr uint32_t kErrRange = 1u << 6;
 // running statistics.  128 bytes, so that segments never share a line.
 struct Seg {
   uint32_t hwm;      // slots handed out by bumping, relative to base
-  uint32_t head;     // ring read position (free slots = tail - head)
-  uint32_t tail;     // ring write position
+  uint32_t head;     // ring read position, in [0, segment size)
+  uint32_t count;    // free slots in the ring, from head on (wrapping)
   uint32_t ticket;   // allocations taken since the last finalise
   uint32_t push;     // frees pushed since the last finalise
   uint32_t st_new;   // running count of allocations
@@ -344,14 +344,20 @@ __device__ inline uint32_t seg_size(uint32_t s, uint32_t cap, uint32_t total) {
   return b >= total ? 0u : (uint32_t)((total - b) < cap ? (total - b) : cap);
 }
 
+// Ring position p + k for p < size and k <= size: one wrap at most, so no
+// division.
+__device__ inline uint32_t ring_pos(uint32_t p, uint32_t k, uint32_t size) {
+  const uint32_t r = p + k;
+  return r >= size ? r - size : r;
+}
+
 // Slot of allocation ticket k of a segment: from its recycle ring first,
 // then by bumping; kNone when the segment is exhausted.  The segment's
-// head/tail/hwm are fixed for the duration of the allocating kernel.
-__device__ inline uint32_t seg_slot(uint32_t head, uint32_t tail, uint32_t hwm, uint32_t k,
+// head/count/hwm are fixed for the duration of the allocating kernel.
+__device__ inline uint32_t seg_slot(uint32_t head, uint32_t count, uint32_t hwm, uint32_t k,
                                     const uint32_t* ring, uint32_t base, uint32_t size) {
-  const uint32_t avail = tail - head;
-  if (k < avail) return ring[base + (uint32_t)(((uint64_t)head + k) % size)];
-  const uint64_t s = (uint64_t)hwm + (k - avail);
+  if (k < count) return ring[base + ring_pos(head, k, size)];
+  const uint64_t s = (uint64_t)hwm + (k - count);
   return s < size ? base + (uint32_t)s : kNone;
 }
 

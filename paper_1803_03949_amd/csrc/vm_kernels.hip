@@ -15,13 +15,16 @@ namespace vm {
 // ============================================================================
 // bookkeeping
 // ============================================================================
+// Close a vertex pool segment after an allocating pass: the ring entries
+// taken are consumed, bumped slots raise the high-water mark, and the slots
+// pushed by frees join the ring.  A free only returns a slot that was in use,
+// so ring entries plus pushes never exceed the segment size.
 __device__ inline void finalise_seg(Seg& g, uint32_t size) {
-  const uint32_t avail = g.tail - g.head;
-  const uint32_t from_ring = min(g.ticket, avail);
-  g.head += from_ring;
+  const uint32_t from_ring = min(g.ticket, g.count);
+  g.head = ring_pos(g.head, from_ring, size);
   const uint64_t hwm = (uint64_t)g.hwm + (g.ticket - from_ring);
   g.hwm = hwm > size ? size : (uint32_t)hwm;
-  g.tail += g.push;
+  g.count = g.count - from_ring + g.push;
   g.ticket = 0;
   g.push = 0;
 }
@@ -705,12 +708,17 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
 // New vertices take slots from the block's pool segment, one atomic per
 // block; the block's edge slots are kept in LDS and the recycled slots it
 // takes are fetched in one batch, so the write pass waits on no memory.
+// The edges with work (a count to write, or a vertex to free) are gathered
+// into a list in LDS while the counts are formed, and the write pass runs
+// over that list, 64 edges per step, instead of over all 1536 edges.
 constexpr int kRingBatch = 256;  // recycled slots fetched per block at once
+constexpr int kWorkCap = 256;    // listed edges per block; more take the row-by-row pass
 
 template <int W>
 __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
   __shared__ uint8_t suses[256 * 12];
   __shared__ uint32_t st_all[W][kRingBatch];  // cube types at local -1..7, then slots
+  __shared__ uint32_t swork_all[W][kWorkCap]; // edge a * 512 + l | count << 11
   __shared__ float sd_all[W][729];            // TSDF at local 0..8
   __shared__ int32_t ses_all[W][3 * kVox];    // slot of edge (a, l) at a * 512 + l
   __shared__ int32_t snb_all[W][27];
@@ -724,11 +732,13 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
   __syncthreads();
   uint8_t* st = reinterpret_cast<uint8_t*>(st_all[wave]);
   uint32_t* sring = st_all[wave];
+  uint32_t* swork = swork_all[wave];
   float* sd = sd_all[wave];
   int32_t* ses = ses_all[wave];
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_vblocks, v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
+  const uint64_t below = lanes_below();
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
     const uint32_t idx = v.vblocks[it.i];
     const uint32_t sg = idx % v.nseg;
@@ -736,7 +746,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     // its pool segment (fixed during this kernel)
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
     const Seg& g = v.vseg[sg];
-    const uint32_t head = g.head, tail = g.tail, hwm = g.hwm;
+    const uint32_t head = g.head, count = g.count, hwm = g.hwm;
     uint32_t has_slot = 0;  // bit 3*lz + a
     {
       int32_t es[24];
@@ -802,7 +812,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     // 8 counts of 8 bits per axis: an edge can carry up to 16 triangles (four
     // in each of its four cubes)
     uint64_t refs[3] = {0, 0, 0};
-    uint32_t nneed = 0, nfree = 0;
+    uint32_t nneed = 0, nfree = 0, nwork = 0;
 #pragma unroll 2
     for (int lz = 0; lz < 8; ++lz) {
       const int tb = (lx + 1) + 9 * (ly + 1) + 81 * (lz + 1);
@@ -817,64 +827,122 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
       const uint32_t hs = has_slot >> (3 * lz);
       nneed += (r0 > 0 && !(hs & 1u)) + (r1 > 0 && !(hs & 2u)) + (r2 > 0 && !(hs & 4u));
       nfree += (r0 == 0 && (hs & 1u)) + (r1 == 0 && (hs & 2u)) + (r2 == 0 && (hs & 4u));
+      // list the layer's edges with work, axis by axis
+      const uint32_t rr[3] = {r0, r1, r2};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const bool w = rr[a] > 0 || ((hs >> a) & 1u);
+        const uint64_t b = __ballot(w);
+        const uint32_t pos = nwork + (uint32_t)__popcll(b & below);
+        if (w && pos < (uint32_t)kWorkCap)
+          swork[pos] = (uint32_t)(a * kVox + q + 64 * lz) | (rr[a] << 11);
+        nwork += (uint32_t)__popcll(b);
+      }
     }
     // one allocation and one recycling atomic per block, issued together;
     // a vertex whose count dropped to zero goes back to the segment's ring
     // at once (Sec. V-E), where it can be taken again once the ring is
     // closed, never by this pass
-    uint32_t total, tfree;
-    uint32_t rank = wave_scan(nneed, &total), frank = wave_scan(nfree, &tfree);
+    const uint32_t total = wave_sum(nneed), tfree = wave_sum(nfree);
     uint32_t base = 0, fbase = 0;
     if (q == 0) {
       if (total) base = atomicAdd(&v.vseg[sg].ticket, total);
       if (tfree) fbase = atomicAdd(&v.vseg[sg].push, tfree);
     }
     base = __shfl(base, 0);
-    frank += __shfl(fbase, 0);
+    fbase = __shfl(fbase, 0);
     const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
+    const uint32_t rtail = ring_pos(head, count, gsize);  // where pushes start
     // the slots of the first kRingBatch allocations, fetched together (the
     // type staging is no longer needed: the batch reuses its LDS)
     wave_sync();
     const uint32_t batch = min(total, (uint32_t)kRingBatch);
     for (uint32_t k = q; k < batch; k += 64)
-      sring[k] = seg_slot(head, tail, hwm, base + k, v.vring, gbase, gsize);
+      sring[k] = seg_slot(head, count, hwm, base + k, v.vring, gbase, gsize);
     wave_sync();
-    const int step[3] = {1, 9, 81};
     uint32_t nnew = 0, nupd = 0;
-#pragma unroll 2
-    for (int lz = 0; lz < 8; ++lz) {
-      const int sdb = lx + 9 * ly + 81 * lz;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u;
-        if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
-        const size_t eo = ((size_t)idx * 3 + a) * kVox + q + 64 * lz;
-        int32_t s = ses[a * kVox + q + 64 * lz];
+    // slot of allocation k of this block (k counted from 0)
+    auto new_slot = [&](uint32_t k) -> uint32_t {
+      return k < batch ? sring[k] : seg_slot(head, count, hwm, base + k, v.vring, gbase, gsize);
+    };
+    // the edge's vertex is no longer used: back to the ring (k-th free of
+    // this block), the edge forgets it
+    auto free_vertex = [&](size_t eo, int32_t s, uint32_t k) {
+      v.vring[gbase + ring_pos(rtail, fbase + k, gsize)] = (uint32_t)s;
+      v.vowner[s] = kNone;
+      v.evtx[eo] = -1;
+      v.eref[eo] = 0;
+    };
+    if (nwork <= (uint32_t)kWorkCap) {
+      uint32_t knew = 0, kfree = 0;
+      for (uint32_t i0 = 0; i0 < nwork; i0 += 64) {
+        const bool act = i0 + q < nwork;
+        const uint32_t item = act ? swork[i0 + q] : 0u;
+        const uint32_t e = item & 2047u, ref = item >> 11;
+        const uint32_t a = e >> 9, l = e & 511u;
+        const int32_t s0 = act ? ses[e] : -1;
+        const bool is_new = act && ref > 0 && s0 < 0, is_free = act && ref == 0;
+        const uint64_t bn = __ballot(is_new), bf = __ballot(is_free);
+        const uint32_t myk = knew + (uint32_t)__popcll(bn & below);
+        const uint32_t myf = kfree + (uint32_t)__popcll(bf & below);
+        knew += (uint32_t)__popcll(bn);
+        kfree += (uint32_t)__popcll(bf);
+        if (!act) continue;
+        const size_t eo = ((size_t)idx * 3 + a) * kVox + l;
         if (ref > 0) {
-          if (s < 0) {
-            const uint32_t ns = rank < batch ? sring[rank]
-                                             : seg_slot(head, tail, hwm, base + rank, v.vring,
-                                                        gbase, gsize);
-            ++rank;
+          if (s0 < 0) {
+            const uint32_t ns = new_slot(myk);
             if (ns == kNone) {
               atomicOr(&v.cnt->error, kErrVertices);
               continue;
             }
-            s = (int32_t)ns;
-            v.evtx[eo] = s;
-            v.vowner[s] = (uint32_t)eo;
+            v.evtx[eo] = (int32_t)ns;
+            v.vowner[ns] = (uint32_t)eo;
             ++nnew;
           } else {
             ++nupd;
           }
-          v.et[eo] = edge_param(sd[sdb], sd[sdb + step[a]]);
+          const int sdb = (int)(l & 7u) + 9 * (int)((l >> 3) & 7u) + 81 * (int)(l >> 6);
+          const int stp = a == 0 ? 1 : (a == 1 ? 9 : 81);
+          v.et[eo] = edge_param(sd[sdb], sd[sdb + stp]);
           v.eref[eo] = (uint8_t)ref;
         } else {
-          // s >= 0: the edge's vertex is no longer used
-          v.vring[gbase + (uint32_t)(((uint64_t)tail + frank++) % gsize)] = (uint32_t)s;
-          v.vowner[s] = kNone;
-          v.evtx[eo] = -1;
-          v.eref[eo] = 0;
+          free_vertex(eo, s0, myf);
+        }
+      }
+    } else {
+      // many edges with work (dense sign fields): row by row over all edges
+      uint32_t dummy;
+      uint32_t rank = wave_scan(nneed, &dummy), frank = wave_scan(nfree, &dummy);
+      const int step[3] = {1, 9, 81};
+#pragma unroll 2
+      for (int lz = 0; lz < 8; ++lz) {
+        const int sdb = lx + 9 * ly + 81 * lz;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u;
+          if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
+          const size_t eo = ((size_t)idx * 3 + a) * kVox + q + 64 * lz;
+          int32_t s = ses[a * kVox + q + 64 * lz];
+          if (ref > 0) {
+            if (s < 0) {
+              const uint32_t ns = new_slot(rank++);
+              if (ns == kNone) {
+                atomicOr(&v.cnt->error, kErrVertices);
+                continue;
+              }
+              s = (int32_t)ns;
+              v.evtx[eo] = s;
+              v.vowner[s] = (uint32_t)eo;
+              ++nnew;
+            } else {
+              ++nupd;
+            }
+            v.et[eo] = edge_param(sd[sdb], sd[sdb + step[a]]);
+            v.eref[eo] = (uint8_t)ref;
+          } else {
+            free_vertex(eo, s, frank++);
+          }
         }
       }
     }
