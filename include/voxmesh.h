@@ -132,7 +132,7 @@ enum {
   VM_TOTAL_NEW_VERTICES = 4,
   VM_TOTAL_UPDATED_VERTICES = 5,
   VM_TOTAL_CHANGED_CUBES = 6,   /* cubes whose triangles were rewritten */
-  VM_TOTAL_GC_SCANNED = 7,      /* vertex slots in use at each vm_gc */
+  VM_TOTAL_GC_SCANNED = 7,      /* reserved, 0: vm_gc scans nothing */
   VM_TOTAL_FREED_VERTICES = 8,
   VM_TOTAL_REFINED_CUBES = 9,
   VM_TOTAL_COUNT = 10
@@ -224,9 +224,13 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream);
 int vm_refine_mesh(vm_volume* vol, hipStream_t stream);
 
 /* Garbage collection (Sec. V-E).  A vertex no triangle uses any more is
- * returned to its pool segment's recycle ring by the extraction (or
- * refinement) that drops its count to zero, and its edge forgets it at
- * once; vm_gc closes the rings so that those slots can be taken again. */
+ * freed by the extraction (or refinement) that drops its count to zero: its
+ * edge forgets it at once, so it is in no download or export from then on,
+ * and its slot goes to its pool segment's recycle ring, which the next
+ * extraction or refinement opens for allocation before it allocates.  So
+ * vm_gc has no device work left and launches nothing; it exists so that a
+ * caller follows the method's steps, and returns VM_OK (VM_ERR_ARG for a
+ * NULL volume). */
 int vm_gc(vm_volume* vol, hipStream_t stream);
 
 /* Compact the mesh into caller buffers (device): verts[vcap][3] FP32

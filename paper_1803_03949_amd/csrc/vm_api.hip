@@ -30,6 +30,8 @@ struct vm_volume {
   uint32_t frame;   // last frame number handed to the device
   uint32_t epoch;   // extraction epoch (pending-list stamps)
   uint32_t pass;    // dirty / vertex-list stamps
+  uint32_t xcount;  // extractions so far (parity selects the dirty-list length)
+  uint32_t vcount;  // extractions and refinements so far (vertex-list length)
   FrameParams last_fp;
   bool have_fp;
   int cus;          // compute units of the device
@@ -392,9 +394,11 @@ int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
 
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
   if (!vol || (scope != VM_SCOPE_DIRTY && scope != VM_SCOPE_ALL)) return VM_ERR_ARG;
-  const VolDev& v = vol->dev;
   const uint32_t pass = ++vol->pass;
-  prep(vol, VM_OP_EXTRACT, stream);
+  // the first kernel starts the call (segments, statistics, list lengths)
+  vol->dev.xsel = ++vol->xcount & 1u;
+  vol->dev.vsel = ++vol->vcount & 1u;
+  const VolDev& v = vol->dev;
   if (scope == VM_SCOPE_ALL)
     VM_LAUNCH(vol, VM_K_DIRTY, k_dirty_all, dim3(vol->grid_items), dim3(256), stream, v, pass);
   else
@@ -410,8 +414,9 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
 
 int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   if (!vol) return VM_ERR_ARG;
-  const VolDev& v = vol->dev;
   const uint32_t pass = ++vol->pass;
+  vol->dev.vsel = ++vol->vcount & 1u;
+  const VolDev& v = vol->dev;
   prep(vol, VM_OP_REFINE, stream);
   VM_LAUNCH_W(vol, VM_K_REFINE, k_classify, stream, v, pass, 1);
   VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
@@ -422,11 +427,12 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
 
 int vm_gc(vm_volume* vol, hipStream_t stream) {
   if (!vol) return VM_ERR_ARG;
-  // the vertex pass already returned every vertex whose count dropped to
-  // zero to its segment's recycle ring; here the rings are closed so that
-  // the slots can be taken again
-  prep(vol, VM_OP_GC, stream);
-  return launched();
+  // nothing to launch: the vertex pass already freed every vertex whose
+  // count dropped to zero (its edge forgot it, its slot went to the
+  // segment's recycle ring), and the next extraction or refinement closes
+  // the rings before it allocates
+  (void)stream;
+  return VM_OK;
 }
 
 int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys, int32_t* tris,
@@ -535,8 +541,8 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   const uint32_t nf = c.n_frame[vol->frame & 1];
   out->frame_blocks = nf < B ? nf : B;
   out->pending_blocks = c.n_pending[vol->epoch & 1];
-  out->dirty_blocks = c.n_dirty;
-  out->vertex_blocks = c.n_vblocks;
+  out->dirty_blocks = c.n_dirty[vol->dev.xsel];
+  out->vertex_blocks = c.n_vblocks[vol->dev.vsel];
   out->changed_cubes = st_chg - c.base_chg;
   out->vertex_slots = vh;
   out->free_vertex_slots = vf;
@@ -600,7 +606,7 @@ int vm_export_block_list(vm_volume* vol, int which, int32_t* coords, int64_t cap
   int r = read_counters(vol, &c, stream);
   if (r != VM_OK) return r;
   const VolDev& v = vol->dev;
-  const uint32_t len = which == 0 ? c.n_frame[vol->frame & 1] : which == 1 ? c.n_dirty : c.n_pending[vol->epoch & 1];
+  const uint32_t len = which == 0 ? c.n_frame[vol->frame & 1] : which == 1 ? c.n_dirty[vol->dev.xsel] : c.n_pending[vol->epoch & 1];
   const size_t cnt = len < v.max_blocks ? len : v.max_blocks;
   *n = (int64_t)cnt;
   const size_t m = (size_t)cap < cnt ? (size_t)cap : cnt;

@@ -82,14 +82,17 @@ struct Counters {
   uint32_t n_blocks;       // pool high-water mark (may exceed capacity on error)
   uint32_t n_frame[2];     // entries of the frame list of frames of each parity
   uint32_t n_pending[2];   // blocks touched since the last extraction (by epoch parity)
-  uint32_t n_dirty;        // blocks of the last extraction / refinement
-  uint32_t n_vblocks;      // blocks whose owned edges get recomputed
+  // list lengths, one slot per call parity: a call appends to its own slot
+  // and clears the other one, which the next call then uses
+  uint32_t n_dirty[2];     // dirty blocks, by extraction parity
+  uint32_t n_vblocks[2];   // blocks whose owned edges get recomputed, by
+                           // extraction / refinement parity
   uint32_t error;
   uint32_t dl_nv, dl_nt;
   uint32_t n_refined;      // cubes re-typed by the last refinement
-  // segment totals when the last extract / refine / gc started
+  // segment totals when the last extract / refine started
   uint32_t base_new, base_upd, base_freed, base_chg, base_ref;
-  uint32_t pad[16];
+  uint32_t pad[14];
   // running totals since the volume was created (not cleared by a reset)
   unsigned long long acc[10];
   unsigned long long pad2[6];
@@ -102,6 +105,8 @@ struct VolDev {
   uint32_t hash_mask;
   int32_t hash_mode;
   uint32_t max_blocks, max_vertices;
+  uint32_t xsel;              // parity of the current extraction (dirty list)
+  uint32_t vsel;              // parity of the current extraction / refinement (vertex list)
   uint32_t nseg;              // pool segments in use (1..kSegs)
   uint32_t vseg_cap;            // vertex slots per segment
   Counters* cnt;
@@ -293,6 +298,22 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A value every lane of the wave holds alike (a list entry read at a
+// wave-uniform index), moved to a scalar register so that the addressing
+// derived from it is scalar.
+__device__ inline uint32_t uniform(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+// The lane index, opaque to loop-invariant code motion: values derived from
+// it inside a loop are recomputed each trip instead of occupying registers
+// for the whole loop.
+__device__ inline int fresh_lane() {
+  int q = __lane_id();
+  asm volatile("" : "+v"(q));
+  return q;
+}
+
 // Exclusive prefix of x over the wave and the wave's total.
 __device__ inline uint32_t wave_scan(uint32_t x, uint32_t* total) {
   const int lane = __lane_id();
@@ -473,9 +494,7 @@ __global__ void k_lookup(VolDev v, const int32_t* __restrict__ coords, int32_t* 
 // pool segments (recycled slots consumed, bump pointers advanced, frees
 // made available), which is idempotent.
 enum {
-  VM_OP_EXTRACT = 1,    // before an extraction: account and reset dirty/vertex lists
-  VM_OP_REFINE = 2,     // before a refinement: reset the vertex list
-  VM_OP_GC = 3,         // before a garbage collection
+  VM_OP_REFINE = 2,     // before a refinement: snapshot, clear the next vertex list
   VM_OP_FINALISE = 4,   // segments only
   VM_OP_RESET = 5       // before a reset: fold segment statistics into the totals
 };

@@ -29,38 +29,47 @@ __device__ inline void finalise_seg(Seg& g, uint32_t size) {
   g.push = 0;
 }
 
-// One wave: lane s finalises vertex pool segment s, the lanes sum the
-// segment statistics, then lane 0 does the operation's resets and snapshots.
+// Start of an extraction (refine = false) or refinement, done by one full
+// wave while nothing else touches the segments: lane s closes vertex pool
+// segment s (slots freed by earlier passes become available), the lanes sum
+// the segment statistics the call reports per call, and lane 0 records them
+// and clears the list lengths of the next call.
+__device__ inline void begin_call(const VolDev& v, bool refine) {
+  const int s = __lane_id();
+  Seg& vs = v.vseg[s];
+  Seg& cs = v.cseg[s];
+  finalise_seg(vs, seg_size(s, v.vseg_cap, v.max_vertices));
+  const uint32_t sum_new = wave_sum(vs.st_new), sum_upd = wave_sum(vs.st_upd);
+  const uint32_t sum_freed = wave_sum(vs.st_freed);
+  const uint32_t sum_chg = wave_sum(cs.st_chg), sum_ref = wave_sum(cs.st_ref);
+  if (s != 0) return;
+  Counters* c = v.cnt;
+  if (!refine) c->n_dirty[v.xsel ^ 1u] = 0;
+  c->n_vblocks[v.vsel ^ 1u] = 0;
+  c->base_new = sum_new;
+  c->base_upd = sum_upd;
+  c->base_freed = sum_freed;
+  c->base_chg = sum_chg;
+  if (refine) c->base_ref = sum_ref;
+}
+
+// One wave: lane s closes vertex pool segment s, the lanes sum the segment
+// statistics, then lane 0 does the operation's resets and snapshots.
 __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
+  if (op == VM_OP_REFINE) {
+    begin_call(v, true);
+    return;
+  }
   const int s = threadIdx.x;
   Seg& vs = v.vseg[s];
   Seg& cs = v.cseg[s];
   finalise_seg(vs, seg_size(s, v.vseg_cap, v.max_vertices));
   const uint32_t sum_new = wave_sum(vs.st_new), sum_upd = wave_sum(vs.st_upd);
-  const uint32_t sum_freed = wave_sum(vs.st_freed), hwm = wave_sum(vs.hwm);
+  const uint32_t sum_freed = wave_sum(vs.st_freed);
   const uint32_t sum_chg = wave_sum(cs.st_chg), sum_ref = wave_sum(cs.st_ref);
   if (s != 0) return;
   Counters* c = v.cnt;
   switch (op) {
-    case VM_OP_EXTRACT:
-      c->n_dirty = 0;
-      c->n_vblocks = 0;
-      c->base_new = sum_new;
-      c->base_upd = sum_upd;
-      c->base_freed = sum_freed;
-      c->base_chg = sum_chg;
-      break;
-    case VM_OP_REFINE:
-      c->n_vblocks = 0;
-      c->base_new = sum_new;
-      c->base_upd = sum_upd;
-      c->base_freed = sum_freed;
-      c->base_chg = sum_chg;
-      c->base_ref = sum_ref;
-      break;
-    case VM_OP_GC:
-      c->acc[VM_TOTAL_GC_SCANNED] += hwm;
-      break;
     case VM_OP_RESET:
       c->acc[VM_TOTAL_NEW_VERTICES] += sum_new;
       c->acc[VM_TOTAL_UPDATED_VERTICES] += sum_upd;
@@ -469,9 +478,12 @@ __global__ __launch_bounds__(512) void k_import_copy(VolDev v, const float* __re
 // Dirty = pending blocks and their allocated neighbours at offsets {-1,0}^3.
 // Candidates (8 per pending block) are claimed through a per-block pass
 // stamp and compacted tile by tile, one atomic per tile.
+// The first wave also starts the extraction (segments, statistics, next
+// list lengths): nothing else in this kernel touches them.
 __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t epoch) {
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase;
+  if (blockIdx.x == 0 && threadIdx.x < 64) begin_call(v, false);
   const uint32_t np = min(v.cnt->n_pending[epoch & 1], v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->n_pending[(epoch + 1) & 1] = 0;
   const uint32_t total = np * 8u;
@@ -495,7 +507,7 @@ __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t
     uint32_t tot;
     uint32_t r = wg_scan(cnt, swave, &tot);
     if (tot == 0) continue;
-    if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_dirty, tot);
+    if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_dirty[v.xsel], tot);
     __syncthreads();
     r += sbase;
 #pragma unroll
@@ -506,13 +518,14 @@ __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t
 }
 
 __global__ __launch_bounds__(256) void k_dirty_all(VolDev v, uint32_t pass) {
+  if (blockIdx.x == 0 && threadIdx.x < 64) begin_call(v, false);
   const uint32_t n = min(v.cnt->n_blocks, v.max_blocks);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     v.dirty[i] = i;
     v.st_dirty[i] = pass;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    v.cnt->n_dirty = n;
+    v.cnt->n_dirty[v.xsel] = n;
     v.cnt->n_pending[0] = 0;
     v.cnt->n_pending[1] = 0;
   }
@@ -555,19 +568,21 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
 // may have moved), and the owners of the edges of changed cubes (this block
 // and, for cubes on its +x/+y/+z faces, neighbours).
 template <int W>
-__global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass, int refine) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(VolDev v, uint32_t pass, int refine) {
   __shared__ float sd_all[W][729];
   __shared__ uint8_t sok_all[W][732];
   __shared__ int32_t snb_all[W][8];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id(), lx = q & 7, ly = q >> 3;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* sd = sd_all[wave];
   uint8_t* sok = sok_all[wave];
   int32_t* snb = snb_all[wave];
-  const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
+  const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
   const int coff[8] = {0, 1, 1 + 9, 9, 81, 1 + 81, 1 + 9 + 81, 9 + 81};
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
+    // lane addressing is formed again per block (fewer registers)
+    const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
     const uint32_t i = it.i;
-    const uint32_t idx = v.dirty[i];
+    const uint32_t idx = uniform(v.dirty[i]);
     const int32_t mynb = q < 8 ? v.nbr[(size_t)idx * 27 + nbr_dir(q & 1, (q >> 1) & 1, q >> 2)] : -1;
     // the block's own types, independent of the halo: load them now
     uint32_t old[8], prev[8];
@@ -675,7 +690,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_classify(VolDev v, uint32_t pass,
 __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase;
-  const uint32_t n = min(v.cnt->n_dirty, v.max_blocks);
+  const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_DIRTY_BLOCKS] += n;
   const uint32_t total = n * 8u;
   for (uint32_t t0 = blockIdx.x * kTile; t0 < total; t0 += gridDim.x * kTile) {
@@ -689,7 +704,7 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
     uint32_t tot;
     uint32_t r = wg_scan(cnt, swave, &tot);
     if (tot == 0) continue;
-    if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_vblocks, tot);
+    if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_vblocks[v.vsel], tot);
     __syncthreads();
     r += sbase;
 #pragma unroll
@@ -723,7 +738,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
   __shared__ int32_t ses_all[W][3 * kVox];    // slot of edge (a, l) at a * 512 + l
   __shared__ int32_t snb_all[W][27];
   static_assert(kRingBatch * 4 >= 732, "type staging fits the slot batch");
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id(), lx = q & 7, ly = q >> 3;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(v.edge_uses);
     uint32_t* dst = reinterpret_cast<uint32_t*>(suses);
@@ -736,12 +751,15 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
   float* sd = sd_all[wave];
   int32_t* ses = ses_all[wave];
   int32_t* snb = snb_all[wave];
-  const uint32_t n = min(v.cnt->n_vblocks, v.max_blocks);
+  const uint32_t n = min(v.cnt->n_vblocks[v.vsel], v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
   const uint64_t below = lanes_below();
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
-    const uint32_t idx = v.vblocks[it.i];
-    const uint32_t sg = idx % v.nseg;
+    // lane addressing is formed again per block rather than held in
+    // registers across the loop
+    const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
+    const uint32_t idx = uniform(v.vblocks[it.i]);
+    const uint32_t sg = uniform(idx % v.nseg);
     // requested at once: the neighbour table, the block's edge slots and
     // its pool segment (fixed during this kernel)
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
@@ -994,10 +1012,10 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
   uint8_t* slist = slist_all[wave];
   uint8_t* stype = stype_all[wave];
   int32_t* snb = snb_all[wave];
-  const uint32_t n = min(v.cnt->n_dirty, v.max_blocks) * 8u;
+  const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks) * 8u;
   const int k = q & 15;
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
-    const uint32_t idx = v.dirty[it.i >> 3];
+    const uint32_t idx = uniform(v.dirty[it.i >> 3]);
     const int lz = (int)(it.i & 7u);
     const uint64_t m = v.chg[(size_t)idx * 8 + lz];
     if (m == 0ull) continue;
