@@ -331,6 +331,16 @@ __device__ inline uint32_t wave_sum(uint32_t x) {
   return x;
 }
 
+// Sum over the wave of per-lane values in [0, 2^B): one ballot per bit,
+// counted in scalar registers, so there is no chain of cross-lane moves.
+template <int B>
+__device__ inline uint32_t wave_sum_bits(uint32_t x) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int b = 0; b < B; ++b) s += (uint32_t)__popcll(__ballot((x >> b) & 1u)) << b;
+  return s;
+}
+
 __device__ inline uint64_t shfl64(uint64_t x, int src) {
   const uint32_t lo = __shfl((uint32_t)x, src), hi = __shfl((uint32_t)(x >> 32), src);
   return ((uint64_t)hi << 32) | lo;
@@ -357,6 +367,33 @@ __device__ inline uint32_t wg_scan(uint32_t x, uint32_t* swave, uint32_t* total)
   __syncthreads();
   *total = all;
   return before + incl - x;
+}
+
+// wg_scan for per-lane values in [0, 2^B): the wave prefix comes from one
+// ballot per bit (lane-masked popcounts), the wave totals go through LDS.
+template <int B>
+__device__ inline uint32_t wg_scan_bits(uint32_t x, uint32_t* swave, uint32_t* total) {
+  const int wave = threadIdx.x >> 6;
+  const int nwave = (blockDim.x + 63) >> 6;
+  const uint64_t below = lanes_below();
+  uint32_t pre = 0, wt = 0;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const uint64_t m = __ballot((x >> b) & 1u);
+    pre += (uint32_t)__popcll(m & below) << b;
+    wt += (uint32_t)__popcll(m) << b;
+  }
+  if (__lane_id() == 0) swave[wave] = wt;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < nwave; ++w) {
+    const uint32_t c = swave[w];
+    if (w < wave) before += c;
+    all += c;
+  }
+  __syncthreads();
+  *total = all;
+  return before + pre;
 }
 
 // Segment bounds.

@@ -182,19 +182,25 @@ __global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
       }
     }
   }
+  // the box's blocks in x-fastest order, stepped with carries (no division)
+  int cx = 0, cy = 0, cz = 0;
   for (int j = 0; __ballot(j < nbox); ++j) {
     bool has = j < nbox;
     uint64_t key = 0;
     if (has) {
-      const int cx = j % ext[0], cy = (j / ext[0]) % ext[1], cz = j / (ext[0] * ext[1]);
       key = pack_key(lo[0] + cx, lo[1] + cy, lo[2] + cz);
+      if (++cx == ext[0]) {
+        cx = 0;
+        if (++cy == ext[1]) cy = 0, ++cz;
+      }
     }
     bool mine = false;  // this lane holds the first copy of its key
     uint64_t todo = __ballot(has);
     while (todo) {
-      const int leader = __ffsll((unsigned long long)todo) - 1;
-      const uint32_t klo = __shfl((uint32_t)key, leader);
-      const uint32_t khi = __shfl((uint32_t)(key >> 32), leader);
+      // the leader is wave-uniform: its key is read lane to scalar
+      const int leader = __builtin_ctzll(todo);
+      const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, leader);
+      const uint32_t khi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), leader);
       const uint64_t lk = ((uint64_t)khi << 32) | klo;
       const bool same = has && key == lk;
       todo &= ~__ballot(same);
@@ -236,9 +242,9 @@ __global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
       pend = isnew || v.st_pending[(uint32_t)(seen & kIdxMask)] != epoch;
     }
     uint32_t t_hit, t_new, t_pend;
-    const uint32_t r_hit = wg_scan(c < nc ? 1u : 0u, swave, &t_hit);
-    const uint32_t r_new = wg_scan(isnew ? 1u : 0u, swave, &t_new);
-    const uint32_t r_pend = wg_scan(pend ? 1u : 0u, swave, &t_pend);
+    const uint32_t r_hit = wg_scan_bits<1>(c < nc ? 1u : 0u, swave, &t_hit);
+    const uint32_t r_new = wg_scan_bits<1>(isnew ? 1u : 0u, swave, &t_new);
+    const uint32_t r_pend = wg_scan_bits<1>(pend ? 1u : 0u, swave, &t_pend);
     if (threadIdx.x == 0) {
       sbase[0] = atomicAdd(&v.cnt->n_frame[fp.frame & 1], t_hit);
       sbase[1] = t_new ? atomicAdd(&v.cnt->n_blocks, t_new) : 0u;
@@ -505,7 +511,7 @@ __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t
       }
     }
     uint32_t tot;
-    uint32_t r = wg_scan(cnt, swave, &tot);
+    uint32_t r = wg_scan_bits<3>(cnt, swave, &tot);  // cnt <= 4
     if (tot == 0) continue;
     if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_dirty[v.xsel], tot);
     __syncthreads();
@@ -572,6 +578,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
   __shared__ float sd_all[W][729];
   __shared__ uint8_t sok_all[W][732];
   __shared__ int32_t snb_all[W][8];
+  __shared__ uint8_t sntri[256];  // triangles of each cube type
+  for (int j = threadIdx.x; j < 256; j += blockDim.x) sntri[j] = v.tri_table[j * 16];
+  __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* sd = sd_all[wave];
   uint8_t* sok = sok_all[wave];
@@ -644,7 +653,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
         nt = valid ? refine_type(old[lz], prev[lz], dc, v.eps) : old[lz];
       }
       if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
-      const int ntri_old = v.tri_table[old[lz] * 16], ntri_new = v.tri_table[nt * 16];
+      const int ntri_old = sntri[old[lz]], ntri_new = sntri[nt];
       const bool tri_change = nt != old[lz] && (ntri_old || ntri_new);
       dtri += ntri_new - ntri_old;
       dtcube += (ntri_new > 0) - (ntri_old > 0);
@@ -672,8 +681,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       }
       v.vcand[(size_t)i * 8 + q] = out;
     }
-    dtri = wave_sum(dtri);
-    dtcube = wave_sum(dtcube);
+    // per lane dtri is in [-40, 40] and dtcube in [-8, 8]: summed offset
+    dtri = (int)wave_sum_bits<7>((uint32_t)(dtri + 40)) - 64 * 40;
+    dtcube = (int)wave_sum_bits<5>((uint32_t)(dtcube + 8)) - 64 * 8;
     if (q == 0 && nchanged) {
       const uint32_t sg = idx % v.nseg;
       atomicAdd(&v.cseg[sg].st_chg, nchanged);
@@ -702,7 +712,7 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
       cnt += got[k] != kNone;
     }
     uint32_t tot;
-    uint32_t r = wg_scan(cnt, swave, &tot);
+    uint32_t r = wg_scan_bits<3>(cnt, swave, &tot);  // cnt <= 4
     if (tot == 0) continue;
     if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_vblocks[v.vsel], tot);
     __syncthreads();
@@ -861,14 +871,15 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     // a vertex whose count dropped to zero goes back to the segment's ring
     // at once (Sec. V-E), where it can be taken again once the ring is
     // closed, never by this pass
-    const uint32_t total = wave_sum(nneed), tfree = wave_sum(nfree);
+    // per lane at most 24 of each (its three edges in eight layers)
+    const uint32_t total = wave_sum_bits<5>(nneed), tfree = wave_sum_bits<5>(nfree);
     uint32_t base = 0, fbase = 0;
     if (q == 0) {
       if (total) base = atomicAdd(&v.vseg[sg].ticket, total);
       if (tfree) fbase = atomicAdd(&v.vseg[sg].push, tfree);
     }
-    base = __shfl(base, 0);
-    fbase = __shfl(fbase, 0);
+    base = uniform(base);
+    fbase = uniform(fbase);
     const uint32_t gbase = sg * v.vseg_cap, gsize = seg_size(sg, v.vseg_cap, v.max_vertices);
     const uint32_t rtail = ring_pos(head, count, gsize);  // where pushes start
     // the slots of the first kRingBatch allocations, fetched together (the
@@ -964,8 +975,8 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
         }
       }
     }
-    nnew = wave_sum(nnew);
-    nupd = wave_sum(nupd);
+    nnew = wave_sum_bits<5>(nnew);
+    nupd = wave_sum_bits<5>(nupd);
     if (q == 0) {
       if (nnew) atomicAdd(&v.vseg[sg].st_new, nnew);
       if (nupd) atomicAdd(&v.vseg[sg].st_upd, nupd);
