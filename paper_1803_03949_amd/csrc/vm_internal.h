@@ -126,7 +126,7 @@ struct VolDev {
   int32_t* evtx;              // [B][3][512] vertex slot of the edge, -1 if none
   float* et;                  // [B][3][512] t of the edge's vertex
   uint8_t* eref;              // [B][3][512] reference count of the edge's vertex
-  uint64_t* chg;              // [B][8] cubes whose triangles changed, per wave
+  uint64_t* chg;              // [B][8] by dirty-list position and z layer: cubes whose triangles changed
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
   uint32_t* st_vtx;           // [B] pass that listed the block for vertices

@@ -658,7 +658,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       dtri += ntri_new - ntri_old;
       dtcube += (ntri_new > 0) - (ntri_old > 0);
       const uint64_t m = __ballot(tri_change);
-      if (q == 0) v.chg[(size_t)idx * 8 + lz] = m;
+      if (q == 0) v.chg[(size_t)i * 8 + lz] = m;  // by dirty-list position
       nchanged += (uint32_t)__popcll(m);
       if (tri_change) {
         // owners of this cube's edges: this block and, on its +x/+y/+z
@@ -731,11 +731,13 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
 // from the end point TSDF values.  The counts come from cube types staged
 // in LDS with the -x/-y/-z halo, so no per-triangle increments are needed.
 // New vertices take slots from the block's pool segment, one atomic per
-// block; the block's edge slots are kept in LDS and the recycled slots it
-// takes are fetched in one batch, so the write pass waits on no memory.
-// The edges with work (a count to write, or a vertex to free) are gathered
-// into a list in LDS while the counts are formed, and the write pass runs
-// over that list, 64 edges per step, instead of over all 1536 edges.
+// block, and the recycled slots it takes are fetched in one batch.  The
+// edges with work (a count to write, or a vertex to free) are gathered into
+// a list in LDS while the counts are formed, with a bit telling whether the
+// edge has a vertex; the write pass runs over that list, 64 edges per step,
+// instead of over all 1536 edges.  Only a vertex being freed needs its slot,
+// which it reads again; the block's slots never occupy LDS, which keeps the
+// wave's LDS small enough for six waves per SIMD.
 constexpr int kRingBatch = 256;  // recycled slots fetched per block at once
 constexpr int kWorkCap = 256;    // listed edges per block; more take the row-by-row pass
 
@@ -745,7 +747,6 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
   __shared__ uint32_t st_all[W][kRingBatch];  // cube types at local -1..7, then slots
   __shared__ uint32_t swork_all[W][kWorkCap]; // edge a * 512 + l | count << 11
   __shared__ float sd_all[W][729];            // TSDF at local 0..8
-  __shared__ int32_t ses_all[W][3 * kVox];    // slot of edge (a, l) at a * 512 + l
   __shared__ int32_t snb_all[W][27];
   static_assert(kRingBatch * 4 >= 732, "type staging fits the slot batch");
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -759,7 +760,6 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
   uint32_t* sring = st_all[wave];
   uint32_t* swork = swork_all[wave];
   float* sd = sd_all[wave];
-  int32_t* ses = ses_all[wave];
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_vblocks[v.vsel], v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
@@ -775,7 +775,9 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
     const Seg& g = v.vseg[sg];
     const uint32_t head = g.head, count = g.count, hwm = g.hwm;
-    uint32_t has_slot = 0;  // bit 3*lz + a
+    // which of the voxel's edges have a vertex (bit 3*lz + a); the slots
+    // themselves are read again only for the vertices that get freed
+    uint32_t has_slot = 0;
     {
       int32_t es[24];
 #pragma unroll
@@ -783,12 +785,8 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) es[3 * lz + a] = v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
 #pragma unroll
-      for (int lz = 0; lz < 8; ++lz)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          ses[a * kVox + q + 64 * lz] = es[3 * lz + a];
-          has_slot |= (uint32_t)(es[3 * lz + a] >= 0) << (3 * lz + a);
-        }
+      for (int k = 23; k >= 0; --k)  // shifted in, so no per-bit mask constants
+        has_slot = (has_slot << 1) | (uint32_t)(es[k] >= 0);
     }
     if (q < 27) snb[q] = mynb;
     wave_sync();
@@ -863,7 +861,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
         const uint64_t b = __ballot(w);
         const uint32_t pos = nwork + (uint32_t)__popcll(b & below);
         if (w && pos < (uint32_t)kWorkCap)
-          swork[pos] = (uint32_t)(a * kVox + q + 64 * lz) | (rr[a] << 11);
+          swork[pos] = (uint32_t)(a * kVox + q + 64 * lz) | (rr[a] << 11) | (((hs >> a) & 1u) << 19);
         nwork += (uint32_t)__popcll(b);
       }
     }
@@ -907,10 +905,9 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
       for (uint32_t i0 = 0; i0 < nwork; i0 += 64) {
         const bool act = i0 + q < nwork;
         const uint32_t item = act ? swork[i0 + q] : 0u;
-        const uint32_t e = item & 2047u, ref = item >> 11;
+        const uint32_t e = item & 2047u, ref = (item >> 11) & 255u, has = item >> 19;
         const uint32_t a = e >> 9, l = e & 511u;
-        const int32_t s0 = act ? ses[e] : -1;
-        const bool is_new = act && ref > 0 && s0 < 0, is_free = act && ref == 0;
+        const bool is_new = act && ref > 0 && !has, is_free = act && ref == 0;
         const uint64_t bn = __ballot(is_new), bf = __ballot(is_free);
         const uint32_t myk = knew + (uint32_t)__popcll(bn & below);
         const uint32_t myf = kfree + (uint32_t)__popcll(bf & below);
@@ -919,7 +916,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
         if (!act) continue;
         const size_t eo = ((size_t)idx * 3 + a) * kVox + l;
         if (ref > 0) {
-          if (s0 < 0) {
+          if (!has) {
             const uint32_t ns = new_slot(myk);
             if (ns == kNone) {
               atomicOr(&v.cnt->error, kErrVertices);
@@ -936,7 +933,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
           v.et[eo] = edge_param(sd[sdb], sd[sdb + stp]);
           v.eref[eo] = (uint8_t)ref;
         } else {
-          free_vertex(eo, s0, myf);
+          free_vertex(eo, v.evtx[eo], myf);
         }
       }
     } else {
@@ -952,17 +949,16 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
           const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u;
           if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
           const size_t eo = ((size_t)idx * 3 + a) * kVox + q + 64 * lz;
-          int32_t s = ses[a * kVox + q + 64 * lz];
+          const bool has = (has_slot >> (3 * lz + a)) & 1u;
           if (ref > 0) {
-            if (s < 0) {
+            if (!has) {
               const uint32_t ns = new_slot(rank++);
               if (ns == kNone) {
                 atomicOr(&v.cnt->error, kErrVertices);
                 continue;
               }
-              s = (int32_t)ns;
-              v.evtx[eo] = s;
-              v.vowner[s] = (uint32_t)eo;
+              v.evtx[eo] = (int32_t)ns;
+              v.vowner[ns] = (uint32_t)eo;
               ++nnew;
             } else {
               ++nupd;
@@ -970,7 +966,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
             v.et[eo] = edge_param(sd[sdb], sd[sdb + step[a]]);
             v.eref[eo] = (uint8_t)ref;
           } else {
-            free_vertex(eo, s, frank++);
+            free_vertex(eo, v.evtx[eo], frank++);
           }
         }
       }
@@ -1025,10 +1021,22 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks) * 8u;
   const int k = q & 15;
-  for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
-    const uint32_t idx = uniform(v.dirty[it.i >> 3]);
+  // item i is layer i % 8 of dirty-list entry i / 8; its change mask sits at
+  // position i.  The next item's mask and block are requested while the
+  // current one is worked on, so an unchanged layer costs no round trip.
+  ItemLoop it = item_loop(v, n, W, wave);
+  uint64_t m_next = 0;
+  uint32_t idx_next = 0;
+  if (it.i < it.end) m_next = v.chg[it.i], idx_next = v.dirty[it.i >> 3];
+  for (; it.i < it.end; it.i += it.step) {
+    const uint32_t mlo = uniform((uint32_t)m_next), mhi = uniform((uint32_t)(m_next >> 32));
+    const uint64_t m = ((uint64_t)mhi << 32) | mlo;
+    const uint32_t idx = uniform(idx_next);
     const int lz = (int)(it.i & 7u);
-    const uint64_t m = v.chg[(size_t)idx * 8 + lz];
+    if (it.i + it.step < it.end) {
+      m_next = v.chg[it.i + it.step];
+      idx_next = v.dirty[(it.i + it.step) >> 3];
+    }
     if (m == 0ull) continue;
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
     const uint32_t mytype = v.tcur[(size_t)idx * kVox + q + 64 * lz];
