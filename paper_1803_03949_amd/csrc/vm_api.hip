@@ -359,7 +359,7 @@ int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* 
   const int npix = K->width * K->height;
   VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3((npix + 1023) / 1024), dim3(1024), stream, v, fp, depth,
             vol->epoch);
-  VM_LAUNCH(vol, VM_K_FUSE, k_fuse, dim3(vol->grid_blocks), dim3(512), stream, v, fp, depth);
+  VM_LAUNCH_W(vol, VM_K_FUSE, k_fuse, stream, v, fp, depth);
   vol->last_fp = fp;
   vol->have_fp = true;
   return launched();
@@ -386,8 +386,7 @@ int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
             v, slots, coords, (uint32_t)n, frame);
   VM_LAUNCH(vol, VM_K_ASSIGN, k_frame_compact, dim3(ncompact), dim3(256), stream, v, frame,
             vol->epoch, per);
-  VM_LAUNCH(vol, VM_K_IMPORT, k_import_copy, dim3(vol->grid_blocks), dim3(512), stream, v, tsdf,
-            weight, frame, rows);
+  VM_LAUNCH_W(vol, VM_K_IMPORT, k_import_copy, stream, v, tsdf, weight, frame, rows);
   vol->have_fp = false;
   return launched();
 }
@@ -469,8 +468,8 @@ int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys, int32_t*
 int vm_extract_backward(vm_volume* vol, const float* dL_dverts, float* dL_dtsdf,
                         hipStream_t stream) {
   if (!vol || !dL_dtsdf) return VM_ERR_ARG;
-  VM_LAUNCH(vol, VM_K_BACKWARD, k_bwd_tsdf, dim3(vol->grid_blocks), dim3(512), stream, vol->dev,
-            dL_dverts, 0, nullptr, 0u, dL_dtsdf);
+  VM_LAUNCH_W(vol, VM_K_BACKWARD, k_bwd_tsdf, stream, vol->dev, dL_dverts, 0, nullptr, 0u,
+              dL_dtsdf);
   return launched();
 }
 
@@ -478,8 +477,8 @@ int vm_extract_backward_slots(vm_volume* vol, const float* dL_dpos, const int32_
                               int64_t n_rows, float* dL_dtsdf, hipStream_t stream) {
   if (!vol || !dL_dpos || !dL_dtsdf || (rows && (n_rows < 0 || n_rows > (int64_t)kMaxBlocks)))
     return VM_ERR_ARG;
-  VM_LAUNCH(vol, VM_K_BACKWARD, k_bwd_tsdf, dim3(vol->grid_blocks), dim3(512), stream, vol->dev,
-            dL_dpos, 1, rows, (uint32_t)(rows ? n_rows : 0), dL_dtsdf);
+  VM_LAUNCH_W(vol, VM_K_BACKWARD, k_bwd_tsdf, stream, vol->dev, dL_dpos, 1, rows,
+              (uint32_t)(rows ? n_rows : 0), dL_dtsdf);
   return launched();
 }
 

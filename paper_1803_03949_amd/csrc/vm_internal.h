@@ -448,10 +448,16 @@ struct FuseSample {
   float dt;
 };
 
-__device__ inline FuseSample fuse_sample(const VolDev& v, const FrameParams& fp,
-                                         const float* __restrict__ depth, int gx, int gy,
-                                         int gz) {
-  FuseSample r{false, false, -1, 0.f};
+// The voxel's nearest pixel (-1 when it is behind the camera or outside the
+// image) and its camera depth z.
+struct FuseProj {
+  int pix;
+  float z;
+};
+
+__device__ inline FuseProj fuse_project(const VolDev& v, const FrameParams& fp, int gx, int gy,
+                                        int gz) {
+  FuseProj r{-1, 0.f};
   float X = (float)gx * v.s, Y = (float)gy * v.s, Z = (float)gz * v.s;
   float xc[3];
 #pragma unroll
@@ -467,16 +473,30 @@ __device__ inline FuseSample fuse_sample(const VolDev& v, const FrameParams& fp,
   float vv = fp.fy * (xc[1] / xc[2]) + fp.cy;
   float fu = floorf(u + 0.5f), fv = floorf(vv + 0.5f);
   if (!(fu >= 0.f && fu < (float)fp.W && fv >= 0.f && fv < (float)fp.H)) return r;
-  int pix = (int)fv * fp.W + (int)fu;
-  float D = depth[pix];
-  if (!depth_ok(D, fp.dmin, fp.dmax)) return r;
-  float sdf = (D - xc[2]) * v.inv_s;
+  r.pix = (int)fv * fp.W + (int)fu;
+  r.z = xc[2];
+  return r;
+}
+
+// The fusion sample from the projection and the pixel's depth D.
+__device__ inline FuseSample fuse_finish(const VolDev& v, const FrameParams& fp, FuseProj p,
+                                         float D) {
+  FuseSample r{false, false, -1, 0.f};
+  if (p.pix < 0 || !depth_ok(D, fp.dmin, fp.dmax)) return r;
+  float sdf = (D - p.z) * v.inv_s;
   if (sdf < -v.mu_v) return r;
   r.upd = true;
   r.clamped = sdf >= v.mu_v;
-  r.pixel = pix;
+  r.pixel = p.pix;
   r.dt = fminf(sdf, v.mu_v);
   return r;
+}
+
+__device__ inline FuseSample fuse_sample(const VolDev& v, const FrameParams& fp,
+                                         const float* __restrict__ depth, int gx, int gy,
+                                         int gz) {
+  const FuseProj p = fuse_project(v, fp, gx, gy, gz);
+  return fuse_finish(v, fp, p, p.pix >= 0 ? depth[p.pix] : 0.f);
 }
 
 __device__ inline float edge_param(float da, float db) {
@@ -495,7 +515,9 @@ __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
                                 const int32_t* __restrict__ coords, uint32_t n,
                                 uint32_t frame);
 __global__ void k_frame_compact(VolDev v, uint32_t frame, uint32_t epoch, uint32_t per_wg);
+template <int W>
 __global__ void k_fuse(VolDev v, FrameParams fp, const float* __restrict__ depth);
+template <int W>
 __global__ void k_import_copy(VolDev v, const float* __restrict__ tsdf,
                               const float* __restrict__ weight, uint32_t frame,
                               int32_t* __restrict__ rows);
@@ -513,6 +535,7 @@ __global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
 __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,
                                     uint64_t* __restrict__ keys, uint32_t vcap);
 __global__ void k_dl_write_triangles(VolDev v, int32_t* __restrict__ tris, uint32_t tcap);
+template <int W>
 __global__ void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv, int by_slot,
                            const int32_t* __restrict__ rows, uint32_t n_rows,
                            float* __restrict__ out);

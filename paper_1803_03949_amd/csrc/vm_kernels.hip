@@ -413,64 +413,112 @@ __device__ inline void init_cube(const VolDev& v, uint32_t idx, int l) {
 // ============================================================================
 // fusion (Eq. 2) and import
 // ============================================================================
-__global__ __launch_bounds__(512) void k_fuse(VolDev v, FrameParams fp,
-                                              const float* __restrict__ depth) {
+// One wave per collected block, eight voxels per lane (one column of the
+// block), so that many blocks are in flight per CU.  The list entry and
+// block key of the wave's next blocks are requested two and one blocks
+// ahead, so a block waits only for its TSDF, weights and depth samples.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
+                                                 const float* __restrict__ depth) {
   const uint32_t n = min(v.cnt->n_frame[fp.frame & 1], v.max_blocks);
-  const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
-  if (blockIdx.x == 0 && l == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
-  for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
-    const uint32_t i = it.i;
-    const uint32_t e = v.frame_list[i];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
+  ItemLoop it = item_loop(v, n, W, wave);
+  auto entry = [&](uint32_t i) -> uint32_t { return i < it.end ? v.frame_list[i] : kNone; };
+  auto key_of = [&](uint32_t e) -> uint64_t {
+    return e != kNone ? v.block_key[e & ~kNewFlag] : 0ull;
+  };
+  uint32_t e1 = uniform(entry(it.i));  // this block's entry and key
+  uint64_t k1 = key_of(e1);
+  uint32_t e2 = entry(it.i + it.step);  // the next block's entry
+  for (; it.i < it.end; it.i += it.step) {
+    const uint32_t e = e1;
+    const uint64_t key = ((uint64_t)uniform((uint32_t)(k1 >> 32)) << 32) | uniform((uint32_t)k1);
+    e1 = uniform(e2);
+    k1 = key_of(e1);
+    e2 = entry(it.i + 2 * it.step);
     if (e == kNone) continue;
+    const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
     const uint32_t idx = e & ~kNewFlag;
     const bool isnew = (e & kNewFlag) != 0;
     int bx, by, bz;
-    unpack_key(v.block_key[idx], bx, by, bz);
-    const size_t o = (size_t)idx * kVox + l;
-    float d = 0.f, w = 0.f;
+    unpack_key(key, bx, by, bz);
+    float d[8], w[8];
     if (isnew) {
-      init_cube(v, idx, l);
-      link_block(v, idx, l);
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) {
+        init_cube(v, idx, q + 64 * lz);
+        d[lz] = 0.f, w[lz] = 0.f;
+      }
+      link_block(v, idx, q);
     } else {
-      d = v.d[o], w = v.w[o];
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) {
+        d[lz] = v.d[(size_t)idx * kVox + q + 64 * lz];
+        w[lz] = v.w[(size_t)idx * kVox + q + 64 * lz];
+      }
     }
-    const FuseSample fs = fuse_sample(v, fp, depth, 8 * bx + lx, 8 * by + ly, 8 * bz + lz);
-    if (fs.upd) {
-      float num = d * w;
-      num = num + fs.dt;
-      const float den = w + 1.0f;
-      d = num / den;
-      w = den;
+    // every voxel's depth sample is requested before any is used (a voxel
+    // that projects nowhere reads pixel 0 and ignores it)
+    FuseProj pr[8];
+    float D[8];
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      pr[lz] = fuse_project(v, fp, 8 * bx + lx, 8 * by + ly, 8 * bz + lz);
+      D[lz] = depth[pr[lz].pix >= 0 ? pr[lz].pix : 0];
     }
-    if (fs.upd || isnew) {
-      v.d[o] = d;
-      v.w[o] = w;
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      const FuseSample fs = fuse_finish(v, fp, pr[lz], D[lz]);
+      const size_t o = (size_t)idx * kVox + q + 64 * lz;
+      if (fs.upd) {
+        float num = d[lz] * w[lz];
+        num = num + fs.dt;
+        const float den = w[lz] + 1.0f;
+        v.d[o] = num / den;
+        v.w[o] = den;
+      } else if (isnew) {
+        v.d[o] = d[lz];
+        v.w[o] = w[lz];
+      }
     }
-    if (l == 0) v.st_frame[idx] = fp.frame;
+    if (q == 0) v.st_frame[idx] = fp.frame;
   }
 }
 
-__global__ __launch_bounds__(512) void k_import_copy(VolDev v, const float* __restrict__ tsdf,
-                                                     const float* __restrict__ weight,
-                                                     uint32_t frame, int32_t* __restrict__ rows) {
+// One wave per imported block, eight voxels per lane: the caller's rows are
+// read first, then the new block is initialised and linked while they
+// arrive.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* __restrict__ tsdf,
+                                                        const float* __restrict__ weight,
+                                                        uint32_t frame, int32_t* __restrict__ rows) {
   const uint32_t n = min(v.cnt->n_frame[frame & 1], v.max_blocks);
-  const int l = threadIdx.x;
-  if (blockIdx.x == 0 && l == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
-  for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
-    const uint32_t i = it.i;
-    const uint32_t e = v.frame_list[i];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
+  for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
+    const uint32_t e = uniform(v.frame_list[it.i]);
+    const uint32_t row = uniform(v.frame_src[it.i]);
     if (e == kNone) continue;
+    const int q = fresh_lane();
     const uint32_t idx = e & ~kNewFlag;
-    if (e & kNewFlag) {
-      init_cube(v, idx, l);
-      link_block(v, idx, l);
+    float d[8], w[8];
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      d[lz] = tsdf[(size_t)row * kVox + q + 64 * lz];
+      w[lz] = weight[(size_t)row * kVox + q + 64 * lz];
     }
-    const uint32_t row = v.frame_src[i];
-    const size_t src = (size_t)row * kVox + l;
-    const size_t o = (size_t)idx * kVox + l;
-    v.d[o] = tsdf[src];
-    v.w[o] = weight[src];
-    if (l == 0) {
+    if (e & kNewFlag) {
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) init_cube(v, idx, q + 64 * lz);
+      link_block(v, idx, q);
+    }
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      v.d[(size_t)idx * kVox + q + 64 * lz] = d[lz];
+      v.w[(size_t)idx * kVox + q + 64 * lz] = w[lz];
+    }
+    if (q == 0) {
       v.st_frame[idx] = frame;
       if (rows) rows[row] = (int32_t)idx;
     }
@@ -1224,80 +1272,170 @@ __global__ __launch_bounds__(256) void k_dl_write_triangles(VolDev v, int32_t* _
 // backward passes
 // ============================================================================
 
-// dL/d(TSDF) at every voxel of every block: gather over the at most six
-// edges incident to the voxel (its own three, and the three owned by its
-// -x/-y/-z neighbours), in a fixed order.
-__global__ __launch_bounds__(512) void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv,
-                                                  int by_slot, const int32_t* __restrict__ rows,
-                                                  uint32_t n_rows, float* __restrict__ out) {
-  __shared__ float sd[1000];  // TSDF at local -1..8
-  __shared__ int32_t snb[27];
+// dL/d(TSDF) of every voxel of the listed blocks, one wave per block and
+// eight voxels per lane.  A voxel's gradient sums, in a fixed order, the
+// contributions of the at most six edges incident to it: per axis its own
+// edge (the voxel is the first end point), then the edge owned by the voxel
+// one step back (the voxel is the second); each contribution is the vertex
+// gradient along the axis times s times dt/dd.  Only edges that carry a
+// vertex contribute, about one in a hundred: the block's 8-bit counts and
+// those of the three back faces are staged in LDS, the (voxel, edge) pairs
+// with a vertex are listed, and slots, end-point TSDF values and upstream
+// gradients are fetched for the listed pairs alone.  The list is worked
+// through layer by layer when it would overflow (dense sign fields).
+constexpr int kGradCap = 384;  // listed pairs per step; one layer has at most 6 * 64
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv,
+                                                     int by_slot, const int32_t* __restrict__ rows,
+                                                     uint32_t n_rows, float* __restrict__ out) {
+  __shared__ __align__(4) uint8_t ser_all[W][3 * kVox + 3 * 64];  // own [a][l], back faces [a][64]
+  __shared__ uint16_t slist_all[W][kGradCap];  // lane | lz << 6 | k << 9 (k = 2a + back)
+  __shared__ float sc_all[W][kGradCap];        // contribution of each listed pair
+  __shared__ uint8_t sf_all[W][kGradCap];      // whether it contributes
+  __shared__ int32_t snb_all[W][27];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint8_t* ser = ser_all[wave];
+  uint16_t* slist = slist_all[wave];
+  float* sc = sc_all[wave];
+  uint8_t* sf = sf_all[wave];
+  int32_t* snb = snb_all[wave];
   const uint32_t nb_all = min(v.cnt->n_blocks, v.max_blocks);
   const uint32_t n = rows ? n_rows : nb_all;
   const uint32_t nv = v.cnt->dl_nv;
-  const int l = threadIdx.x, lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
-  const int lc[3] = {lx, ly, lz};
-  // upstream gradient row of the vertex on edge e (slot s), -1 if none
-  auto grad_row = [&](size_t e) -> int32_t {
-    const int32_t s = v.evtx[e];
-    if (s < 0 || v.eref[e] == 0) return -1;
-    if (by_slot) return s;
-    const int32_t r = v.vdl[s];
-    return r >= 0 && (uint32_t)r < nv ? r : -1;
-  };
-  for (ItemLoop it = item_loop(v, n, 1, 0); it.i < it.end; it.i += it.step) {
-    const int32_t idx = rows ? rows[it.i] : (int32_t)it.i;
+  const uint64_t below = lanes_below();
+  for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
+    const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
+    const int32_t idx = rows ? (int32_t)uniform((uint32_t)rows[it.i]) : (int32_t)it.i;
+    float* o = out + (size_t)it.i * kVox;
     if (idx < 0 || (uint32_t)idx >= nb_all) {
-      out[(size_t)it.i * kVox + l] = 0.f;
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) o[q + 64 * lz] = 0.f;
       continue;
     }
-    if (l < 27) snb[l] = v.nbr[(size_t)idx * 27 + l];
-    __syncthreads();
-    for (int j = l; j < 1000; j += 512) {
-      const int x = j % 10 - 1, y = (j / 10) % 10 - 1, z = j / 100 - 1;
-      const int nb = snb[nbr_dir(x < 0 ? -1 : (x > 7 ? 1 : 0), y < 0 ? -1 : (y > 7 ? 1 : 0),
-                                 z < 0 ? -1 : (z > 7 ? 1 : 0))];
-      sd[j] = nb >= 0 ? v.d[(size_t)nb * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)] : 0.f;
-    }
-    __syncthreads();
-    const int c = (lx + 1) + 10 * (ly + 1) + 100 * (lz + 1);
-    const int step[3] = {1, 10, 100};
-    float acc = 0.f;
+    // the block's counts (3 x 512 bytes, six words per lane) and its
+    // neighbours; then the back faces: the -a neighbour's counts at
+    // coordinate 7 along a, indexed by the two other coordinates
+    const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
+    const uint32_t* er32 = reinterpret_cast<const uint32_t*>(v.eref + (size_t)idx * 3 * kVox);
+    uint32_t ownw[6];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      // the edge this voxel owns: it is the first end point
-      int32_t r = grad_row(((size_t)idx * 3 + a) * kVox + l);
-      if (r >= 0) {
-        const float da = sd[c], db = sd[c + step[a]];
-        if (da != db) {
-          const float g = dL_dv[3 * (size_t)r + a] * v.s;
-          const float den = (da - db) * (da - db);
-          acc = acc + g * (-db / den);
+    for (int j = 0; j < 6; ++j) ownw[j] = er32[q + 64 * j];
+    if (q < 27) snb[q] = mynb;
+    wave_sync();
+    const int32_t bnx = snb[nbr_dir(-1, 0, 0)], bny = snb[nbr_dir(0, -1, 0)],
+                  bnz = snb[nbr_dir(0, 0, -1)];
+    const uint8_t fx = bnx >= 0 ? v.eref[((size_t)bnx * 3 + 0) * kVox + 7 + 8 * lx + 64 * ly] : 0;
+    const uint8_t fy = bny >= 0 ? v.eref[((size_t)bny * 3 + 1) * kVox + lx + 56 + 64 * ly] : 0;
+    const uint8_t fz = bnz >= 0 ? v.eref[((size_t)bnz * 3 + 2) * kVox + 448 + q] : 0;
+    uint32_t* ser32 = reinterpret_cast<uint32_t*>(ser);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ser32[q + 64 * j] = ownw[j];
+    ser[3 * kVox + q] = fx;
+    ser[3 * kVox + 64 + q] = fy;
+    ser[3 * kVox + 128 + q] = fz;
+    wave_sync();
+    // which incident edges of the lane's eight voxels carry a vertex
+    uint64_t act = 0;  // bit 6 * lz + k
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      const int l = q + 64 * lz;
+      const uint32_t r0 = ser[l], r1 = ser[kVox + l], r2 = ser[2 * kVox + l];
+      const uint32_t b0 = lx > 0 ? ser[l - 1] : ser[3 * kVox + ly + 8 * lz];
+      const uint32_t b1 = ly > 0 ? ser[kVox + l - 8] : ser[3 * kVox + 64 + lx + 8 * lz];
+      const uint32_t b2 = lz > 0 ? ser[2 * kVox + l - 64] : ser[3 * kVox + 128 + q];
+      const uint64_t m = (uint64_t)(r0 != 0) | (uint64_t)(b0 != 0) << 1 | (uint64_t)(r1 != 0) << 2 |
+                         (uint64_t)(b1 != 0) << 3 | (uint64_t)(r2 != 0) << 4 |
+                         (uint64_t)(b2 != 0) << 5;
+      act |= m << (6 * lz);
+    }
+    uint32_t cnt = 0;
+    int lz0 = 0;
+    // contributions of the listed pairs, then the sums of layers [lz0, lz1)
+    auto flush = [&](int lz1) {
+      wave_sync();
+      for (uint32_t i0 = 0; i0 < cnt; i0 += 64) {
+        const uint32_t i = i0 + q;
+        if (i >= cnt) continue;
+        const uint32_t e = slist[i];
+        const int p = (int)(e & 63u), pz = (int)((e >> 6) & 7u), k = (int)(e >> 9);
+        const int a = k >> 1, back = k & 1;
+        const int pc = a == 0 ? (p & 7) : (a == 1 ? (p >> 3) : pz);
+        const int lstep = a == 0 ? 1 : (a == 1 ? 8 : 64);
+        const int l = p + 64 * pz;
+        // owner voxel (block ob, local ol) and far end point (fb, fl)
+        int32_t ob = idx, fb = idx;
+        int ol = l, fl = l;
+        if (!back) {
+          if (pc < 7) fl = l + lstep;
+          else fb = snb[nbr_dir(a == 0, a == 1, a == 2)], fl = l - 7 * lstep;
+        } else {
+          if (pc > 0) ol = l - lstep;
+          else ob = snb[nbr_dir(-(a == 0), -(a == 1), -(a == 2))], ol = l + 7 * lstep;
         }
-      }
-      // the edge its -a neighbour owns: it is the second end point
-      const int back = lc[a] - 1;
-      const int dir = nbr_dir(a == 0 && back < 0 ? -1 : 0, a == 1 && back < 0 ? -1 : 0,
-                              a == 2 && back < 0 ? -1 : 0);
-      const int32_t nb = snb[dir];
-      if (nb >= 0) {
-        // local index of the owner: one step back along a, wrapping into
-        // the -a neighbour block when this voxel is on the block's face
-        const int lstep = a == 0 ? 1 : a == 1 ? 8 : 64;
-        const int ol = back < 0 ? l + 7 * lstep : l - lstep;
-        r = grad_row(((size_t)nb * 3 + a) * kVox + ol);
-        if (r >= 0) {
-          const float da = sd[c - step[a]], db = sd[c];
-          if (da != db) {
+        bool ok = false;
+        float cval = 0.f;
+        if (ob >= 0 && fb >= 0) {
+          const int32_t s = v.evtx[((size_t)ob * 3 + a) * kVox + ol];
+          const float da = v.d[(size_t)ob * kVox + ol], db = v.d[(size_t)fb * kVox + fl];
+          int32_t r = -1;
+          if (s >= 0) {
+            if (by_slot) {
+              r = s;
+            } else {
+              r = v.vdl[s];
+              if (!(r >= 0 && (uint32_t)r < nv)) r = -1;
+            }
+          }
+          if (r >= 0 && da != db) {
             const float g = dL_dv[3 * (size_t)r + a] * v.s;
             const float den = (da - db) * (da - db);
-            acc = acc + g * (da / den);
+            cval = back ? g * (da / den) : g * (-db / den);
+            ok = true;
           }
         }
+        sc[i] = cval;
+        sf[i] = ok;
+      }
+      wave_sync();
+      uint32_t pos = 0;  // the list order, replayed
+      for (int lz = lz0; lz < lz1; ++lz) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const bool on = (act >> (6 * lz + k)) & 1u;
+          const uint64_t b = __ballot(on);
+          if (on) {
+            const uint32_t i = pos + (uint32_t)__popcll(b & below);
+            if (sf[i]) acc = acc + sc[i];
+          }
+          pos += (uint32_t)__popcll(b);
+        }
+        o[q + 64 * lz] = acc;
+      }
+      wave_sync();
+    };
+    for (int lz = 0; lz < 8; ++lz) {
+      uint64_t bk[6];
+      uint32_t lc = 0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        bk[k] = __ballot((act >> (6 * lz + k)) & 1u);
+        lc += (uint32_t)__popcll(bk[k]);
+      }
+      if (cnt + lc > (uint32_t)kGradCap) {
+        flush(lz);
+        cnt = 0;
+        lz0 = lz;
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if ((bk[k] >> q) & 1u)
+          slist[cnt + (uint32_t)__popcll(bk[k] & below)] = (uint16_t)(q | lz << 6 | k << 9);
+        cnt += (uint32_t)__popcll(bk[k]);
       }
     }
-    out[(size_t)it.i * kVox + l] = acc;
-    __syncthreads();
+    flush(8);
   }
 }
 
@@ -1375,5 +1513,14 @@ template __global__ void k_vertices<8>(VolDev);
 template __global__ void k_triangles<2>(VolDev);
 template __global__ void k_triangles<4>(VolDev);
 template __global__ void k_triangles<8>(VolDev);
+template __global__ void k_fuse<2>(VolDev, FrameParams, const float*);
+template __global__ void k_fuse<4>(VolDev, FrameParams, const float*);
+template __global__ void k_fuse<8>(VolDev, FrameParams, const float*);
+template __global__ void k_import_copy<2>(VolDev, const float*, const float*, uint32_t, int32_t*);
+template __global__ void k_import_copy<4>(VolDev, const float*, const float*, uint32_t, int32_t*);
+template __global__ void k_import_copy<8>(VolDev, const float*, const float*, uint32_t, int32_t*);
+template __global__ void k_bwd_tsdf<2>(VolDev, const float*, int, const int32_t*, uint32_t, float*);
+template __global__ void k_bwd_tsdf<4>(VolDev, const float*, int, const int32_t*, uint32_t, float*);
+template __global__ void k_bwd_tsdf<8>(VolDev, const float*, int, const int32_t*, uint32_t, float*);
 
 }  // namespace vm
