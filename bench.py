@@ -91,8 +91,8 @@ def algorithmic_bytes(tot, npix):
         "collect": 4 * npix * tot["frames"],
         "fuse": 4 * npix * tot["frames"] + 8192 * tot["frame_blocks"],
         "classify": 5632 * tot["dirty_blocks"],
-        "vertices": 8704 * tot["vertex_blocks"] + 5 * tot["updated_vertices"]
-        + 13 * tot["new_vertices"] + 12 * tot["freed_vertices"],
+        "vertices": 4096 * tot["vertex_blocks"] + 5 * tot["updated_vertices"]
+        + 13 * tot["new_vertices"] + 13 * tot["freed_vertices"],
         "triangles": 96 * tot["changed_cubes"],
     }
 

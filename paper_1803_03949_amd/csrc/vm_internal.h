@@ -123,7 +123,8 @@ struct VolDev {
   float* w;                   // [B][512]
   uint8_t* tprev;             // [B][512]
   uint8_t* tcur;              // [B][512]
-  int32_t* evtx;              // [B][3][512] vertex slot of the edge, -1 if none
+  int32_t* evtx;              // [B][3][512] vertex slot of the edge: valid where eref > 0
+                              // (-1 after a failed allocation), stale elsewhere
   float* et;                  // [B][3][512] t of the edge's vertex
   uint8_t* eref;              // [B][3][512] reference count of the edge's vertex
   uint64_t* chg;              // [B][8] by dirty-list position and z layer: cubes whose triangles changed

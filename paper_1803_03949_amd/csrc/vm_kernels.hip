@@ -400,14 +400,14 @@ __device__ inline void link_block(const VolDev& v, uint32_t idx, int l) {
   v.nbr[(size_t)nb * 27 + (26 - l)] = (int32_t)idx;
 }
 
+// A new block's cube l: no type, and its three edges carry no vertex (a
+// count of zero; the slot is meaningful only under a nonzero count, so it
+// is not written).
 __device__ inline void init_cube(const VolDev& v, uint32_t idx, int l) {
   const size_t o = (size_t)idx * kVox + l;
   v.tprev[o] = 0;
   v.tcur[o] = 0;
-  for (int a = 0; a < 3; ++a) {
-    v.evtx[((size_t)idx * 3 + a) * kVox + l] = -1;
-    v.eref[((size_t)idx * 3 + a) * kVox + l] = 0;
-  }
+  for (int a = 0; a < 3; ++a) v.eref[((size_t)idx * 3 + a) * kVox + l] = 0;
 }
 
 // ============================================================================
@@ -823,18 +823,19 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
     const Seg& g = v.vseg[sg];
     const uint32_t head = g.head, count = g.count, hwm = g.hwm;
-    // which of the voxel's edges have a vertex (bit 3*lz + a); the slots
-    // themselves are read again only for the vertices that get freed
+    // which of the voxel's edges have a vertex (bit 3*lz + a): those with a
+    // nonzero count; the slots themselves are read only for the vertices
+    // that get freed
     uint32_t has_slot = 0;
     {
-      int32_t es[24];
+      uint32_t er[24];
 #pragma unroll
       for (int lz = 0; lz < 8; ++lz)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) es[3 * lz + a] = v.evtx[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
+        for (int a = 0; a < 3; ++a) er[3 * lz + a] = v.eref[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
 #pragma unroll
       for (int k = 23; k >= 0; --k)  // shifted in, so no per-bit mask constants
-        has_slot = (has_slot << 1) | (uint32_t)(es[k] >= 0);
+        has_slot = (has_slot << 1) | (uint32_t)(er[k] != 0);
     }
     if (q < 27) snb[q] = mynb;
     wave_sync();
@@ -945,7 +946,6 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     auto free_vertex = [&](size_t eo, int32_t s, uint32_t k) {
       v.vring[gbase + ring_pos(rtail, fbase + k, gsize)] = (uint32_t)s;
       v.vowner[s] = kNone;
-      v.evtx[eo] = -1;
       v.eref[eo] = 0;
     };
     if (nwork <= (uint32_t)kWorkCap) {
@@ -967,7 +967,10 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
           if (!has) {
             const uint32_t ns = new_slot(myk);
             if (ns == kNone) {
+              // pool exhausted: the edge stays without a vertex, and its
+              // triangles will reference none
               atomicOr(&v.cnt->error, kErrVertices);
+              v.evtx[eo] = -1;
               continue;
             }
             v.evtx[eo] = (int32_t)ns;
@@ -1003,6 +1006,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
               const uint32_t ns = new_slot(rank++);
               if (ns == kNone) {
                 atomicOr(&v.cnt->error, kErrVertices);
+                v.evtx[eo] = -1;
                 continue;
               }
               v.evtx[eo] = (int32_t)ns;
