@@ -39,11 +39,11 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 5803.8, "write_kib": 710.3, "source_sha1": "6e1c151cc034"},
-    "fuse": {"fetch_kib": 12366.1, "write_kib": 14724.7, "source_sha1": "db66a28e5bab"},
-    "classify": {"fetch_kib": 26952.6, "write_kib": 3889.5, "source_sha1": "cdc7fa06f21a"},
-    "vertices": {"fetch_kib": 30692.0, "write_kib": 9920.0, "source_sha1": "661bdb0572f6"},
-    "triangles": {"fetch_kib": 5182.4, "write_kib": 3631.5, "source_sha1": "4b7e0e805794"},
+    "collect": {"fetch_kib": 5928.6, "write_kib": 773.2, "source_sha1": "e188ea6d96a7"},
+    "fuse": {"fetch_kib": 11883.7, "write_kib": 13146.3, "source_sha1": "5ed07757d33f"},
+    "classify": {"fetch_kib": 27066.6, "write_kib": 3919.0, "source_sha1": "efe3f34b9cd7"},
+    "vertices": {"fetch_kib": 20649.3, "write_kib": 9229.3, "source_sha1": "e532706d785b"},
+    "triangles": {"fetch_kib": 5206.7, "write_kib": 3631.5, "source_sha1": "fcad3041d068"},
 }
 
 
@@ -294,12 +294,11 @@ def grad_scene_fwd_bwd(dev):
             "note": "includes the host synchronisation of the mesh download"}
 
 
-def batched(args, dev):
+def batch_workload(dev):
+    """The 64 sphere volumes of the batched workload, on the device."""
     import torch
 
     import scenes
-    from paper_1803_03949_amd.batch import (BatchMesher, PlainMesher, autotune,
-                                            default_space, sphere_loss_grad)
 
     t0 = time.time()
     vols = scenes.batch_volumes(seed=5, n=64, voxel_m=0.008)
@@ -317,10 +316,20 @@ def batched(args, dev):
                            device=dev)
     radii = torch.tensor([v.meta["target_radius"] for v in vols], dtype=torch.float32,
                          device=dev)
-    N = int(sum(sizes))
-    log(f"64 volumes, {N} blocks (sizes {min(sizes)}..{max(sizes)}), built in "
+    log(f"64 volumes, {sum(sizes)} blocks (sizes {min(sizes)}..{max(sizes)}), built in "
         f"{time.time() - t0:.1f}s")
+    return coords, tsdf, weight, centers, radii
 
+
+def batched(args, dev):
+    import torch
+
+    from paper_1803_03949_amd.batch import (BatchMesher, PlainMesher, autotune,
+                                            default_space, sphere_loss_grad)
+
+    coords, tsdf, weight, centers, radii = batch_workload(dev)
+    sizes = [len(c) for c in coords]
+    N = int(sum(sizes))
     b = BatchMesher(0.008, coords, tsdf, weight, sphere_loss_grad(centers, radii))
     space = default_space() if args.tune_full else \
         [p for p in default_space() if p["block_groups_per_cu"] == 8]
@@ -371,6 +380,21 @@ def batched(args, dev):
     return out
 
 
+def batched_replays(args, dev):
+    """The batched step alone (default mapping, graph replays), for profiling."""
+    import torch
+
+    from paper_1803_03949_amd.batch import BatchMesher, sphere_loss_grad
+
+    coords, tsdf, weight, centers, radii = batch_workload(dev)
+    b = BatchMesher(0.008, coords, tsdf, weight, sphere_loss_grad(centers, radii))
+    b.capture()
+    ms = median_ms(b.replay, args.batch_reps)
+    n = int(sum(len(c) for c in coords))
+    log(f"batched fwd+bwd {ms:.3f} ms ({n / ms * 1e3:.3e} blocks/s), default mapping")
+    return {"batched_ms": ms, "blocks": n, "batched_blocks_per_s": n / ms * 1e3}
+
+
 def cpu_baseline(frames, seq, n=3):
     import oracle
     import scenes
@@ -399,6 +423,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="headline workload only (for profiling runs)")
     ap.add_argument("--tune-full", action="store_true")
+    ap.add_argument("--only", choices=["batch", "fine"],
+                    help="profiling: run only this workload (batch: graph replays of the 64 "
+                         "volumes with the default mapping; fine: the 4 mm sequence) and print "
+                         "its figures")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -422,6 +450,12 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe_mib} MiB read + written")
         del a, b
+    if args.only == "batch":
+        print(json.dumps(batched_replays(args, dev)))
+        return
+    if args.only == "fine":
+        print(json.dumps(room_fine(args, dev)))
+        return
     head, frames, seq = room_fusion(args, dev)
     extras = {}
     if not args.no_extras:
