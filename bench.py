@@ -198,6 +198,58 @@ def room_fusion(args, dev):
     return fields, frames, seq
 
 
+def mesh_memory(args, dev, frames, seq):
+    """Mesh size over the 8 mm room sequence (Sec. VI-B, Table I): live
+    vertices V and triangles F every 10 frames, against a triangle soup that
+    stores three vertices per triangle (the comparison the paper draws), and
+    the bytes per cube of this layout."""
+    import ctypes
+
+    import torch
+
+    import scenes
+    from paper_1803_03949_amd import Volume, binding
+
+    depth = torch.from_numpy(np.stack(frames)).to(dev)
+    vol = Volume(seq.voxel_m, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23, device=dev)
+    series = []
+    for k in range(len(frames)):
+        vol.integrate(depth[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        vol.extract()
+        vol.gc()
+        if (k + 1) % 10 == 0 or k + 1 == len(frames):
+            st = vol.status()
+            nv = st["vertex_slots"] - st["free_vertex_slots"]
+            series.append({"frame": k + 1, "blocks": st["blocks"], "vertices": nv,
+                           "triangles": st["triangles"], "soup_vertices": 3 * st["triangles"]})
+
+    # bytes per block and per vertex of capacity, from the workspace sizing
+    def ws(**kw):
+        c = dict(voxel_m=0.008, trunc_vox=4.0, refine_eps_vox=0.5, hash_log2=20,
+                 max_blocks=1 << 17, max_vertices=1 << 23, hash_mode=0, batch_volumes=0)
+        c.update(kw)
+        n = ctypes.c_size_t()
+        binding.lib().vm_volume_bytes(ctypes.byref(binding.vm_config(**c)), ctypes.byref(n))
+        return n.value
+    per_block = (ws(max_blocks=(1 << 17) + 4096) - ws()) / 4096
+    per_vertex = (ws(max_vertices=(1 << 23) + 65536) - ws()) / 65536
+    last = series[-1]
+    in_use = last["blocks"] * per_block + last["vertices"] * per_vertex
+    out = {"series": series, "vertices": last["vertices"], "triangles": last["triangles"],
+           "soup_vertices": last["soup_vertices"],
+           "soup_over_shared": last["soup_vertices"] / max(1, last["vertices"]),
+           "triangles_per_vertex": last["triangles"] / max(1, last["vertices"]),
+           "bytes_per_block": per_block, "bytes_per_cube": per_block / 512,
+           "bytes_per_vertex": per_vertex, "in_use_MB": in_use / 1e6,
+           "paper_bytes_per_cube": {"as_built": 56, "minimised": 24}}
+    log(f"mesh memory: V {last['vertices']}, F {last['triangles']}, soup 3F "
+        f"{last['soup_vertices']} ({out['soup_over_shared']:.2f}x V), "
+        f"{out['bytes_per_cube']:.1f} B per cube of capacity")
+    del vol, depth
+    torch.cuda.empty_cache()
+    return out
+
+
 def sphere_extract(dev):
     import torch
 
@@ -459,6 +511,7 @@ def main():
     head, frames, seq = room_fusion(args, dev)
     extras = {}
     if not args.no_extras:
+        extras["mesh_memory_8mm"] = mesh_memory(args, dev, frames, seq)
         extras["sphere_512_blocks"] = sphere_extract(dev)
         log(f"sphere: {extras['sphere_512_blocks']}")
         extras["grad_scene_128"] = grad_scene_fwd_bwd(dev)

@@ -237,3 +237,29 @@ def test_wide_truncation_band():
         g.extract()
         o.extract()
     compare_all(g, o)
+
+
+def test_mesh_size_counters_match_oracle():
+    """The counters the mesh-memory report reads (status triangles, live
+    vertex slots, blocks) against the oracle's mesh after every frame: the
+    report's V and F are these numbers (Sec. VI-B compares vertex counts)."""
+    seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=0.03)
+    g = new_volume(seq.voxel_m)
+    o = oracle.OracleVolume(seq.voxel_m, 4.0, 0.5)
+    for k in range(0, 30, 3):
+        depth = seq.frame(k)
+        g.integrate(to_dev(depth)[0], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        o.integrate(depth, scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        g.extract()
+        o.extract()
+        g.gc()
+        o.gc()
+        st = g.status()
+        nv = len(o.vertices()["keys"])
+        nt = len(o.triangles())
+        assert st["vertex_slots"] - st["free_vertex_slots"] == nv, k
+        assert st["triangles"] == nt, k
+        assert st["blocks"] == len(o.blocks()["coords"]), k
+        # a vertex count above half the triangle count is what a shared-vertex
+        # mesh must show (Sec. VI-B); a soup would hold 3F
+        assert nt / 2 <= nv < 3 * nt, k
