@@ -235,16 +235,22 @@ def mesh_memory(args, dev, frames, seq):
     per_vertex = (ws(max_vertices=(1 << 23) + 65536) - ws()) / 65536
     last = series[-1]
     in_use = last["blocks"] * per_block + last["vertices"] * per_vertex
+    # vertex normals of the final mesh (download first: they follow its rows)
+    verts, _, _ = vol.download(with_keys=False)
+    normals_ms = median_ms(vol.download_normals, 20)
+    assert len(vol.download_normals()) == len(verts)
     out = {"series": series, "vertices": last["vertices"], "triangles": last["triangles"],
            "soup_vertices": last["soup_vertices"],
            "soup_over_shared": last["soup_vertices"] / max(1, last["vertices"]),
            "triangles_per_vertex": last["triangles"] / max(1, last["vertices"]),
            "bytes_per_block": per_block, "bytes_per_cube": per_block / 512,
            "bytes_per_vertex": per_vertex, "in_use_MB": in_use / 1e6,
-           "paper_bytes_per_cube": {"as_built": 56, "minimised": 24}}
+           "paper_bytes_per_cube": {"as_built": 56, "minimised": 24},
+           "normals_ms": normals_ms, "normals_per_s": len(verts) / normals_ms * 1e3}
     log(f"mesh memory: V {last['vertices']}, F {last['triangles']}, soup 3F "
         f"{last['soup_vertices']} ({out['soup_over_shared']:.2f}x V), "
-        f"{out['bytes_per_cube']:.1f} B per cube of capacity")
+        f"{out['bytes_per_cube']:.1f} B per cube of capacity; normals of {len(verts)} vertices in "
+        f"{normals_ms:.3f} ms")
     del vol, depth
     torch.cuda.empty_cache()
     return out

@@ -244,6 +244,21 @@ int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys,
                      int32_t* tris, int64_t vcap, int64_t tcap, int64_t* nv,
                      int64_t* nt, hipStream_t stream);
 
+/* Unit normals of the vertices of the last vm_download_mesh, in its row
+ * order: normals[cap][3] FP32 (device).  Sec. IV keeps a normal in every
+ * vertex record without fixing how it is formed; here it is the TSDF
+ * gradient interpolated along the vertex's edge at its parameter t and
+ * normalised, pointing to increasing TSDF (the outside, the side the
+ * triangles face).  The gradient at a voxel is, per axis, the central
+ * difference over its two neighbours when both are observed (allocated
+ * block, weight > 0), the one-sided difference when one is, 0 when neither
+ * is; a vertex whose interpolated gradient vanishes gets (0, 0, 0).
+ * Call after vm_download_mesh and before the volume changes
+ * (VM_ERR_ARG otherwise, or for a NULL volume); VM_ERR_CAPACITY (nothing
+ * written) when cap is below the downloaded vertex count.  Stream-ordered;
+ * does not synchronise. */
+int vm_download_normals(vm_volume* vol, float* normals, int64_t cap, hipStream_t stream);
+
 /* Gradient of a loss through the vertex positions of the last download to
  * the fused TSDF, with connectivity fixed: for the vertex on edge (g, a),
  * dv/dt = s * e_a, dt/dd(g) = -d(g+a)/(d(g)-d(g+a))^2 and

@@ -71,6 +71,7 @@ def lib():
             "orc_edge_ends": (None, [P]),
             "orc_grad_tsdf64": (None, [vp, P, P]),
             "orc_positions64": (None, [vp, i, i, i, d, P]),
+            "orc_normals64": (None, [vp, P, P]),
             "orc_grad_fusion64": (None, [vp, P, P, P]),
             "orc_positions64_depth": (None, [vp, i, d, P]),
             "orc_num_fused": (i, [vp]),
@@ -242,6 +243,17 @@ class OracleVolume:
         out = np.zeros((n, 512), np.float64)
         lib().orc_grad_tsdf64(self._h, _ptr(dL_dv), _ptr(out))
         return out
+
+    def normals64(self):
+        """FP64 unit normals (n_live, 3) of the live vertices in key order, and
+        the gradient length before normalisation (n_live,): the TSDF gradient
+        (central differences over observed voxels, one-sided at the edge of
+        the observed region) interpolated along the vertex's edge at t."""
+        n = lib().orc_num_vertices(self._h, 1)
+        out = np.zeros((n, 3), np.float64)
+        ln = np.zeros(n, np.float64)
+        lib().orc_normals64(self._h, _ptr(out), _ptr(ln))
+        return out, ln
 
     def positions64(self, voxel=(0, 0, 0), delta: float = 0.0) -> np.ndarray:
         nv = lib().orc_num_vertices(self._h, 1)

@@ -860,6 +860,49 @@ void orc_positions64(void* h, int gx, int gy, int gz, double delta, double* pos)
   }
 }
 
+// Vertex normals.  READING: Sec. IV keeps a normal in every vertex record
+// but does not say how it is formed.  Here: the TSDF gradient at a voxel by
+// central differences over observed neighbours (allocated block, weight >
+// 0), per axis (d(x+e) - d(x-e)) / 2, one-sided d(x+e) - d(x) or
+// d(x) - d(x-e) when only one neighbour is observed, 0 when neither is; the
+// gradient is interpolated along the vertex's edge at its parameter t (the
+// stored FP32 value) and normalised, 0 when it vanishes.  It points to
+// increasing TSDF, the outside of the surface.  out: n_live*3, key order;
+// len: the length before normalisation, n_live.
+static void tsdf_gradient64(Volume& v, int gx, int gy, int gz, double g[3]) {
+  float d0 = 0, w0 = 0;
+  voxel(v, gx, gy, gz, d0, w0);
+  for (int i = 0; i < 3; ++i) {
+    const int ex = i == 0, ey = i == 1, ez = i == 2;
+    float dp = 0, wp = 0, dm = 0, wm = 0;
+    const bool hp = voxel(v, gx + ex, gy + ey, gz + ez, dp, wp) && wp > 0.f;
+    const bool hm = voxel(v, gx - ex, gy - ey, gz - ez, dm, wm) && wm > 0.f;
+    if (hp && hm) g[i] = ((double)dp - (double)dm) / 2.0;
+    else if (hp) g[i] = (double)dp - (double)d0;
+    else if (hm) g[i] = (double)d0 - (double)dm;
+    else g[i] = 0.0;
+  }
+}
+
+void orc_normals64(void* h, double* out, double* len) {
+  Volume& v = *(Volume*)h;
+  size_t i = 0;
+  for (auto& kv : v.verts) {
+    if (kv.second.ref <= 0) continue;
+    const EdgeKey& k = kv.first;
+    const int ox = k.axis == 0, oy = k.axis == 1, oz = k.axis == 2;
+    double g0[3], g1[3], n[3];
+    tsdf_gradient64(v, k.x, k.y, k.z, g0);
+    tsdf_gradient64(v, k.x + ox, k.y + oy, k.z + oz, g1);
+    const double t = kv.second.t;
+    for (int j = 0; j < 3; ++j) n[j] = (1.0 - t) * g0[j] + t * g1[j];
+    const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int j = 0; j < 3; ++j) out[3 * i + j] = l > 0.0 ? n[j] / l : 0.0;
+    len[i] = l;
+    ++i;
+  }
+}
+
 // Backward of the last fusion (Eq. 2), all branches held fixed.
 // dL_dd1: dL/d(fused TSDF), block export order (n*512).  Writes dL/d(TSDF
 // before fusion) in the same order and dL/dD for every pixel (H*W).

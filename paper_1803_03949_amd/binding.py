@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
             "vm_refine_mesh": [P, P],
             "vm_gc": [P, P],
             "vm_download_mesh": [P, P, P, P, I64, I64, PI64, PI64, P],
+            "vm_download_normals": [P, P, I64, P],
             "vm_extract_backward": [P, P, P, P],
             "vm_integrate_backward": [P, P, P, P, P, P],
             "vm_get_status": [P, ctypes.POINTER(vm_status), P],
@@ -244,7 +245,17 @@ class Volume:
                                       ctypes.byref(nv), ctypes.byref(nt), _stream(stream)),
                "vm_download_mesh")
         verts, tris = verts[: nv.value], tris[: nt.value]
+        self._dl_nv = nv.value
         return verts, tris, (keys[: nv.value] if keys is not None else None)
+
+    def download_normals(self, stream=None) -> torch.Tensor:
+        """Unit normals (V, 3) f32 of the vertices of the last download, in its
+        row order (call right after `download`, before the volume changes)."""
+        nv = getattr(self, "_dl_nv", 0)
+        out = torch.empty((max(nv, 1), 3), dtype=torch.float32, device=self.device)
+        _check(lib().vm_download_normals(self.h, _ptr(out), max(nv, 1), _stream(stream)),
+               "vm_download_normals")
+        return out[:nv]
 
     def export_blocks(self, stream=None):
         n = ctypes.c_int64()

@@ -31,6 +31,7 @@ struct vm_volume {
   uint32_t epoch;   // extraction epoch (pending-list stamps)
   uint32_t pass;    // dirty / vertex-list stamps
   uint32_t xcount;  // extractions so far (parity selects the dirty-list length)
+  int64_t dl_nv;    // vertices of the last download (-1: none since the mesh changed)
   uint32_t vcount;  // extractions and refinements so far (vertex-list length)
   FrameParams last_fp;
   bool have_fp;
@@ -172,6 +173,7 @@ int clear_state(vm_volume* vol, hipStream_t stream, bool full) {
   vol->epoch = 1;
   vol->pass = 0;
   vol->have_fp = false;
+  vol->dl_nv = -1;
   return hip_status(e);
 }
 
@@ -355,6 +357,7 @@ int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* 
   fp.dmin = K->min_depth_m, fp.dmax = K->max_depth_m;
   fp.W = K->width, fp.H = K->height;
   fp.frame = ++vol->frame;
+  vol->dl_nv = -1;
   const VolDev& v = vol->dev;
   const int npix = K->width * K->height;
   VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3((npix + 1023) / 1024), dim3(1024), stream, v, fp, depth,
@@ -380,6 +383,7 @@ int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
   if (n == 0) return VM_OK;
   const VolDev& v = vol->dev;
   const uint32_t frame = ++vol->frame;
+  vol->dl_nv = -1;
   const uint32_t per = compact_per_wg(v);
   const uint32_t ncompact = (v.hash_mask + per) / per;
   VM_LAUNCH(vol, VM_K_IMPORT, k_import_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), stream,
@@ -394,6 +398,7 @@ int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
   if (!vol || (scope != VM_SCOPE_DIRTY && scope != VM_SCOPE_ALL)) return VM_ERR_ARG;
   const uint32_t pass = ++vol->pass;
+  vol->dl_nv = -1;
   // the first kernel starts the call (segments, statistics, list lengths)
   vol->dev.xsel = ++vol->xcount & 1u;
   vol->dev.vsel = ++vol->vcount & 1u;
@@ -414,6 +419,7 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
 int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   if (!vol) return VM_ERR_ARG;
   const uint32_t pass = ++vol->pass;
+  vol->dl_nv = -1;
   vol->dev.vsel = ++vol->vcount & 1u;
   const VolDev& v = vol->dev;
   prep(vol, VM_OP_REFINE, stream);
@@ -460,9 +466,19 @@ int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys, int32_t*
   if (r != VM_OK) return r;
   *nv = c.dl_nv;
   *nt = c.dl_nt;
+  vol->dl_nv = c.dl_nv;
   if (c.error) return error_code(c.error);
   if ((int64_t)c.dl_nv > vcap || (int64_t)c.dl_nt > tcap) return VM_ERR_CAPACITY;
   return VM_OK;
+}
+
+int vm_download_normals(vm_volume* vol, float* normals, int64_t cap, hipStream_t stream) {
+  if (!vol || (cap > 0 && !normals) || cap < 0) return VM_ERR_ARG;
+  if (vol->dl_nv < 0) return VM_ERR_ARG;
+  if (cap < vol->dl_nv) return VM_ERR_CAPACITY;
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_normals, dim3(vol->grid_items), dim3(256), stream, vol->dev,
+            normals);
+  return launched();
 }
 
 int vm_extract_backward(vm_volume* vol, const float* dL_dverts, float* dL_dtsdf,

@@ -536,6 +536,7 @@ __global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
 __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,
                                     uint64_t* __restrict__ keys, uint32_t vcap);
 __global__ void k_dl_write_triangles(VolDev v, int32_t* __restrict__ tris, uint32_t tcap);
+__global__ void k_dl_normals(VolDev v, float* __restrict__ normals);
 template <int W>
 __global__ void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv, int by_slot,
                            const int32_t* __restrict__ rows, uint32_t n_rows,

@@ -1272,6 +1272,59 @@ __global__ __launch_bounds__(256) void k_dl_write_triangles(VolDev v, int32_t* _
   }
 }
 
+// TSDF at voxel (x, y, z) local to block idx, coordinates in [-1, 9]; false
+// when the voxel is not observed (block not allocated, or weight 0).
+__device__ inline bool observed_tsdf(const VolDev& v, uint32_t idx, int x, int y, int z,
+                                     float& d) {
+  const int32_t nb = v.nbr[(size_t)idx * 27 + nbr_dir(x >> 3, y >> 3, z >> 3)];
+  if (nb < 0) return false;
+  const size_t o = (size_t)nb * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7);
+  d = v.d[o];
+  return v.w[o] > 0.f;
+}
+
+// TSDF gradient at a voxel: per axis the central difference over its two
+// neighbours, one-sided when only one is observed, 0 when neither is.
+__device__ inline void tsdf_gradient(const VolDev& v, uint32_t idx, int x, int y, int z,
+                                     float g[3]) {
+  float d0 = 0.f;
+  observed_tsdf(v, idx, x, y, z, d0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int ex = i == 0, ey = i == 1, ez = i == 2;
+    float dp = 0.f, dm = 0.f;
+    const bool hp = observed_tsdf(v, idx, x + ex, y + ey, z + ez, dp);
+    const bool hm = observed_tsdf(v, idx, x - ex, y - ey, z - ez, dm);
+    g[i] = hp && hm ? (dp - dm) * 0.5f : (hp ? dp - d0 : (hm ? d0 - dm : 0.f));
+  }
+}
+
+// Unit normals of the vertices of the last download, in its row order (the
+// paper keeps a normal in every vertex, Sec. IV): the TSDF gradient at the
+// edge's two end points, interpolated at t and normalised, (0, 0, 0) when it
+// vanishes; it points to increasing TSDF.  One lane per pool slot.
+__global__ __launch_bounds__(256) void k_dl_normals(VolDev v, float* __restrict__ normals) {
+  const uint32_t nv = v.cnt->dl_nv;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < v.max_vertices;
+       s += gridDim.x * blockDim.x) {
+    if (!item_count(v, 0, s)) continue;
+    const int32_t row = v.vdl[s];
+    if (row < 0 || (uint32_t)row >= nv) continue;
+    const uint32_t eo = v.vowner[s];
+    const uint32_t idx = eo / (3 * kVox), a = (eo / kVox) % 3, l = eo % kVox;
+    const int x = (int)(l & 7u), y = (int)((l >> 3) & 7u), z = (int)(l >> 6);
+    const float t = v.et[eo];
+    float g0[3], g1[3], n[3];
+    tsdf_gradient(v, idx, x, y, z, g0);
+    tsdf_gradient(v, idx, x + (a == 0), y + (a == 1), z + (a == 2), g1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n[j] = (1.f - t) * g0[j] + t * g1[j];
+    const float len = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) normals[3 * (size_t)row + j] = len > 0.f ? n[j] / len : 0.f;
+  }
+}
+
 // ============================================================================
 // backward passes
 // ============================================================================

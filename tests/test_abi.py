@@ -26,7 +26,7 @@ def test_header_declares_the_method_calls():
     for required in ["vm_create_volume", "vm_integrate_depth", "vm_extract_mesh",
                      "vm_refine_mesh", "vm_gc", "vm_download_mesh", "vm_extract_backward",
                      "vm_integrate_backward", "vm_import_batch", "vm_export_positions",
-                     "vm_extract_backward_slots", "vm_set_launch"]:
+                     "vm_extract_backward_slots", "vm_set_launch", "vm_download_normals"]:
         assert required in names
 
 
@@ -134,3 +134,4 @@ def test_null_arguments_are_rejected():
     assert L.vm_import_batch(None, None, None, None, None, 0, None, None) == -1
     assert L.vm_export_positions(None, None, None, 0, None) == -1
     assert L.vm_set_launch(None, None) == -1
+    assert L.vm_download_normals(None, None, 0, None) == -1
