@@ -79,7 +79,7 @@ enum { VM_SCOPE_DIRTY = 0, VM_SCOPE_ALL = 1 };
 /* Volume configuration.  Sizes are capacities of the caller buffer: per
  * block of max_blocks about 51 KiB (TSDF and weight 4 KiB, types 1 KiB,
  * vertex slot, t and count of its 1536 owned edges 13.5 KiB, the triangles
- * of its 512 cubes 32 KiB) and per vertex of max_vertices 12 bytes, plus 16
+ * of its 512 cubes 32 KiB) and per vertex of max_vertices 16 bytes, plus 16
  * bytes per hash slot. */
 typedef struct vm_config {
   float voxel_m;        /* cube edge length s in metres (e.g. 0.008) */
@@ -258,6 +258,18 @@ int vm_download_mesh(vm_volume* vol, float* verts, uint64_t* edge_keys,
  * written) when cap is below the downloaded vertex count.  Stream-ordered;
  * does not synchronise. */
 int vm_download_normals(vm_volume* vol, float* normals, int64_t cap, hipStream_t stream);
+
+/* Birth frames of the vertices of the last vm_download_mesh, in its row
+ * order: births[cap] (device).  A volume counts frames (vm_integrate_depth
+ * and import calls since creation or the last reset, the first being 1); a
+ * vertex's birth frame is the frame of the extraction or refinement at the
+ * end of which its reference count was positive while at the end of the
+ * previous pass it was zero or the vertex did not exist, i.e. how long it has
+ * been held (the paper visualises this duration, Fig. 1).  Call after
+ * vm_download_mesh and before the volume changes (VM_ERR_ARG otherwise, or
+ * for a NULL volume); VM_ERR_CAPACITY (nothing written) when cap is below
+ * the downloaded vertex count.  Stream-ordered; does not synchronise. */
+int vm_download_births(vm_volume* vol, uint32_t* births, int64_t cap, hipStream_t stream);
 
 /* Gradient of a loss through the vertex positions of the last download to
  * the fused TSDF, with connectivity fixed: for the vertex on edge (g, a),

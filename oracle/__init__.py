@@ -72,6 +72,7 @@ def lib():
             "orc_grad_tsdf64": (None, [vp, P, P]),
             "orc_positions64": (None, [vp, i, i, i, d, P]),
             "orc_normals64": (None, [vp, P, P]),
+            "orc_export_births": (None, [vp, P]),
             "orc_grad_fusion64": (None, [vp, P, P, P]),
             "orc_positions64_depth": (None, [vp, i, d, P]),
             "orc_num_fused": (i, [vp]),
@@ -242,6 +243,14 @@ class OracleVolume:
         dL_dv = np.ascontiguousarray(dL_dv, dtype=np.float64)
         out = np.zeros((n, 512), np.float64)
         lib().orc_grad_tsdf64(self._h, _ptr(dL_dv), _ptr(out))
+        return out
+
+    def births(self) -> np.ndarray:
+        """Birth frame (n_live,) of each live vertex, key order: the frame of
+        the pass at whose end its count last became positive."""
+        n = lib().orc_num_vertices(self._h, 1)
+        out = np.zeros(n, np.int32)
+        lib().orc_export_births(self._h, _ptr(out))
         return out
 
     def normals64(self):

@@ -85,6 +85,8 @@ struct Block {
 struct Vertex {
   float t;   // edge parameter: position = owner + t * axis (voxel units)
   int ref;   // reference count = number of triangles using the vertex
+  int born = 0;       // frame of the pass at whose end the count last became positive
+  bool live = false;  // count positive at the end of the last pass
 };
 
 // Per-voxel record of the last fusion, kept for the backward pass.
@@ -305,6 +307,7 @@ struct Volume {
   std::vector<float> last_depth;
   int W = 0, H = 0;
   float fx = 0, fy = 0, cx = 0, cy = 0, dmin = 0, dmax = 0;
+  int frame = 0;  // integrations and imports so far (the first is frame 1)
 };
 
 Block* find_block(Volume& v, const I3& b) {
@@ -365,7 +368,7 @@ void touch_vertices(Volume& v, const I3& c, unsigned type) {
     float t = edge_t_of(v, k);
     auto it = v.verts.find(k);
     if (it == v.verts.end())
-      v.verts[k] = Vertex{t, 0};
+      v.verts[k] = Vertex{t, 0, 0, false};
     else
       it->second.t = t;
   }
@@ -392,6 +395,20 @@ void retriangulate(Volume& v, const I3& c, unsigned type) {
       v.verts[tr.e[i]].ref += 1;
     }
     out.push_back(tr);
+  }
+}
+
+// Birth frames (READING: the paper shows how long each vertex has been held,
+// Fig. 1, without defining it): at the end of every extraction or
+// refinement, a vertex whose count is positive but was not at the end of
+// the previous pass (or that did not exist) is stamped with the current
+// frame.  Counts are judged at pass ends only; within a pass they move
+// triangle by triangle.
+void stamp_births(Volume& v) {
+  for (auto& kv : v.verts) {
+    Vertex& x = kv.second;
+    if (x.ref > 0 && !x.live) x.born = v.frame;
+    x.live = x.ref > 0;
   }
 }
 
@@ -464,6 +481,7 @@ void orc_destroy(void* h) { delete (Volume*)h; }
 int orc_integrate(void* h, const float* depth, int W, int H, float fx, float fy,
                   float cx, float cy, float dmin, float dmax, const float* T) {
   Volume& v = *(Volume*)h;
+  ++v.frame;
   float Rcw[3][3], tcw[3], Rwc[3][3], twc[3];
   for (int i = 0; i < 3; ++i) {
     for (int j = 0; j < 3; ++j) Rcw[i][j] = T[4 * i + j];
@@ -573,6 +591,7 @@ void orc_restrict_blocks(void* h, const int* coords, int n) {
 // touched for the next extraction.
 int orc_import_blocks(void* h, const int* coords, const float* d, const float* w, int n) {
   Volume& v = *(Volume*)h;
+  ++v.frame;
   std::set<I3> touched;
   for (int i = 0; i < n; ++i) {
     I3 b{coords[3 * i], coords[3 * i + 1], coords[3 * i + 2]};
@@ -609,6 +628,7 @@ int orc_extract(void* h, int scope) {
   }
   extract_blocks(v, dirty);
   v.pending_touched.clear();
+  stamp_births(v);
   return (int)dirty.size();
 }
 
@@ -636,7 +656,15 @@ int orc_refine(void* h) {
     blk->cur[local_index(c.x - 8 * b.x, c.y - 8 * b.y, c.z - 8 * b.z)] = (uint8_t)ca.second;
     retriangulate(v, c, ca.second);
   }
+  stamp_births(v);
   return (int)changed.size();
+}
+
+void orc_export_births(void* h, int* out) {
+  Volume& v = *(Volume*)h;
+  size_t i = 0;
+  for (auto& kv : v.verts)
+    if (kv.second.ref > 0) out[i++] = kv.second.born;
 }
 
 // Garbage collection (Sec. V-E): vertices no triangle references are freed.

@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
             "vm_gc": [P, P],
             "vm_download_mesh": [P, P, P, P, I64, I64, PI64, PI64, P],
             "vm_download_normals": [P, P, I64, P],
+            "vm_download_births": [P, P, I64, P],
             "vm_extract_backward": [P, P, P, P],
             "vm_integrate_backward": [P, P, P, P, P, P],
             "vm_get_status": [P, ctypes.POINTER(vm_status), P],
@@ -255,6 +256,16 @@ class Volume:
         out = torch.empty((max(nv, 1), 3), dtype=torch.float32, device=self.device)
         _check(lib().vm_download_normals(self.h, _ptr(out), max(nv, 1), _stream(stream)),
                "vm_download_normals")
+        return out[:nv]
+
+    def download_births(self, stream=None) -> torch.Tensor:
+        """Birth frames (V,) int32 of the vertices of the last download, in its
+        row order: the frame of the pass in which each vertex's count last
+        became positive (frames count integrations and imports from 1)."""
+        nv = getattr(self, "_dl_nv", 0)
+        out = torch.empty(max(nv, 1), dtype=torch.int32, device=self.device)
+        _check(lib().vm_download_births(self.h, _ptr(out), max(nv, 1), _stream(stream)),
+               "vm_download_births")
         return out[:nv]
 
     def export_blocks(self, stream=None):

@@ -120,6 +120,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->vowner = (uint32_t*)take(4 * V);
   v->vring = (uint32_t*)take(4 * V);
   v->vdl = (int32_t*)take(4 * V);
+  v->vbirth = (uint32_t*)take(4 * V);
   v->chunks = (uint32_t*)take(4 * kChunkWords * C);
   v->scan = (uint32_t*)take(4 * scan);
   v->scan_cap = (uint32_t)scan;
@@ -401,6 +402,7 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
   vol->dl_nv = -1;
   // the first kernel starts the call (segments, statistics, list lengths)
   vol->dev.xsel = ++vol->xcount & 1u;
+  vol->dev.frame = vol->frame;
   vol->dev.vsel = ++vol->vcount & 1u;
   const VolDev& v = vol->dev;
   if (scope == VM_SCOPE_ALL)
@@ -421,6 +423,7 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   const uint32_t pass = ++vol->pass;
   vol->dl_nv = -1;
   vol->dev.vsel = ++vol->vcount & 1u;
+  vol->dev.frame = vol->frame;
   const VolDev& v = vol->dev;
   prep(vol, VM_OP_REFINE, stream);
   VM_LAUNCH_W(vol, VM_K_REFINE, k_classify, stream, v, pass, 1);
@@ -478,6 +481,15 @@ int vm_download_normals(vm_volume* vol, float* normals, int64_t cap, hipStream_t
   if (cap < vol->dl_nv) return VM_ERR_CAPACITY;
   VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_normals, dim3(vol->grid_items), dim3(256), stream, vol->dev,
             normals);
+  return launched();
+}
+
+int vm_download_births(vm_volume* vol, uint32_t* births, int64_t cap, hipStream_t stream) {
+  if (!vol || (cap > 0 && !births) || cap < 0) return VM_ERR_ARG;
+  if (vol->dl_nv < 0) return VM_ERR_ARG;
+  if (cap < vol->dl_nv) return VM_ERR_CAPACITY;
+  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_dl_births, dim3(vol->grid_items), dim3(256), stream, vol->dev,
+            births);
   return launched();
 }
 

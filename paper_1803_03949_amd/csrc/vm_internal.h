@@ -106,6 +106,7 @@ struct VolDev {
   int32_t hash_mode;
   uint32_t max_blocks, max_vertices;
   uint32_t xsel;              // parity of the current extraction (dirty list)
+  uint32_t frame;             // frames (integrations, imports) since the last reset
   uint32_t vsel;              // parity of the current extraction / refinement (vertex list)
   uint32_t nseg;              // pool segments in use (1..kSegs)
   uint32_t vseg_cap;            // vertex slots per segment
@@ -141,6 +142,7 @@ struct VolDev {
   uint32_t* vowner;           // [V] index into the edge arrays, kNone if free
   uint32_t* vring;            // [V]
   int32_t* vdl;               // [V] row in the last download, -1 if none
+  uint32_t* vbirth;           // [V] frame in which the vertex last became used
   uint32_t* chunks;           // [B][512][16] triangles of every cube
   uint32_t* scan;             // [scan_cap] download partial sums
   uint32_t scan_cap;
@@ -537,6 +539,7 @@ __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,
                                     uint64_t* __restrict__ keys, uint32_t vcap);
 __global__ void k_dl_write_triangles(VolDev v, int32_t* __restrict__ tris, uint32_t tcap);
 __global__ void k_dl_normals(VolDev v, float* __restrict__ normals);
+__global__ void k_dl_births(VolDev v, uint32_t* __restrict__ births);
 template <int W>
 __global__ void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv, int by_slot,
                            const int32_t* __restrict__ rows, uint32_t n_rows,

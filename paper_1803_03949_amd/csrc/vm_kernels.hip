@@ -975,6 +975,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
             }
             v.evtx[eo] = (int32_t)ns;
             v.vowner[ns] = (uint32_t)eo;
+            v.vbirth[ns] = v.frame;
             ++nnew;
           } else {
             ++nupd;
@@ -1011,6 +1012,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
               }
               v.evtx[eo] = (int32_t)ns;
               v.vowner[ns] = (uint32_t)eo;
+              v.vbirth[ns] = v.frame;
               ++nnew;
             } else {
               ++nupd;
@@ -1322,6 +1324,19 @@ __global__ __launch_bounds__(256) void k_dl_normals(VolDev v, float* __restrict_
     const float len = sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
 #pragma unroll
     for (int j = 0; j < 3; ++j) normals[3 * (size_t)row + j] = len > 0.f ? n[j] / len : 0.f;
+  }
+}
+
+// Birth frames of the vertices of the last download, in its row order: the
+// frame (integration or import count) of the pass in which the vertex's
+// count last became positive.
+__global__ __launch_bounds__(256) void k_dl_births(VolDev v, uint32_t* __restrict__ births) {
+  const uint32_t nv = v.cnt->dl_nv;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < v.max_vertices;
+       s += gridDim.x * blockDim.x) {
+    if (!item_count(v, 0, s)) continue;
+    const int32_t row = v.vdl[s];
+    if (row >= 0 && (uint32_t)row < nv) births[row] = v.vbirth[s];
   }
 }
 
