@@ -256,6 +256,48 @@ def mesh_memory(args, dev, frames, seq):
     return out
 
 
+def sharing_ablation(args, dev, frames, seq, vertices_us):
+    """The paper's two vertex-sharing schemes (Sec. V-C; compared in Sec. VI-A)
+    over the 8 mm room sequence, each with its own vertex state kept across
+    frames, timed per frame with events, beside edge ownership (the vertex
+    pass of the headline, which also forms counts and frees vertices)."""
+    import torch
+
+    import scenes
+    from paper_1803_03949_amd import Volume
+
+    depth = torch.from_numpy(np.stack(frames)).to(dev)
+    vol = Volume(seq.voxel_m, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23, device=dev)
+    n = (1 << 17) * 3 * 512
+    states = [(torch.full((n,), -1, dtype=torch.int32, device=dev),
+               torch.zeros(n, dtype=torch.float32, device=dev),
+               torch.zeros(1, dtype=torch.int32, device=dev)) for _ in range(2)]
+    ev = [[], []]
+    for k in range(len(frames)):
+        vol.integrate(depth[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        vol.extract()
+        vol.gc()
+        for scheme in (0, 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            vol.sharing_ablation(scheme, *states[scheme])
+            b.record()
+            ev[scheme].append((a, b))
+    torch.cuda.synchronize()
+    us = [1000.0 * float(np.mean([a.elapsed_time(b) for a, b in e])) for e in ev]
+    (s0, t0, c0), (s1, t1, c1) = states
+    same = bool(torch.equal(s0 >= 0, s1 >= 0)) and bool(torch.equal(t0[s0 >= 0], t1[s1 >= 0]))
+    out = {"lock_based_us_per_frame": us[0], "lock_free_us_per_frame": us[1],
+           "lock_free_over_lock_based": us[1] / us[0],
+           "edge_ownership_vertex_pass_us": vertices_us,
+           "vertices_initialised": int(c0.item()), "same_vertices_and_t": same}
+    log(f"sharing ablation: lock-based {us[0]:.1f} us, lock-free {us[1]:.1f} us per frame "
+        f"({us[1] / us[0]:.2f}x), edge ownership vertex pass {vertices_us:.1f} us; same {same}")
+    del vol, depth, states
+    torch.cuda.empty_cache()
+    return out
+
+
 def sphere_extract(dev):
     import torch
 
@@ -518,6 +560,8 @@ def main():
     extras = {}
     if not args.no_extras:
         extras["mesh_memory_8mm"] = mesh_memory(args, dev, frames, seq)
+        extras["sharing_ablation_8mm"] = sharing_ablation(
+            args, dev, frames, seq, head["kernels"]["vertices"]["us_per_launch"])
         extras["sphere_512_blocks"] = sphere_extract(dev)
         log(f"sphere: {extras['sphere_512_blocks']}")
         extras["grad_scene_128"] = grad_scene_fwd_bwd(dev)

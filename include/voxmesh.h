@@ -149,12 +149,13 @@ enum {
   VM_K_CLASSIFY = 6,     /* cube types */
   VM_K_REFINE = 7,       /* cube types, refinement pass */
   VM_K_VERTICES = 8,     /* edge-owned vertices and reference counts */
-  VM_K_TRIANGLES = 9,    /* triangle chunks of changed cubes */
+  VM_K_TRIANGLES = 9,    /* triangle records of changed cubes */
   VM_K_GC = 10,          /* (reserved: recycling runs in the vertex pass) */
   VM_K_DOWNLOAD = 11,    /* download compaction (all its kernels) */
   VM_K_BACKWARD = 12,    /* backward passes */
   VM_K_COUNTERS = 13,    /* single-lane bookkeeping kernels */
-  VM_K_COUNT = 14
+  VM_K_ABLATION = 14,    /* vm_sharing_ablation (the paper's sharing schemes) */
+  VM_K_COUNT = 15
 };
 
 typedef struct vm_volume vm_volume;
@@ -270,6 +271,26 @@ int vm_download_normals(vm_volume* vol, float* normals, int64_t cap, hipStream_t
  * for a NULL volume); VM_ERR_CAPACITY (nothing written) when cap is below
  * the downloaded vertex count.  Stream-ordered; does not synchronise. */
 int vm_download_births(vm_volume* vol, uint32_t* births, int64_t cap, hipStream_t stream);
+
+/* Ablation (not part of the method's path): the two GPU schemes Sec. V-C
+ * gives for initialising each vertex once while the cubes around its edge
+ * run in parallel, which Sec. VI-A times against each other, reproduced for
+ * measurement beside edge ownership.  Over the cubes of the last
+ * extraction's dirty blocks, one lane per cube: for every edge the cube's
+ * current type uses, a vertex is allocated if the edge has none (an atomic
+ * add on *counter, as from a heap) and the edge parameter t is written.
+ * scheme 0, lock-based: the first lane to claim the edge (compare-and-swap)
+ * allocates; one launch.  scheme 1, lock-free: the cubes of each 2x2x2 cell
+ * in four groups of two at opposite corners, which share no edge; four
+ * launches, one per group.  State (device, the caller's, kept across
+ * calls): edge_slot and edge_t of max_blocks * 3 * 512 entries indexed
+ * (block * 3 + axis) * 512 + voxel, edge_slot -1 for edges without a vertex
+ * (the caller fills it before the first call); *counter the number of
+ * vertices allocated.  Both schemes leave the same set of edges with a
+ * vertex and the same t.  VM_ERR_ARG for NULL arguments or another scheme.
+ * Stream-ordered. */
+int vm_sharing_ablation(vm_volume* vol, int scheme, int32_t* edge_slot, float* edge_t,
+                        uint32_t* counter, hipStream_t stream);
 
 /* Gradient of a loss through the vertex positions of the last download to
  * the fused TSDF, with connectivity fixed: for the vertex on edge (g, a),

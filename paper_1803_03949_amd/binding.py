@@ -66,7 +66,7 @@ _STATUS_FIELDS = ["blocks", "frame_blocks", "pending_blocks", "dirty_blocks", "v
 TOTALS = ["frames", "frame_blocks", "dirty_blocks", "vertex_blocks", "new_vertices",
           "updated_vertices", "changed_cubes", "gc_scanned", "freed_vertices", "refined_cubes"]
 KERNELS = ["collect", "assign", "link", "fuse", "import", "dirty", "classify", "refine",
-           "vertices", "triangles", "gc", "download", "backward", "counters"]
+           "vertices", "triangles", "gc", "download", "backward", "counters", "ablation"]
 
 
 class vm_status(ctypes.Structure):
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
             "vm_download_mesh": [P, P, P, P, I64, I64, PI64, PI64, P],
             "vm_download_normals": [P, P, I64, P],
             "vm_download_births": [P, P, I64, P],
+            "vm_sharing_ablation": [P, ctypes.c_int, P, P, P, P],
             "vm_extract_backward": [P, P, P, P],
             "vm_integrate_backward": [P, P, P, P, P, P],
             "vm_get_status": [P, ctypes.POINTER(vm_status), P],
@@ -257,6 +258,15 @@ class Volume:
         _check(lib().vm_download_normals(self.h, _ptr(out), max(nv, 1), _stream(stream)),
                "vm_download_normals")
         return out[:nv]
+
+    def sharing_ablation(self, scheme: int, edge_slot: torch.Tensor, edge_t: torch.Tensor,
+                         counter: torch.Tensor, stream=None):
+        """The paper's vertex-sharing schemes over the last extraction's dirty
+        cubes (0: lock-based, 1: lock-free in four groups), on caller state:
+        edge_slot int32 and edge_t float32 of max_blocks*3*512 entries
+        (edge_slot -1 where no vertex), counter int32 (1,)."""
+        _check(lib().vm_sharing_ablation(self.h, int(scheme), _ptr(edge_slot), _ptr(edge_t),
+                                         _ptr(counter), _stream(stream)), "vm_sharing_ablation")
 
     def download_births(self, stream=None) -> torch.Tensor:
         """Birth frames (V,) int32 of the vertices of the last download, in its

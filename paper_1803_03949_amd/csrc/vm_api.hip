@@ -493,6 +493,22 @@ int vm_download_births(vm_volume* vol, uint32_t* births, int64_t cap, hipStream_
   return launched();
 }
 
+int vm_sharing_ablation(vm_volume* vol, int scheme, int32_t* edge_slot, float* edge_t,
+                        uint32_t* counter, hipStream_t stream) {
+  if (!vol || !edge_slot || !edge_t || !counter || (scheme != 0 && scheme != 1))
+    return VM_ERR_ARG;
+  const dim3 g(vol->grid_items), b(256);
+  if (scheme == 0) {
+    VM_LAUNCH(vol, VM_K_ABLATION, k_share_lock, g, b, stream, vol->dev, edge_slot, edge_t,
+              counter);
+  } else {
+    for (int group = 0; group < 4; ++group)
+      VM_LAUNCH(vol, VM_K_ABLATION, k_share_free, g, b, stream, vol->dev, group, edge_slot,
+                edge_t, counter);
+  }
+  return launched();
+}
+
 int vm_extract_backward(vm_volume* vol, const float* dL_dverts, float* dL_dtsdf,
                         hipStream_t stream) {
   if (!vol || !dL_dtsdf) return VM_ERR_ARG;

@@ -540,6 +540,10 @@ __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,
 __global__ void k_dl_write_triangles(VolDev v, int32_t* __restrict__ tris, uint32_t tcap);
 __global__ void k_dl_normals(VolDev v, float* __restrict__ normals);
 __global__ void k_dl_births(VolDev v, uint32_t* __restrict__ births);
+__global__ void k_share_lock(VolDev v, int32_t* __restrict__ slot, float* __restrict__ tv,
+                             uint32_t* __restrict__ counter);
+__global__ void k_share_free(VolDev v, int group, int32_t* __restrict__ slot,
+                             float* __restrict__ tv, uint32_t* __restrict__ counter);
 template <int W>
 __global__ void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv, int by_slot,
                            const int32_t* __restrict__ rows, uint32_t n_rows,

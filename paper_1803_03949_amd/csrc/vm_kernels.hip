@@ -1136,6 +1136,87 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
 }
 
 // ============================================================================
+// ablation: the paper's two ways of sharing vertices between cubes
+// ============================================================================
+// Sec. V-C gives two GPU schemes that initialise each vertex once while the
+// cubes around its edge run in parallel, and Sec. VI-A times them against
+// each other.  These kernels reproduce both, for measurement beside edge
+// ownership, on the cubes of the last extraction's dirty blocks, one lane
+// per cube: for every edge its type uses, a vertex is allocated (one atomic
+// on a global counter, as from a heap) if the edge has none, and the edge
+// parameter t is written.  The state is the caller's: slot[e] (-1: none) and
+// t[e], e = (block * 3 + axis) * 512 + voxel, kept across calls.
+
+// Index of the owner edge of cube-edge e of cube l in block idx, -1 when the
+// owner block is not allocated; t receives its parameter.
+__device__ inline int64_t cube_edge_slot_index(const VolDev& v, uint32_t idx, int l, int e,
+                                               float& t) {
+  int ox, oy, oz, axis;
+  edge_owner(e, ox, oy, oz, axis);
+  const int x = (l & 7) + ox, y = ((l >> 3) & 7) + oy, z = (l >> 6) + oz;
+  const int32_t nb = v.nbr[(size_t)idx * 27 + nbr_dir(x >> 3, y >> 3, z >> 3)];
+  const int fx = x + (axis == 0), fy = y + (axis == 1), fz = z + (axis == 2);
+  const int32_t fb = v.nbr[(size_t)idx * 27 + nbr_dir(fx >> 3, fy >> 3, fz >> 3)];
+  if (nb < 0 || fb < 0) return -1;
+  const int ol = (x & 7) + 8 * (y & 7) + 64 * (z & 7);
+  t = edge_param(v.d[(size_t)nb * kVox + ol],
+                 v.d[(size_t)fb * kVox + (fx & 7) + 8 * (fy & 7) + 64 * (fz & 7)]);
+  return ((int64_t)nb * 3 + axis) * kVox + ol;
+}
+
+// Lock-based: the first lane to take an edge (compare-and-swap from -1)
+// allocates its vertex; every lane using the edge writes the same t.
+__global__ __launch_bounds__(256) void k_share_lock(VolDev v, int32_t* __restrict__ slot,
+                                                    float* __restrict__ tv,
+                                                    uint32_t* __restrict__ counter) {
+  const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks) * kVox;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t idx = v.dirty[i / kVox];
+    const int l = (int)(i % kVox);
+    const uint32_t type = v.tcur[(size_t)idx * kVox + l];
+    if (v.tri_table[type * 16] == 0) continue;
+    for (int e = 0; e < 12; ++e) {
+      if (!v.edge_uses[type * 12 + e]) continue;
+      float t;
+      const int64_t eo = cube_edge_slot_index(v, idx, l, e, t);
+      if (eo < 0) continue;
+      if (atomicCAS(&slot[eo], -1, -2) == -1) slot[eo] = (int32_t)atomicAdd(counter, 1u);
+      tv[eo] = t;
+    }
+  }
+}
+
+// Lock-free: the cubes of each 2x2x2 cell form four groups of two at
+// opposite corners (parities 000/111, 100/011, 010/101, 001/110); no two
+// cubes of a group share an edge, so within one launch a lane allocates
+// without any claim.  The four groups are four launches.
+__global__ __launch_bounds__(256) void k_share_free(VolDev v, int group,
+                                                    int32_t* __restrict__ slot,
+                                                    float* __restrict__ tv,
+                                                    uint32_t* __restrict__ counter) {
+  const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks) * 128u;
+  const int first = group == 0 ? 0 : (1 << (group - 1));  // parity x | y << 1 | z << 2
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t idx = v.dirty[i / 128u];
+    const int k = (int)(i % 128u), cell = k & 63;
+    const int p = (k >> 6) ? first ^ 7 : first;
+    const int x = 2 * (cell & 3) + (p & 1), y = 2 * ((cell >> 2) & 3) + ((p >> 1) & 1),
+              z = 2 * (cell >> 4) + (p >> 2);
+    const int l = x + 8 * y + 64 * z;
+    const uint32_t type = v.tcur[(size_t)idx * kVox + l];
+    if (v.tri_table[type * 16] == 0) continue;
+    for (int e = 0; e < 12; ++e) {
+      if (!v.edge_uses[type * 12 + e]) continue;
+      float t;
+      const int64_t eo = cube_edge_slot_index(v, idx, l, e, t);
+      if (eo < 0) continue;
+      if (slot[eo] < 0) slot[eo] = (int32_t)atomicAdd(counter, 1u);
+      tv[eo] = t;
+    }
+  }
+}
+
+// ============================================================================
 // download: two-level exclusive scans over the vertex and triangle pools
 // ============================================================================
 constexpr int kScanItems = 1024;  // items per workgroup (256 lanes x 4)
