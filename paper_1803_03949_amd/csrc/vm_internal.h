@@ -48,7 +48,9 @@ constexpr uint32_t kNewFlag = 0x80000000u;   // frame-list entry: block is new
 constexpr int kChunkWords = 16;              // 5 triangles * 3 slots, 1 spare
 constexpr int kMaxBlocks = 1 << 21;
 constexpr int kSegs = 64;                    // pool segments
-constexpr int kTile = 1024;                  // list items per compaction workgroup
+constexpr int kTile = 256;                   // list items per compaction workgroup (256 lanes)
+constexpr int kTilePer = kTile / 256;        // items per lane
+constexpr int kTileBits = kTilePer < 2 ? 1 : (kTilePer < 4 ? 2 : 3);  // bits of a lane's count
 
 // Error bits (bit k <-> VM error code -(k+2)).
 constexpr uint32_t kErrHash = 1u << 0;

@@ -542,11 +542,11 @@ __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->n_pending[(epoch + 1) & 1] = 0;
   const uint32_t total = np * 8u;
   for (uint32_t t0 = blockIdx.x * kTile; t0 < total; t0 += gridDim.x * kTile) {
-    int32_t got[4];
+    int32_t got[kTilePer];
     uint32_t cnt = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t t = t0 + threadIdx.x * 4 + k;
+    for (int k = 0; k < kTilePer; ++k) {
+      const uint32_t t = t0 + threadIdx.x * kTilePer + k;
       got[k] = -1;
       if (t >= total) continue;
       const uint32_t idx = v.pending[t >> 3], o = t & 7u;
@@ -559,13 +559,13 @@ __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t
       }
     }
     uint32_t tot;
-    uint32_t r = wg_scan_bits<3>(cnt, swave, &tot);  // cnt <= 4
+    uint32_t r = wg_scan_bits<kTileBits>(cnt, swave, &tot);  // cnt <= kTilePer
     if (tot == 0) continue;
     if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_dirty[v.xsel], tot);
     __syncthreads();
     r += sbase;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kTilePer; ++k)
       if (got[k] >= 0) v.dirty[r++] = (uint32_t)got[k];
     __syncthreads();
   }
@@ -752,21 +752,21 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_DIRTY_BLOCKS] += n;
   const uint32_t total = n * 8u;
   for (uint32_t t0 = blockIdx.x * kTile; t0 < total; t0 += gridDim.x * kTile) {
-    uint32_t got[4], cnt = 0;
+    uint32_t got[kTilePer], cnt = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t t = t0 + threadIdx.x * 4 + k;
+    for (int k = 0; k < kTilePer; ++k) {
+      const uint32_t t = t0 + threadIdx.x * kTilePer + k;
       got[k] = t < total ? v.vcand[t] : kNone;
       cnt += got[k] != kNone;
     }
     uint32_t tot;
-    uint32_t r = wg_scan_bits<3>(cnt, swave, &tot);  // cnt <= 4
+    uint32_t r = wg_scan_bits<kTileBits>(cnt, swave, &tot);  // cnt <= kTilePer
     if (tot == 0) continue;
     if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_vblocks[v.vsel], tot);
     __syncthreads();
     r += sbase;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kTilePer; ++k)
       if (got[k] != kNone) v.vblocks[r++] = got[k];
     __syncthreads();
   }
