@@ -97,6 +97,7 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
 // list (blocks touched since the last extraction) and, for blocks new to
 // the hash, pool indices, given here with their neighbour tables cleared.
 constexpr int kClaimCap = 1024;  // claims per workgroup gathered in LDS
+constexpr int kWaveKeys = 128;   // distinct keys a wave gathers before claiming them
 
 // List a claimed block: frame list entry, pending list entry (once per
 // extraction epoch) and, for a block new to the hash, its pool index (slot
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
                                                  const float* __restrict__ depth, uint32_t epoch) {
   __shared__ unsigned long long sseen[kClaimCap];  // slot contents seen by the claim
   __shared__ uint32_t sslot[kClaimCap];
+  __shared__ unsigned long long skeys_all[16][kWaveKeys];  // each wave's gathered keys
   __shared__ uint32_t nclaim;
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase[3];
@@ -182,8 +184,47 @@ __global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
       }
     }
   }
+  // The wave first gathers the distinct keys of its pixels' boxes in LDS
+  // (duplicates between box positions j are left to the claim below), then
+  // its lanes insert and claim them together: the hash probes and claims of
+  // all positions overlap instead of following one another.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned long long* skeys = skeys_all[wave];
+  uint32_t nkeys = 0;
+  auto claim_keys = [&]() {
+    wave_sync();
+    for (uint32_t i0 = 0; i0 < nkeys; i0 += 64) {
+      const uint32_t i = i0 + __lane_id();
+      if (i >= nkeys) continue;
+      const uint64_t key = skeys[i];
+      unsigned long long seen = 0;
+      const int64_t s = hash_insert_seen(v, key, &seen);
+      if (s < 0) {
+        atomicOr(&v.cnt->error, kErrHash);
+        continue;
+      }
+      // one claim per block and frame wins
+      if (v.slot_stamp[s] == fp.frame || atomicExch(&v.slot_stamp[s], fp.frame) == fp.frame)
+        continue;
+      const uint32_t c = atomicAdd(&nclaim, 1u);
+      if (c < kClaimCap) {
+        sslot[c] = (uint32_t)s;
+        sseen[c] = seen;
+      } else {
+        // more claims than the workgroup gathers: list this one alone
+        const bool isnew = (uint32_t)(seen & kIdxMask) == kPending;
+        const bool pend = isnew || v.st_pending[(uint32_t)(seen & kIdxMask)] != epoch;
+        list_claim(v, (uint32_t)s, seen, pend, atomicAdd(&v.cnt->n_frame[fp.frame & 1], 1u),
+                   pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], 1u) : 0u,
+                   isnew ? atomicAdd(&v.cnt->n_blocks, 1u) : 0u, epoch);
+      }
+    }
+    nkeys = 0;
+    wave_sync();
+  };
   // the box's blocks in x-fastest order, stepped with carries (no division)
   int cx = 0, cy = 0, cz = 0;
+  const uint64_t below = lanes_below();
   for (int j = 0; __ballot(j < nbox); ++j) {
     bool has = j < nbox;
     uint64_t key = 0;
@@ -207,29 +248,13 @@ __global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
       if ((int)__lane_id() == leader) mine = true;
       if (same) has = false;
     }
-    if (!mine) continue;
-    unsigned long long seen = 0;
-    const int64_t s = hash_insert_seen(v, key, &seen);
-    if (s < 0) {
-      atomicOr(&v.cnt->error, kErrHash);
-      continue;
-    }
-    // one claim per block and frame wins
-    if (v.slot_stamp[s] == fp.frame || atomicExch(&v.slot_stamp[s], fp.frame) == fp.frame)
-      continue;
-    const uint32_t c = atomicAdd(&nclaim, 1u);
-    if (c < kClaimCap) {
-      sslot[c] = (uint32_t)s;
-      sseen[c] = seen;
-    } else {
-      // more claims than the workgroup gathers: list this one alone
-      const bool isnew = (uint32_t)(seen & kIdxMask) == kPending;
-      const bool pend = isnew || v.st_pending[(uint32_t)(seen & kIdxMask)] != epoch;
-      list_claim(v, (uint32_t)s, seen, pend, atomicAdd(&v.cnt->n_frame[fp.frame & 1], 1u),
-                 pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], 1u) : 0u,
-                 isnew ? atomicAdd(&v.cnt->n_blocks, 1u) : 0u, epoch);
-    }
+    const uint64_t bm = __ballot(mine);
+    const uint32_t nm = (uint32_t)__popcll(bm);
+    if (nkeys + nm > (uint32_t)kWaveKeys) claim_keys();
+    if (mine) skeys[nkeys + (uint32_t)__popcll(bm & below)] = key;
+    nkeys += nm;
   }
+  claim_keys();
   __syncthreads();
   const uint32_t nc = min(nclaim, (uint32_t)kClaimCap);
   for (uint32_t c0 = 0; c0 < nc; c0 += blockDim.x) {
