@@ -1,0 +1,139 @@
+"""Degenerate inputs through the C-ABI, against the oracle where it applies:
+an empty volume, a frame without a valid pixel, an import of no blocks, a
+single valid pixel, extraction with nothing new, refinement applied twice,
+and a camera at the edge of the representable block range (pixels whose
+box leaves [-8192, 8191] are skipped, reading 4 of the collection band)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from paper_1803_03949_amd import Volume
+from tests.gpu_compare import compare_all, compare_blocks, to_dev
+
+pytestmark = pytest.mark.gpu
+
+S = 0.03
+
+
+def pair(**kw):
+    args = dict(hash_log2=14, max_blocks=1 << 12, max_vertices=1 << 18)
+    args.update(kw)
+    return Volume(S, **args), oracle.OracleVolume(S, 4.0, 0.5)
+
+
+def both(g, o, depth, pose, dmin=0.4, dmax=3.0):
+    g.integrate(to_dev(depth)[0], scenes.K, pose, dmin, dmax)
+    o.integrate(depth, scenes.K, pose, dmin, dmax)
+
+
+def frame_sets(g, o):
+    gf = {tuple(x) for x in g.block_list("frame").tolist()}
+    of = {tuple(x) for x in o.block_set("frame").tolist()}
+    return gf, of
+
+
+def test_empty_volume_calls():
+    g, _ = pair()
+    g.extract()
+    g.refine()
+    g.gc()
+    g.extract(scope_all=True)
+    verts, tris, keys = g.download()
+    assert len(verts) == 0 and len(tris) == 0 and len(keys) == 0
+    assert len(g.download_normals()) == 0 and len(g.download_births()) == 0
+    st = g.status()
+    assert st["blocks"] == 0 and st["triangles"] == 0 and st["error"] == 0
+
+
+def test_frame_without_valid_pixels():
+    g, o = pair()
+    pose = np.eye(4, dtype=np.float32)
+    bad = np.zeros((480, 640), np.float32)
+    bad[:100] = np.nan
+    bad[100:200] = np.inf
+    bad[200:300] = -1.0
+    bad[300:400] = 5.0  # beyond the depth range
+    both(g, o, bad, pose)
+    assert frame_sets(g, o) == (set(), set())
+    g.extract()
+    o.extract()
+    compare_all(g, o)
+    assert g.status()["blocks"] == 0
+
+
+def test_import_of_no_blocks():
+    g, _ = pair()
+    z = torch.zeros((0, 512), dtype=torch.float32, device="cuda")
+    g.import_blocks(torch.zeros((0, 3), dtype=torch.int32, device="cuda"), z, z)
+    g.extract(scope_all=True)
+    assert g.status()["blocks"] == 0 and g.status()["error"] == 0
+
+
+def test_single_valid_pixel():
+    g, o = pair()
+    d = np.zeros((480, 640), np.float32)
+    d[240, 320] = 1.7
+    pose = np.eye(4, dtype=np.float32)
+    both(g, o, d, pose)
+    gf, of = frame_sets(g, o)
+    assert gf == of and 1 <= len(gf) <= 8
+    g.extract()
+    o.extract()
+    compare_all(g, o)
+
+
+def test_extraction_with_nothing_new_and_double_refinement():
+    seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=S, holes=True)
+    g, o = pair()
+    both(g, o, seq.frame(0), seq.poses[0], seq.min_depth, seq.max_depth)
+    g.extract()
+    o.extract()
+    g.refine()
+    o.refine()
+    g.refine()  # idempotent (reading 9)
+    o.refine()
+    compare_all(g, o)
+    g.extract()  # nothing touched since: no dirty block, mesh unchanged
+    o.extract()
+    assert len(g.block_list("dirty")) == 0 and len(o.block_set("dirty")) == 0
+    compare_all(g, o)
+
+
+@pytest.mark.parametrize("axis_sign", [(0, 1.0), (1, 1.0), (2, -1.0)])
+def test_camera_at_the_block_range_edge(axis_sign):
+    """The camera sits just inside the representable range: pixels whose
+    collection box crosses [-8192, 8191] blocks are skipped, the others
+    collected, identically on both sides."""
+    axis, sign = axis_sign
+    seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=S)
+    depth = seq.frame(0)
+    pose = seq.poses[0].astype(np.float64).copy()
+    # the camera 1 m inside the last representable block boundary, looking
+    # towards it
+    edge = (8192.0 if sign > 0 else -8192.0) * 8 * S
+    pose[axis, 3] = edge - sign * 1.0
+    pose = pose.astype(np.float32)
+    # a rough host count (float64, not the method's arithmetic) that this
+    # pose puts the far end of many pixels' bands beyond the edge
+    H, W = depth.shape
+    v_, u_ = np.mgrid[0:H, 0:W]
+    fx, fy, cx, cy = scenes.K
+    z = depth.astype(np.float64) + 4 * S
+    ray = np.stack([(u_ - cx) / fx * z, (v_ - cy) / fy * z, z], -1)
+    world = ray @ pose[:3, :3].astype(np.float64).T + pose[:3, 3]
+    ok = (depth >= seq.min_depth) & (depth <= seq.max_depth)
+    beyond = (world[..., axis] * sign > abs(edge)) & ok
+    assert 1000 < beyond.sum() < ok.sum() - 1000
+    g, o = pair(hash_log2=16, max_blocks=1 << 14)
+    both(g, o, depth, pose, seq.min_depth, seq.max_depth)
+    gf, of = frame_sets(g, o)
+    assert gf == of and len(gf) > 40
+    c = np.array(sorted(gf))
+    assert c.min() >= -8192 and c.max() <= 8191
+    # blocks up to the edge itself are collected
+    assert (c[:, axis].max() == 8191) if sign > 0 else (c[:, axis].min() == -8192)
+    g.extract()
+    o.extract()
+    compare_all(g, o)
