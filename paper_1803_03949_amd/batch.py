@@ -31,22 +31,19 @@ from .binding import SLOT_SPAN, Volume
 def sphere_loss_grad(centers: torch.Tensor, radii: torch.Tensor):
     """dL/dp for L = sum over live vertices of (|p - c_k| - r_k)^2, with
     (c_k, r_k) the target sphere of the vertex's volume k.  Elementwise
-    operations only (no reductions), so the function can be graph-captured."""
+    operations only (no reductions), so the function can be graph-captured,
+    and every entry goes through the same operations in the same order
+    whatever the pool size.  Entries with slot -1 (no vertex) get 0."""
+    centers = centers.reshape(-1, 3).contiguous()
+    radii = radii.reshape(-1).contiguous()
 
     def grad(pos: torch.Tensor, slot: torch.Tensor, out: torch.Tensor):
         k = slot.clamp(min=0).long()
-        c = centers.index_select(0, k)
-        dx = pos[:, 0] - c[:, 0]
-        dy = pos[:, 1] - c[:, 1]
-        dz = pos[:, 2] - c[:, 2]
-        dist = torch.sqrt(dx * dx + dy * dy + dz * dz)
-        live = slot >= 0
-        scale = torch.where(live & (dist > 0), 2.0 * (dist - radii.index_select(0, k)) / dist,
-                            torch.zeros_like(dist))
-        out[:, 0] = scale * dx
-        out[:, 1] = scale * dy
-        out[:, 2] = scale * dz
-        return out
+        d = pos - centers.index_select(0, k)
+        dd = d * d
+        dist = (dd[:, 0] + dd[:, 1]).add_(dd[:, 2]).sqrt_().clamp_min_(1e-30)
+        scale = torch.where(slot >= 0, 2.0 * (dist - radii.index_select(0, k)) / dist, 0.0)
+        return torch.mul(d, scale[:, None], out=out)
 
     return grad
 

@@ -50,7 +50,9 @@ constexpr int kMaxBlocks = 1 << 21;
 constexpr int kSegs = 64;                    // pool segments
 constexpr int kTile = 256;                   // list items per compaction workgroup (256 lanes)
 constexpr int kTilePer = kTile / 256;        // items per lane
-constexpr int kTileBits = kTilePer < 2 ? 1 : (kTilePer < 4 ? 2 : 3);  // bits of a lane's count
+// bits that hold a count in [0, n]
+constexpr int count_bits(int n) { return n < 2 ? 1 : (n < 4 ? 2 : (n < 8 ? 3 : 4)); }
+constexpr int kTileBits = count_bits(kTilePer);  // bits of a lane's count
 
 // Error bits (bit k <-> VM error code -(k+2)).
 constexpr uint32_t kErrHash = 1u << 0;

@@ -770,28 +770,34 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
 
 // Compact the vertex-block candidates (8 per dirty block, already claimed),
 // one atomic per tile.
+// The candidate list is 8 entries per dirty block and mostly empty, and
+// can be long (every block of a large import), so each lane takes 8 entries
+// (coalesced: entry k of a lane sits k * 256 past the first) and a tile of
+// 2048 entries costs one atomic on the list length.
+constexpr int kVbPer = 8;
 __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase;
   const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_DIRTY_BLOCKS] += n;
   const uint32_t total = n * 8u;
-  for (uint32_t t0 = blockIdx.x * kTile; t0 < total; t0 += gridDim.x * kTile) {
-    uint32_t got[kTilePer], cnt = 0;
+  constexpr uint32_t kT = 256 * kVbPer;
+  for (uint32_t t0 = blockIdx.x * kT; t0 < total; t0 += gridDim.x * kT) {
+    uint32_t got[kVbPer], cnt = 0;
 #pragma unroll
-    for (int k = 0; k < kTilePer; ++k) {
-      const uint32_t t = t0 + threadIdx.x * kTilePer + k;
+    for (int k = 0; k < kVbPer; ++k) {
+      const uint32_t t = t0 + k * 256 + threadIdx.x;
       got[k] = t < total ? v.vcand[t] : kNone;
       cnt += got[k] != kNone;
     }
     uint32_t tot;
-    uint32_t r = wg_scan_bits<kTileBits>(cnt, swave, &tot);  // cnt <= kTilePer
+    uint32_t r = wg_scan_bits<count_bits(kVbPer)>(cnt, swave, &tot);
     if (tot == 0) continue;
     if (threadIdx.x == 0) sbase = atomicAdd(&v.cnt->n_vblocks[v.vsel], tot);
     __syncthreads();
     r += sbase;
 #pragma unroll
-    for (int k = 0; k < kTilePer; ++k)
+    for (int k = 0; k < kVbPer; ++k)
       if (got[k] != kNone) v.vblocks[r++] = got[k];
     __syncthreads();
   }
