@@ -197,7 +197,9 @@ int vm_integrate_depth(vm_volume* vol, const float* depth,
  * for volumes sampled from an analytic field rather than fused.
  * coords: device, n*3 int32 block coordinates (distinct); tsdf, weight:
  * device, n*512 FP32 in local voxel order.  The blocks count as touched for
- * the next VM_SCOPE_DIRTY extraction. */
+ * the next VM_SCOPE_DIRTY extraction.  New blocks take pool rows in input
+ * order (into an empty volume, input row i becomes pool row i), so rows
+ * given in a spatial order keep neighbouring blocks close in memory. */
 int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
                      const float* weight, int64_t n, hipStream_t stream);
 
@@ -358,8 +360,13 @@ typedef struct vm_launch {
                                  (fusion, import, backward), 1..16 */
   int32_t item_groups_per_cu; /* workgroups per compute unit of the list
                                  kernels (256 lanes), 1..32 */
-  int32_t block_order;        /* 0: block i goes to workgroup i mod grid;
-                                 1: each workgroup takes a contiguous run */
+  int32_t block_order;        /* bit 0 clear: block i goes to workgroup
+                                 i mod grid; set: each workgroup takes a
+                                 contiguous run.  Bit 1 set: the list is
+                                 first cut into 8 contiguous ranges, one
+                                 per XCD (workgroup b runs on XCD b mod
+                                 8), so that neighbouring list entries
+                                 share an L2.  0..3 */
 } vm_launch;
 
 /* Set / read the mapping.  VM_ERR_ARG for values outside the ranges. */

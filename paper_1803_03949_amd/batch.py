@@ -195,7 +195,7 @@ def default_space():
     for w in (2, 4, 8):
         for groups in (8 // w * 4, 8 // w * 8):  # 16 or 32 waves per CU
             for bg in (2, 4, 8):
-                for order in (0, 1):
+                for order in (0, 1, 2, 3):
                     out.append(dict(wave_group_size=w, wave_groups_per_cu=max(1, groups),
                                     block_groups_per_cu=bg, item_groups_per_cu=8,
                                     block_order=order))

@@ -67,7 +67,7 @@ bool launch_ok(const vm_launch* l) {
          l->wave_groups_per_cu >= 1 && l->wave_groups_per_cu <= 32 &&
          l->block_groups_per_cu >= 1 && l->block_groups_per_cu <= 16 &&
          l->item_groups_per_cu >= 1 && l->item_groups_per_cu <= 32 &&
-         (l->block_order == 0 || l->block_order == 1);
+         l->block_order >= 0 && l->block_order <= 3;
 }
 
 void apply_launch(vm_volume* vol, const vm_launch& l) {
@@ -88,7 +88,8 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   };
   const size_t H = (size_t)1 << c.hash_log2, B = (size_t)c.max_blocks,
                V = (size_t)c.max_vertices, C = B * kVox;
-  const size_t scan = (V > C ? V : C) / 1024 + 2;
+  // download parts, or three counts per import part
+  const size_t scan = (V > C ? V : C) / 1024 + 2 + 3 * (B / kImportRows + 1);
   v->cnt = (Counters*)take(sizeof(Counters));
   v->vseg = (Seg*)take(sizeof(Seg) * kSegs);
   v->cseg = (Seg*)take(sizeof(Seg) * kSegs);
@@ -113,6 +114,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->st_frame = (uint32_t*)take(4 * B);
   v->frame_list = (uint32_t*)take(4 * B);
   v->frame_src = (uint32_t*)take(4 * B);
+  v->row_slot = (uint32_t*)take(4 * B);
   v->pending = (uint32_t*)take(4 * B);
   v->dirty = (uint32_t*)take(4 * B);
   v->vcand = (uint32_t*)take(4 * 8 * B);
@@ -240,14 +242,6 @@ void prof_end(vm_volume* vol, int kid, hipEvent_t a, hipStream_t s) {
 
 void prep(vm_volume* vol, int op, hipStream_t s) {
   VM_LAUNCH(vol, VM_K_COUNTERS, k_prep, dim3(1), dim3(kSegs), s, vol->dev, op, 0u);
-}
-
-// Hash slots scanned per workgroup by the frame compaction: at most 256
-// workgroups, at least 4096 slots each.
-uint32_t compact_per_wg(const VolDev& v) {
-  const uint32_t H = v.hash_mask + 1;
-  uint32_t per = (H + 255) / 256;
-  return per < 4096 ? 4096 : per;
 }
 
 // Host copy of the counters and both segment tables.
@@ -385,12 +379,17 @@ int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
   const VolDev& v = vol->dev;
   const uint32_t frame = ++vol->frame;
   vol->dl_nv = -1;
-  const uint32_t per = compact_per_wg(v);
-  const uint32_t ncompact = (v.hash_mask + per) / per;
+  // blocks are listed, and new ones numbered, in row order: a caller's
+  // spatially ordered rows give a spatially ordered pool
+  const uint32_t nparts = (uint32_t)((n + kImportRows - 1) / kImportRows);
   VM_LAUNCH(vol, VM_K_IMPORT, k_import_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), stream,
             v, slots, coords, (uint32_t)n, frame);
-  VM_LAUNCH(vol, VM_K_ASSIGN, k_frame_compact, dim3(ncompact), dim3(256), stream, v, frame,
-            vol->epoch, per);
+  VM_LAUNCH(vol, VM_K_ASSIGN, k_import_count, dim3(nparts), dim3(kImportRows), stream, v,
+            (uint32_t)n, vol->epoch);
+  VM_LAUNCH(vol, VM_K_ASSIGN, k_import_scan, dim3(1), dim3(1024), stream, v, nparts, frame,
+            vol->epoch);
+  VM_LAUNCH(vol, VM_K_ASSIGN, k_import_assign, dim3(nparts), dim3(kImportRows), stream, v,
+            (uint32_t)n, nparts, vol->epoch);
   VM_LAUNCH_W(vol, VM_K_IMPORT, k_import_copy, stream, v, tsdf, weight, frame, rows);
   vol->have_fp = false;
   return launched();

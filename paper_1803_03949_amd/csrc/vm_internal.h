@@ -139,6 +139,7 @@ struct VolDev {
   uint32_t* st_frame;         // [B] last frame that fused the block
   uint32_t* frame_list;       // [B] pool index | kNewFlag
   uint32_t* frame_src;        // [B] import: source row of each entry
+  uint32_t* row_slot;         // [B] import: hash slot of each source row (kNone if refused)
   uint32_t* pending;          // [B]
   uint32_t* dirty;            // [B]
   uint32_t* vcand;            // [8B] vertex-block candidates of each dirty block
@@ -170,16 +171,28 @@ __device__ inline void block_frame(const VolDev& v, int& bx, int& slot) {
 }
 
 // Items of a loop shared by `lanes` workers per workgroup (waves or whole
-// workgroups, lanes = 1): strided (item i to workgroup i / lanes mod grid)
-// or contiguous runs of about n / grid items per workgroup.
+// workgroups, lanes = 1).  Order bit 0: strided (item i to workgroup
+// i / lanes mod grid) or contiguous runs of about n / grid items per
+// workgroup.  Bit 1: the list is first cut into 8 equal contiguous ranges,
+// one per XCD (workgroup b runs on XCD b mod 8, and each XCD has an L2 of
+// its own), which that XCD's workgroups then share as bit 0 says; so
+// neighbouring list entries are handled under one L2.
 struct ItemLoop {
   uint32_t i, end, step;
 };
 __device__ inline ItemLoop item_loop(const VolDev& v, uint32_t n, uint32_t lanes, uint32_t lane) {
-  if (v.order == 0) return {blockIdx.x * lanes + lane, n, gridDim.x * lanes};
-  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
-  const uint32_t b = min(n, blockIdx.x * per);
-  return {b + lane, min(n, b + per), lanes};
+  uint32_t lo = 0, hi = n, wg = blockIdx.x, groups = gridDim.x;
+  if ((v.order & 2u) && gridDim.x >= 8) {
+    const uint32_t x = blockIdx.x & 7u;
+    lo = (uint32_t)((uint64_t)n * x / 8);
+    hi = (uint32_t)((uint64_t)n * (x + 1) / 8);
+    wg = blockIdx.x >> 3;
+    groups = (gridDim.x >> 3) + (x < (gridDim.x & 7u) ? 1u : 0u);
+  }
+  if ((v.order & 1u) == 0) return {lo + wg * lanes + lane, hi, groups * lanes};
+  const uint32_t per = (hi - lo + groups - 1) / groups;
+  const uint32_t b = min(hi, lo + wg * per);
+  return {b + lane, min(hi, b + per), lanes};
 }
 
 // Per-frame camera parameters, passed by value.
@@ -521,7 +534,10 @@ __global__ void k_collect(VolDev v, FrameParams fp, const float* __restrict__ de
 __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
                                 const int32_t* __restrict__ coords, uint32_t n,
                                 uint32_t frame);
-__global__ void k_frame_compact(VolDev v, uint32_t frame, uint32_t epoch, uint32_t per_wg);
+__global__ void k_import_count(VolDev v, uint32_t n, uint32_t epoch);
+__global__ void k_import_scan(VolDev v, uint32_t nparts, uint32_t frame, uint32_t epoch);
+__global__ void k_import_assign(VolDev v, uint32_t n, uint32_t nparts, uint32_t epoch);
+constexpr int kImportRows = 256;  // import rows per workgroup of the row-order compaction
 template <int W>
 __global__ void k_fuse(VolDev v, FrameParams fp, const float* __restrict__ depth);
 template <int W>

@@ -291,6 +291,7 @@ __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
     v.cnt->acc[VM_TOTAL_FRAMES] += 1;
   }
   if (i >= n) return;
+  v.row_slot[i] = kNone;  // until the row's key is in the table
   int x = coords[3 * i];
   const int y = coords[3 * i + 1], z = coords[3 * i + 2];
   if (slots) {
@@ -312,102 +313,106 @@ __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
   }
   v.slot_stamp[s] = frame;
   v.slot_src[s] = i;
+  v.row_slot[i] = (uint32_t)s;
 }
 
-// Scan a contiguous range of hash slots per workgroup for the slots this
-// frame stamped: give new keys a pool index, publish it, and append the
-// blocks to the frame list and (once per extraction epoch) to the pending
-// list.  Two passes over the range: count, one atomic per list, write.
-__global__ __launch_bounds__(256) void k_frame_compact(VolDev v, uint32_t frame, uint32_t epoch,
-                                                       uint32_t per_wg) {
+// Row-order compaction of an import.  Of the rows naming one key, the row
+// recorded last in its slot speaks for it.  Such a row lists its block in
+// the frame list, numbers it when it is new and adds it to the pending list
+// once per extraction epoch, all in row order: counts per part of
+// kImportRows rows, one workgroup's scan over the parts, then the writes.
+struct ImportRow {
+  uint32_t s;       // hash slot
+  uint32_t idx;     // pool index, kPending when new
+  bool hit, fresh, pend;
+};
+__device__ inline ImportRow import_row(const VolDev& v, uint32_t i, uint32_t n, uint32_t epoch) {
+  ImportRow r{kNone, kNone, false, false, false};
+  if (i >= n) return r;
+  r.s = v.row_slot[i];
+  if (r.s == kNone || v.slot_src[r.s] != i) return r;
+  r.hit = true;
+  r.idx = (uint32_t)(v.slots[r.s] & kIdxMask);
+  r.fresh = r.idx == kPending;
+  r.pend = r.fresh || v.st_pending[r.idx] != epoch;
+  return r;
+}
+
+__global__ __launch_bounds__(kImportRows) void k_import_count(VolDev v, uint32_t n,
+                                                               uint32_t epoch) {
   __shared__ uint32_t swave[16];
-  __shared__ uint32_t sbase[3];
-  const uint32_t H = v.hash_mask + 1;
-  const uint32_t b0 = blockIdx.x * per_wg;
-  if (b0 >= H) return;
-  const uint32_t b1 = min(H, b0 + per_wg);
-  // stamps of 16 slots per lane per round, loaded before they are examined
-  constexpr int kR = 16;
-  uint32_t nhit = 0, nnew = 0, npend = 0;
-  for (uint32_t r0 = b0; r0 < b1; r0 += kR * blockDim.x) {
-    uint32_t stamp[kR];
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      const uint32_t s = r0 + r * blockDim.x + threadIdx.x;
-      stamp[r] = s < b1 ? v.slot_stamp[s] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      if (stamp[r] != frame) continue;
-      const uint32_t s = r0 + r * blockDim.x + threadIdx.x;
-      ++nhit;
-      const uint32_t idx = (uint32_t)(v.slots[s] & kIdxMask);
-      if (idx == kPending) ++nnew, ++npend;
-      else npend += v.st_pending[idx] != epoch;
-    }
-  }
+  const ImportRow r = import_row(v, blockIdx.x * kImportRows + threadIdx.x, n, epoch);
   uint32_t t_hit, t_new, t_pend;
-  uint32_t r_hit = wg_scan(nhit, swave, &t_hit);
-  uint32_t r_new = wg_scan(nnew, swave, &t_new);
-  uint32_t r_pend = wg_scan(npend, swave, &t_pend);
-  if (t_hit == 0) return;
+  wg_scan_bits<1>(r.hit, swave, &t_hit);
+  wg_scan_bits<1>(r.fresh, swave, &t_new);
+  wg_scan_bits<1>(r.pend, swave, &t_pend);
   if (threadIdx.x == 0) {
-    sbase[0] = atomicAdd(&v.cnt->n_frame[frame & 1], t_hit);
-    sbase[1] = t_new ? atomicAdd(&v.cnt->n_blocks, t_new) : 0u;
-    sbase[2] = t_pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], t_pend) : 0u;
+    v.scan[3 * blockIdx.x] = t_hit;
+    v.scan[3 * blockIdx.x + 1] = t_new;
+    v.scan[3 * blockIdx.x + 2] = t_pend;
   }
+}
+
+// Exclusive scans of the three per-part counts, offset by the list lengths
+// and the pool high-water mark, which then grow by the totals.
+__global__ __launch_bounds__(1024) void k_import_scan(VolDev v, uint32_t nparts, uint32_t frame,
+                                                      uint32_t epoch) {
+  __shared__ uint32_t swave[16];
+  __shared__ uint32_t carry[3];
+  uint32_t* len[3] = {&v.cnt->n_frame[frame & 1], &v.cnt->n_blocks, &v.cnt->n_pending[epoch & 1]};
+  if (threadIdx.x < 3) carry[threadIdx.x] = *len[threadIdx.x];
   __syncthreads();
-  r_hit += sbase[0];
-  r_new += sbase[1];
-  r_pend += sbase[2];
-  for (uint32_t r0 = b0; r0 < b1; r0 += kR * blockDim.x) {
-    uint32_t stamp[kR];
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      const uint32_t s = r0 + r * blockDim.x + threadIdx.x;
-      stamp[r] = s < b1 ? v.slot_stamp[s] : 0u;
+  for (uint32_t base = 0; base < nparts; base += 1024) {
+    const uint32_t p = base + threadIdx.x;
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t x = p < nparts ? v.scan[3 * p + k] : 0u;
+      uint32_t all;
+      const uint32_t before = wg_scan(x, swave, &all);
+      if (p < nparts) v.scan[3 * p + k] = carry[k] + before;
+      __syncthreads();
+      if (threadIdx.x == 0) carry[k] += all;
+      __syncthreads();
     }
-    for (int r = 0; r < kR; ++r) {
-      if (stamp[r] != frame) continue;
-      const uint32_t s = r0 + r * blockDim.x + threadIdx.x;
-      const unsigned long long val = v.slots[s];
-      uint32_t idx = (uint32_t)(val & kIdxMask);
-      uint32_t entry;
-      bool pend;
-      if (idx == kPending) {
-        const uint32_t t = r_new++;
-        pend = true;
-        if (t < v.max_blocks) {
-          idx = t;
-          const uint64_t key = val >> kIdxBits;
-          v.slots[s] = (key << kIdxBits) | idx;
-          v.block_key[idx] = key;
-          int32_t* nb = v.nbr + (size_t)idx * 27;
-          for (int d = 0; d < 27; ++d) nb[d] = d == kSelf ? (int32_t)idx : -1;
-          entry = idx | kNewFlag;
-        } else {
-          atomicOr(&v.cnt->error, kErrBlocks);
-          idx = kNone;
-          entry = kNone;
-        }
-      } else {
-        entry = idx;
-        pend = v.st_pending[idx] != epoch;
-      }
-      const uint32_t pos = r_hit++;
-      if (pos < v.max_blocks) {
-        v.frame_list[pos] = entry;
-        v.frame_src[pos] = v.slot_src[s];
-      } else {
-        atomicOr(&v.cnt->error, kErrBlocks);
-      }
-      if (pend) {
-        const uint32_t p = r_pend++;
-        if (idx != kNone) v.st_pending[idx] = epoch;
-        if (p < v.max_blocks) v.pending[p] = idx;
-        else atomicOr(&v.cnt->error, kErrBlocks);
-      }
+  }
+  if (threadIdx.x < 3) *len[threadIdx.x] = carry[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kImportRows) void k_import_assign(VolDev v, uint32_t n,
+                                                                uint32_t nparts, uint32_t epoch) {
+  __shared__ uint32_t swave[16];
+  const uint32_t i = blockIdx.x * kImportRows + threadIdx.x;
+  const ImportRow r = import_row(v, i, n, epoch);
+  uint32_t t_hit, t_new, t_pend;
+  const uint32_t pos = v.scan[3 * blockIdx.x] + wg_scan_bits<1>(r.hit, swave, &t_hit);
+  const uint32_t t = v.scan[3 * blockIdx.x + 1] + wg_scan_bits<1>(r.fresh, swave, &t_new);
+  const uint32_t p = v.scan[3 * blockIdx.x + 2] + wg_scan_bits<1>(r.pend, swave, &t_pend);
+  if (!r.hit) return;
+  uint32_t idx = r.idx, entry = r.idx;
+  if (r.fresh) {
+    if (t < v.max_blocks) {
+      idx = t;
+      const uint64_t key = v.slots[r.s] >> kIdxBits;
+      v.slots[r.s] = (key << kIdxBits) | idx;
+      v.block_key[idx] = key;
+      int32_t* nb = v.nbr + (size_t)idx * 27;
+      for (int d = 0; d < 27; ++d) nb[d] = d == kSelf ? (int32_t)idx : -1;
+      entry = idx | kNewFlag;
+    } else {
+      atomicOr(&v.cnt->error, kErrBlocks);
+      idx = kNone;
+      entry = kNone;
     }
+  }
+  if (pos < v.max_blocks) {
+    v.frame_list[pos] = entry;
+    v.frame_src[pos] = i;
+  } else {
+    atomicOr(&v.cnt->error, kErrBlocks);
+  }
+  if (r.pend) {
+    if (idx != kNone) v.st_pending[idx] = epoch;
+    if (p < v.max_blocks) v.pending[p] = idx;
+    else atomicOr(&v.cnt->error, kErrBlocks);
   }
 }
 

@@ -124,7 +124,7 @@ def test_graph_replays_match_eager():
 
 
 @pytest.mark.parametrize("w", [2, 4, 8])
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_every_mapping_gives_identical_bits(w, order):
     vols, coords, tsdf, weight, centers, radii = workload(n=4, seed=10)
     b = BatchMesher(S, coords, tsdf, weight, sphere_loss_grad(centers, radii))
