@@ -671,12 +671,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     const uint32_t i = it.i;
     const uint32_t idx = uniform(v.dirty[i]);
     const int32_t mynb = q < 8 ? v.nbr[(size_t)idx * 27 + nbr_dir(q & 1, (q >> 1) & 1, q >> 2)] : -1;
-    // the block's own types, independent of the halo: load them now
+    // the block's own types, independent of the halo: load them now (the
+    // previous applied types only for refinement)
     uint32_t old[8], prev[8];
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
       old[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
-      prev[lz] = v.tprev[(size_t)idx * kVox + q + 64 * lz];
+      prev[lz] = refine ? v.tprev[(size_t)idx * kVox + q + 64 * lz] : 0u;
     }
     if (q < 8) snb[q] = mynb;
     wave_sync();
