@@ -356,10 +356,34 @@ def room_fine(args, dev):
     dt = time.perf_counter() - t0
     tot = {k: v - tot0[k] for k, v in vol.totals().items()}
     st = vol.status()
+    # one more pass with every kernel bracketed by events: per-kernel rates
+    # against algorithmic bytes (classification in refine mode counted with
+    # classification: both classify dirty blocks)
+    vol.profile(True)
+    step()
+    torch.cuda.synchronize()
+    vol.profile(False)
+    prof = vol.profile_read()
+    if "refine" in prof:
+        n, ms = prof.pop("refine")
+        n0, ms0 = prof.get("classify", (0, 0.0))
+        prof["classify"] = (n0 + n, ms0 + ms)
+    algo = algorithmic_bytes(tot, depth.shape[1] * depth.shape[2])
+    kernels = {}
+    for k, (n, ms) in prof.items():
+        e = {"launches": n, "us_per_launch": round(1000 * ms / n, 3)}
+        if k in algo and ms > 0:
+            e["bytes_per_launch"] = algo[k] // max(n, 1)
+            e["GBps"] = round(algo[k] / (ms * 1e-3) / 1e9, 2)
+            e["frac_of_hbm_peak"] = round(algo[k] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+        kernels[k] = e
     out = {"frames_per_s": args.fine_frames / dt, "ms_per_frame": 1000 * dt / args.fine_frames,
            "frames": args.fine_frames, "blocks": st["blocks"],
-           "dirty_blocks_per_s": tot["dirty_blocks"] / dt, "refined_cubes": tot["refined_cubes"]}
+           "dirty_blocks_per_s": tot["dirty_blocks"] / dt, "refined_cubes": tot["refined_cubes"],
+           "kernels": kernels}
     log(f"4 mm + refine: {out['frames_per_s']:.1f} frames/s, blocks {st['blocks']}")
+    for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["us_per_launch"] * kv[1]["launches"]):
+        log(f"  {k:10s} {e}")
     del vol, depth
     torch.cuda.empty_cache()
     return out

@@ -30,19 +30,22 @@ from .binding import SLOT_SPAN, Volume
 
 def sphere_loss_grad(centers: torch.Tensor, radii: torch.Tensor):
     """dL/dp for L = sum over live vertices of (|p - c_k| - r_k)^2, with
-    (c_k, r_k) the target sphere of the vertex's volume k.  Elementwise
-    operations only (no reductions), so the function can be graph-captured,
-    and every entry goes through the same operations in the same order
-    whatever the pool size.  Entries with slot -1 (no vertex) get 0."""
-    centers = centers.reshape(-1, 3).contiguous()
-    radii = radii.reshape(-1).contiguous()
+    (c_k, r_k) the target sphere of the vertex's volume k.  No reduction
+    across entries, so the function can be graph-captured, and every entry
+    goes through the same operations whatever the pool size.  Entries with
+    slot -1 (no vertex, position 0) index an extra sphere of radius 0 at the
+    origin, whose gradient at the origin is 0."""
+    dev = centers.device
+    zero = torch.zeros(1, dtype=torch.float32, device=dev)
+    centers = torch.cat([centers.reshape(-1, 3).float(), zero.expand(1, 3)]).contiguous()
+    radii = torch.cat([radii.reshape(-1).float(), zero]).contiguous()
+    rows = centers.shape[0]
 
     def grad(pos: torch.Tensor, slot: torch.Tensor, out: torch.Tensor):
-        k = slot.clamp(min=0).long()
+        k = slot.remainder(rows)  # -1 -> the extra sphere
         d = pos - centers.index_select(0, k)
-        dd = d * d
-        dist = (dd[:, 0] + dd[:, 1]).add_(dd[:, 2]).sqrt_().clamp_min_(1e-30)
-        scale = torch.where(slot >= 0, 2.0 * (dist - radii.index_select(0, k)) / dist, 0.0)
+        dist = torch.linalg.vector_norm(d, dim=1).clamp_min_(1e-30)
+        scale = (dist - radii.index_select(0, k)).div_(dist).mul_(2.0)
         return torch.mul(d, scale[:, None], out=out)
 
     return grad
