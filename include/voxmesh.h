@@ -79,8 +79,8 @@ enum { VM_SCOPE_DIRTY = 0, VM_SCOPE_ALL = 1 };
 /* Volume configuration.  Sizes are capacities of the caller buffer: per
  * block of max_blocks about 51 KiB (TSDF and weight 4 KiB, types 1 KiB,
  * vertex slot, t and count of its 1536 owned edges 13.5 KiB, the triangles
- * of its 512 cubes 32 KiB) and per vertex of max_vertices 16 bytes, plus 16
- * bytes per hash slot. */
+ * of its 512 cubes 32 KiB, a 64-byte mask of its observed voxels) and per
+ * vertex of max_vertices 16 bytes, plus 16 bytes per hash slot. */
 typedef struct vm_config {
   float voxel_m;        /* cube edge length s in metres (e.g. 0.008) */
   float trunc_vox;      /* truncation mu in voxel units (e.g. 4) */

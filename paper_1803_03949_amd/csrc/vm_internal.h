@@ -12,7 +12,8 @@
 //             weight f32[512], previous/current cube type u8[512],
 //             edge->vertex slot i32[3][512] (the three edges every voxel
 //             owns), cube->triangle chunk i32[512], changed-cube bitmask
-//             u64[8], pass stamps.
+//             u64[8], observed-voxel (weight > 0) bitmask u64[8], pass
+//             stamps.
 //   vertices  per edge (block-local, next to the edge->vertex slot): the
 //             vertex's t f32 and reference count u8; per pool slot: owner
 //             edge (index into the edge arrays, kNone when free), recycle
@@ -133,6 +134,7 @@ struct VolDev {
   float* et;                  // [B][3][512] t of the edge's vertex
   uint8_t* eref;              // [B][3][512] reference count of the edge's vertex
   uint64_t* chg;              // [B][8] by dirty-list position and z layer: cubes whose triangles changed
+  uint64_t* wmask;            // [B][8] per z layer: voxels with weight > 0 (bit x + 8y)
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
   uint32_t* st_vtx;           // [B] pass that listed the block for vertices

@@ -511,6 +511,8 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
         v.d[o] = d[lz];
         v.w[o] = w[lz];
       }
+      const uint64_t m = __ballot(fs.upd || w[lz] > 0.f);
+      if (q == 0) v.wmask[(size_t)idx * 8 + lz] = m;
     }
     if (q == 0) v.st_frame[idx] = fp.frame;
   }
@@ -547,6 +549,8 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
     for (int lz = 0; lz < 8; ++lz) {
       v.d[(size_t)idx * kVox + q + 64 * lz] = d[lz];
       v.w[(size_t)idx * kVox + q + 64 * lz] = w[lz];
+      const uint64_t m = __ballot(w[lz] > 0.f);
+      if (q == 0) v.wmask[(size_t)idx * 8 + lz] = m;
     }
     if (q == 0) {
       v.st_frame[idx] = frame;
@@ -682,19 +686,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     if (q < 8) snb[q] = mynb;
     wave_sync();
     {
-      // all loads of the 9^3 halo first, then the LDS stores
-      float dv[12], wv[12];
+      // all loads of the 9^3 halo first, then the LDS stores; whether a
+      // corner is observed comes from its block's weight mask (one 64-byte
+      // line per block) rather than from the weights
+      float dv[12];
+      uint32_t ok = 0;
 #pragma unroll
       for (int it = 0; it < 12; ++it) {
         const int j = q + 64 * it;
-        dv[it] = 0.f, wv[it] = 0.f;
+        dv[it] = 0.f;
         if (j < 729) {
           const int x = j % 9, y = (j / 9) % 9, z = j / 81;
           const int nb = snb[(x >> 3) | ((y >> 3) << 1) | ((z >> 3) << 2)];
           if (nb >= 0) {
-            const size_t o = (size_t)nb * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7);
-            dv[it] = v.d[o];
-            wv[it] = v.w[o];
+            const int l = (x & 7) + 8 * (y & 7);
+            dv[it] = v.d[(size_t)nb * kVox + l + 64 * (z & 7)];
+            const uint32_t* mw = reinterpret_cast<const uint32_t*>(v.wmask);
+            ok |= ((mw[((size_t)nb * 8 + (z & 7)) * 2 + (l >> 5)] >> (l & 31)) & 1u) << it;
           }
         }
       }
@@ -703,7 +711,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
         const int j = q + 64 * it;
         if (j < 729) {
           sd[j] = dv[it];
-          sok[j] = wv[it] > 0.f;
+          sok[j] = (ok >> it) & 1u;
         }
       }
     }
