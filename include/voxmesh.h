@@ -326,6 +326,21 @@ int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
                     const float* tsdf, const float* weight, int64_t n,
                     int32_t* rows, hipStream_t stream);
 
+/* Use caller memory as the volume's TSDF and weight storage, so that an
+ * import does not copy them (many volumes imported again for every
+ * forward + backward, as in a training loop).  tsdf, weight: device,
+ * max_blocks*512 FP32 each, in pool row order (row r = the block at pool
+ * row r), 4-byte aligned, owned by the caller, who keeps them alive and
+ * does not write them while the volume uses them; both NULL returns the
+ * volume to its own arrays (their contents are then undefined).  While
+ * bound, vm_import_blocks / vm_import_batch must pass these same two
+ * pointers (else VM_ERR_ARG), and every imported row must become the pool
+ * row of the same number (import into an empty volume, distinct keys, see
+ * vm_import_blocks); a row that does not sets VM_ERR_RANGE.  Fusion writes
+ * the bound arrays.  Takes effect for calls made after it; kernels already
+ * enqueued keep the arrays they were given. */
+int vm_bind_tsdf(vm_volume* vol, float* tsdf, float* weight);
+
 /* Positions of every vertex pool entry, uncompacted and without
  * synchronising (for graph capture): pos (device, cap*3 FP32 metres, slot
  * frame) and slot_of (device int32 cap, may be NULL) get, for each entry

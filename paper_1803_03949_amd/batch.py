@@ -74,11 +74,16 @@ class BatchMesher:
 
     coords: list of (n_i, 3) int32 block coordinates, 0 <= x <= 62;
     tsdf, weight: (sum n_i, 512) FP32 device tensors in the same order.
+    With zero_copy (the default) the volume uses tsdf and weight as its own
+    storage (`Volume.bind_tsdf`): every import numbers the blocks in input
+    order into the emptied volume, so row i of the tensors is pool row i and
+    nothing is copied; the tensors must stay alive and unchanged between
+    runs, or change only through the caller's own updates between them.
     After `run()` (eager) or `replay()` (graph), `grad` holds dL/dTSDF in the
     input order, `pos`/`slot` the vertex positions per pool entry."""
 
     def __init__(self, voxel_m: float, coords: list, tsdf: torch.Tensor, weight: torch.Tensor,
-                 loss_grad, trunc_vox: float = 4.0):
+                 loss_grad, trunc_vox: float = 4.0, zero_copy: bool = True):
         self.n_vol = len(coords)
         sizes = [int(len(c)) for c in coords]
         self.sizes = sizes
@@ -96,6 +101,8 @@ class BatchMesher:
                                                 sizes)).to(dev)
         self.tsdf = tsdf
         self.weight = weight
+        if zero_copy:
+            self.vol.bind_tsdf(tsdf, weight)
         self.rows = torch.empty(N, dtype=torch.int32, device=dev)
         self.pos = torch.empty((V, 3), dtype=torch.float32, device=dev)
         self.slot = torch.empty(V, dtype=torch.int32, device=dev)
@@ -142,7 +149,7 @@ class PlainMesher:
     """The same step volume by volume, each in its own plain volume."""
 
     def __init__(self, voxel_m: float, coords: list, tsdf: torch.Tensor, weight: torch.Tensor,
-                 loss_grads: list, trunc_vox: float = 4.0):
+                 loss_grads: list, trunc_vox: float = 4.0, zero_copy: bool = True):
         self.vols, self.items = [], []
         off = 0
         for i, c in enumerate(coords):
@@ -161,6 +168,8 @@ class PlainMesher:
                 dpos=torch.zeros((V, 3), dtype=torch.float32, device=dev),
                 grad=torch.empty((n, 512), dtype=torch.float32, device=dev),
                 loss_grad=loss_grads[i]))
+            if zero_copy:
+                vol.bind_tsdf(self.items[-1]["tsdf"], self.items[-1]["weight"])
             self.vols.append(vol)
             off += n
 

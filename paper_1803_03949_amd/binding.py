@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
             "vm_download_normals": [P, P, I64, P],
             "vm_download_births": [P, P, I64, P],
             "vm_sharing_ablation": [P, ctypes.c_int, P, P, P, P],
+            "vm_bind_tsdf": [P, P, P],
             "vm_extract_backward": [P, P, P, P],
             "vm_integrate_backward": [P, P, P, P, P, P],
             "vm_get_status": [P, ctypes.POINTER(vm_status), P],
@@ -193,9 +194,24 @@ class Volume:
         n = coords.shape[0]
         assert coords.is_cuda and coords.dtype == torch.int32 and coords.is_contiguous()
         assert tsdf.dtype == torch.float32 and weight.dtype == torch.float32
-        assert tsdf.numel() == 512 * n and weight.numel() == 512 * n
+        assert tsdf.numel() >= 512 * n and weight.numel() >= 512 * n  # rows 0..n-1 are read
         _check(lib().vm_import_blocks(self.h, _ptr(coords), _ptr(tsdf), _ptr(weight), n,
                                       _stream(stream)), "vm_import_blocks")
+
+    def bind_tsdf(self, tsdf: torch.Tensor | None, weight: torch.Tensor | None):
+        """Use (max_blocks, 512) FP32 device tensors as the volume's TSDF and
+        weight storage (imports then pass these same tensors and copy
+        nothing); None, None returns to the volume's own arrays."""
+        if tsdf is None and weight is None:
+            _check(lib().vm_bind_tsdf(self.h, None, None), "vm_bind_tsdf")
+            self._bound = None
+            return
+        B = self.cfg.max_blocks
+        for t in (tsdf, weight):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+            assert t.numel() == 512 * B
+        _check(lib().vm_bind_tsdf(self.h, _ptr(tsdf), _ptr(weight)), "vm_bind_tsdf")
+        self._bound = (tsdf, weight)  # kept alive while bound
 
     def import_batch(self, slots: torch.Tensor | None, coords: torch.Tensor, tsdf: torch.Tensor,
                      weight: torch.Tensor, rows: torch.Tensor | None = None, stream=None):
@@ -204,7 +220,7 @@ class Volume:
         n = coords.shape[0]
         assert coords.is_cuda and coords.dtype == torch.int32 and coords.is_contiguous()
         assert tsdf.dtype == torch.float32 and weight.dtype == torch.float32
-        assert tsdf.numel() == 512 * n and weight.numel() == 512 * n
+        assert tsdf.numel() >= 512 * n and weight.numel() >= 512 * n  # rows 0..n-1 are read
         if slots is not None:
             assert slots.is_cuda and slots.dtype == torch.int32 and slots.numel() == n
         if rows is not None:

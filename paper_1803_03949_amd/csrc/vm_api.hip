@@ -27,6 +27,8 @@ struct vm_volume {
   char* mem;
   size_t bytes;
   VolDev dev;
+  float* own_d;     // the workspace's TSDF and weight arrays (d, w when unbound)
+  float* own_w;
   uint32_t frame;   // last frame number handed to the device
   uint32_t epoch;   // extraction epoch (pending-list stamps)
   uint32_t pass;    // dirty / vertex-list stamps
@@ -299,6 +301,9 @@ int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes, hipStrea
     return VM_ERR_HIP;
   }
   v.batch = (uint32_t)cfg->batch_volumes;
+  v.bound = 0;
+  vol->own_d = v.d;
+  vol->own_w = v.w;
   vol->cus = cus;
   apply_launch(vol, vm_launch{4, 16, 8, 8, 0});
   vol->prof = 0;
@@ -374,7 +379,8 @@ int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
                     const float* tsdf, const float* weight, int64_t n, int32_t* rows,
                     hipStream_t stream) {
   if (!vol || n < 0 || n > (int64_t)vol->dev.max_blocks ||
-      (n > 0 && (!coords || !tsdf || !weight)) || (vol->dev.batch != 0) != (slots != nullptr))
+      (n > 0 && (!coords || !tsdf || !weight)) || (vol->dev.batch != 0) != (slots != nullptr) ||
+      (vol->dev.bound && n > 0 && (tsdf != vol->dev.d || weight != vol->dev.w)))
     return VM_ERR_ARG;
   if (n == 0) return VM_OK;
   const VolDev& v = vol->dev;
@@ -394,6 +400,17 @@ int vm_import_batch(vm_volume* vol, const int32_t* slots, const int32_t* coords,
   VM_LAUNCH_W(vol, VM_K_IMPORT, k_import_copy, stream, v, tsdf, weight, frame, rows);
   vol->have_fp = false;
   return launched();
+}
+
+int vm_bind_tsdf(vm_volume* vol, float* tsdf, float* weight) {
+  if (!vol || (tsdf == nullptr) != (weight == nullptr) || ((uintptr_t)tsdf & 3) ||
+      ((uintptr_t)weight & 3))
+    return VM_ERR_ARG;
+  VolDev& v = vol->dev;
+  v.d = tsdf ? tsdf : vol->own_d;
+  v.w = weight ? weight : vol->own_w;
+  v.bound = tsdf ? 1u : 0u;
+  return VM_OK;
 }
 
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {

@@ -154,6 +154,7 @@ struct VolDev {
   uint32_t* scan;             // [scan_cap] download partial sums
   uint32_t scan_cap;
   uint32_t batch;             // number of volume slots, 0 for a plain volume
+  uint32_t bound;             // d and w are the caller's arrays (vm_bind_tsdf)
   uint32_t order;             // 0: strided block-to-workgroup mapping, 1: runs
 };
 

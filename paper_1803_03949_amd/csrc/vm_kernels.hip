@@ -520,7 +520,9 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
 
 // One wave per imported block, eight voxels per lane: the caller's rows are
 // read first, then the new block is initialised and linked while they
-// arrive.
+// arrive.  With bound arrays (the caller's rows are the volume's TSDF and
+// weights) a block must land on its own row, and only the weights are read,
+// for the observed-voxel mask.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* __restrict__ tsdf,
                                                         const float* __restrict__ weight,
@@ -534,10 +536,14 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
     if (e == kNone) continue;
     const int q = fresh_lane();
     const uint32_t idx = e & ~kNewFlag;
+    if (v.bound && idx != row) {
+      if (q == 0) atomicOr(&v.cnt->error, kErrRange);
+      continue;
+    }
     float d[8], w[8];
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
-      d[lz] = tsdf[(size_t)row * kVox + q + 64 * lz];
+      d[lz] = v.bound ? 0.f : tsdf[(size_t)row * kVox + q + 64 * lz];
       w[lz] = weight[(size_t)row * kVox + q + 64 * lz];
     }
     if (e & kNewFlag) {
@@ -547,8 +553,10 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
     }
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
-      v.d[(size_t)idx * kVox + q + 64 * lz] = d[lz];
-      v.w[(size_t)idx * kVox + q + 64 * lz] = w[lz];
+      if (!v.bound) {
+        v.d[(size_t)idx * kVox + q + 64 * lz] = d[lz];
+        v.w[(size_t)idx * kVox + q + 64 * lz] = w[lz];
+      }
       const uint64_t m = __ballot(w[lz] > 0.f);
       if (q == 0) v.wmask[(size_t)idx * 8 + lz] = m;
     }

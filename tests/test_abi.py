@@ -27,7 +27,7 @@ def test_header_declares_the_method_calls():
                      "vm_refine_mesh", "vm_gc", "vm_download_mesh", "vm_extract_backward",
                      "vm_integrate_backward", "vm_import_batch", "vm_export_positions",
                      "vm_extract_backward_slots", "vm_set_launch", "vm_download_normals",
-                     "vm_download_births"]:
+                     "vm_download_births", "vm_bind_tsdf"]:
         assert required in names
 
 
@@ -137,3 +137,4 @@ def test_null_arguments_are_rejected():
     assert L.vm_set_launch(None, None) == -1
     assert L.vm_download_normals(None, None, 0, None) == -1
     assert L.vm_download_births(None, None, 0, None) == -1
+    assert L.vm_bind_tsdf(None, None, None) == -1
