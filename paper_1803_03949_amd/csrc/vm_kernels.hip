@@ -665,15 +665,15 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
 // and, for cubes on its +x/+y/+z faces, neighbours).
 template <int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(VolDev v, uint32_t pass, int refine) {
-  __shared__ float sd_all[W][729];
-  __shared__ uint8_t sok_all[W][732];
+  __shared__ float sd_all[W][729];     // TSDF (refinement only)
+  __shared__ uint8_t sbits_all[W][732]; // bit 0: TSDF < 0, bit 1: observed
   __shared__ int32_t snb_all[W][8];
   __shared__ uint8_t sntri[256];  // triangles of each cube type
   for (int j = threadIdx.x; j < 256; j += blockDim.x) sntri[j] = v.tri_table[j * 16];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* sd = sd_all[wave];
-  uint8_t* sok = sok_all[wave];
+  uint8_t* sbits = sbits_all[wave];
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
   const int coff[8] = {0, 1, 1 + 9, 9, 81, 1 + 81, 1 + 9 + 81, 9 + 81};
@@ -697,54 +697,73 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       // all loads of the 9^3 halo first, then the LDS stores; whether a
       // corner is observed comes from its block's weight mask (one 64-byte
       // line per block) rather than from the weights
+      // cell j = q + 64 it sits at x + 9y + 81z; as j steps by 64 = 7*9 + 1,
+      // (x, y, z) steps by (1, 7, 0) with carries.  Byte offsets from the
+      // arrays' bases fit 32 bits (at most 2^21 blocks of 2 KiB).
+      const char* dbase = reinterpret_cast<const char*>(v.d);
+      const char* mbase = reinterpret_cast<const char*>(v.wmask);
       float dv[12];
       uint32_t ok = 0;
+      int x = q % 9, y = q / 9, z = 0;
 #pragma unroll
       for (int it = 0; it < 12; ++it) {
         const int j = q + 64 * it;
         dv[it] = 0.f;
         if (j < 729) {
-          const int x = j % 9, y = (j / 9) % 9, z = j / 81;
           const int nb = snb[(x >> 3) | ((y >> 3) << 1) | ((z >> 3) << 2)];
           if (nb >= 0) {
-            const int l = (x & 7) + 8 * (y & 7);
-            dv[it] = v.d[(size_t)nb * kVox + l + 64 * (z & 7)];
-            const uint32_t* mw = reinterpret_cast<const uint32_t*>(v.wmask);
-            ok |= ((mw[((size_t)nb * 8 + (z & 7)) * 2 + (l >> 5)] >> (l & 31)) & 1u) << it;
+            const uint32_t l = (uint32_t)((x & 7) + 8 * (y & 7)), lz = (uint32_t)(z & 7);
+            dv[it] = *reinterpret_cast<const float*>(dbase + ((uint32_t)nb * 2048u +
+                                                              (l + 64u * lz) * 4u));
+            const uint32_t mword = *reinterpret_cast<const uint32_t*>(
+                mbase + ((uint32_t)nb * 64u + lz * 8u + (l >> 5) * 4u));
+            ok |= ((mword >> (l & 31u)) & 1u) << it;
           }
         }
+        x += 1;
+        y += 7;
+        if (x == 9) x = 0, ++y;
+        if (y >= 9) y -= 9, ++z;
       }
 #pragma unroll
       for (int it = 0; it < 12; ++it) {
         const int j = q + 64 * it;
         if (j < 729) {
-          sd[j] = dv[it];
-          sok[j] = (ok >> it) & 1u;
+          if (refine) sd[j] = dv[it];
+          sbits[j] = (uint8_t)((dv[it] < 0.f ? 1u : 0u) | (((ok >> it) & 1u) << 1));
         }
       }
     }
     wave_sync();
     uint32_t flags = 0, nchanged = 0;
     int dtri = 0, dtcube = 0;  // change of the triangle and triangle-cube counts
+    // the lane's column of cubes shares corner faces between layers: face
+    // z holds the signs of corners (x, y), (x+1, y), (x+1, y+1), (x, y+1) at
+    // height z in bits 0..3 (the cyclic corner order) and, in bit 4, whether
+    // all four are observed; cube z is faces z and z+1
+    auto face = [&](int z) -> uint32_t {
+      const int b = lx + 9 * ly + 81 * z;
+      const uint32_t c0 = sbits[b], c1 = sbits[b + 1], c2 = sbits[b + 10], c3 = sbits[b + 9];
+      return (c0 & 1u) | ((c1 & 1u) << 1) | ((c2 & 1u) << 2) | ((c3 & 1u) << 3) |
+             ((c0 & c1 & c2 & c3 & 2u) << 3);
+    };
+    uint32_t f_lo = face(0);
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
-      const int base = lx + 9 * ly + 81 * lz;
-      bool valid = true;
-      uint32_t t = 0;
-      float dc[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        valid = valid && sok[base + coff[k]];
-        dc[k] = sd[base + coff[k]];
-        t |= (uint32_t)(dc[k] < 0.f) << k;
-      }
-      if (!valid) t = 0;
+      const uint32_t f_hi = face(lz + 1);
+      const bool valid = (f_lo & f_hi & 16u) != 0;
+      const uint32_t t = valid ? (f_lo & 15u) | ((f_hi & 15u) << 4) : 0u;
+      f_lo = f_hi;
       const size_t o = (size_t)idx * kVox + q + 64 * lz;
       uint32_t nt;
       if (!refine) {
         v.tprev[o] = (uint8_t)old[lz];
         nt = t;
       } else {
+        const int base = lx + 9 * ly + 81 * lz;
+        float dc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dc[k] = sd[base + coff[k]];
         nt = valid ? refine_type(old[lz], prev[lz], dc, v.eps) : old[lz];
       }
       if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
