@@ -890,6 +890,18 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
     const uint32_t idx = uniform(v.vblocks[it.i]);
     const uint32_t sg = uniform(idx % v.nseg);
+    // the block's edge arrays, addressed by block-local edge a * 512 + l;
+    // pool and halo arrays by 32-bit byte offsets from their bases (every
+    // index here is below 2^30 entries of 4 bytes)
+    const size_t eb = (size_t)idx * (3 * kVox);
+    int32_t* evtx_b = v.evtx + eb;
+    float* et_b = v.et + eb;
+    uint8_t* eref_b = v.eref + eb;
+    const uint8_t* tcur_bytes = v.tcur;
+    const char* d_bytes = reinterpret_cast<const char*>(v.d);
+    auto pool32 = [](uint32_t* base, uint32_t s) -> uint32_t& {
+      return *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + s * 4u);
+    };
     // requested at once: the neighbour table, the block's edge slots and
     // its pool segment (fixed during this kernel)
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
@@ -904,7 +916,7 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
 #pragma unroll
       for (int lz = 0; lz < 8; ++lz)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) er[3 * lz + a] = v.eref[((size_t)idx * 3 + a) * kVox + q + 64 * lz];
+        for (int a = 0; a < 3; ++a) er[3 * lz + a] = eref_b[a * kVox + q + 64 * lz];
 #pragma unroll
       for (int k = 23; k >= 0; --k)  // shifted in, so no per-bit mask constants
         has_slot = (has_slot << 1) | (uint32_t)(er[k] != 0);
@@ -937,10 +949,14 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
           int x, y, z;
           halo_cell(h, -1, x, y, z);
           const int nb = snb[nbr_dir(x < 0 ? -1 : 0, y < 0 ? -1 : 0, z < 0 ? -1 : 0)];
-          if (nb >= 0) th[r] = v.tcur[(size_t)nb * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+          if (nb >= 0)
+            th[r] = tcur_bytes[(uint32_t)nb * 512u + (uint32_t)((x & 7) + 8 * (y & 7) + 64 * (z & 7))];
           halo_cell(h, 8, x, y, z);
           const int nb2 = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
-          if (nb2 >= 0) dh[r] = v.d[(size_t)nb2 * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+          if (nb2 >= 0)
+            dh[r] = *reinterpret_cast<const float*>(
+                d_bytes + ((uint32_t)nb2 * 2048u +
+                           (uint32_t)((x & 7) + 8 * (y & 7) + 64 * (z & 7)) * 4u));
         }
       }
 #pragma unroll
@@ -1015,10 +1031,10 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     };
     // the edge's vertex is no longer used: back to the ring (k-th free of
     // this block), the edge forgets it
-    auto free_vertex = [&](size_t eo, int32_t s, uint32_t k) {
-      v.vring[gbase + ring_pos(rtail, fbase + k, gsize)] = (uint32_t)s;
-      v.vowner[s] = kNone;
-      v.eref[eo] = 0;
+    auto free_vertex = [&](uint32_t e, int32_t s, uint32_t k) {
+      pool32(v.vring, gbase + ring_pos(rtail, fbase + k, gsize)) = (uint32_t)s;
+      pool32(v.vowner, (uint32_t)s) = kNone;
+      eref_b[e] = 0;
     };
     if (nwork <= (uint32_t)kWorkCap) {
       uint32_t knew = 0, kfree = 0;
@@ -1034,7 +1050,6 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
         knew += (uint32_t)__popcll(bn);
         kfree += (uint32_t)__popcll(bf);
         if (!act) continue;
-        const size_t eo = ((size_t)idx * 3 + a) * kVox + l;
         if (ref > 0) {
           if (!has) {
             const uint32_t ns = new_slot(myk);
@@ -1042,22 +1057,22 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
               // pool exhausted: the edge stays without a vertex, and its
               // triangles will reference none
               atomicOr(&v.cnt->error, kErrVertices);
-              v.evtx[eo] = -1;
+              evtx_b[e] = -1;
               continue;
             }
-            v.evtx[eo] = (int32_t)ns;
-            v.vowner[ns] = (uint32_t)eo;
-            v.vbirth[ns] = v.frame;
+            evtx_b[e] = (int32_t)ns;
+            pool32(v.vowner, ns) = (uint32_t)eb + e;
+            pool32(v.vbirth, ns) = v.frame;
             ++nnew;
           } else {
             ++nupd;
           }
           const int sdb = (int)(l & 7u) + 9 * (int)((l >> 3) & 7u) + 81 * (int)(l >> 6);
           const int stp = a == 0 ? 1 : (a == 1 ? 9 : 81);
-          v.et[eo] = edge_param(sd[sdb], sd[sdb + stp]);
-          v.eref[eo] = (uint8_t)ref;
+          et_b[e] = edge_param(sd[sdb], sd[sdb + stp]);
+          eref_b[e] = (uint8_t)ref;
         } else {
-          free_vertex(eo, v.evtx[eo], myf);
+          free_vertex(e, evtx_b[e], myf);
         }
       }
     } else {
@@ -1072,27 +1087,27 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
         for (int a = 0; a < 3; ++a) {
           const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u;
           if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
-          const size_t eo = ((size_t)idx * 3 + a) * kVox + q + 64 * lz;
+          const uint32_t e = (uint32_t)(a * kVox + q + 64 * lz);
           const bool has = (has_slot >> (3 * lz + a)) & 1u;
           if (ref > 0) {
             if (!has) {
               const uint32_t ns = new_slot(rank++);
               if (ns == kNone) {
                 atomicOr(&v.cnt->error, kErrVertices);
-                v.evtx[eo] = -1;
+                evtx_b[e] = -1;
                 continue;
               }
-              v.evtx[eo] = (int32_t)ns;
-              v.vowner[ns] = (uint32_t)eo;
-              v.vbirth[ns] = v.frame;
+              evtx_b[e] = (int32_t)ns;
+              pool32(v.vowner, ns) = (uint32_t)eb + e;
+              pool32(v.vbirth, ns) = v.frame;
               ++nnew;
             } else {
               ++nupd;
             }
-            v.et[eo] = edge_param(sd[sdb], sd[sdb + step[a]]);
-            v.eref[eo] = (uint8_t)ref;
+            et_b[e] = edge_param(sd[sdb], sd[sdb + step[a]]);
+            eref_b[e] = (uint8_t)ref;
           } else {
-            free_vertex(eo, v.evtx[eo], frank++);
+            free_vertex(e, evtx_b[e], frank++);
           }
         }
       }
