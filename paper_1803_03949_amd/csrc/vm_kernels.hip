@@ -497,6 +497,7 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
       pr[lz] = fuse_project(v, fp, 8 * bx + lx, 8 * by + ly, 8 * bz + lz);
       D[lz] = depth[pr[lz].pix >= 0 ? pr[lz].pix : 0];
     }
+    uint64_t mine = 0;  // lane lz < 8 keeps the observed mask of layer lz
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
       const FuseSample fs = fuse_finish(v, fp, pr[lz], D[lz]);
@@ -512,8 +513,9 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
         v.w[o] = w[lz];
       }
       const uint64_t m = __ballot(fs.upd || w[lz] > 0.f);
-      if (q == 0) v.wmask[(size_t)idx * 8 + lz] = m;
+      if (q == lz) mine = m;
     }
+    if (q < 8) v.wmask[(size_t)idx * 8 + q] = mine;
     if (q == 0) v.st_frame[idx] = fp.frame;
   }
 }
