@@ -1138,61 +1138,68 @@ __device__ inline void edge_owner(int e, int& ox, int& oy, int& oz, int& axis) {
   axis = (int)(p >> 3);
 }
 
-// One wave per (dirty block, z layer): every cube of the layer whose
-// triangles changed and whose new type has triangles gets them rewritten
-// (Sec. V-D) as the vertex slots of the owning edges, into the cube's own
-// record; unchanged cubes keep theirs, and a cube without triangles needs no
-// write (its type says so).  Each record (64 bytes) is written by 16 lanes;
-// the edge-slot gathers of 32 cubes are issued before their stores.  Work
-// per wave is at most one layer of 64 cubes, so a block with many changed
-// cubes is spread over up to eight waves.
-template <int W>
-__global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
-  __shared__ uint8_t stri[256 * 16];
-  __shared__ uint8_t slist_all[W][64];  // changed cubes of the layer (x + 8y)
-  __shared__ uint8_t stype_all[W][64];  // their types
-  __shared__ int32_t snb_all[W][27];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id();
-  {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(v.tri_table);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(stri);
-    for (int j = threadIdx.x; j < 256 * 16 / 4; j += blockDim.x) dst[j] = src[j];
-  }
-  __syncthreads();
-  uint8_t* slist = slist_all[wave];
-  uint8_t* stype = stype_all[wave];
-  int32_t* snb = snb_all[wave];
-  const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks) * 8u;
+// One wave per (dirty block, group of G z layers): every cube of the group
+// whose triangles changed and whose new type has triangles gets them
+// rewritten (Sec. V-D) as the vertex slots of the owning edges, into the
+// cube's own record; unchanged cubes keep theirs, and a cube without
+// triangles needs no write (its type says so).  Each record (64 bytes) is
+// written by 16 lanes; the edge-slot gathers of 32 cubes are issued before
+// their stores.  A short dirty list takes one layer per wave (G = 1), so a
+// block with many changed cubes is spread over up to eight waves; a long one
+// takes four layers per wave (G = 4), so each half block costs one
+// neighbour-table and one type round trip instead of four.
+template <int W, int G>
+__device__ inline void triangle_items(const VolDev& v, const uint8_t* stri, uint16_t* slist,
+                                      uint8_t* stype, int32_t* snb, int wave, uint32_t nd) {
+  constexpr uint32_t kGroups = 8 / G;  // items per block
+  const int q = __lane_id();
   const int k = q & 15;
-  // item i is layer i % 8 of dirty-list entry i / 8; its change mask sits at
-  // position i.  The next item's mask and block are requested while the
-  // current one is worked on, so an unchanged layer costs no round trip.
-  ItemLoop it = item_loop(v, n, W, wave);
-  uint64_t m_next = 0;
+  const uint64_t below = lanes_below();
+  // item i is layers (i % kGroups) * G .. + G - 1 of dirty-list entry
+  // i / kGroups; its change masks sit at positions 8 * entry + layer.  The
+  // next item's masks and block are requested while the current one is
+  // worked on, so an unchanged item costs no round trip.
+  ItemLoop it = item_loop(v, nd * kGroups, W, wave);
+  uint64_t m_next[G];
   uint32_t idx_next = 0;
-  if (it.i < it.end) m_next = v.chg[it.i], idx_next = v.dirty[it.i >> 3];
+  auto fetch = [&](uint32_t i) {
+    const uint32_t e = i / kGroups, lz0 = (i % kGroups) * G;
+#pragma unroll
+    for (int g = 0; g < G; ++g) m_next[g] = v.chg[(size_t)e * 8 + lz0 + g];
+    idx_next = v.dirty[e];
+  };
+  if (it.i < it.end) fetch(it.i);
   for (; it.i < it.end; it.i += it.step) {
-    const uint32_t mlo = uniform((uint32_t)m_next), mhi = uniform((uint32_t)(m_next >> 32));
-    const uint64_t m = ((uint64_t)mhi << 32) | mlo;
-    const uint32_t idx = uniform(idx_next);
-    const int lz = (int)(it.i & 7u);
-    if (it.i + it.step < it.end) {
-      m_next = v.chg[it.i + it.step];
-      idx_next = v.dirty[(it.i + it.step) >> 3];
+    uint64_t m[G];
+    uint64_t any = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint32_t lo = uniform((uint32_t)m_next[g]), hi = uniform((uint32_t)(m_next[g] >> 32));
+      m[g] = ((uint64_t)hi << 32) | lo;
+      any |= m[g];
     }
-    if (m == 0ull) continue;
+    const uint32_t idx = uniform(idx_next);
+    const int lz0 = (int)((it.i % kGroups) * G);
+    if (it.i + it.step < it.end) fetch(it.i + it.step);
+    if (any == 0ull) continue;
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
-    const uint32_t mytype = v.tcur[(size_t)idx * kVox + q + 64 * lz];
+    uint32_t mytype[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) mytype[g] = v.tcur[(size_t)idx * kVox + q + 64 * (lz0 + g)];
     if (q < 27) snb[q] = mynb;
-    // changed cubes whose new type has triangles, in lane order
-    const uint64_t w = __ballot(((m >> q) & 1ull) && stri[mytype * 16] != 0);
-    if ((w >> q) & 1ull) {
-      const int pos = __popcll(w & lanes_below());
-      slist[pos] = (uint8_t)q;
-      stype[pos] = (uint8_t)mytype;
+    // changed cubes whose new type has triangles, layer by layer in lane order
+    uint32_t nw = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint64_t w = __ballot(((m[g] >> q) & 1ull) && stri[mytype[g] * 16] != 0);
+      if ((w >> q) & 1ull) {
+        const uint32_t pos = nw + (uint32_t)__popcll(w & below);
+        slist[pos] = (uint16_t)(q + 64 * g);
+        stype[pos] = (uint8_t)mytype[g];
+      }
+      nw += (uint32_t)__popcll(w);
     }
     wave_sync();
-    const uint32_t nw = (uint32_t)__popcll(w);
     for (uint32_t c0 = 0; c0 < nw; c0 += 32) {
       uint32_t word[8];
       int32_t dst[8];
@@ -1204,7 +1211,7 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
         if (c >= nw) continue;
         const uint32_t type = stype[c], ntri = stri[type * 16];
         if (k >= (int)(3 * ntri)) continue;
-        const int l = slist[c] + 64 * lz;
+        const int l = (int)slist[c] + 64 * lz0;
         dst[r] = l;
         int ox, oy, oz, axis;
         edge_owner(stri[type * 16 + 1 + k], ox, oy, oz, axis);
@@ -1222,6 +1229,29 @@ __global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
     }
     wave_sync();
   }
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
+  __shared__ uint8_t stri[256 * 16];
+  __shared__ uint16_t slist_all[W][256];  // changed cubes of the item (x + 8y + 64 g)
+  __shared__ uint8_t stype_all[W][256];   // their types
+  __shared__ int32_t snb_all[W][27];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(v.tri_table);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(stri);
+    for (int j = threadIdx.x; j < 256 * 16 / 4; j += blockDim.x) dst[j] = src[j];
+  }
+  __syncthreads();
+  const uint32_t nd = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
+  // half blocks per wave once single layers would give every wave of the
+  // grid more than four items (measured on MI355X: four layers per item beat
+  // one, two and eight on the 4 mm sequence and on the 64-volume batch)
+  if ((uint64_t)nd * 8 <= 4ull * gridDim.x * W)
+    triangle_items<W, 1>(v, stri, slist_all[wave], stype_all[wave], snb_all[wave], wave, nd);
+  else
+    triangle_items<W, 4>(v, stri, slist_all[wave], stype_all[wave], snb_all[wave], wave, nd);
 }
 
 // ============================================================================
