@@ -97,7 +97,8 @@ struct Counters {
   uint32_t n_refined;      // cubes re-typed by the last refinement
   // segment totals when the last extract / refine started
   uint32_t base_new, base_upd, base_freed, base_chg, base_ref;
-  uint32_t pad[14];
+  uint32_t import_base;    // blocks in the pool before the last import
+  uint32_t pad[13];
   // running totals since the volume was created (not cleared by a reset)
   unsigned long long acc[10];
   unsigned long long pad2[6];

@@ -362,6 +362,7 @@ __global__ __launch_bounds__(1024) void k_import_scan(VolDev v, uint32_t nparts,
   uint32_t* len[3] = {&v.cnt->n_frame[frame & 1], &v.cnt->n_blocks, &v.cnt->n_pending[epoch & 1]};
   if (threadIdx.x < 3) carry[threadIdx.x] = *len[threadIdx.x];
   __syncthreads();
+  if (threadIdx.x == 0) v.cnt->import_base = carry[1];
   for (uint32_t base = 0; base < nparts; base += 1024) {
     const uint32_t p = base + threadIdx.x;
     for (int k = 0; k < 3; ++k) {
@@ -417,9 +418,11 @@ __global__ __launch_bounds__(kImportRows) void k_import_assign(VolDev v, uint32_
 }
 
 // Link a new block with its 26 neighbours in both directions (lanes 0..26
-// of the workgroup handling it).
-__device__ inline void link_block(const VolDev& v, uint32_t idx, int l) {
-  if (l >= 27 || l == kSelf) return;
+// of the workgroup handling it).  With forward_only, only the 13 neighbours
+// after it (l > kSelf) are looked up: enough when every block present is
+// new in the same call, as each pair is then linked by its first block.
+__device__ inline void link_block(const VolDev& v, uint32_t idx, int l, bool forward_only = false) {
+  if (l >= 27 || l == kSelf || (forward_only && l < kSelf)) return;
   int x, y, z;
   unpack_key(v.block_key[idx], x, y, z);
   const int nx = x + l % 3 - 1, ny = y + (l / 3) % 3 - 1, nz = z + l / 9 - 1;
@@ -532,6 +535,8 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
   const uint32_t n = min(v.cnt->n_frame[frame & 1], v.max_blocks);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
+  // into an empty pool every neighbour is new too: link forward only
+  const bool forward_only = v.cnt->import_base == 0;
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
     const uint32_t e = uniform(v.frame_list[it.i]);
     const uint32_t row = uniform(v.frame_src[it.i]);
@@ -551,7 +556,7 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
     if (e & kNewFlag) {
 #pragma unroll
       for (int lz = 0; lz < 8; ++lz) init_cube(v, idx, q + 64 * lz);
-      link_block(v, idx, q);
+      link_block(v, idx, q, forward_only);
     }
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
