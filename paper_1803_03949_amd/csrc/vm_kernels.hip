@@ -864,7 +864,8 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
 // edge has a vertex; the write pass runs over that list, 64 edges per step,
 // instead of over all 1536 edges.  Only a vertex being freed needs its slot,
 // which it reads again; the block's slots never occupy LDS, which keeps the
-// wave's LDS small enough for six waves per SIMD.
+// wave's LDS small enough for seven waves per SIMD (with four waves per
+// workgroup; scalar registers then limit it).
 constexpr int kRingBatch = 256;  // recycled slots fetched per block at once
 constexpr int kWorkCap = 256;    // listed edges per block; more take the row-by-row pass
 
