@@ -1627,6 +1627,12 @@ __global__ __launch_bounds__(64 * W) void k_bwd_tsdf(VolDev v, const float* __re
                          (uint64_t)(b2 != 0) << 5;
       act |= m << (6 * lz);
     }
+    if (__ballot(act != 0ull) == 0ull) {
+      // no incident edge of the block carries a vertex
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) o[q + 64 * lz] = 0.f;
+      continue;
+    }
     uint32_t cnt = 0;
     int lz0 = 0;
     // contributions of the listed pairs, then the sums of layers [lz0, lz1)
