@@ -931,40 +931,59 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     }
     if (q < 27) snb[q] = mynb;
     wave_sync();
-    {
-      // own block into LDS: cube types at local 0..7, TSDF at local 0..7
-      uint32_t tv[8];
-      float dv[8];
+    // The TSDF (own block and +x/+y/+z halo) serves only edges with work: it
+    // is requested with the types when the block already carries a vertex,
+    // else only once the counts show work (a block that neither has nor
+    // needs a vertex reads none of it).
+    const bool d_early = __ballot(has_slot != 0u) != 0ull;
+    auto d_halo = [&](int r) -> float {
+      const int h = q + 64 * r;
+      if (h >= 217) return 0.f;
+      int x, y, z;
+      halo_cell(h, 8, x, y, z);
+      const int nb2 = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
+      if (nb2 < 0) return 0.f;
+      return *reinterpret_cast<const float*>(
+          d_bytes + ((uint32_t)nb2 * 2048u + (uint32_t)((x & 7) + 8 * (y & 7) + 64 * (z & 7)) * 4u));
+    };
+    auto d_store = [&](const float* dv, const float* dh) {
 #pragma unroll
-      for (int lz = 0; lz < 8; ++lz) {
-        tv[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
-        dv[lz] = v.d[(size_t)idx * kVox + q + 64 * lz];
-      }
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz) {
-        st[(lx + 1) + 9 * (ly + 1) + 81 * (lz + 1)] = (uint8_t)tv[lz];
-        sd[lx + 9 * ly + 81 * lz] = dv[lz];
-      }
-      // halos: cube types of the -x/-y/-z neighbours (local -1) and TSDF of
-      // the +x/+y/+z neighbours (local 8), 217 cells each
-      uint32_t th[4];
-      float dh[4];
+      for (int lz = 0; lz < 8; ++lz) sd[lx + 9 * ly + 81 * lz] = dv[lz];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int h = q + 64 * r;
-        th[r] = 0, dh[r] = 0.f;
+        if (h < 217) {
+          int x, y, z;
+          halo_cell(h, 8, x, y, z);
+          sd[x + 9 * y + 81 * z] = dh[r];
+        }
+      }
+    };
+    {
+      // own block into LDS: cube types at local 0..7, TSDF at local 0..7
+      uint32_t tv[8];
+      float dv[8], dh[4];
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) {
+        tv[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
+        dv[lz] = d_early ? v.d[(size_t)idx * kVox + q + 64 * lz] : 0.f;
+      }
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) st[(lx + 1) + 9 * (ly + 1) + 81 * (lz + 1)] = (uint8_t)tv[lz];
+      // halos: cube types of the -x/-y/-z neighbours (local -1) and TSDF of
+      // the +x/+y/+z neighbours (local 8), 217 cells each
+      uint32_t th[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int h = q + 64 * r;
+        th[r] = 0;
+        dh[r] = d_early ? d_halo(r) : 0.f;
         if (h < 217) {
           int x, y, z;
           halo_cell(h, -1, x, y, z);
           const int nb = snb[nbr_dir(x < 0 ? -1 : 0, y < 0 ? -1 : 0, z < 0 ? -1 : 0)];
           if (nb >= 0)
             th[r] = tcur_bytes[(uint32_t)nb * 512u + (uint32_t)((x & 7) + 8 * (y & 7) + 64 * (z & 7))];
-          halo_cell(h, 8, x, y, z);
-          const int nb2 = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
-          if (nb2 >= 0)
-            dh[r] = *reinterpret_cast<const float*>(
-                d_bytes + ((uint32_t)nb2 * 2048u +
-                           (uint32_t)((x & 7) + 8 * (y & 7) + 64 * (z & 7)) * 4u));
         }
       }
 #pragma unroll
@@ -974,10 +993,9 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
           int x, y, z;
           halo_cell(h, -1, x, y, z);
           st[(x + 1) + 9 * (y + 1) + 81 * (z + 1)] = (uint8_t)th[r];
-          halo_cell(h, 8, x, y, z);
-          sd[x + 9 * y + 81 * z] = dh[r];
         }
       }
+      if (d_early) d_store(dv, dh);
     }
     wave_sync();
     // 8 counts of 8 bits per axis: an edge can carry up to 16 triangles (four
@@ -1009,6 +1027,14 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
           swork[pos] = (uint32_t)(a * kVox + q + 64 * lz) | (rr[a] << 11) | (((hs >> a) & 1u) << 19);
         nwork += (uint32_t)__popcll(b);
       }
+    }
+    if (!d_early && nwork > 0) {
+      float dv[8], dh[4];
+#pragma unroll
+      for (int lz = 0; lz < 8; ++lz) dv[lz] = v.d[(size_t)idx * kVox + q + 64 * lz];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dh[r] = d_halo(r);
+      d_store(dv, dh);
     }
     // one allocation and one recycling atomic per block, issued together;
     // a vertex whose count dropped to zero goes back to the segment's ring
