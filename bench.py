@@ -39,11 +39,11 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 5120.8, "write_kib": 952.1, "source_sha1": "e5dd002ceb0c"},
-    "fuse": {"fetch_kib": 10941.1, "write_kib": 12435.4, "source_sha1": "07b4fdca9c04"},
-    "classify": {"fetch_kib": 12747.7, "write_kib": 3636.5, "source_sha1": "b6e9291df145"},
-    "vertices": {"fetch_kib": 20889.4, "write_kib": 9532.3, "source_sha1": "b15a4001c699"},
-    "triangles": {"fetch_kib": 4912.4, "write_kib": 3368.4, "source_sha1": "5cc60573fbfd"},
+    "collect": {"fetch_kib": 4994.7, "write_kib": 932.3, "source_sha1": "e5dd002ceb0c"},
+    "fuse": {"fetch_kib": 10668.8, "write_kib": 12127.6, "source_sha1": "07b4fdca9c04"},
+    "classify": {"fetch_kib": 12434.3, "write_kib": 3548.4, "source_sha1": "b6e9291df145"},
+    "vertices": {"fetch_kib": 17112.1, "write_kib": 9291.7, "source_sha1": "b06e1d73e560"},
+    "triangles": {"fetch_kib": 4789.8, "write_kib": 3285.1, "source_sha1": "5cc60573fbfd"},
 }
 
 
