@@ -216,6 +216,18 @@ int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
  * is the number of triangles using it. */
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream);
 
+/* vm_extract_mesh with the triangle records written on tri_stream, which
+ * first waits (an event) for the vertex pass on `stream`; work enqueued on
+ * `stream` afterwards that reads vertices but not triangles (positions,
+ * vm_extract_backward*) can then run alongside the triangle pass.  The
+ * caller makes `stream` wait for tri_stream before anything that reads or
+ * writes the mesh again (downloads, exports, the next extraction or
+ * refinement).  tri_stream == stream is vm_extract_mesh.  Streams at the
+ * default priority; both may be under graph capture (the wait joins
+ * tri_stream to the capture). */
+int vm_extract_mesh_split(vm_volume* vol, int scope, hipStream_t stream,
+                          hipStream_t tri_stream);
+
 /* Hamming-distance refinement (Sec. V-F, Eqs. 3-5) of the cubes of the last
  * extraction: a valid cube with type t and previous type p is set to the
  * regular type r_j when d_H(t,p) <= 3, d_H(t,r_j) <= 3 and |d(c_k)| < eps

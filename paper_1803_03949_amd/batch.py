@@ -103,6 +103,9 @@ class BatchMesher:
         self.weight = weight
         if zero_copy:
             self.vol.bind_tsdf(tsdf, weight)
+        # the triangle pass runs here, beside positions, loss and backward,
+        # which read vertices only (default priority, like every stream)
+        self.tri_stream = torch.cuda.Stream(device=dev)
         self.rows = torch.empty(N, dtype=torch.int32, device=dev)
         self.pos = torch.empty((V, 3), dtype=torch.float32, device=dev)
         self.slot = torch.empty(V, dtype=torch.int32, device=dev)
@@ -112,14 +115,17 @@ class BatchMesher:
         self.graph = None
 
     def run(self, stream=None):
-        """The whole step, enqueued on the current stream."""
+        """The whole step, enqueued on the current stream (the triangle pass
+        on a side stream that the current one joins at the end)."""
         v = self.vol
-        v.reset(stream)
-        v.import_batch(self.slots, self.coords, self.tsdf, self.weight, self.rows, stream)
-        v.extract(scope_all=True, stream=stream)
-        v.positions(self.pos, self.slot, stream)
+        cur = torch.cuda.current_stream(v.device) if stream is None else stream
+        v.reset(cur)
+        v.import_batch(self.slots, self.coords, self.tsdf, self.weight, self.rows, cur)
+        v.extract(scope_all=True, stream=cur, tri_stream=self.tri_stream)
+        v.positions(self.pos, self.slot, cur)
         self.loss_grad(self.pos, self.slot, self.dpos)
-        v.extract_backward_slots(self.dpos, self.rows, self.grad, stream)
+        v.extract_backward_slots(self.dpos, self.rows, self.grad, cur)
+        cur.wait_stream(self.tri_stream)
 
     def capture(self):
         """Capture `run` in a HIP graph (after one eager warm-up run)."""
@@ -172,15 +178,20 @@ class PlainMesher:
                 vol.bind_tsdf(self.items[-1]["tsdf"], self.items[-1]["weight"])
             self.vols.append(vol)
             off += n
+        self.tri_stream = torch.cuda.Stream(device=self.vols[0].device) if self.vols else None
 
     def run(self):
+        """Volume after volume on the current stream, each volume's triangle
+        pass on the side stream as in the batch."""
         for v, it in zip(self.vols, self.items):
             v.reset()
             v.import_batch(None, it["coords"], it["tsdf"], it["weight"], it["rows"])
-            v.extract(scope_all=True)
+            v.extract(scope_all=True, tri_stream=self.tri_stream)
             v.positions(it["pos"], it["slot"])
             it["loss_grad"](it["pos"], it["slot"], it["dpos"])
             v.extract_backward_slots(it["dpos"], it["rows"], it["grad"])
+        if self.tri_stream is not None:
+            torch.cuda.current_stream().wait_stream(self.tri_stream)
 
     def grad(self) -> torch.Tensor:
         return torch.cat([it["grad"] for it in self.items])

@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
             "vm_download_births": [P, P, I64, P],
             "vm_sharing_ablation": [P, ctypes.c_int, P, P, P, P],
             "vm_bind_tsdf": [P, P, P],
+            "vm_extract_mesh_split": [P, ctypes.c_int, P, P],
             "vm_extract_backward": [P, P, P, P],
             "vm_integrate_backward": [P, P, P, P, P, P],
             "vm_get_status": [P, ctypes.POINTER(vm_status), P],
@@ -228,9 +229,16 @@ class Volume:
         _check(lib().vm_import_batch(self.h, _ptr(slots), _ptr(coords), _ptr(tsdf), _ptr(weight),
                                      n, _ptr(rows), _stream(stream)), "vm_import_batch")
 
-    def extract(self, scope_all: bool = False, stream=None):
-        _check(lib().vm_extract_mesh(self.h, VM_SCOPE_ALL if scope_all else VM_SCOPE_DIRTY,
-                                     _stream(stream)), "vm_extract_mesh")
+    def extract(self, scope_all: bool = False, stream=None, tri_stream=None):
+        """Mesh extraction; with tri_stream (a torch stream) the triangle pass
+        runs there once the vertex pass is done (vm_extract_mesh_split): the
+        caller joins it before the mesh is read or changed again."""
+        scope = VM_SCOPE_ALL if scope_all else VM_SCOPE_DIRTY
+        if tri_stream is None:
+            _check(lib().vm_extract_mesh(self.h, scope, _stream(stream)), "vm_extract_mesh")
+        else:
+            _check(lib().vm_extract_mesh_split(self.h, scope, _stream(stream), _stream(tri_stream)),
+                   "vm_extract_mesh_split")
 
     def refine(self, stream=None):
         _check(lib().vm_refine_mesh(self.h, _stream(stream)), "vm_refine_mesh")

@@ -44,6 +44,7 @@ struct vm_volume {
   int grid_waves;   // workgroups of wave-per-block kernels
   uint32_t prof;    // bit k: bracket launches of kernel k with events
   std::vector<hipEvent_t> ev_free;
+  hipEvent_t split_ev = nullptr;  // vertex pass done (vm_extract_mesh_split)
   std::vector<ProfRec> recs;
 };
 
@@ -302,6 +303,10 @@ int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes, hipStrea
   }
   v.batch = (uint32_t)cfg->batch_volumes;
   v.bound = 0;
+  if (hipEventCreateWithFlags(&vol->split_ev, hipEventDisableTiming) != hipSuccess) {
+    delete vol;
+    return VM_ERR_HIP;
+  }
   vol->own_d = v.d;
   vol->own_w = v.w;
   vol->cus = cus;
@@ -320,6 +325,7 @@ int vm_destroy_volume(vm_volume* vol) {
   if (!vol) return VM_ERR_ARG;
   for (auto& r : vol->recs) vol->ev_free.push_back(r.a), vol->ev_free.push_back(r.b);
   for (hipEvent_t e : vol->ev_free) (void)hipEventDestroy(e);
+  if (vol->split_ev) (void)hipEventDestroy(vol->split_ev);
   delete vol;
   return VM_OK;
 }
@@ -414,6 +420,10 @@ int vm_bind_tsdf(vm_volume* vol, float* tsdf, float* weight) {
 }
 
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
+  return vm_extract_mesh_split(vol, scope, stream, stream);
+}
+
+int vm_extract_mesh_split(vm_volume* vol, int scope, hipStream_t stream, hipStream_t tri_stream) {
   if (!vol || (scope != VM_SCOPE_DIRTY && scope != VM_SCOPE_ALL)) return VM_ERR_ARG;
   const uint32_t pass = ++vol->pass;
   vol->dl_nv = -1;
@@ -431,7 +441,14 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
   VM_LAUNCH_W(vol, VM_K_CLASSIFY, k_classify, stream, v, pass, 0);
   VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
   VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
-  VM_LAUNCH_W(vol, VM_K_TRIANGLES, k_triangles, stream, v);
+  if (tri_stream != stream) {
+    // the triangle records need only the vertex slots: hand them to the
+    // other stream once the vertex pass is done
+    hipError_t e = hipEventRecord(vol->split_ev, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(tri_stream, vol->split_ev, 0);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  VM_LAUNCH_W(vol, VM_K_TRIANGLES, k_triangles, tri_stream, v);
   return launched();
 }
 

@@ -27,7 +27,7 @@ def test_header_declares_the_method_calls():
                      "vm_refine_mesh", "vm_gc", "vm_download_mesh", "vm_extract_backward",
                      "vm_integrate_backward", "vm_import_batch", "vm_export_positions",
                      "vm_extract_backward_slots", "vm_set_launch", "vm_download_normals",
-                     "vm_download_births", "vm_bind_tsdf"]:
+                     "vm_download_births", "vm_bind_tsdf", "vm_extract_mesh_split"]:
         assert required in names
 
 
@@ -138,3 +138,4 @@ def test_null_arguments_are_rejected():
     assert L.vm_download_normals(None, None, 0, None) == -1
     assert L.vm_download_births(None, None, 0, None) == -1
     assert L.vm_bind_tsdf(None, None, None) == -1
+    assert L.vm_extract_mesh_split(None, 0, None, None) == -1
