@@ -1,8 +1,9 @@
 """Degenerate inputs through the C-ABI, against the oracle where it applies:
 an empty volume, a frame without a valid pixel, an import of no blocks, a
 single valid pixel, extraction with nothing new, refinement applied twice,
-and a camera at the edge of the representable block range (pixels whose
-box leaves [-8192, 8191] are skipped, reading 4 of the collection band)."""
+a camera at the edge of the representable block range (pixels whose box
+leaves [-8192, 8191] are skipped, reading 4 of the collection band), and
+the triangle pass on a second stream."""
 import numpy as np
 import pytest
 import torch
@@ -137,3 +138,17 @@ def test_camera_at_the_block_range_edge(axis_sign):
     g.extract()
     o.extract()
     compare_all(g, o)
+
+
+def test_split_extraction_matches_oracle():
+    """The triangle pass on a second stream (vm_extract_mesh_split), joined
+    before the mesh is read, gives the oracle's mesh frame after frame."""
+    seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=S)
+    g, o = pair()
+    side = torch.cuda.Stream()
+    for k in range(0, 12, 3):
+        both(g, o, seq.frame(k), seq.poses[k], seq.min_depth, seq.max_depth)
+        g.extract(tri_stream=side)
+        torch.cuda.current_stream().wait_stream(side)
+        o.extract()
+        compare_all(g, o)
