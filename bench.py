@@ -127,22 +127,13 @@ def room_fusion(args, dev):
     depth = torch.from_numpy(np.stack(frames)).to(dev)
     poses = list(seq.poses)
     vol = Volume(seq.voxel_m, hash_log2=20, max_blocks=1 << 17, max_vertices=1 << 23, device=dev)
-    # Frames are pipelined: a frame's triangle pass runs on a side stream
-    # while the next frame is collected and fused (those read and write
-    # neither triangles nor what the triangle pass reads of existing
-    # blocks); the next extraction waits for it.
-    main = torch.cuda.current_stream(dev)
-    side = torch.cuda.Stream(device=dev)
 
     def step():
         vol.reset()
         for k in range(args.frames):
             vol.integrate(depth[k], scenes.K, poses[k], seq.min_depth, seq.max_depth)
-            if k:
-                main.wait_stream(side)
-            vol.extract(tri_stream=side)
+            vol.extract()
             vol.gc()
-        main.wait_stream(side)
 
     for _ in range(args.warmup):
         step()

@@ -178,20 +178,16 @@ class PlainMesher:
                 vol.bind_tsdf(self.items[-1]["tsdf"], self.items[-1]["weight"])
             self.vols.append(vol)
             off += n
-        self.tri_stream = torch.cuda.Stream(device=self.vols[0].device) if self.vols else None
 
     def run(self):
-        """Volume after volume on the current stream, each volume's triangle
-        pass on the side stream as in the batch."""
+        """Volume after volume on the current stream."""
         for v, it in zip(self.vols, self.items):
             v.reset()
             v.import_batch(None, it["coords"], it["tsdf"], it["weight"], it["rows"])
-            v.extract(scope_all=True, tri_stream=self.tri_stream)
+            v.extract(scope_all=True)
             v.positions(it["pos"], it["slot"])
             it["loss_grad"](it["pos"], it["slot"], it["dpos"])
             v.extract_backward_slots(it["dpos"], it["rows"], it["grad"])
-        if self.tri_stream is not None:
-            torch.cuda.current_stream().wait_stream(self.tri_stream)
 
     def grad(self) -> torch.Tensor:
         return torch.cat([it["grad"] for it in self.items])
