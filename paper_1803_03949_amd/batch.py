@@ -30,9 +30,10 @@ from .binding import SLOT_SPAN, Volume
 
 def sphere_loss_grad(centers: torch.Tensor, radii: torch.Tensor):
     """dL/dp for L = sum over live vertices of (|p - c_k| - r_k)^2, with
-    (c_k, r_k) the target sphere of the vertex's volume k.  No reduction
-    across entries, so the function can be graph-captured, and every entry
-    goes through the same operations whatever the pool size.  Entries with
+    (c_k, r_k) the target sphere of the vertex's volume k.  Elementwise
+    operations only (the distance as two hypot calls), so the function can
+    be graph-captured and every entry goes through the same operations
+    whatever the pool size.  Entries with
     slot -1 (no vertex, position 0) index an extra sphere of radius 0 at the
     origin, whose gradient at the origin is 0."""
     dev = centers.device
@@ -44,7 +45,7 @@ def sphere_loss_grad(centers: torch.Tensor, radii: torch.Tensor):
     def grad(pos: torch.Tensor, slot: torch.Tensor, out: torch.Tensor):
         k = slot.remainder(rows)  # -1 -> the extra sphere
         d = pos - centers.index_select(0, k)
-        dist = torch.linalg.vector_norm(d, dim=1).clamp_min_(1e-30)
+        dist = torch.hypot(torch.hypot(d[:, 0], d[:, 1]), d[:, 2]).clamp_min_(1e-30)
         scale = (dist - radii.index_select(0, k)).div_(dist).mul_(2.0)
         return torch.mul(d, scale[:, None], out=out)
 
