@@ -39,11 +39,11 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 4916.3, "write_kib": 921.8, "source_sha1": "e5dd002ceb0c"},
-    "fuse": {"fetch_kib": 10483.4, "write_kib": 11917.1, "source_sha1": "07b4fdca9c04"},
-    "classify": {"fetch_kib": 12219.2, "write_kib": 3486.0, "source_sha1": "b6e9291df145"},
-    "vertices": {"fetch_kib": 16816.5, "write_kib": 9131.0, "source_sha1": "b06e1d73e560"},
-    "triangles": {"fetch_kib": 4706.9, "write_kib": 3228.0, "source_sha1": "5cc60573fbfd"},
+    "collect": {"fetch_kib": 4854.7, "write_kib": 907.3, "source_sha1": "e5dd002ceb0c"},
+    "fuse": {"fetch_kib": 10376.8, "write_kib": 11794.2, "source_sha1": "07b4fdca9c04"},
+    "classify": {"fetch_kib": 12089.7, "write_kib": 3453.3, "source_sha1": "b6e9291df145"},
+    "vertices": {"fetch_kib": 16642.0, "write_kib": 9037.7, "source_sha1": "b06e1d73e560"},
+    "triangles": {"fetch_kib": 4658.3, "write_kib": 3194.7, "source_sha1": "5cc60573fbfd"},
 }
 
 
