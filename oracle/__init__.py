@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call([
-            "g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
+            "g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
             "-fPIC", "-shared", "-o", tmp, _SRC,
         ])
         os.replace(tmp, _LIB)
@@ -47,6 +47,8 @@ def lib():
         sig = {
             "orc_create": (vp, [f, f, f]),
             "orc_destroy": (None, [vp]),
+            "orc_set_threads": (None, [vp, i]),
+            "orc_keep_fusion": (None, [vp, i]),
             "orc_integrate": (i, [vp, P, i, i, f, f, f, f, f, f, P]),
             "orc_restrict_blocks": (None, [vp, P, i]),
             "orc_import_blocks": (i, [vp, P, P, P, i]),
@@ -150,9 +152,15 @@ def edge_ends() -> np.ndarray:
 class OracleVolume:
     """One hashed TSDF volume with its mesh, on the host."""
 
-    def __init__(self, voxel_m: float, trunc_vox: float = 4.0, refine_eps_vox: float = 0.5):
+    def __init__(self, voxel_m: float, trunc_vox: float = 4.0, refine_eps_vox: float = 0.5,
+                 threads: int = 1, keep_fusion: bool = True):
+        """threads: threads of the loops over blocks (the result does not
+        depend on it); keep_fusion: keep per-voxel records of the last
+        fusion for grad_fusion64 (off for long forward-only sequences)."""
         self.voxel_m = float(np.float32(voxel_m))
         self._h = lib().orc_create(float(voxel_m), float(trunc_vox), float(refine_eps_vox))
+        lib().orc_set_threads(self._h, int(threads))
+        lib().orc_keep_fusion(self._h, 1 if keep_fusion else 0)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -308,6 +308,16 @@ struct Volume {
   int W = 0, H = 0;
   float fx = 0, fy = 0, cx = 0, cy = 0, dmin = 0, dmax = 0;
   int frame = 0;  // integrations and imports so far (the first is frame 1)
+
+  // Threads for the loops over blocks (and pixel rows) below.  Every such
+  // loop computes per block what the single-threaded loop computes, and
+  // the shared maps (vertices, triangles, fusion records) are updated
+  // afterwards in one thread, in the same order, so the result does not
+  // depend on the thread count.
+  int threads = 1;
+  // Keep per-voxel fusion records for the backward pass (off: the forward
+  // steps alone, for long sequences).
+  bool keep_fuse = true;
 };
 
 Block* find_block(Volume& v, const I3& b) {
@@ -360,42 +370,66 @@ float edge_t_of(Volume& v, const EdgeKey& e) {
 }
 
 // Lazy vertex initialisation / update (Sec. V-C) for every edge the cube's
-// applied type uses.
-void touch_vertices(Volume& v, const I3& c, unsigned type) {
+// applied type uses: the edges and their t (appended to out), then the map
+// update, which creates a vertex on first use and otherwise rewrites its t.
+void cube_vertices(Volume& v, const I3& c, unsigned type,
+                   std::vector<std::pair<EdgeKey, float>>& out) {
   for (int e = 0; e < 12; ++e) {
     if (!edge_crosses(type, e)) continue;
     EdgeKey k = cube_edge_key(c, e);
-    float t = edge_t_of(v, k);
-    auto it = v.verts.find(k);
-    if (it == v.verts.end())
-      v.verts[k] = Vertex{t, 0, 0, false};
-    else
-      it->second.t = t;
+    out.push_back({k, edge_t_of(v, k)});
   }
 }
 
+void apply_vertices(Volume& v, const std::vector<std::pair<EdgeKey, float>>& edges) {
+  for (auto& kt : edges) {
+    auto it = v.verts.find(kt.first);
+    if (it == v.verts.end())
+      v.verts[kt.first] = Vertex{kt.second, 0, 0, false};
+    else
+      it->second.t = kt.second;
+  }
+}
+
+void touch_vertices(Volume& v, const I3& c, unsigned type) {
+  std::vector<std::pair<EdgeKey, float>> edges;
+  cube_vertices(v, c, type, edges);
+  apply_vertices(v, edges);
+}
+
+// The triangles of a cube of the given type, as edge keys.
+std::vector<Tri> cube_tri_keys(const I3& c, unsigned type) {
+  std::vector<Tri> out;
+  if (type == 0 || type == 255) return out;
+  std::vector<std::array<int, 3>> tris;
+  cube_triangles(type, tris);
+  for (auto& t3 : tris) {
+    Tri tr;
+    for (int i = 0; i < 3; ++i) tr.e[i] = cube_edge_key(c, t3[i]);
+    out.push_back(tr);
+  }
+  return out;
+}
+
 // Triangulation with reference counting (Sec. V-D, V-E): clear the cube's
-// old triangles (-1 on their vertices) and create those of the new type
-// (+1).
-void retriangulate(Volume& v, const I3& c, unsigned type) {
+// old triangles (-1 on their vertices) and create the new ones (+1).
+void retriangulate(Volume& v, const I3& c, const std::vector<Tri>& fresh) {
   auto it = v.cube_tris.find(c);
   if (it != v.cube_tris.end()) {
     for (auto& tr : it->second)
       for (int i = 0; i < 3; ++i) v.verts[tr.e[i]].ref -= 1;
     v.cube_tris.erase(it);
   }
-  if (type == 0 || type == 255) return;
-  std::vector<std::array<int, 3>> tris;
-  cube_triangles(type, tris);
+  if (fresh.empty()) return;
   std::vector<Tri>& out = v.cube_tris[c];
-  for (auto& t3 : tris) {
-    Tri tr;
-    for (int i = 0; i < 3; ++i) {
-      tr.e[i] = cube_edge_key(c, t3[i]);
-      v.verts[tr.e[i]].ref += 1;
-    }
+  for (const Tri& tr : fresh) {
+    for (int i = 0; i < 3; ++i) v.verts[tr.e[i]].ref += 1;
     out.push_back(tr);
   }
+}
+
+void retriangulate(Volume& v, const I3& c, unsigned type) {
+  retriangulate(v, c, cube_tri_keys(c, type));
 }
 
 // Birth frames (READING: the paper shows how long each vertex has been held,
@@ -413,9 +447,17 @@ void stamp_births(Volume& v) {
 }
 
 // Extraction over a set of blocks: cube types, then vertices, then
-// triangles, in the paper's order (Sec. V-B to V-D).
+// triangles, in the paper's order (Sec. V-B to V-D).  The per-block work of
+// each step (types; edge keys and t of the vertices to create or update;
+// triangles of changed cubes) runs over blocks in parallel, and the
+// vertex and triangle maps are then updated in one thread in block, cube
+// and edge order.
 void extract_blocks(Volume& v, const std::set<I3>& dirty) {
-  for (const I3& b : dirty) {
+  const std::vector<I3> list(dirty.begin(), dirty.end());
+  const long n = (long)list.size();
+#pragma omp parallel for schedule(dynamic, 4) num_threads(v.threads)
+  for (long i = 0; i < n; ++i) {
+    const I3& b = list[i];
     Block* blk = find_block(v, b);
     for (int l = 0; l < 512; ++l) {
       I3 c{8 * b.x + (l & 7), 8 * b.y + ((l >> 3) & 7), 8 * b.z + (l >> 6)};
@@ -426,22 +468,34 @@ void extract_blocks(Volume& v, const std::set<I3>& dirty) {
       blk->cur[l] = valid ? (uint8_t)type : 0;
     }
   }
-  for (const I3& b : dirty) {
+  // vertices of every meshed cube: (edge, t) per block, then the map
+  std::vector<std::vector<std::pair<EdgeKey, float>>> touch(list.size());
+#pragma omp parallel for schedule(dynamic, 4) num_threads(v.threads)
+  for (long i = 0; i < n; ++i) {
+    const I3& b = list[i];
     Block* blk = find_block(v, b);
     for (int l = 0; l < 512; ++l) {
       if (!blk->cur[l]) continue;
       I3 c{8 * b.x + (l & 7), 8 * b.y + ((l >> 3) & 7), 8 * b.z + (l >> 6)};
-      touch_vertices(v, c, blk->cur[l]);
+      cube_vertices(v, c, blk->cur[l], touch[i]);
     }
   }
-  for (const I3& b : dirty) {
+  for (auto& per_block : touch) apply_vertices(v, per_block);
+  // triangles of cubes whose type changed (t_i != t_{i-1}); the others keep
+  // theirs
+  std::vector<std::vector<std::pair<I3, std::vector<Tri>>>> tris(list.size());
+#pragma omp parallel for schedule(dynamic, 4) num_threads(v.threads)
+  for (long i = 0; i < n; ++i) {
+    const I3& b = list[i];
     Block* blk = find_block(v, b);
     for (int l = 0; l < 512; ++l) {
       if (blk->cur[l] == blk->prev[l]) continue;  // t_i == t_{i-1}: keep
       I3 c{8 * b.x + (l & 7), 8 * b.y + ((l >> 3) & 7), 8 * b.z + (l >> 6)};
-      retriangulate(v, c, blk->cur[l]);
+      tris[i].push_back({c, cube_tri_keys(c, blk->cur[l])});
     }
   }
+  for (auto& per_block : tris)
+    for (auto& ct : per_block) retriangulate(v, ct.first, ct.second);
   v.last_dirty = dirty;
 }
 
@@ -469,6 +523,11 @@ void* orc_create(float voxel_m, float trunc_vox, float refine_eps_vox) {
 }
 
 void orc_destroy(void* h) { delete (Volume*)h; }
+
+// Threads of the loops over blocks (1: single-threaded; results do not depend
+// on it) and whether fusion keeps per-voxel records for the backward pass.
+void orc_set_threads(void* h, int n) { ((Volume*)h)->threads = n < 1 ? 1 : n; }
+void orc_keep_fusion(void* h, int on) { ((Volume*)h)->keep_fuse = on != 0; }
 
 // Block collection (Eq. 1) and TSDF fusion (Eq. 2) of one depth frame.
 // depth: H*W metres, row-major; cam_to_world: 4x4 row-major FP32 pose.
@@ -498,58 +557,70 @@ int orc_integrate(void* h, const float* depth, int W, int H, float fx, float fy,
   v.W = W, v.H = H, v.fx = fx, v.fy = fy, v.cx = cx, v.cy = cy, v.dmin = dmin, v.dmax = dmax;
   v.last_depth.assign(depth, depth + (size_t)W * H);
 
-  // --- block collection ---
+  // --- block collection (pixel rows in parallel, each into its own set) ---
   std::set<I3> touched;
-  for (int py = 0; py < H; ++py) {
-    for (int px = 0; px < W; ++px) {
-      float D = depth[(size_t)py * W + px];
-      if (!depth_valid(D, dmin, dmax)) continue;
-      float xn = ((float)px - cx) / fx;
-      float yn = ((float)py - cy) / fy;
-      int bmin[3], bmax[3];
-      bool in_range = true;
-      for (int end = 0; end < 2; ++end) {
-        float z = end == 0 ? D - v.mu_m : D + v.mu_m;
-        float p[3] = {xn * z, yn * z, z};
-        for (int i = 0; i < 3; ++i) {
-          float P = Rcw[i][0] * p[0];
-          P = P + Rcw[i][1] * p[1];
-          P = P + Rcw[i][2] * p[2];
-          P = P + tcw[i];
-          float fb = std::floor(P * v.inv_block);
-          if (!(fb >= (float)kKeyMin && fb <= (float)kKeyMax)) { in_range = false; break; }
-          int b = (int)fb;
-          if (end == 0) bmin[i] = bmax[i] = b;
-          else bmin[i] = std::min(bmin[i], b), bmax[i] = std::max(bmax[i], b);
-        }
-        if (!in_range) break;
-      }
-      if (!in_range) continue;
-      for (int bz = bmin[2]; bz <= bmax[2]; ++bz)
-        for (int by = bmin[1]; by <= bmax[1]; ++by)
-          for (int bx = bmin[0]; bx <= bmax[0]; ++bx) {
-            const I3 b{bx, by, bz};
-            if (v.only.empty() || v.only.count(b)) touched.insert(b);
+#pragma omp parallel num_threads(v.threads)
+  {
+    std::set<I3> mine;
+#pragma omp for schedule(static)
+    for (int py = 0; py < H; ++py) {
+      for (int px = 0; px < W; ++px) {
+        float D = depth[(size_t)py * W + px];
+        if (!depth_valid(D, dmin, dmax)) continue;
+        float xn = ((float)px - cx) / fx;
+        float yn = ((float)py - cy) / fy;
+        int bmin[3], bmax[3];
+        bool in_range = true;
+        for (int end = 0; end < 2; ++end) {
+          float z = end == 0 ? D - v.mu_m : D + v.mu_m;
+          float p[3] = {xn * z, yn * z, z};
+          for (int i = 0; i < 3; ++i) {
+            float P = Rcw[i][0] * p[0];
+            P = P + Rcw[i][1] * p[1];
+            P = P + Rcw[i][2] * p[2];
+            P = P + tcw[i];
+            float fb = std::floor(P * v.inv_block);
+            if (!(fb >= (float)kKeyMin && fb <= (float)kKeyMax)) { in_range = false; break; }
+            int b = (int)fb;
+            if (end == 0) bmin[i] = bmax[i] = b;
+            else bmin[i] = std::min(bmin[i], b), bmax[i] = std::max(bmax[i], b);
           }
+          if (!in_range) break;
+        }
+        if (!in_range) continue;
+        for (int bz = bmin[2]; bz <= bmax[2]; ++bz)
+          for (int by = bmin[1]; by <= bmax[1]; ++by)
+            for (int bx = bmin[0]; bx <= bmax[0]; ++bx) {
+              const I3 b{bx, by, bz};
+              if (v.only.empty() || v.only.count(b)) mine.insert(b);
+            }
+      }
     }
+#pragma omp critical
+    touched.insert(mine.begin(), mine.end());
   }
   for (const I3& b : touched)
     if (!find_block(v, b)) new_block(v, b);
 
-  // --- fusion ---
+  // --- fusion (blocks in parallel; each voxel's update is its own) ---
   v.fuse.clear();
-  for (const I3& b : touched) {
+  const std::vector<I3> list(touched.begin(), touched.end());
+  const long n = (long)list.size();
+  std::vector<std::vector<std::pair<I3, FuseRec>>> recs(v.keep_fuse ? list.size() : 0);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(v.threads)
+  for (long i = 0; i < n; ++i) {
+    const I3& b = list[i];
     Block* blk = find_block(v, b);
     for (int l = 0; l < 512; ++l) {
       int gx = 8 * b.x + (l & 7), gy = 8 * b.y + ((l >> 3) & 7), gz = 8 * b.z + (l >> 6);
       float X = (float)gx * v.s, Y = (float)gy * v.s, Z = (float)gz * v.s;
       float xc[3];
-      for (int i = 0; i < 3; ++i) {
-        float a = Rwc[i][0] * X;
-        a = a + Rwc[i][1] * Y;
-        a = a + Rwc[i][2] * Z;
-        a = a + twc[i];
-        xc[i] = a;
+      for (int j = 0; j < 3; ++j) {
+        float a = Rwc[j][0] * X;
+        a = a + Rwc[j][1] * Y;
+        a = a + Rwc[j][2] * Z;
+        a = a + twc[j];
+        xc[j] = a;
       }
       if (!(xc[2] > 0.f)) continue;
       float u = fx * (xc[0] / xc[2]) + cx;
@@ -562,16 +633,19 @@ int orc_integrate(void* h, const float* depth, int W, int H, float fx, float fy,
       float sdf = (D - xc[2]) * v.inv_s;
       if (sdf < -v.mu_v) continue;
       float dt = std::fmin(sdf, v.mu_v);
-      FuseRec rec{(double)blk->d[l], (double)blk->w[l], (double)xc[2], vi * W + ui,
-                  sdf >= v.mu_v ? 1 : 0};
+      if (v.keep_fuse)
+        recs[i].push_back({I3{gx, gy, gz}, FuseRec{(double)blk->d[l], (double)blk->w[l],
+                                                   (double)xc[2], vi * W + ui,
+                                                   sdf >= v.mu_v ? 1 : 0}});
       float num = blk->d[l] * blk->w[l];
       num = num + dt;
       float den = blk->w[l] + 1.0f;
       blk->d[l] = num / den;
       blk->w[l] = den;
-      v.fuse[I3{gx, gy, gz}] = rec;
     }
   }
+  for (auto& per_block : recs)
+    for (auto& r : per_block) v.fuse[r.first] = r.second;
   v.frame_touched = touched;
   v.pending_touched.insert(touched.begin(), touched.end());
   return (int)touched.size();
@@ -636,8 +710,13 @@ int orc_extract(void* h, int scope) {
 // Returns the number of cubes whose type changed.
 int orc_refine(void* h) {
   Volume& v = *(Volume*)h;
-  std::vector<std::pair<I3, unsigned>> changed;
-  for (const I3& b : v.last_dirty) {
+  // the applied types of the last extraction's cubes, blocks in parallel
+  const std::vector<I3> list(v.last_dirty.begin(), v.last_dirty.end());
+  const long n = (long)list.size();
+  std::vector<std::vector<std::pair<I3, unsigned>>> per_block(list.size());
+#pragma omp parallel for schedule(dynamic, 4) num_threads(v.threads)
+  for (long i = 0; i < n; ++i) {
+    const I3& b = list[i];
     Block* blk = find_block(v, b);
     for (int l = 0; l < 512; ++l) {
       I3 c{8 * b.x + (l & 7), 8 * b.y + ((l >> 3) & 7), 8 * b.z + (l >> 6)};
@@ -645,9 +724,11 @@ int orc_refine(void* h) {
       float dc[8];
       if (!classify(v, c, raw, dc)) continue;
       unsigned a = refine_type(blk->cur[l], blk->prev[l], dc, v.eps);
-      if (a != blk->cur[l]) changed.push_back({c, a});
+      if (a != blk->cur[l]) per_block[i].push_back({c, a});
     }
   }
+  std::vector<std::pair<I3, unsigned>> changed;
+  for (auto& pb : per_block) changed.insert(changed.end(), pb.begin(), pb.end());
   for (auto& ca : changed) touch_vertices(v, ca.first, ca.second);
   for (auto& ca : changed) {
     const I3& c = ca.first;

@@ -287,7 +287,10 @@ __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
                                 const int32_t* __restrict__ coords, uint32_t n, uint32_t frame) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
+    // this import's list starts empty, and so does the next frame's: an
+    // integration appends to its own parity's list without clearing it
     v.cnt->n_frame[frame & 1] = 0;
+    v.cnt->n_frame[(frame + 1) & 1] = 0;
     v.cnt->acc[VM_TOTAL_FRAMES] += 1;
   }
   if (i >= n) return;

@@ -82,7 +82,7 @@ def test_polygons_cover_exactly_the_crossing_edges(t):
     # complement has the same edge set (a vertex per sign change)
     assert crossing_edges(255 - t) == crossing_edges(t)
     tris = oracle.cube_triangles(t)
-    assert len(tris) <= 5                       # "up to 5 triangles" (Sec. IV)
+    assert len(tris) <= 5                       # at most five per cube (Sec. IV)
     assert len(tris) == sum(len(p) - 2 for p in polys)
     assert all(3 <= len(p) <= 7 for p in polys)
 
