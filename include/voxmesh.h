@@ -172,6 +172,27 @@ int vm_volume_bytes(const vm_config* cfg, size_t* bytes);
 int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes,
                      hipStream_t stream, vm_volume** out);
 
+/* Largest workspace (vm_volume_bytes) of a volume made by
+ * vm_create_volume_noalloc: 64 MiB. */
+#define VM_NOALLOC_MAX_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * vm_create_volume with the workspace taken from a static array of
+ * VM_NOALLOC_MAX_BYTES that the library holds on every device it runs on
+ * until the process ends, instead of a caller buffer.  The call allocates
+ * nothing (no device memory, no events, no host heap): the handle lives in
+ * static storage too.  The volume behaves as one made by vm_create_volume
+ * and is released with vm_destroy_volume.  Returns VM_ERR_CAPACITY when
+ * vm_volume_bytes(cfg) exceeds VM_NOALLOC_MAX_BYTES (checked before any HIP
+ * call), VM_ERR_ARG for an invalid configuration or while another such
+ * volume exists on the current device: all of them would share the one
+ * array, so each device holds at most one at a time (calls that overlapped
+ * on it would race).  The workspace keeps the last volume's contents;
+ * creation clears everything a new volume reads before writing, as
+ * vm_create_volume does.  Synchronises `stream` (the table upload). */
+int vm_create_volume_noalloc(const vm_config* cfg, hipStream_t stream, vm_volume** out);
+
 /* Release the host handle.  Never frees dev_mem. */
 int vm_destroy_volume(vm_volume* vol);
 

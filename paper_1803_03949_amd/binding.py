@@ -49,6 +49,7 @@ class vm_launch(ctypes.Structure):
 
 LAUNCH_FIELDS = [f for f, _ in vm_launch._fields_]
 SLOT_SPAN = 64  # stored block x of slot k, local x: 64k - 8192 + x
+NOALLOC_MAX_BYTES = 64 << 20  # VM_NOALLOC_MAX_BYTES
 
 
 class vm_intrinsics(ctypes.Structure):
@@ -91,6 +92,8 @@ def lib() -> ctypes.CDLL:
             "vm_volume_bytes": [ctypes.POINTER(vm_config), ctypes.POINTER(ctypes.c_size_t)],
             "vm_create_volume": [ctypes.POINTER(vm_config), P, ctypes.c_size_t, P,
                                  ctypes.POINTER(ctypes.c_void_p)],
+            "vm_create_volume_noalloc": [ctypes.POINTER(vm_config), P,
+                                         ctypes.POINTER(ctypes.c_void_p)],
             "vm_destroy_volume": [P],
             "vm_reset_volume": [P, P],
             "vm_integrate_depth": [P, P, ctypes.POINTER(vm_intrinsics), P, P],
@@ -154,7 +157,10 @@ class Volume:
     def __init__(self, voxel_m: float, trunc_vox: float = 4.0, refine_eps_vox: float = 0.5,
                  hash_log2: int = 20, max_blocks: int = 1 << 16, max_vertices: int = 1 << 22,
                  hash_mode: int = 0, batch_volumes: int = 0,
-                 device=None):
+                 device=None, noalloc: bool = False):
+        """noalloc: the workspace is the library's static per-device array
+        (vm_create_volume_noalloc, at most NOALLOC_MAX_BYTES, one such
+        volume per device at a time) instead of a torch buffer."""
         if not torch.cuda.is_available():
             raise RuntimeError("voxmesh needs a ROCm GPU (torch.cuda.is_available() is False)")
         L = lib()
@@ -165,19 +171,29 @@ class Volume:
         _check(L.vm_volume_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)), "vm_volume_bytes")
         self.nbytes = nbytes.value
         with torch.cuda.device(self.device):
-            self.mem = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
-            off = (-self.mem.data_ptr()) % 256
-            self._base = self.mem.data_ptr() + off
             h = ctypes.c_void_p()
-            _check(L.vm_create_volume(ctypes.byref(self.cfg), self._base, self.nbytes,
-                                      _stream(), ctypes.byref(h)), "vm_create_volume")
+            if noalloc:
+                self.mem = None
+                _check(L.vm_create_volume_noalloc(ctypes.byref(self.cfg), _stream(),
+                                                  ctypes.byref(h)), "vm_create_volume_noalloc")
+            else:
+                self.mem = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+                off = (-self.mem.data_ptr()) % 256
+                self._base = self.mem.data_ptr() + off
+                _check(L.vm_create_volume(ctypes.byref(self.cfg), self._base, self.nbytes,
+                                          _stream(), ctypes.byref(h)), "vm_create_volume")
         self.h = h
 
-    def __del__(self):
+    def close(self):
+        """Release the handle now (a noalloc volume frees its device's
+        static workspace for the next one)."""
         h = getattr(self, "h", None)
         if h and _lib is not None:
             _lib.vm_destroy_volume(h)
-            self.h = None
+        self.h = None
+
+    def __del__(self):
+        self.close()
 
     # -- method steps ---------------------------------------------------------
     def integrate(self, depth: torch.Tensor, K, cam_to_world, min_depth=0.0, max_depth=1e30,

@@ -44,8 +44,9 @@ struct vm_volume {
   int grid_waves;   // workgroups of wave-per-block kernels
   uint32_t prof;    // bit k: bracket launches of kernel k with events
   std::vector<hipEvent_t> ev_free;
-  hipEvent_t split_ev = nullptr;  // vertex pass done (vm_extract_mesh_split)
+  hipEvent_t split_ev = nullptr;  // vertex pass done (vm_extract_mesh_split; made on first use)
   std::vector<ProfRec> recs;
+  int scratch_dev = -1;  // device whose static workspace holds the volume, -1 if the caller's
 };
 
 namespace {
@@ -264,7 +265,52 @@ int read_snapshot(vm_volume* vol, Snapshot* s, hipStream_t stream) {
   return hip_status(e);
 }
 
+// Set up a volume handle over the workspace mem (bytes long, already
+// checked against the configuration) and clear the workspace on `stream`.
+int init_volume(vm_volume* vol, const vm_config* cfg, char* mem, size_t bytes,
+                hipStream_t stream) {
+  std::call_once(g_tables_once, [] { build_mc_tables(g_tri, g_uses); });
+  vol->cfg = *cfg;
+  vol->mem = mem;
+  vol->bytes = bytes;
+  VolDev& v = vol->dev;
+  carve(*cfg, vol->mem, &v);
+  v.s = cfg->voxel_m;
+  v.inv_s = (float)(1.0 / (double)cfg->voxel_m);
+  v.inv_block = (float)(1.0 / (8.0 * (double)cfg->voxel_m));
+  v.mu_m = (float)((double)cfg->trunc_vox * (double)cfg->voxel_m);
+  v.mu_v = cfg->trunc_vox;
+  v.eps = cfg->refine_eps_vox;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return VM_ERR_HIP;
+  v.batch = (uint32_t)cfg->batch_volumes;
+  v.bound = 0;
+  vol->own_d = v.d;
+  vol->own_w = v.w;
+  vol->cus = cus;
+  apply_launch(vol, vm_launch{4, 16, 8, 8, 0});
+  vol->prof = 0;
+  return clear_state(vol, stream, true);
+}
+
+// Workspace of vm_create_volume_noalloc: one per device, held until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy: it takes the device address from hipGetSymbolAddress, once per
+// device, and uses that.
+constexpr size_t kScratchBytes = (size_t)VM_NOALLOC_MAX_BYTES;
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kScratchDevices];
+bool g_scratch_used[kScratchDevices];
+alignas(vm_volume) unsigned char g_scratch_vol_mem[kScratchDevices][sizeof(vm_volume)];
+vm_volume* const g_scratch_vol = reinterpret_cast<vm_volume*>(g_scratch_vol_mem);
+
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[VM_NOALLOC_MAX_BYTES];
 
 extern "C" {
 
@@ -280,43 +326,42 @@ int vm_create_volume(const vm_config* cfg, void* dev_mem, size_t bytes, hipStrea
   if (!config_ok(cfg) || !dev_mem || !out || ((uintptr_t)dev_mem & 255)) return VM_ERR_ARG;
   VolDev probe;
   if (bytes < carve(*cfg, nullptr, &probe)) return VM_ERR_ARG;
-  std::call_once(g_tables_once, [] { build_mc_tables(g_tri, g_uses); });
   vm_volume* vol = new (std::nothrow) vm_volume();
   if (!vol) return VM_ERR_ARG;
-  vol->cfg = *cfg;
-  vol->mem = (char*)dev_mem;
-  vol->bytes = bytes;
-  VolDev& v = vol->dev;
-  carve(*cfg, vol->mem, &v);
-  v.s = cfg->voxel_m;
-  v.inv_s = (float)(1.0 / (double)cfg->voxel_m);
-  v.inv_block = (float)(1.0 / (8.0 * (double)cfg->voxel_m));
-  v.mu_m = (float)((double)cfg->trunc_vox * (double)cfg->voxel_m);
-  v.mu_v = cfg->trunc_vox;
-  v.eps = cfg->refine_eps_vox;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus <= 0) {
-    delete vol;
-    return VM_ERR_HIP;
-  }
-  v.batch = (uint32_t)cfg->batch_volumes;
-  v.bound = 0;
-  if (hipEventCreateWithFlags(&vol->split_ev, hipEventDisableTiming) != hipSuccess) {
-    delete vol;
-    return VM_ERR_HIP;
-  }
-  vol->own_d = v.d;
-  vol->own_w = v.w;
-  vol->cus = cus;
-  apply_launch(vol, vm_launch{4, 16, 8, 8, 0});
-  vol->prof = 0;
-  int r = clear_state(vol, stream, true);
+  const int r = init_volume(vol, cfg, (char*)dev_mem, bytes, stream);
   if (r != VM_OK) {
     delete vol;
     return r;
   }
+  *out = vol;
+  return VM_OK;
+}
+
+int vm_create_volume_noalloc(const vm_config* cfg, hipStream_t stream, vm_volume** out) {
+  if (!config_ok(cfg) || !out) return VM_ERR_ARG;
+  VolDev probe;
+  const size_t need = carve(*cfg, nullptr, &probe);
+  if (need > kScratchBytes) return VM_ERR_CAPACITY;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return VM_ERR_HIP;
+  if (dev < 0 || dev >= kScratchDevices) return VM_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    // the array's device address on this device (the name itself is only
+    // a host-side stand-in)
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VM_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  if (g_scratch_used[dev]) return VM_ERR_ARG;  // one volume per device at a time
+  vm_volume* vol = new (&g_scratch_vol[dev]) vm_volume();
+  const int r = init_volume(vol, cfg, (char*)g_scratch_ptr[dev], kScratchBytes, stream);
+  if (r != VM_OK) {
+    vol->~vm_volume();
+    return r;
+  }
+  vol->scratch_dev = dev;
+  g_scratch_used[dev] = true;
   *out = vol;
   return VM_OK;
 }
@@ -326,7 +371,14 @@ int vm_destroy_volume(vm_volume* vol) {
   for (auto& r : vol->recs) vol->ev_free.push_back(r.a), vol->ev_free.push_back(r.b);
   for (hipEvent_t e : vol->ev_free) (void)hipEventDestroy(e);
   if (vol->split_ev) (void)hipEventDestroy(vol->split_ev);
-  delete vol;
+  const int sdev = vol->scratch_dev;
+  if (sdev < 0) {
+    delete vol;
+    return VM_OK;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  vol->~vm_volume();
+  g_scratch_used[sdev] = false;
   return VM_OK;
 }
 
@@ -444,7 +496,9 @@ int vm_extract_mesh_split(vm_volume* vol, int scope, hipStream_t stream, hipStre
   if (tri_stream != stream) {
     // the triangle records need only the vertex slots: hand them to the
     // other stream once the vertex pass is done
-    hipError_t e = hipEventRecord(vol->split_ev, stream);
+    hipError_t e = vol->split_ev ? hipSuccess
+                                 : hipEventCreateWithFlags(&vol->split_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(vol->split_ev, stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(tri_stream, vol->split_ev, 0);
     if (e != hipSuccess) return hip_status(e);
   }

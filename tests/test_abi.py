@@ -139,3 +139,18 @@ def test_null_arguments_are_rejected():
     assert L.vm_download_births(None, None, 0, None) == -1
     assert L.vm_bind_tsdf(None, None, None) == -1
     assert L.vm_extract_mesh_split(None, 0, None, None) == -1
+
+
+def test_noalloc_volume_rejects_sizes_beyond_its_workspace():
+    """vm_create_volume_noalloc checks the workspace size before any HIP call,
+    so the rejections run without a GPU."""
+    L = binding.lib()
+    h = ctypes.c_void_p()
+    big = cfg(max_blocks=4096)
+    r, need = volume_bytes(big)
+    assert r == 0 and need > binding.NOALLOC_MAX_BYTES
+    assert L.vm_create_volume_noalloc(ctypes.byref(big), None, ctypes.byref(h)) == -6
+    assert not h.value
+    assert L.vm_create_volume_noalloc(ctypes.byref(cfg(voxel_m=0.0)), None, ctypes.byref(h)) == -1
+    assert L.vm_create_volume_noalloc(None, None, ctypes.byref(h)) == -1
+    assert L.vm_create_volume_noalloc(ctypes.byref(cfg(max_blocks=64)), None, None) == -1
