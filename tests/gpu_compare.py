@@ -84,3 +84,33 @@ def compare_all(gvol, ovol):
 
 def to_dev(*arrays):
     return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+def batch_vertices(gvol):
+    """Live vertices of a batched volume from its vertex pool: slot, edge
+    (gx, gy, gz, axis) in the slot's own frame, t and count."""
+    from paper_1803_03949_amd.binding import SLOT_SPAN
+    v = gvol.export_vertices()
+    ref = v["ref"].cpu().numpy()
+    live = ref > 0
+    edges = key_to_edge(v["keys"].cpu().numpy()[live])
+    slot = (edges[:, 0] // 8 + 8192) // SLOT_SPAN
+    edges[:, 0] -= 8 * (SLOT_SPAN * slot - 8192)
+    return slot, edges, v["t"].cpu().numpy()[live], ref[live]
+
+
+def compare_slot_vertices(bv, k, ovol):
+    """Slot k of batch_vertices(...) against an oracle volume holding that
+    slot's blocks alone: vertex set and counts exact, t within TOL."""
+    slot, edges, t, ref = bv
+    mine = slot == k
+    e, tk, rk = edges[mine], t[mine], ref[mine]
+    order = np.lexsort(e.T[::-1])
+    e, tk, rk = e[order], tk[order], rk[order]
+    o = ovol.vertices(live_only=True)
+    assert e.shape == o["keys"].shape, (k, e.shape, o["keys"].shape)
+    assert (e == o["keys"]).all(), f"vertex set of slot {k} differs"
+    assert (rk == o["ref"]).all(), f"reference counts of slot {k} differ"
+    dt = np.abs(tk.astype(np.float64) - o["t"]).max(initial=0)
+    assert dt <= TOL, (k, dt)
+    return dict(nv=int(len(e)), max_t=float(dt))

@@ -67,6 +67,13 @@ def check_samples(full, o, samples):
     b, blocks, verts, ek = full
     ob, orow, overts, otri = oracle_state(o)
     ek_blocks, otri_blocks = triangle_blocks(ek), triangle_blocks(otri)
+    wanted = set(map(tuple, samples.tolist()))
+    by_owner_g, by_owner_o = {}, {}
+    for src, dst in ((verts, by_owner_g), (overts, by_owner_o)):
+        for k, v in src.items():
+            ob_k = owner_block(k)
+            if ob_k in wanted:
+                dst.setdefault(ob_k, {})[k] = v
     for s in map(tuple, samples.tolist()):
         # membership of the whole neighbourhood
         for n in map(tuple, neighbourhood([s]).tolist()):
@@ -80,8 +87,8 @@ def check_samples(full, o, samples):
         assert np.array_equal(b["cur"][i], ob["cur"][j]), s
         assert np.array_equal(b["prev"][i], ob["prev"][j]), s
         # vertices the block owns
-        mine_g = {k: v for k, v in verts.items() if owner_block(k) == s}
-        mine_o = {k: v for k, v in overts.items() if owner_block(k) == s}
+        mine_g = by_owner_g.get(s, {})
+        mine_o = by_owner_o.get(s, {})
         assert mine_g.keys() == mine_o.keys(), s
         for k in mine_g:
             assert mine_g[k][1] == mine_o[k][1], (s, k)

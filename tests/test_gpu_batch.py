@@ -4,18 +4,20 @@ every workgroup mapping.
 
 Bar: the batch is an exact re-arrangement of the per-volume work, so the
 vertex set (positions) and the TSDF gradient must agree bit for bit with
-the plain per-volume path; against the oracle's FP64 gradient the FP32
-kernels are held to 1e-4 relative (floor 1e-4 of the largest magnitude)."""
+the plain per-volume path; against the oracle, each slot's vertex set and
+counts are exact and its edge parameters t within 1e-5 voxel, and the
+FP32 TSDF gradient is within 1e-4 relative (floor 1e-4 of the largest
+magnitude) of the oracle's FP64 one."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import scenes
-from paper_1803_03949_amd import Volume, VmError, key_to_edge
-from paper_1803_03949_amd.binding import SLOT_SPAN
+from paper_1803_03949_amd import Volume, VmError
 from paper_1803_03949_amd.batch import (BatchMesher, PlainMesher, canonical_vertices,
                                         sphere_loss_grad)
+from tests.gpu_compare import batch_vertices, compare_slot_vertices
 
 pytestmark = pytest.mark.gpu
 
@@ -70,18 +72,15 @@ def test_batch_gradient_matches_oracle():
     b.run()
     torch.cuda.synchronize()
     g = b.grad.cpu().numpy()
-    verts, _, vkeys = b.vol.download()
-    verts = verts.cpu().numpy().astype(np.float64)
-    edges = key_to_edge(vkeys)
-    # stored block x of slot k is 64k - 8192 + local x
-    slot = (edges[:, 0] // 8 + 8192) // SLOT_SPAN
-    edges[:, 0] -= 8 * (SLOT_SPAN * slot - 8192)
+    bv = batch_vertices(b.vol)
     off = 0
     for k, v in enumerate(vols):
         c, d, w = v.blocks()
         o = oracle.OracleVolume(S)
         o.import_blocks(c, d, w)
         o.extract(scope_all=True)
+        # the vertex set, counts and edge parameters t of the slot
+        compare_slot_vertices(bv, k, o)
         pos = o.positions64()
         ctr, r = v.meta["center"], v.meta["target_radius"]
         dist = np.linalg.norm(pos - ctr, axis=1)
@@ -94,13 +93,6 @@ def test_batch_gradient_matches_oracle():
         got = g[off:off + len(c)]
         floor = 1e-4 * np.abs(want).max()
         assert np.all(np.abs(got - want) <= 1e-4 * np.abs(want) + floor), k
-        # the vertex set itself: oracle edges and positions vs the slot frame
-        keys = o.vertices()["keys"]
-        want_pos = {tuple(e): p for e, p in zip(keys.tolist(), pos)}
-        mine = slot == k
-        assert int(mine.sum()) == len(want_pos)
-        for e, p in zip(edges[mine].tolist(), verts[mine]):
-            assert np.abs(p - want_pos[tuple(e)]).max() <= 1e-5 * S + 2e-7
         off += len(c)
 
 

@@ -1,13 +1,16 @@
 """Full-size parity of the batched forward + backward: the 64-volume
 workload (182,689 blocks) at the benchmark's size, captured in a HIP graph
 and replayed with the library's default mapping (every mapping gives the
-same bits, tests/test_gpu_batch.py).  The oracle cannot run all 64 volumes
-in seconds, but each slot is an independent volume, so a few sampled
-volumes are computed by the oracle alone and compared with their slots:
-vertex set and triangle connectivity exactly, positions to 1e-5 voxel,
-the TSDF gradient to 1e-4 relative against FP64.  Over the whole batch:
+same bits, tests/test_gpu_batch.py).  Each slot is an independent volume,
+so volumes are computed by the oracle alone and compared with their slots:
+the smallest, three seeded picks and the three largest (up to 18,954
+blocks).  Vertex set, counts and triangle connectivity exactly, edge
+parameters t to 1e-5 voxel, the TSDF gradient to 1e-4 relative against
+FP64.  Over the whole batch:
 no error, every triangle inside one slot, every vertex count equal to the
 number of triangle corners that use the vertex, finite gradients."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -18,6 +21,7 @@ from paper_1803_03949_amd import key_to_edge
 from paper_1803_03949_amd.batch import BatchMesher, sphere_loss_grad
 from paper_1803_03949_amd.binding import SLOT_SPAN
 from tests import meshutil
+from tests.gpu_compare import batch_vertices, compare_slot_vertices
 
 pytestmark = pytest.mark.gpu
 
@@ -45,13 +49,12 @@ def full_batch():
     b.replay()
     torch.cuda.synchronize()
     st = b.vol.status()
-    verts, tris, vkeys = b.vol.download()
+    _, tris, vkeys = b.vol.download()
     edges = key_to_edge(vkeys)
     slot = (edges[:, 0] // 8 + 8192) // SLOT_SPAN
     edges[:, 0] -= 8 * (SLOT_SPAN * slot - 8192)
     return dict(vols=vols, coords=coords, b=b, st=st, grad=b.grad.cpu().numpy(),
-                verts=verts.cpu().numpy().astype(np.float64), tris=tris.cpu().numpy(),
-                edges=edges, slot=slot)
+                tris=tris.cpu().numpy(), edges=edges, slot=slot, bv=batch_vertices(b.vol))
 
 
 def test_whole_batch_properties(full_batch):
@@ -74,34 +77,38 @@ def test_whole_batch_properties(full_batch):
     assert len(dl_keys) == fb["st"]["vertex_slots"] - fb["st"]["free_vertex_slots"]
 
 
-@pytest.mark.parametrize("pick", [0, 1, 2, 3])
+def pick_volume(sizes, pick):
+    """The smallest volume, seeded picks among the rest, and the largest ones."""
+    order = np.argsort(sizes, kind="stable")
+    if pick == "smallest":
+        return int(order[0])
+    if pick.startswith("largest"):
+        return int(order[-int(pick[-1])])
+    return int(np.random.default_rng(int(pick[-1])).choice(order[1:-3]))
+
+
+@pytest.mark.parametrize("pick", ["smallest", "seeded1", "seeded2", "seeded3",
+                                  "largest1", "largest2", "largest3"])
 def test_sampled_volume_matches_oracle(full_batch, pick):
     fb = full_batch
     sizes = np.array([len(c) for c in fb["coords"]])
-    small = np.flatnonzero(sizes <= 3000)
-    # the smallest volume, then seeded picks among those the oracle finishes fast
-    k = int(small[np.argmin(sizes[small])]) if pick == 0 else \
-        int(np.random.default_rng(pick).choice(small))
+    k = pick_volume(sizes, pick)
     print(f"[batch-full] volume {k}, {sizes[k]} blocks", flush=True)
     v = fb["vols"][k]
     c, d, w = v.blocks()
-    o = oracle.OracleVolume(S)
+    o = oracle.OracleVolume(S, threads=min(16, os.cpu_count() or 1))
     o.import_blocks(c, d, w)
     o.extract(scope_all=True)
-    # vertex set and positions
-    mine = fb["slot"] == k
-    keys = o.vertices()["keys"]
-    pos = o.positions64()
-    assert int(mine.sum()) == len(keys)
-    want = {tuple(e): p for e, p in zip(keys.tolist(), pos)}
-    for e, p in zip(fb["edges"][mine].tolist(), fb["verts"][mine]):
-        assert np.abs(p - want[tuple(e)]).max() <= 1e-5 * S + 2e-7
+    # vertex set, counts and edge parameters t
+    compare_slot_vertices(fb["bv"], k, o)
     # triangle connectivity
+    mine = fb["slot"] == k
     t = fb["tris"][mine[fb["tris"][:, 0]]]
     got = meshutil.canonical_triangles(fb["edges"][t])
     ref = meshutil.canonical_triangles(o.triangles())
     assert got.shape == ref.shape and (got == ref).all()
     # TSDF gradient of the sphere loss, FP64
+    pos = o.positions64()
     ctr, r = v.meta["center"], v.meta["target_radius"]
     dist = np.linalg.norm(pos - ctr, axis=1)
     dLdv = (2 * (dist - r) / dist)[:, None] * (pos - ctr)

@@ -1,6 +1,8 @@
 """Full-size parity: the workloads at the sizes and launch configuration the
-benchmark times, checked on sampled outputs the oracle can compute alone,
-plus properties that hold at any size.
+benchmark times.  The 8 mm sequence is replayed by the whole oracle and the
+final states are compared in full; the 4 mm sequence with refinement is
+checked on 50 sampled neighbourhoods the oracle computes alone, plus
+properties that hold at any size.
 
 Sampling: collection and fusion of a block depend only on the depth frames
 and on the block itself, and the mesh inside a block (cube types and their
@@ -24,7 +26,7 @@ import torch
 import oracle
 import scenes
 from paper_1803_03949_amd import Volume, key_to_edge
-from tests.gpu_compare import to_dev
+from tests.gpu_compare import compare_all, to_dev
 from tests.sampling import check_invariants, check_samples, neighbourhood, sample_blocks, state
 
 pytestmark = pytest.mark.gpu
@@ -49,7 +51,9 @@ def render(seq, n):
 
 def test_room_sequence_8mm_full_size():
     """100 frames, 640x480, 8 mm, 2^20 hash slots, integrate+extract+gc per
-    frame, the benchmark's volume and launch configuration."""
+    frame, the benchmark's volume and launch configuration, against the
+    unrestricted oracle replaying the whole sequence: every block, cube
+    type, vertex and triangle of the final state."""
     seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=0.008)
     frames = render(seq, 100)
     print("[full] room 8 mm: GPU", flush=True)
@@ -59,17 +63,19 @@ def test_room_sequence_8mm_full_size():
         g.integrate(depth[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
         g.extract()
         g.gc()
-    state = gpu_state(g)
-    check_invariants(state)
-    samples = sample_blocks(state[1], np.random.default_rng(21), 10, 4)
-    print(f"[full] room 8 mm: oracle on {len(samples)} sampled neighbourhoods", flush=True)
-    o = oracle.OracleVolume(0.008)
-    o.restrict(neighbourhood(samples.tolist()))
+    assert g.status()["error"] == 0
+    check_invariants(gpu_state(g))
+    print("[full] room 8 mm: oracle, whole sequence", flush=True)
+    o = oracle.OracleVolume(0.008, threads=min(16, os.cpu_count() or 1), keep_fusion=False)
     for k in range(100):
         o.integrate(frames[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
         o.extract()
         o.gc()
-    check_samples(state, o, samples)
+        if (k + 1) % 20 == 0:
+            print(f"[full] room 8 mm: oracle frame {k + 1}", flush=True)
+    info = compare_all(g, o)
+    print(f"[full] room 8 mm: {info}", flush=True)
+    assert info["nv"] > 10 ** 6
 
 
 def test_room_sequence_4mm_refine_full_size():
@@ -88,9 +94,9 @@ def test_room_sequence_4mm_refine_full_size():
     state = gpu_state(g)
     check_invariants(state)
     assert g.totals()["refined_cubes"] > 0
-    samples = sample_blocks(state[1], np.random.default_rng(22), 5, 2)
+    samples = sample_blocks(state[1], np.random.default_rng(22), 40, 10)
     print(f"[full] room 4 mm: oracle on {len(samples)} sampled neighbourhoods", flush=True)
-    o = oracle.OracleVolume(0.004)
+    o = oracle.OracleVolume(0.004, threads=min(16, os.cpu_count() or 1), keep_fusion=False)
     o.restrict(neighbourhood(samples.tolist()))
     for k in range(500):
         o.integrate(frames[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
