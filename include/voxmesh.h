@@ -23,8 +23,8 @@
  *   and every input/output array is a caller pointer.  Pointers documented
  *   as "device" must be device (or managed) memory; "host" pointers are read
  *   before the call returns.
- * - Capacity overflow inside a kernel (hash table, block pool, vertex pool,
- *   triangle pool) sets a sticky error bit in the volume; the next
+ * - Capacity overflow inside a kernel (hash table, block pool, vertex pool)
+ *   sets a sticky error bit in the volume; the next
  *   synchronising call returns the matching VM_ERR_* code.  The volume is
  *   not usable for meshing after such an error (reset it).
  * - Lattice: voxel g (integer 3-vector) sits at world position g * voxel_m;
@@ -68,8 +68,8 @@ enum {
   VM_ERR_HASH_FULL = -2,       /* hash table probe sequence exhausted */
   VM_ERR_BLOCK_POOL_FULL = -3, /* more blocks than max_blocks */
   VM_ERR_VERTEX_POOL_FULL = -4,/* more live vertices than max_vertices */
-  VM_ERR_TRI_POOL_FULL = -5,   /* reserved (triangles are stored per cube) */
-  VM_ERR_CAPACITY = -6,        /* caller output buffer too small */
+                               /* (-5 is not used: triangles take no pool) */
+  VM_ERR_CAPACITY = -6,        /* caller output buffer or workspace too small */
   VM_ERR_HIP = -7,             /* a HIP runtime call failed */
   VM_ERR_RANGE = -8            /* a block coordinate outside [-8192, 8191] */
 };
@@ -77,10 +77,11 @@ enum {
 enum { VM_SCOPE_DIRTY = 0, VM_SCOPE_ALL = 1 };
 
 /* Volume configuration.  Sizes are capacities of the caller buffer: per
- * block of max_blocks about 51 KiB (TSDF and weight 4 KiB, types 1 KiB,
- * vertex slot, t and count of its 1536 owned edges 13.5 KiB, the triangles
- * of its 512 cubes 32 KiB, a 64-byte mask of its observed voxels) and per
- * vertex of max_vertices 16 bytes, plus 16 bytes per hash slot. */
+ * block of max_blocks about 18.9 KiB (TSDF and weight 4 KiB, types 1 KiB,
+ * vertex slot, t and count of its 1536 owned edges 13.5 KiB, a 64-byte mask
+ * of its observed voxels, lists and stamps), per vertex of max_vertices 16
+ * bytes, plus 16 bytes per hash slot.  Triangles take no memory of their
+ * own: a cube's type names them (see vm_extract_mesh). */
 typedef struct vm_config {
   float voxel_m;        /* cube edge length s in metres (e.g. 0.008) */
   float trunc_vox;      /* truncation mu in voxel units (e.g. 4) */
@@ -131,31 +132,30 @@ enum {
   VM_TOTAL_VERTEX_BLOCKS = 3,   /* blocks whose owned edges were recomputed */
   VM_TOTAL_NEW_VERTICES = 4,
   VM_TOTAL_UPDATED_VERTICES = 5,
-  VM_TOTAL_CHANGED_CUBES = 6,   /* cubes whose triangles were rewritten */
-  VM_TOTAL_GC_SCANNED = 7,      /* reserved, 0: vm_gc scans nothing */
+  VM_TOTAL_CHANGED_CUBES = 6,   /* cubes whose triangles were replaced */
+  VM_TOTAL_NEW_TRIANGLES = 7,   /* triangles of those cubes' new types */
   VM_TOTAL_FREED_VERTICES = 8,
   VM_TOTAL_REFINED_CUBES = 9,
-  VM_TOTAL_COUNT = 10
+  VM_TOTAL_DROPPED_TRIANGLES = 10, /* triangles of those cubes' old types */
+  VM_TOTAL_COUNT = 11
 };
 
 /* Kernels, for vm_profile_read. */
 enum {
   VM_K_COLLECT = 0,      /* block collection along pixel rays (Eq. 1) */
-  VM_K_ASSIGN = 1,       /* pool indices for new blocks */
-  VM_K_LINK = 2,         /* neighbour links of new blocks */
-  VM_K_FUSE = 3,         /* TSDF fusion (Eq. 2) */
-  VM_K_IMPORT = 4,       /* vm_import_blocks copy and insert */
-  VM_K_DIRTY = 5,        /* dirty block list */
-  VM_K_CLASSIFY = 6,     /* cube types */
-  VM_K_REFINE = 7,       /* cube types, refinement pass */
-  VM_K_VERTICES = 8,     /* edge-owned vertices and reference counts */
-  VM_K_TRIANGLES = 9,    /* triangle records of changed cubes */
-  VM_K_GC = 10,          /* (reserved: recycling runs in the vertex pass) */
-  VM_K_DOWNLOAD = 11,    /* download compaction (all its kernels) */
-  VM_K_BACKWARD = 12,    /* backward passes */
-  VM_K_COUNTERS = 13,    /* single-lane bookkeeping kernels */
-  VM_K_ABLATION = 14,    /* vm_sharing_ablation (the paper's sharing schemes) */
-  VM_K_COUNT = 15
+  VM_K_ASSIGN = 1,       /* import: pool indices for new blocks, in row order */
+  VM_K_FUSE = 2,         /* TSDF fusion (Eq. 2) */
+  VM_K_IMPORT = 3,       /* import: hash inserts, block state and copies */
+  VM_K_DIRTY = 4,        /* dirty block list, vertex block list */
+  VM_K_CLASSIFY = 5,     /* cube types, which also replace triangles */
+  VM_K_REFINE = 6,       /* cube types, refinement pass */
+  VM_K_VERTICES = 7,     /* edge-owned vertices, reference counts, recycling */
+  VM_K_DOWNLOAD = 8,     /* download compaction (all its kernels) */
+  VM_K_BACKWARD = 9,     /* backward passes */
+  VM_K_COUNTERS = 10,    /* single-wave bookkeeping kernels */
+  VM_K_ABLATION = 11,    /* vm_sharing_ablation (the paper's sharing schemes) */
+  VM_K_POSITIONS = 12,   /* vm_export_positions */
+  VM_K_COUNT = 13
 };
 
 typedef struct vm_volume vm_volume;
@@ -230,24 +230,14 @@ int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
  * block.  For each such cube: type t with bit k = [d(c_k) < 0] over the
  * corners in cyclic order (0,0,0) (1,0,0) (1,1,0) (0,1,0) (0,0,1) (1,0,1)
  * (1,1,1) (0,1,1); a cube with a corner in a missing block or with weight 0
- * has type 0.  The previous type is kept (t_{i-1}).  Cubes whose type
- * changed get new triangles; every edge used by some cube's triangles holds
- * one vertex at t = d(g)/(d(g) - d(g+a)) (0.5 if equal), created on first
- * use and updated when its end points move; each vertex's reference count
- * is the number of triangles using it. */
+ * has type 0.  The previous type is kept (t_{i-1}).  A cube's triangles are
+ * those its type names, each as three cube edges: writing a changed type
+ * replaces them, an unchanged cube keeps them (Sec. V-D), and they are
+ * resolved to vertex indices only by a download.  Every edge used by some
+ * cube's triangles holds one vertex at t = d(g)/(d(g) - d(g+a)) (0.5 if
+ * equal), created on first use and updated when its end points move; each
+ * vertex's reference count is the number of triangles using it. */
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream);
-
-/* vm_extract_mesh with the triangle records written on tri_stream, which
- * first waits (an event) for the vertex pass on `stream`; work enqueued on
- * `stream` afterwards that reads vertices but not triangles (positions,
- * vm_extract_backward*) can then run alongside the triangle pass.  The
- * caller makes `stream` wait for tri_stream before anything that reads or
- * writes the mesh again (downloads, exports, the next extraction or
- * refinement).  tri_stream == stream is vm_extract_mesh.  Streams at the
- * default priority; both may be under graph capture (the wait joins
- * tri_stream to the capture). */
-int vm_extract_mesh_split(vm_volume* vol, int scope, hipStream_t stream,
-                          hipStream_t tri_stream);
 
 /* Hamming-distance refinement (Sec. V-F, Eqs. 3-5) of the cubes of the last
  * extraction: a valid cube with type t and previous type p is set to the
@@ -269,7 +259,11 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream);
  * NULL volume). */
 int vm_gc(vm_volume* vol, hipStream_t stream);
 
-/* Compact the mesh into caller buffers (device): verts[vcap][3] FP32
+/* The mesh handed over as plain arrays, the step the paper times as
+ * "compressing" the mesh for rendering (Sec. VI, Table I): live vertices
+ * compacted in pool order, each cube's triangles resolved from its type
+ * through the edges' owner voxels to vertex rows.  Caller buffers
+ * (device): verts[vcap][3] FP32
  * metres (vertex on edge (g, a): g*s with (g_a + t)*s on axis a),
  * edge_keys[vcap] (may be NULL), tris[tcap][3] int32 indices into verts,
  * oriented counter-clockwise seen from the outside (d > 0).  *nv, *nt

@@ -104,9 +104,6 @@ class BatchMesher:
         self.weight = weight
         if zero_copy:
             self.vol.bind_tsdf(tsdf, weight)
-        # the triangle pass runs here, beside positions, loss and backward,
-        # which read vertices only (default priority, like every stream)
-        self.tri_stream = torch.cuda.Stream(device=dev)
         self.rows = torch.empty(N, dtype=torch.int32, device=dev)
         self.pos = torch.empty((V, 3), dtype=torch.float32, device=dev)
         self.slot = torch.empty(V, dtype=torch.int32, device=dev)
@@ -116,17 +113,15 @@ class BatchMesher:
         self.graph = None
 
     def run(self, stream=None):
-        """The whole step, enqueued on the current stream (the triangle pass
-        on a side stream that the current one joins at the end)."""
+        """The whole step, enqueued on the current stream."""
         v = self.vol
         cur = torch.cuda.current_stream(v.device) if stream is None else stream
         v.reset(cur)
         v.import_batch(self.slots, self.coords, self.tsdf, self.weight, self.rows, cur)
-        v.extract(scope_all=True, stream=cur, tri_stream=self.tri_stream)
+        v.extract(scope_all=True, stream=cur)
         v.positions(self.pos, self.slot, cur)
         self.loss_grad(self.pos, self.slot, self.dpos)
         v.extract_backward_slots(self.dpos, self.rows, self.grad, cur)
-        cur.wait_stream(self.tri_stream)
 
     def capture(self):
         """Capture `run` in a HIP graph (after one eager warm-up run)."""

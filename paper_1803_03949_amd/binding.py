@@ -22,7 +22,7 @@ VM_OK = 0
 VM_SCOPE_DIRTY, VM_SCOPE_ALL = 0, 1
 ERRORS = {
     -1: "VM_ERR_ARG", -2: "VM_ERR_HASH_FULL", -3: "VM_ERR_BLOCK_POOL_FULL",
-    -4: "VM_ERR_VERTEX_POOL_FULL", -5: "VM_ERR_TRI_POOL_FULL", -6: "VM_ERR_CAPACITY",
+    -4: "VM_ERR_VERTEX_POOL_FULL", -6: "VM_ERR_CAPACITY",
     -7: "VM_ERR_HIP", -8: "VM_ERR_RANGE",
 }
 
@@ -65,9 +65,10 @@ _STATUS_FIELDS = ["blocks", "frame_blocks", "pending_blocks", "dirty_blocks", "v
 
 
 TOTALS = ["frames", "frame_blocks", "dirty_blocks", "vertex_blocks", "new_vertices",
-          "updated_vertices", "changed_cubes", "gc_scanned", "freed_vertices", "refined_cubes"]
-KERNELS = ["collect", "assign", "link", "fuse", "import", "dirty", "classify", "refine",
-           "vertices", "triangles", "gc", "download", "backward", "counters", "ablation"]
+          "updated_vertices", "changed_cubes", "new_triangles", "freed_vertices",
+          "refined_cubes", "dropped_triangles"]
+KERNELS = ["collect", "assign", "fuse", "import", "dirty", "classify", "refine", "vertices",
+           "download", "backward", "counters", "ablation", "positions"]
 
 
 class vm_status(ctypes.Structure):
@@ -106,7 +107,6 @@ def lib() -> ctypes.CDLL:
             "vm_download_births": [P, P, I64, P],
             "vm_sharing_ablation": [P, ctypes.c_int, P, P, P, P],
             "vm_bind_tsdf": [P, P, P],
-            "vm_extract_mesh_split": [P, ctypes.c_int, P, P],
             "vm_extract_backward": [P, P, P, P],
             "vm_integrate_backward": [P, P, P, P, P, P],
             "vm_get_status": [P, ctypes.POINTER(vm_status), P],
@@ -245,16 +245,10 @@ class Volume:
         _check(lib().vm_import_batch(self.h, _ptr(slots), _ptr(coords), _ptr(tsdf), _ptr(weight),
                                      n, _ptr(rows), _stream(stream)), "vm_import_batch")
 
-    def extract(self, scope_all: bool = False, stream=None, tri_stream=None):
-        """Mesh extraction; with tri_stream (a torch stream) the triangle pass
-        runs there once the vertex pass is done (vm_extract_mesh_split): the
-        caller joins it before the mesh is read or changed again."""
+    def extract(self, scope_all: bool = False, stream=None):
+        """Mesh extraction (dirty blocks, or every block with scope_all)."""
         scope = VM_SCOPE_ALL if scope_all else VM_SCOPE_DIRTY
-        if tri_stream is None:
-            _check(lib().vm_extract_mesh(self.h, scope, _stream(stream)), "vm_extract_mesh")
-        else:
-            _check(lib().vm_extract_mesh_split(self.h, scope, _stream(stream), _stream(tri_stream)),
-                   "vm_extract_mesh_split")
+        _check(lib().vm_extract_mesh(self.h, scope, _stream(stream)), "vm_extract_mesh")
 
     def refine(self, stream=None):
         _check(lib().vm_refine_mesh(self.h, _stream(stream)), "vm_refine_mesh")

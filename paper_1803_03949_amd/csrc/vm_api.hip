@@ -44,7 +44,6 @@ struct vm_volume {
   int grid_waves;   // workgroups of wave-per-block kernels
   uint32_t prof;    // bit k: bracket launches of kernel k with events
   std::vector<hipEvent_t> ev_free;
-  hipEvent_t split_ev = nullptr;  // vertex pass done (vm_extract_mesh_split; made on first use)
   std::vector<ProfRec> recs;
   int scratch_dev = -1;  // device whose static workspace holds the volume, -1 if the caller's
 };
@@ -111,7 +110,6 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->evtx = (int32_t*)take(4 * 3 * kVox * B);
   v->et = (float*)take(4 * 3 * kVox * B);
   v->eref = (uint8_t*)take(3 * kVox * B);
-  v->chg = (uint64_t*)take(8 * 8 * B);
   v->wmask = (uint64_t*)take(8 * 8 * B);
   v->st_pending = (uint32_t*)take(4 * B);
   v->st_dirty = (uint32_t*)take(4 * B);
@@ -128,7 +126,6 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->vring = (uint32_t*)take(4 * V);
   v->vdl = (int32_t*)take(4 * V);
   v->vbirth = (uint32_t*)take(4 * V);
-  v->chunks = (uint32_t*)take(4 * kChunkWords * C);
   v->scan = (uint32_t*)take(4 * scan);
   v->scan_cap = (uint32_t)scan;
   v->max_blocks = (uint32_t)B;
@@ -370,7 +367,6 @@ int vm_destroy_volume(vm_volume* vol) {
   if (!vol) return VM_ERR_ARG;
   for (auto& r : vol->recs) vol->ev_free.push_back(r.a), vol->ev_free.push_back(r.b);
   for (hipEvent_t e : vol->ev_free) (void)hipEventDestroy(e);
-  if (vol->split_ev) (void)hipEventDestroy(vol->split_ev);
   const int sdev = vol->scratch_dev;
   if (sdev < 0) {
     delete vol;
@@ -472,10 +468,6 @@ int vm_bind_tsdf(vm_volume* vol, float* tsdf, float* weight) {
 }
 
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
-  return vm_extract_mesh_split(vol, scope, stream, stream);
-}
-
-int vm_extract_mesh_split(vm_volume* vol, int scope, hipStream_t stream, hipStream_t tri_stream) {
   if (!vol || (scope != VM_SCOPE_DIRTY && scope != VM_SCOPE_ALL)) return VM_ERR_ARG;
   const uint32_t pass = ++vol->pass;
   vol->dl_nv = -1;
@@ -493,16 +485,6 @@ int vm_extract_mesh_split(vm_volume* vol, int scope, hipStream_t stream, hipStre
   VM_LAUNCH_W(vol, VM_K_CLASSIFY, k_classify, stream, v, pass, 0);
   VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
   VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
-  if (tri_stream != stream) {
-    // the triangle records need only the vertex slots: hand them to the
-    // other stream once the vertex pass is done
-    hipError_t e = vol->split_ev ? hipSuccess
-                                 : hipEventCreateWithFlags(&vol->split_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(vol->split_ev, stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(tri_stream, vol->split_ev, 0);
-    if (e != hipSuccess) return hip_status(e);
-  }
-  VM_LAUNCH_W(vol, VM_K_TRIANGLES, k_triangles, tri_stream, v);
   return launched();
 }
 
@@ -517,7 +499,6 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   VM_LAUNCH_W(vol, VM_K_REFINE, k_classify, stream, v, pass, 1);
   VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
   VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
-  VM_LAUNCH_W(vol, VM_K_TRIANGLES, k_triangles, stream, v);
   return launched();
 }
 
@@ -619,7 +600,7 @@ int vm_export_positions(vm_volume* vol, float* pos, int32_t* slot_of, int64_t ca
   if (!vol || !pos) return VM_ERR_ARG;
   if (cap < (int64_t)vol->dev.max_vertices) return VM_ERR_CAPACITY;
   prep(vol, VM_OP_FINALISE, stream);
-  VM_LAUNCH(vol, VM_K_DOWNLOAD, k_positions, dim3(vol->grid_items), dim3(256), stream, vol->dev,
+  VM_LAUNCH(vol, VM_K_POSITIONS, k_positions, dim3(vol->grid_items), dim3(256), stream, vol->dev,
             pos, slot_of);
   return launched();
 }
@@ -786,6 +767,8 @@ int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream) {
     t[VM_TOTAL_FREED_VERTICES] += sn.vseg[k].st_freed;
     t[VM_TOTAL_CHANGED_CUBES] += sn.cseg[k].st_chg;
     t[VM_TOTAL_REFINED_CUBES] += sn.cseg[k].st_ref;
+    t[VM_TOTAL_NEW_TRIANGLES] += sn.cseg[k].st_fnew;
+    t[VM_TOTAL_DROPPED_TRIANGLES] += sn.cseg[k].st_fold;
   }
   for (int i = 0; i < n; ++i) out[i] = (int64_t)t[i];
   return VM_OK;

@@ -1,26 +1,24 @@
 // Internal device-side layout and helpers of the voxmesh library (gfx950).
 //
-// Volume state lives in one caller-provided device buffer, carved into
-// structure-of-arrays regions (block-major, voxel-minor) so that the 512
-// lanes of a workgroup that handles one 8^3 block read and write contiguous
-// 2 KiB rows:
+// Volume state lives in one workspace buffer, carved into structure-of-arrays
+// regions (block-major, voxel-minor): the kernels that give each 8^3 block
+// one wave (eight voxels or cubes per lane, one column of 8 along z) read
+// and write a block's rows as coalesced 2 KiB runs.
 //   hash      u64 slot = (42-bit block key << 22) | 22-bit pool index,
 //             all-ones = empty; open addressing with linear probing and
 //             64-bit compare-and-swap inserts, no deletion; a per-slot frame
 //             stamp marks the blocks a frame collected.
 //   blocks    key u64, 27-neighbour index table, TSDF f32[512],
 //             weight f32[512], previous/current cube type u8[512],
-//             edge->vertex slot i32[3][512] (the three edges every voxel
-//             owns), cube->triangle chunk i32[512], changed-cube bitmask
-//             u64[8], observed-voxel (weight > 0) bitmask u64[8], pass
-//             stamps.
-//   vertices  per edge (block-local, next to the edge->vertex slot): the
-//             vertex's t f32 and reference count u8; per pool slot: owner
-//             edge (index into the edge arrays, kNone when free), recycle
-//             ring, download row.
-//   triangles one 64-byte record per cube, at a fixed place in its block's
-//             region: up to 5 triangles as 3 vertex slots each (the cube's
-//             type says how many are valid).
+//             per owned edge (three per voxel): vertex slot i32, the
+//             vertex's t f32 and reference count u8; observed-voxel
+//             (weight > 0) bitmask u64[8]; pass stamps.
+//   vertices  per pool slot: owner edge (index into the edge arrays, kNone
+//             when free), recycle ring, download row, birth frame.
+//   triangles no storage of their own: a cube's applied type names its
+//             triangles and each triangle's three edges, and each edge
+//             holds its one vertex, so the types are the triangle records;
+//             a download resolves them to vertex rows.
 //
 // Contention on single counters is what limits a GPU here, not bytes: every
 // list is built with at most one atomic per workgroup, and the vertex pool
@@ -46,7 +44,6 @@ constexpr uint32_t kPending = kIdxMask - 1;
 constexpr int kKeyBias = 8192;               // block coords in [-8192, 8191]
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kNewFlag = 0x80000000u;   // frame-list entry: block is new
-constexpr int kChunkWords = 16;              // 5 triangles * 3 slots, 1 spare
 constexpr int kMaxBlocks = 1 << 21;
 constexpr int kSegs = 64;                    // pool segments
 constexpr int kTile = 256;                   // list items per compaction workgroup (256 lanes)
@@ -59,7 +56,6 @@ constexpr int kTileBits = count_bits(kTilePer);  // bits of a lane's count
 constexpr uint32_t kErrHash = 1u << 0;
 constexpr uint32_t kErrBlocks = 1u << 1;
 constexpr uint32_t kErrVertices = 1u << 2;
-constexpr uint32_t kErrTris = 1u << 3;
 constexpr uint32_t kErrRange = 1u << 6;
 
 // One pool segment: slots [base, base + size) of the pool, with its own
@@ -78,7 +74,9 @@ struct Seg {
   uint32_t st_ref;   // running count of cubes re-typed by refinement
   int32_t st_tri;    // running change of the number of triangles
   int32_t st_tcube;  // running change of the number of cubes with triangles
-  uint32_t pad[20];
+  uint32_t st_fnew;  // running count of triangles of changed cubes' new types
+  uint32_t st_fold;  // running count of triangles of changed cubes' old types
+  uint32_t pad[18];
 };
 static_assert(sizeof(Seg) == 128, "segment record size");
 
@@ -100,8 +98,8 @@ struct Counters {
   uint32_t import_base;    // blocks in the pool before the last import
   uint32_t pad[13];
   // running totals since the volume was created (not cleared by a reset)
-  unsigned long long acc[10];
-  unsigned long long pad2[6];
+  unsigned long long acc[12];
+  unsigned long long pad2[4];
 };
 static_assert(sizeof(Counters) == 256, "counter record size");
 
@@ -134,7 +132,6 @@ struct VolDev {
                               // (-1 after a failed allocation), stale elsewhere
   float* et;                  // [B][3][512] t of the edge's vertex
   uint8_t* eref;              // [B][3][512] reference count of the edge's vertex
-  uint64_t* chg;              // [B][8] by dirty-list position and z layer: cubes whose triangles changed
   uint64_t* wmask;            // [B][8] per z layer: voxels with weight > 0 (bit x + 8y)
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
@@ -151,7 +148,6 @@ struct VolDev {
   uint32_t* vring;            // [V]
   int32_t* vdl;               // [V] row in the last download, -1 if none
   uint32_t* vbirth;           // [V] frame in which the vertex last became used
-  uint32_t* chunks;           // [B][512][16] triangles of every cube
   uint32_t* scan;             // [scan_cap] download partial sums
   uint32_t scan_cap;
   uint32_t batch;             // number of volume slots, 0 for a plain volume
@@ -555,8 +551,6 @@ __global__ void k_classify(VolDev v, uint32_t pass, int refine);
 __global__ void k_vblock_compact(VolDev v);
 template <int W>
 __global__ void k_vertices(VolDev v);
-template <int W>
-__global__ void k_triangles(VolDev v);
 __global__ void k_dl_count(VolDev v, int what);
 __global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
 __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,

@@ -1,12 +1,13 @@
 // HIP kernels of the voxmesh library for gfx950 (wave64).
 //
-// Work that is per block (fusion, classification, vertex update, triangle
-// rewrite, backward) runs one 512-lane workgroup per 8^3 block, one lane per
-// voxel/cube, with the block and its one-voxel halo staged in LDS.  Work
-// lists live on the device and every kernel loops over its list with a grid
-// stride, so the host never waits for a count.  Lists are compacted with one
-// atomic per workgroup; pool allocations take one atomic per block on the
-// block's pool segment.
+// Per-block work (fusion, import, classification, vertices, the TSDF
+// backward) gives each 8^3 block one wave: lane q owns the column of eight
+// voxels or cubes at (q & 7, q >> 3), and the block's halo is staged in the
+// wave's own LDS, so waves of a workgroup never wait for each other.  Work
+// lists live on the device and every kernel loops over its list on a grid
+// sized to the device, so the host never waits for a count.  Lists are
+// compacted with one atomic per workgroup; pool allocations take one atomic
+// per block on the block's pool segment.
 #include "voxmesh.h"
 #include "vm_internal.h"
 
@@ -67,10 +68,13 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
   const uint32_t sum_new = wave_sum(vs.st_new), sum_upd = wave_sum(vs.st_upd);
   const uint32_t sum_freed = wave_sum(vs.st_freed);
   const uint32_t sum_chg = wave_sum(cs.st_chg), sum_ref = wave_sum(cs.st_ref);
+  const uint32_t sum_fnew = wave_sum(cs.st_fnew), sum_fold = wave_sum(cs.st_fold);
   if (s != 0) return;
   Counters* c = v.cnt;
   switch (op) {
     case VM_OP_RESET:
+      c->acc[VM_TOTAL_NEW_TRIANGLES] += sum_fnew;
+      c->acc[VM_TOTAL_DROPPED_TRIANGLES] += sum_fold;
       c->acc[VM_TOTAL_NEW_VERTICES] += sum_new;
       c->acc[VM_TOTAL_UPDATED_VERTICES] += sum_upd;
       c->acc[VM_TOTAL_FREED_VERTICES] += sum_freed;
@@ -667,12 +671,13 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
 // plus the +x/+y/+z halo layer (9^3) are staged in the wave's LDS.
 // refine = 0: new cube types from the signs (Sec. V-B), previous type
 // saved.  refine = 1: Eqs. (3)-(5) applied to the current types (Sec. V-F).
-// Cubes whose triangles change are recorded in the block's bitmask (one
-// 64-bit word per z layer) for k_triangles.  The blocks whose vertices must
-// be recomputed are claimed (once per pass) and written as candidates at
-// fixed positions 8i..8i+7: on extraction this block (its edges' end points
-// may have moved), and the owners of the edges of changed cubes (this block
-// and, for cubes on its +x/+y/+z faces, neighbours).
+// Writing a cube's new type replaces its triangles (Sec. V-D): the type
+// names them and the edges they use, and a cube whose type is unchanged
+// keeps them.  The blocks whose vertices must be recomputed are claimed
+// (once per pass) and written as candidates at fixed positions 8i..8i+7: on
+// extraction this block (its edges' end points may have moved), and the
+// owners of the edges of changed cubes (this block and, for cubes on its
+// +x/+y/+z faces, neighbours).
 template <int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(VolDev v, uint32_t pass, int refine) {
   __shared__ float sd_all[W][729];     // TSDF (refinement only)
@@ -747,6 +752,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     wave_sync();
     uint32_t flags = 0, nchanged = 0;
     int dtri = 0, dtcube = 0;  // change of the triangle and triangle-cube counts
+    uint32_t fnew = 0, fold = 0;  // triangles of changed cubes' new and old types
     // the lane's column of cubes shares corner faces between layers: face
     // z holds the signs of corners (x, y), (x+1, y), (x+1, y+1), (x, y+1) at
     // height z in bits 0..3 (the cyclic corner order) and, in bit 4, whether
@@ -781,9 +787,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       const bool tri_change = nt != old[lz] && (ntri_old || ntri_new);
       dtri += ntri_new - ntri_old;
       dtcube += (ntri_new > 0) - (ntri_old > 0);
-      const uint64_t m = __ballot(tri_change);
-      if (q == 0) v.chg[(size_t)i * 8 + lz] = m;  // by dirty-list position
-      nchanged += (uint32_t)__popcll(m);
+      if (tri_change) fnew += ntri_new, fold += ntri_old;
+      nchanged += (uint32_t)__popcll(__ballot(tri_change));
       if (tri_change) {
         // owners of this cube's edges: this block and, on its +x/+y/+z
         // faces, the neighbours (never the +x+y+z corner one)
@@ -808,12 +813,17 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     // per lane dtri is in [-40, 40] and dtcube in [-8, 8]: summed offset
     dtri = (int)wave_sum_bits<7>((uint32_t)(dtri + 40)) - 64 * 40;
     dtcube = (int)wave_sum_bits<5>((uint32_t)(dtcube + 8)) - 64 * 8;
+    // per lane fnew and fold are at most 40 (5 triangles in 8 cubes)
+    fnew = wave_sum_bits<6>(fnew);
+    fold = wave_sum_bits<6>(fold);
     if (q == 0 && nchanged) {
       const uint32_t sg = idx % v.nseg;
       atomicAdd(&v.cseg[sg].st_chg, nchanged);
       if (refine) atomicAdd(&v.cseg[sg].st_ref, nchanged);
       if (dtri) atomicAdd(&v.cseg[sg].st_tri, dtri);
       if (dtcube) atomicAdd(&v.cseg[sg].st_tcube, dtcube);
+      if (fnew) atomicAdd(&v.cseg[sg].st_fnew, fnew);
+      if (fold) atomicAdd(&v.cseg[sg].st_fold, fold);
     }
     wave_sync();
   }
@@ -1173,122 +1183,6 @@ __device__ inline void edge_owner(int e, int& ox, int& oy, int& oz, int& axis) {
   axis = (int)(p >> 3);
 }
 
-// One wave per (dirty block, group of G z layers): every cube of the group
-// whose triangles changed and whose new type has triangles gets them
-// rewritten (Sec. V-D) as the vertex slots of the owning edges, into the
-// cube's own record; unchanged cubes keep theirs, and a cube without
-// triangles needs no write (its type says so).  Each record (64 bytes) is
-// written by 16 lanes; the edge-slot gathers of 32 cubes are issued before
-// their stores.  A short dirty list takes one layer per wave (G = 1), so a
-// block with many changed cubes is spread over up to eight waves; a long one
-// takes four layers per wave (G = 4), so each half block costs one
-// neighbour-table and one type round trip instead of four.
-template <int W, int G>
-__device__ inline void triangle_items(const VolDev& v, const uint8_t* stri, uint16_t* slist,
-                                      uint8_t* stype, int32_t* snb, int wave, uint32_t nd) {
-  constexpr uint32_t kGroups = 8 / G;  // items per block
-  const int q = __lane_id();
-  const int k = q & 15;
-  const uint64_t below = lanes_below();
-  // item i is layers (i % kGroups) * G .. + G - 1 of dirty-list entry
-  // i / kGroups; its change masks sit at positions 8 * entry + layer.  The
-  // next item's masks and block are requested while the current one is
-  // worked on, so an unchanged item costs no round trip.
-  ItemLoop it = item_loop(v, nd * kGroups, W, wave);
-  uint64_t m_next[G];
-  uint32_t idx_next = 0;
-  auto fetch = [&](uint32_t i) {
-    const uint32_t e = i / kGroups, lz0 = (i % kGroups) * G;
-#pragma unroll
-    for (int g = 0; g < G; ++g) m_next[g] = v.chg[(size_t)e * 8 + lz0 + g];
-    idx_next = v.dirty[e];
-  };
-  if (it.i < it.end) fetch(it.i);
-  for (; it.i < it.end; it.i += it.step) {
-    uint64_t m[G];
-    uint64_t any = 0;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const uint32_t lo = uniform((uint32_t)m_next[g]), hi = uniform((uint32_t)(m_next[g] >> 32));
-      m[g] = ((uint64_t)hi << 32) | lo;
-      any |= m[g];
-    }
-    const uint32_t idx = uniform(idx_next);
-    const int lz0 = (int)((it.i % kGroups) * G);
-    if (it.i + it.step < it.end) fetch(it.i + it.step);
-    if (any == 0ull) continue;
-    const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
-    uint32_t mytype[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) mytype[g] = v.tcur[(size_t)idx * kVox + q + 64 * (lz0 + g)];
-    if (q < 27) snb[q] = mynb;
-    // changed cubes whose new type has triangles, layer by layer in lane order
-    uint32_t nw = 0;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const uint64_t w = __ballot(((m[g] >> q) & 1ull) && stri[mytype[g] * 16] != 0);
-      if ((w >> q) & 1ull) {
-        const uint32_t pos = nw + (uint32_t)__popcll(w & below);
-        slist[pos] = (uint16_t)(q + 64 * g);
-        stype[pos] = (uint8_t)mytype[g];
-      }
-      nw += (uint32_t)__popcll(w);
-    }
-    wave_sync();
-    for (uint32_t c0 = 0; c0 < nw; c0 += 32) {
-      uint32_t word[8];
-      int32_t dst[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const uint32_t c = c0 + 4 * r + (q >> 4);
-        word[r] = kNone;
-        dst[r] = -1;
-        if (c >= nw) continue;
-        const uint32_t type = stype[c], ntri = stri[type * 16];
-        if (k >= (int)(3 * ntri)) continue;
-        const int l = (int)slist[c] + 64 * lz0;
-        dst[r] = l;
-        int ox, oy, oz, axis;
-        edge_owner(stri[type * 16 + 1 + k], ox, oy, oz, axis);
-        const int x = (l & 7) + ox, y = ((l >> 3) & 7) + oy, z = (l >> 6) + oz;
-        const int32_t nb = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
-        if (nb >= 0) {
-          const int32_t s =
-              v.evtx[((size_t)nb * 3 + axis) * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
-          word[r] = s >= 0 ? (uint32_t)s : kNone;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (dst[r] >= 0) v.chunks[((size_t)idx * kVox + dst[r]) * kChunkWords + k] = word[r];
-    }
-    wave_sync();
-  }
-}
-
-template <int W>
-__global__ __launch_bounds__(64 * W) void k_triangles(VolDev v) {
-  __shared__ uint8_t stri[256 * 16];
-  __shared__ uint16_t slist_all[W][256];  // changed cubes of the item (x + 8y + 64 g)
-  __shared__ uint8_t stype_all[W][256];   // their types
-  __shared__ int32_t snb_all[W][27];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(v.tri_table);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(stri);
-    for (int j = threadIdx.x; j < 256 * 16 / 4; j += blockDim.x) dst[j] = src[j];
-  }
-  __syncthreads();
-  const uint32_t nd = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
-  // half blocks per wave once single layers would give every wave of the
-  // grid more than four items (measured on MI355X: four layers per item beat
-  // one, two and eight on the 4 mm sequence and on the 64-volume batch)
-  if ((uint64_t)nd * 8 <= 4ull * gridDim.x * W)
-    triangle_items<W, 1>(v, stri, slist_all[wave], stype_all[wave], snb_all[wave], wave, nd);
-  else
-    triangle_items<W, 4>(v, stri, slist_all[wave], stype_all[wave], snb_all[wave], wave, nd);
-}
-
 // ============================================================================
 // ablation: the paper's two ways of sharing vertices between cubes
 // ============================================================================
@@ -1487,6 +1381,10 @@ __global__ __launch_bounds__(256) void k_positions(VolDev v, float* __restrict__
   }
 }
 
+// Triangles of every cube, in pool order: the cube's type lists its
+// triangles as cube edges, each edge is resolved to the vertex its owner
+// voxel holds (the owner block through the cube's neighbour table), and the
+// vertex to its row in this download.
 __global__ __launch_bounds__(256) void k_dl_write_triangles(VolDev v, int32_t* __restrict__ tris,
                                                             uint32_t tcap) {
   __shared__ uint32_t swave[16];
@@ -1498,12 +1396,20 @@ __global__ __launch_bounds__(256) void k_dl_write_triangles(VolDev v, int32_t* _
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = i0 + k;
     const uint32_t ntri = item_count(v, 1, i);
-    const uint32_t* ch = v.chunks + (size_t)i * kChunkWords;
+    if (ntri == 0) continue;
+    const uint32_t idx = i / kVox, l = i % kVox, type = v.tcur[i];
+    const uint8_t* edges = v.tri_table + type * 16 + 1;
     for (uint32_t t = 0; t < ntri; ++t, ++j) {
       if (j >= tcap) continue;
       for (int q = 0; q < 3; ++q) {
-        const uint32_t s = ch[3 * t + q];
-        tris[3 * (size_t)j + q] = s == kNone ? -1 : v.vdl[s];
+        int ox, oy, oz, axis;
+        edge_owner(edges[3 * t + q], ox, oy, oz, axis);
+        const int x = (int)(l & 7u) + ox, y = (int)((l >> 3) & 7u) + oy, z = (int)(l >> 6) + oz;
+        const int32_t nb = v.nbr[(size_t)idx * 27 + nbr_dir(x >> 3, y >> 3, z >> 3)];
+        int32_t s = -1;
+        if (nb >= 0)
+          s = v.evtx[((size_t)nb * 3 + axis) * kVox + (x & 7) + 8 * (y & 7) + 64 * (z & 7)];
+        tris[3 * (size_t)j + q] = s < 0 ? -1 : v.vdl[s];
       }
     }
   }
@@ -1823,9 +1729,6 @@ template __global__ void k_classify<8>(VolDev, uint32_t, int);
 template __global__ void k_vertices<2>(VolDev);
 template __global__ void k_vertices<4>(VolDev);
 template __global__ void k_vertices<8>(VolDev);
-template __global__ void k_triangles<2>(VolDev);
-template __global__ void k_triangles<4>(VolDev);
-template __global__ void k_triangles<8>(VolDev);
 template __global__ void k_fuse<2>(VolDev, FrameParams, const float*);
 template __global__ void k_fuse<4>(VolDev, FrameParams, const float*);
 template __global__ void k_fuse<8>(VolDev, FrameParams, const float*);

@@ -27,7 +27,7 @@ def test_header_declares_the_method_calls():
                      "vm_refine_mesh", "vm_gc", "vm_download_mesh", "vm_extract_backward",
                      "vm_integrate_backward", "vm_import_batch", "vm_export_positions",
                      "vm_extract_backward_slots", "vm_set_launch", "vm_download_normals",
-                     "vm_download_births", "vm_bind_tsdf", "vm_extract_mesh_split"]:
+                     "vm_download_births", "vm_bind_tsdf", "vm_create_volume_noalloc"]:
         assert required in names
 
 
@@ -104,11 +104,11 @@ def test_volume_bytes_grows_with_every_capacity():
     r, base = volume_bytes(cfg())
     assert r == binding.VM_OK and base > 0
     # per block: TSDF + weight + two types per voxel, vertex slot, t and
-    # count of its three edges, the 64-byte triangle record of every cube
-    # (the header's figure of about 51 KiB)
+    # count of its three edges, masks, lists and stamps; no triangle storage
+    # (the header's figure of about 18.9 KiB)
     r, more = volume_bytes(cfg(max_blocks=8192))
     per_block = (more - base) / 4096
-    assert r == 0 and 512 * (4 + 4 + 1 + 1 + 3 * (4 + 4 + 1) + 64) <= per_block < 52 * 1024
+    assert r == 0 and 512 * (4 + 4 + 1 + 1 + 3 * (4 + 4 + 1)) <= per_block < 19 * 1024
     r, more = volume_bytes(cfg(max_vertices=1 << 19))
     assert r == 0 and 16 * (1 << 18) <= more - base < 17 * (1 << 18)
     r, more = volume_bytes(cfg(hash_log2=17))
@@ -138,7 +138,6 @@ def test_null_arguments_are_rejected():
     assert L.vm_download_normals(None, None, 0, None) == -1
     assert L.vm_download_births(None, None, 0, None) == -1
     assert L.vm_bind_tsdf(None, None, None) == -1
-    assert L.vm_extract_mesh_split(None, 0, None, None) == -1
 
 
 def test_noalloc_volume_rejects_sizes_beyond_its_workspace():

@@ -138,17 +138,3 @@ def test_camera_at_the_block_range_edge(axis_sign):
     g.extract()
     o.extract()
     compare_all(g, o)
-
-
-def test_split_extraction_matches_oracle():
-    """The triangle pass on a second stream (vm_extract_mesh_split), joined
-    before the mesh is read, gives the oracle's mesh frame after frame."""
-    seq = scenes.room_sequence(seed=2, n_frames=100, voxel_m=S)
-    g, o = pair()
-    side = torch.cuda.Stream()
-    for k in range(0, 12, 3):
-        both(g, o, seq.frame(k), seq.poses[k], seq.min_depth, seq.max_depth)
-        g.extract(tri_stream=side)
-        torch.cuda.current_stream().wait_stream(side)
-        o.extract()
-        compare_all(g, o)
