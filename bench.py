@@ -8,7 +8,11 @@ over the timed steps, with every depth frame already resident in HBM.
 
 Prints one JSON line.  Beside the headline value it reports:
   - the roofline of the dominant kernel, timed with HIP events around that
-    kernel's launches inside the timed region;
+    kernel's launches inside the timed region, on the bytes the method must
+    move per unit of work (`algorithmic_bytes`), with the bytes the kernel
+    itself reads and writes beside them;
+  - the whole frame (fusion + extraction + garbage collection) against the
+    same peak, and blocks meshed per second;
   - the single-sphere extraction (512 blocks, blocks meshed per second);
   - the 4 mm sequence with holes and refinement (frames per second);
   - differentiable extraction of the 128^3 scene (forward + backward time);
@@ -43,7 +47,6 @@ MEASURED_TRAFFIC = {
     "fuse": {"fetch_kib": 10376.8, "write_kib": 11794.2, "source_sha1": "07b4fdca9c04"},
     "classify": {"fetch_kib": 12089.7, "write_kib": 3453.3, "source_sha1": "b6e9291df145"},
     "vertices": {"fetch_kib": 16642.0, "write_kib": 9037.7, "source_sha1": "b06e1d73e560"},
-    "triangles": {"fetch_kib": 4658.3, "write_kib": 3194.7, "source_sha1": "5cc60573fbfd"},
 }
 
 
@@ -83,18 +86,52 @@ def render_frames(seq, ks, workers):
         return list(ex.map(seq.frame, ks))
 
 
-def algorithmic_bytes(tot, npix):
-    """Bytes each kernel must move for the work in `tot` (running totals):
-    halo re-reads and hash-probe misses excluded; per-unit figures as
-    derived in the design notes."""
+def algorithmic_bytes(tot, npix, refine=False):
+    """Bytes the method must move for the work in `tot` (differences of the
+    device's running totals), per kernel and per step, after the survey's
+    per-unit figures: fusion 4*W*H per frame (the depth image, charged to
+    collection, which reads it first) + 8192 per collected block (TSDF and
+    weight read and written); extraction 4096 per dirty block (TSDF and
+    weight) + 1024 (t_{i-1} and t_i read and written), 20 per new or updated
+    vertex, 12 per new triangle and 8 per changed triangle (new or dropped:
+    its reference counts move); garbage collection 8 per freed vertex.
+    Halo re-reads, hash probes and list bookkeeping are excluded.  The
+    triangle terms belong to no kernel here: a cube's type is its triangle
+    record, so no kernel writes triangles; the step total keeps them, as
+    the method's figure.  With refine, every extraction was followed by one
+    refinement over the same dirty blocks, charged 3072 per block (TSDF read,
+    types read and written) to the refinement pass."""
+    dirty = tot["dirty_blocks"] // 2 if refine else tot["dirty_blocks"]
+    kernels = {
+        "collect": 4 * npix * tot["frames"],
+        "fuse": 8192 * tot["frame_blocks"],
+        "classify": 5120 * dirty,
+        "vertices": 20 * (tot["new_vertices"] + tot["updated_vertices"])
+        + 8 * tot["freed_vertices"],
+    }
+    if refine:
+        kernels["refine"] = 3072 * dirty
+    triangles = 12 * tot["new_triangles"] + 8 * (tot["new_triangles"] + tot["dropped_triangles"])
+    return kernels, sum(kernels.values()) + triangles
+
+
+def touched_bytes(tot, npix):
+    """Bytes each kernel reads and writes by design (its own inputs and
+    outputs, once each, halo re-reads excluded), the figure a kernel's
+    speed of light is judged by: the vertex pass, for one, reads the types
+    and TSDF of every block it recomputes, which the method's figure charges
+    to classification alone."""
     return {
         "collect": 4 * npix * tot["frames"],
         "fuse": 4 * npix * tot["frames"] + 8192 * tot["frame_blocks"],
         "classify": 5632 * tot["dirty_blocks"],
         "vertices": 4096 * tot["vertex_blocks"] + 5 * tot["updated_vertices"]
         + 13 * tot["new_vertices"] + 13 * tot["freed_vertices"],
-        "triangles": 96 * tot["changed_cubes"],
     }
+
+
+def frac(nbytes, ms):
+    return nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS
 
 
 def median_ms(fn, reps, warm=2):
@@ -149,13 +186,17 @@ def room_fusion(args, dev):
     vol.profile(False)
     prof = vol.profile_read()
     tot = {k: v - tot0[k] for k, v in vol.totals().items()}
-    algo = algorithmic_bytes(tot, npix)
+    algo, _ = algorithmic_bytes(tot, npix)
+    touched = touched_bytes(tot, npix)
     kernels = {}
     for k, (n, ms) in prof.items():
         e = {"launches": n, "ms_total": round(ms, 4), "us_per_launch": round(1000 * ms / n, 3)}
         if k in algo and ms > 0:
             e["bytes_per_launch"] = algo[k] // max(n, 1)
             e["GBps"] = round(algo[k] / (ms * 1e-3) / 1e9, 2)
+            e["frac"] = round(frac(algo[k], ms), 5)
+            e["touched_bytes_per_launch"] = touched[k] // max(n, 1)
+            e["touched_frac"] = round(frac(touched[k], ms), 5)
             e["hbm_bytes_per_launch"] = measured_traffic(k)
         kernels[k] = e
     dom = max((k for k in kernels if k in algo), key=lambda k: kernels[k]["ms_total"])
@@ -172,12 +213,19 @@ def room_fusion(args, dev):
     vol.profile(False)
     n_dom, ms_dom = vol.profile_read()[dom]
     tot = {k: v - tot0[k] for k, v in vol.totals().items()}
-    bytes_dom = algorithmic_bytes(tot, npix)[dom]
+    algo, step_total = algorithmic_bytes(tot, npix)
+    bytes_dom = algo[dom]
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                 "traffic": measured_traffic(dom), "bytes_per_launch": bytes_dom // max(n_dom, 1),
-                "us_per_launch": round(1000 * ms_dom / n_dom, 3)}
+                "us_per_launch": round(1000 * ms_dom / n_dom, 3),
+                "touched_bytes_per_launch": touched_bytes(tot, npix)[dom] // max(n_dom, 1),
+                "touched_frac": frac(touched_bytes(tot, npix)[dom], ms_dom)}
+    # the whole frame (fusion + extraction + GC) against the same peak
+    frame = {"bytes_per_frame": step_total // (args.frames * args.steps),
+             "us_per_frame": 1e6 * dt / (args.frames * args.steps),
+             "frac": frac(step_total, 1e3 * dt)}
     fps = args.frames * args.steps / dt
 
     # the same steps without any event
@@ -191,7 +239,8 @@ def room_fusion(args, dev):
     for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_total"]):
         log(f"  {k:10s} {e}")
     fields = {"value": fps, "ms_per_step": 1000.0 * dt / args.steps, "roofline": roofline,
-              "value_without_events": fps_noev, "blocks": st["blocks"],
+              "frame": frame, "value_without_events": fps_noev, "blocks": st["blocks"],
+              "blocks_meshed_per_s": tot["dirty_blocks"] / dt,
               "totals_per_step": {k: v // args.steps for k, v in tot.items()},
               "kernels": kernels}
     del vol
@@ -357,29 +406,29 @@ def room_fine(args, dev):
     tot = {k: v - tot0[k] for k, v in vol.totals().items()}
     st = vol.status()
     # one more pass with every kernel bracketed by events: per-kernel rates
-    # against algorithmic bytes (classification in refine mode counted with
-    # classification: both classify dirty blocks)
+    # against algorithmic bytes
     vol.profile(True)
     step()
     torch.cuda.synchronize()
     vol.profile(False)
     prof = vol.profile_read()
-    if "refine" in prof:
-        n, ms = prof.pop("refine")
-        n0, ms0 = prof.get("classify", (0, 0.0))
-        prof["classify"] = (n0 + n, ms0 + ms)
-    algo = algorithmic_bytes(tot, depth.shape[1] * depth.shape[2])
+    npix = depth.shape[1] * depth.shape[2]
+    algo, step_total = algorithmic_bytes(tot, npix, refine=True)
     kernels = {}
     for k, (n, ms) in prof.items():
         e = {"launches": n, "us_per_launch": round(1000 * ms / n, 3)}
         if k in algo and ms > 0:
             e["bytes_per_launch"] = algo[k] // max(n, 1)
             e["GBps"] = round(algo[k] / (ms * 1e-3) / 1e9, 2)
-            e["frac_of_hbm_peak"] = round(algo[k] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+            e["frac"] = round(frac(algo[k], ms), 5)
         kernels[k] = e
     out = {"frames_per_s": args.fine_frames / dt, "ms_per_frame": 1000 * dt / args.fine_frames,
            "frames": args.fine_frames, "blocks": st["blocks"],
-           "dirty_blocks_per_s": tot["dirty_blocks"] / dt, "refined_cubes": tot["refined_cubes"],
+           "blocks_meshed_per_s": tot["dirty_blocks"] // 2 / dt,
+           "refined_cubes": tot["refined_cubes"],
+           "frame": {"bytes_per_frame": step_total // args.fine_frames,
+                     "us_per_frame": 1e6 * dt / args.fine_frames,
+                     "frac": frac(step_total, 1e3 * dt)},
            "kernels": kernels}
     log(f"4 mm + refine: {out['frames_per_s']:.1f} frames/s, blocks {st['blocks']}")
     for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["us_per_launch"] * kv[1]["launches"]):
@@ -445,6 +494,18 @@ def batch_workload(dev):
     return coords, tsdf, weight, centers, radii
 
 
+def batch_step_bytes(tot):
+    """Bytes the batched forward + backward must move per step, after the
+    survey's per-unit figures: the extraction of every block (as for a
+    frame) and the backward, 12 per vertex (dL/dv) + 4096 per block (TSDF
+    and edge reads) + 2048 per block (dL/dTSDF written)."""
+    f_new, f_drop = tot["new_triangles"], tot["dropped_triangles"]
+    extract = (5120 * tot["dirty_blocks"] + 20 * (tot["new_vertices"] + tot["updated_vertices"])
+               + 12 * f_new + 8 * (f_new + f_drop) + 8 * tot["freed_vertices"])
+    backward = 12 * tot["new_vertices"] + 6144 * tot["frame_blocks"]
+    return extract + backward
+
+
 def batched(args, dev):
     import torch
 
@@ -458,7 +519,10 @@ def batched(args, dev):
     space = default_space() if args.tune_full else \
         [p for p in default_space() if p["block_groups_per_cu"] == 8]
     tune = autotune(b, space=space, reps=5, log=log)
+    tot0 = b.vol.totals()
     batch_ms = median_ms(b.replay, args.batch_reps)
+    tot = {k: (v - tot0[k]) // (args.batch_reps + 2) for k, v in b.vol.totals().items()}
+    step_bytes = batch_step_bytes(tot)
     default_launch = dict(wave_group_size=4, wave_groups_per_cu=16, block_groups_per_cu=8,
                           item_groups_per_cu=8, block_order=0)
     b.set_launch(**default_launch)
@@ -495,7 +559,9 @@ def batched(args, dev):
         "speedup_vs_plain_graph": plain_graph_ms / batch_ms,
         "identical_to_plain": identical,
         "tuned_launch": tune["launch"], "tune_points": tune.get("points"),
-        "tune_cached": tune.get("cached"),
+        "tune_cached": tune.get("cached"), "replays_timed": args.batch_reps,
+        "step": {"bytes_per_step": step_bytes, "frac": frac(step_bytes, batch_ms),
+                 "vertices": tot["new_vertices"]},
     }
     log(f"batched fwd+bwd {batch_ms:.3f} ms ({out['batched_blocks_per_s']:.3e} blocks/s), "
         f"plain {plain_ms:.3f} ms, plain graph {plain_graph_ms:.3f} ms, identical {identical}")
@@ -519,20 +585,47 @@ def batched_replays(args, dev):
     return {"batched_ms": ms, "blocks": n, "batched_blocks_per_s": n / ms * 1e3}
 
 
-def cpu_baseline(frames, seq, n=3):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(frames, seq, budget_s=20.0, single_budget_s=12.0):
+    """The oracle on the host cores over the headline sequence from its first
+    frame, integrate + extract + gc per frame, until a time budget is spent:
+    threads over blocks on every core the box gives (at most 16), then a
+    single thread.  The oracle's results do not depend on its thread
+    count."""
     import oracle
     import scenes
 
-    o = oracle.OracleVolume(seq.voxel_m)
-    c0 = time.perf_counter()
-    for k in range(n):
-        o.integrate(frames[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
-        o.extract()
-        o.gc()
-    cdt = time.perf_counter() - c0
-    return {"value": n / cdt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} frames of the same sequence, integrate+extract+gc, "
-                      "single thread"}
+    threads = min(16, os.cpu_count() or 1)
+    legs = {}
+    for name, thr, budget in (("threads", threads, budget_s), ("single", 1, single_budget_s)):
+        o = oracle.OracleVolume(seq.voxel_m, threads=thr, keep_fusion=False)
+        n = 0
+        c0 = time.perf_counter()
+        while n < len(frames) and time.perf_counter() - c0 < budget:
+            o.integrate(frames[n], scenes.K, seq.poses[n], seq.min_depth, seq.max_depth)
+            o.extract()
+            o.gc()
+            n += 1
+        cdt = time.perf_counter() - c0
+        legs[name] = {"frames": n, "seconds": round(cdt, 3), "frames_per_s": n / cdt,
+                      "threads": thr}
+        log(f"cpu oracle, {thr} threads: {n} frames in {cdt:.1f}s ({n / cdt:.3f} frames/s)")
+        del o
+    t = legs["threads"]
+    return {"value": t["frames_per_s"], "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {t['frames']} frames of the same 8 mm room sequence, integrate + "
+                      f"extract + gc per frame, {threads} threads (about {budget_s:.0f} s of "
+                      "work)",
+            "single_thread": legs["single"], "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def main():
@@ -542,7 +635,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--fine-frames", type=int, default=500)
-    ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--batch-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline workload only (for profiling runs)")
@@ -610,6 +703,11 @@ def main():
         "config": {"workload": f"room sequence, {args.frames} frames 640x480, 8 mm voxels, "
                                "8^3 blocks, 2^20 hash slots, integrate+extract+gc per frame"},
         "roofline": head["roofline"],
+        "frame": head["frame"],
+        "blocks_meshed_per_s": head["blocks_meshed_per_s"],
+        "batched": ({k: extras["batched_64_volumes"][k] for k in
+                     ("batched_blocks_per_s", "plain_blocks_per_s", "speedup_vs_plain", "step")}
+                    if "batched_64_volumes" in extras else None),
         "cpu_baseline": cpu,
         "value_without_events": head["value_without_events"],
         "blocks": head["blocks"],
