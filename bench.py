@@ -523,6 +523,8 @@ def batched(args, dev):
     batch_ms = median_ms(b.replay, args.batch_reps)
     tot = {k: (v - tot0[k]) // (args.batch_reps + 2) for k, v in b.vol.totals().items()}
     step_bytes = batch_step_bytes(tot)
+    # the library's own graphs (vm_extract_batch), the loss between them
+    lib_ms = median_ms(b.step, args.batch_reps)
     default_launch = dict(wave_group_size=4, wave_groups_per_cu=16, block_groups_per_cu=8,
                           item_groups_per_cu=8, block_order=0)
     b.set_launch(**default_launch)
@@ -552,6 +554,7 @@ def batched(args, dev):
     out = {
         "volumes": 64, "blocks": N, "sizes": sizes,
         "batched_blocks_per_s": N / (batch_ms / 1000), "batched_ms": batch_ms,
+        "library_graphs_ms": lib_ms,
         "batched_default_mapping_ms": default_ms,
         "plain_blocks_per_s": N / (plain_ms / 1000), "plain_ms": plain_ms,
         "plain_graph_ms": plain_graph_ms,
@@ -563,7 +566,8 @@ def batched(args, dev):
         "step": {"bytes_per_step": step_bytes, "frac": frac(step_bytes, batch_ms),
                  "vertices": tot["new_vertices"]},
     }
-    log(f"batched fwd+bwd {batch_ms:.3f} ms ({out['batched_blocks_per_s']:.3e} blocks/s), "
+    log(f"batched fwd+bwd {batch_ms:.3f} ms ({out['batched_blocks_per_s']:.3e} blocks/s; "
+        f"{lib_ms:.3f} ms with the library's graphs), "
         f"plain {plain_ms:.3f} ms, plain graph {plain_graph_ms:.3f} ms, identical {identical}")
     del b, p, g
     torch.cuda.empty_cache()

@@ -67,7 +67,7 @@ enum {
   VM_ERR_ARG = -1,             /* invalid argument or configuration */
   VM_ERR_HASH_FULL = -2,       /* hash table probe sequence exhausted */
   VM_ERR_BLOCK_POOL_FULL = -3, /* more blocks than max_blocks */
-  VM_ERR_VERTEX_POOL_FULL = -4,/* more live vertices than max_vertices */
+  VM_ERR_VERTEX_POOL_FULL = -4,/* a vertex pool segment is full (max_vertices) */
                                /* (-5 is not used: triangles take no pool) */
   VM_ERR_CAPACITY = -6,        /* caller output buffer or workspace too small */
   VM_ERR_HIP = -7,             /* a HIP runtime call failed */
@@ -88,7 +88,17 @@ typedef struct vm_config {
   float refine_eps_vox; /* refinement threshold epsilon, voxel units (Eq. 5) */
   int32_t hash_log2;    /* hash table holds 2^hash_log2 slots, 10..28 */
   int32_t max_blocks;   /* block pool capacity, 1 .. 2^21 */
-  int32_t max_vertices; /* vertex pool capacity, 1 .. 2^30 */
+  int32_t max_vertices; /* vertex pool capacity, 1 .. 2^30, split into
+                           n = clamp(max_blocks / 256, 1, 64) segments of
+                           ceil(max_vertices / n) slots (the last one the
+                           remainder): the block at pool
+                           row b creates its vertices in segment b mod n
+                           only (one allocation atomic per block and
+                           segment), so VM_ERR_VERTEX_POOL_FULL is raised
+                           when one segment's share is exhausted, which can
+                           come before max_vertices live vertices when the
+                           surface crowds the blocks of one segment
+                           (vm_status reports the fullest segment) */
   int32_t hash_mode;    /* 0: mixing hash; 1: every key starts probing at
                            slot 0 (long probe chains, for testing only) */
   int32_t batch_volumes;/* 0: a plain volume; m in 1..256: a batch of m
@@ -120,6 +130,9 @@ typedef struct vm_status {
   int64_t updated_vertices; /* vertices whose position was rewritten */
   int64_t freed_vertices;   /* vertices recycled by the last extract/refine */
   int64_t refined_cubes;    /* cubes re-typed by the last vm_refine_mesh */
+  int64_t vertex_segments;  /* segments of the vertex pool (see max_vertices) */
+  int64_t segment_capacity; /* vertex slots per segment */
+  int64_t max_segment_live; /* live vertices of the fullest segment */
 } vm_status;
 
 /* Running totals of work done since the volume was created (kept across
@@ -388,6 +401,47 @@ int vm_export_positions(vm_volume* vol, float* pos, int32_t* slot_of,
 int vm_extract_backward_slots(vm_volume* vol, const float* dL_dpos,
                               const int32_t* rows, int64_t n_rows,
                               float* dL_dtsdf, hipStream_t stream);
+
+/* Arguments of vm_extract_batch: the blocks of every slot and the
+ * forward's and backward's arrays (all device memory, owned by the caller,
+ * kept alive and at the same addresses while their graphs are reused). */
+typedef struct vm_batch_io {
+  const int32_t* slots;  /* n: slot of each block (NULL for a plain volume) */
+  const int32_t* coords; /* n*3: block coordinates in the slot's frame */
+  const float* tsdf;     /* n*512: TSDF rows (the bound array when bound) */
+  const float* weight;   /* n*512: weight rows (likewise) */
+  int64_t n;             /* blocks, 1 .. max_blocks */
+  int32_t* rows;         /* n, out: pool row of each block */
+  float* pos;            /* pos_cap*3, out: position per vertex pool entry */
+  int32_t* slot_of;      /* pos_cap, out (may be NULL): slot per entry, -1 none */
+  int64_t pos_cap;       /* at least max_vertices */
+  const float* dL_dpos;  /* pos_cap*3, in: gradient per vertex pool entry */
+  float* dL_dtsdf;       /* n*512, out: gradient per block, input row order */
+} vm_batch_io;
+
+enum { VM_BATCH_FORWARD = 1, VM_BATCH_BACKWARD = 2 };
+
+/* The batched forward and backward of many independent volumes (the slots
+ * of a batch volume, or one plain volume), each phase one HIP graph that
+ * the library captures on the first call and replays on later calls with
+ * the same arguments, mapping and bound storage (anything else captures
+ * again).  VM_BATCH_FORWARD: empty the volume, import the n blocks
+ * (vm_import_batch, rows out), extract the mesh of every block
+ * (vm_extract_mesh with VM_SCOPE_ALL) and write every vertex pool entry's
+ * position (vm_export_positions).  VM_BATCH_BACKWARD: the TSDF gradient
+ * from io->dL_dpos (vm_extract_backward_slots over io->rows), for the mesh
+ * of the last forward; the caller computes dL_dpos from the forward's pos
+ * in between.  One phase per call: a forward assigns pool entries in no
+ * fixed order, so a dL_dpos exists only after it.  On a stream that is
+ * being captured, on the
+ * legacy default stream (which cannot be captured) and while profiling,
+ * the phases are enqueued as plain launches instead.  After a replay the
+ * volume's host-side state is what the captured forward left, so status,
+ * download and export calls see the replayed mesh.  VM_ERR_ARG for invalid
+ * arguments, a phase other than the two, or a volume that rejects the
+ * import (see vm_import_batch);
+ * VM_ERR_CAPACITY when pos_cap < max_vertices.  Stream-ordered. */
+int vm_extract_batch(vm_volume* vol, const vm_batch_io* io, int phase, hipStream_t stream);
 
 /* Workgroup mapping of the volume's kernels; results do not depend on it
  * (bit for bit), only speed does.  Defaults: {4, 16, 8, 8, 0} (the fastest

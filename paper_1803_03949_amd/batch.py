@@ -2,9 +2,12 @@
 
 All volumes live in one batched library volume (one slot each), so every
 kernel of the sequence -- reset, import, classification, vertices,
-triangles, positions, backward -- runs once over the blocks of all of them,
-on a grid sized to the device rather than to one volume.  The sequence is
-captured once in a HIP graph (torch.cuda.CUDAGraph) and replayed.
+positions, backward -- runs once over the blocks of all of them, on a grid
+sized to the device rather than to one volume.  The forward and the
+backward are the library's vm_extract_batch phases, each a HIP graph the
+library captures once and replays; the whole step, the caller's loss
+included, can also be captured into one torch graph (the library then
+launches its kernels into that capture).
 
 The loss is the caller's: a function from (positions, slot of each vertex
 pool entry) to dL/dpositions made of elementwise torch operations, so that
@@ -25,7 +28,7 @@ import zlib
 import numpy as np
 import torch
 
-from .binding import SLOT_SPAN, Volume
+from .binding import SLOT_SPAN, VM_BATCH_BACKWARD, VM_BATCH_FORWARD, Volume
 
 
 def sphere_loss_grad(centers: torch.Tensor, radii: torch.Tensor):
@@ -62,11 +65,21 @@ def sphere_loss(pos: torch.Tensor, slot: torch.Tensor, centers, radii) -> float:
 
 
 def vertex_capacity(n_blocks: int) -> int:
-    """Vertex pool size for a volume of n_blocks blocks holding a
+    """A generous vertex pool size for a volume of n_blocks blocks holding a
     sphere-like surface: 64 per block plus 8192 (the 64 workload volumes
     hold 15 vertices per block on average, at most 102 per block in volumes
     of a few blocks, which the constant covers)."""
     return 64 * n_blocks + 8192
+
+
+def fitted_capacity(status: dict, margin: float = 1.25) -> int:
+    """Vertex pool size from a volume's status after a forward: every
+    segment gets `margin` times the fullest one's live vertices plus 64, so
+    the positions export and the caller's loss walk about `margin` times
+    the live vertices rather than the generous bound.  A later forward
+    whose surface outgrows it raises VM_ERR_VERTEX_POOL_FULL (refit then)."""
+    per = int(math.ceil(margin * status["max_segment_live"])) + 64
+    return status["vertex_segments"] * per
 
 
 class BatchMesher:
@@ -84,13 +97,22 @@ class BatchMesher:
     input order, `pos`/`slot` the vertex positions per pool entry."""
 
     def __init__(self, voxel_m: float, coords: list, tsdf: torch.Tensor, weight: torch.Tensor,
-                 loss_grad, trunc_vox: float = 4.0, zero_copy: bool = True):
+                 loss_grad, trunc_vox: float = 4.0, zero_copy: bool = True,
+                 max_vertices: int | None = None):
+        """max_vertices: the vertex pool size; None fits it to the workload
+        with one probing forward at the generous bound (`fitted_capacity`)."""
         self.n_vol = len(coords)
         sizes = [int(len(c)) for c in coords]
         self.sizes = sizes
         N = sum(sizes)
         self.n_blocks = N
-        V = vertex_capacity(N)
+        if max_vertices is None:
+            probe = BatchMesher(voxel_m, coords, tsdf, weight, loss_grad, trunc_vox, zero_copy,
+                                max_vertices=vertex_capacity(N))
+            probe.forward()
+            max_vertices = fitted_capacity(probe.vol.status())
+            del probe
+        V = max_vertices
         hash_log2 = max(12, int(math.ceil(math.log2(max(2 * N, 2)))))
         self.vol = Volume(voxel_m, trunc_vox=trunc_vox, hash_log2=hash_log2, max_blocks=N,
                           max_vertices=V, batch_volumes=self.n_vol)
@@ -111,17 +133,39 @@ class BatchMesher:
         self.grad = torch.empty((N, 512), dtype=torch.float32, device=dev)
         self.loss_grad = loss_grad
         self.graph = None
+        self.io = self.vol.batch_io(self.slots, self.coords, tsdf, weight, self.rows, self.pos,
+                                    self.slot, self.dpos, self.grad)
+        # the library captures its graphs on a stream of its own caller's
+        # (the legacy default stream cannot be captured); default priority
+        self.stream = torch.cuda.Stream(device=dev)
 
     def run(self, stream=None):
-        """The whole step, enqueued on the current stream."""
+        """The whole step on `stream` (default: the current one): the
+        library's forward, the caller's loss gradient, the library's
+        backward.  On the legacy default stream, or under a capture, the
+        library's phases are plain launches; elsewhere they are its graphs."""
         v = self.vol
         cur = torch.cuda.current_stream(v.device) if stream is None else stream
-        v.reset(cur)
-        v.import_batch(self.slots, self.coords, self.tsdf, self.weight, self.rows, cur)
-        v.extract(scope_all=True, stream=cur)
-        v.positions(self.pos, self.slot, cur)
-        self.loss_grad(self.pos, self.slot, self.dpos)
-        v.extract_backward_slots(self.dpos, self.rows, self.grad, cur)
+        v.extract_batch(self.io, VM_BATCH_FORWARD, cur)
+        with torch.cuda.stream(cur):
+            self.loss_grad(self.pos, self.slot, self.dpos)
+        v.extract_batch(self.io, VM_BATCH_BACKWARD, cur)
+
+    def forward(self):
+        """The library's forward alone, on the mesher's stream, joined."""
+        cur = torch.cuda.current_stream(self.vol.device)
+        self.stream.wait_stream(cur)
+        self.vol.extract_batch(self.io, VM_BATCH_FORWARD, self.stream)
+        cur.wait_stream(self.stream)
+
+    def step(self):
+        """`run` on the mesher's own stream, joined to the current stream on
+        both sides: the library replays its own forward and backward graphs,
+        the loss gradient runs between them."""
+        cur = torch.cuda.current_stream(self.vol.device)
+        self.stream.wait_stream(cur)
+        self.run(self.stream)
+        cur.wait_stream(self.stream)
 
     def capture(self):
         """Capture `run` in a HIP graph (after one eager warm-up run)."""
@@ -152,12 +196,21 @@ class PlainMesher:
 
     def __init__(self, voxel_m: float, coords: list, tsdf: torch.Tensor, weight: torch.Tensor,
                  loss_grads: list, trunc_vox: float = 4.0, zero_copy: bool = True):
+        """Each volume's vertex pool fitted as the batch's is (one probing
+        forward per volume at the generous bound)."""
         self.vols, self.items = [], []
         off = 0
         for i, c in enumerate(coords):
             n = int(len(c))
-            V = vertex_capacity(n)
             hash_log2 = max(12, int(math.ceil(math.log2(max(2 * n, 2)))))
+            probe = Volume(voxel_m, trunc_vox=trunc_vox, hash_log2=hash_log2, max_blocks=n,
+                           max_vertices=vertex_capacity(n))
+            cdev = torch.from_numpy(np.asarray(c, np.int32).reshape(-1, 3)).to(probe.device)
+            probe.import_blocks(cdev, tsdf[off:off + n].contiguous(),
+                                weight[off:off + n].contiguous())
+            probe.extract(scope_all=True)
+            V = fitted_capacity(probe.status())
+            del probe
             vol = Volume(voxel_m, trunc_vox=trunc_vox, hash_log2=hash_log2, max_blocks=n,
                          max_vertices=V)
             dev = vol.device

@@ -52,6 +52,17 @@ SLOT_SPAN = 64  # stored block x of slot k, local x: 64k - 8192 + x
 NOALLOC_MAX_BYTES = 64 << 20  # VM_NOALLOC_MAX_BYTES
 
 
+class vm_batch_io(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_void_p), ("coords", ctypes.c_void_p),
+                ("tsdf", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("rows", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("slot_of", ctypes.c_void_p),
+                ("pos_cap", ctypes.c_int64), ("dL_dpos", ctypes.c_void_p),
+                ("dL_dtsdf", ctypes.c_void_p)]
+
+
+VM_BATCH_FORWARD, VM_BATCH_BACKWARD = 1, 2
+
+
 class vm_intrinsics(ctypes.Structure):
     _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
                 ("cy", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
@@ -61,7 +72,7 @@ class vm_intrinsics(ctypes.Structure):
 _STATUS_FIELDS = ["blocks", "frame_blocks", "pending_blocks", "dirty_blocks", "vertex_blocks",
                   "changed_cubes", "vertex_slots", "free_vertex_slots", "triangles",
                   "tri_cubes", "new_vertices", "updated_vertices", "freed_vertices",
-                  "refined_cubes"]
+                  "refined_cubes", "vertex_segments", "segment_capacity", "max_segment_live"]
 
 
 TOTALS = ["frames", "frame_blocks", "dirty_blocks", "vertex_blocks", "new_vertices",
@@ -118,6 +129,7 @@ def lib() -> ctypes.CDLL:
             "vm_import_batch": [P, P, P, P, P, I64, P, P],
             "vm_export_positions": [P, P, P, I64, P],
             "vm_extract_backward_slots": [P, P, P, I64, P, P],
+            "vm_extract_batch": [P, ctypes.POINTER(vm_batch_io), ctypes.c_int, P],
             "vm_set_launch": [P, ctypes.POINTER(vm_launch)],
             "vm_get_launch": [P, ctypes.POINTER(vm_launch)],
             "vm_profile": [P, ctypes.c_int],
@@ -422,6 +434,30 @@ class Volume:
         _check(lib().vm_extract_backward_slots(self.h, _ptr(dL_dpos), _ptr(rows), n, _ptr(out),
                                                _stream(stream)), "vm_extract_backward_slots")
         return out[:n]
+
+    def batch_io(self, slots, coords, tsdf, weight, rows, pos, slot_of, dL_dpos, dL_dtsdf):
+        """vm_batch_io over device tensors (which the caller keeps alive and in
+        place while graphs captured with it are replayed)."""
+        n = coords.shape[0]
+        for t, dt in ((coords, torch.int32), (tsdf, torch.float32), (weight, torch.float32),
+                      (rows, torch.int32), (pos, torch.float32), (dL_dpos, torch.float32),
+                      (dL_dtsdf, torch.float32)):
+            assert t.is_cuda and t.dtype == dt and t.is_contiguous()
+        assert tsdf.numel() >= 512 * n and weight.numel() >= 512 * n and rows.numel() == n
+        assert dL_dtsdf.numel() >= 512 * n and dL_dpos.shape[0] >= pos.shape[0]
+        if slots is not None:
+            assert slots.is_cuda and slots.dtype == torch.int32 and slots.numel() == n
+        if slot_of is not None:
+            assert slot_of.is_cuda and slot_of.dtype == torch.int32 and slot_of.numel() >= pos.shape[0]
+        return vm_batch_io(_ptr(slots), _ptr(coords), _ptr(tsdf), _ptr(weight), n, _ptr(rows),
+                           _ptr(pos), _ptr(slot_of), pos.shape[0], _ptr(dL_dpos), _ptr(dL_dtsdf))
+
+    def extract_batch(self, io: vm_batch_io, phase: int, stream=None):
+        """vm_extract_batch: VM_BATCH_FORWARD or VM_BATCH_BACKWARD, each a
+        graph the library captures once and replays (plain launches on a
+        stream under capture or on the legacy default stream)."""
+        _check(lib().vm_extract_batch(self.h, ctypes.byref(io), int(phase), _stream(stream)),
+               "vm_extract_batch")
 
     def set_launch(self, **kw):
         cur = self.get_launch()

@@ -23,6 +23,16 @@ struct vm_volume {
     int kid;
     hipEvent_t a, b;
   };
+  // A captured phase of vm_extract_batch with what it was captured for,
+  // and the host-side state the captured forward left.
+  struct BatchGraph {
+    hipGraphExec_t exec = nullptr;
+    vm_batch_io io;
+    vm_launch launch;
+    const float* d;
+    const float* w;
+    uint32_t frame, epoch, pass, xcount, vcount, xsel, vsel, dev_frame;
+  };
   vm_config cfg;
   char* mem;
   size_t bytes;
@@ -46,6 +56,7 @@ struct vm_volume {
   std::vector<hipEvent_t> ev_free;
   std::vector<ProfRec> recs;
   int scratch_dev = -1;  // device whose static workspace holds the volume, -1 if the caller's
+  BatchGraph bgraph[2];  // vm_extract_batch: forward, backward
 };
 
 namespace {
@@ -262,6 +273,75 @@ int read_snapshot(vm_volume* vol, Snapshot* s, hipStream_t stream) {
   return hip_status(e);
 }
 
+// One phase of vm_extract_batch as plain launches (0 forward, 1 backward).
+int batch_enqueue(vm_volume* vol, const vm_batch_io& io, int ph, hipStream_t s) {
+  if (ph == 1)
+    return vm_extract_backward_slots(vol, io.dL_dpos, io.rows, io.n, io.dL_dtsdf, s);
+  int r = vm_reset_volume(vol, s);
+  if (r == VM_OK)
+    r = vm_import_batch(vol, io.slots, io.coords, io.tsdf, io.weight, io.n, io.rows, s);
+  if (r == VM_OK) r = vm_extract_mesh(vol, VM_SCOPE_ALL, s);
+  if (r == VM_OK) r = vm_export_positions(vol, io.pos, io.slot_of, io.pos_cap, s);
+  return r;
+}
+
+// Host-side state of a volume that its calls advance.
+void save_host_state(const vm_volume* vol, vm_volume::BatchGraph& g) {
+  g.frame = vol->frame, g.epoch = vol->epoch, g.pass = vol->pass;
+  g.xcount = vol->xcount, g.vcount = vol->vcount;
+  g.xsel = vol->dev.xsel, g.vsel = vol->dev.vsel, g.dev_frame = vol->dev.frame;
+}
+
+void load_host_state(vm_volume* vol, const vm_volume::BatchGraph& g) {
+  vol->frame = g.frame, vol->epoch = g.epoch, vol->pass = g.pass;
+  vol->xcount = g.xcount, vol->vcount = g.vcount;
+  vol->dev.xsel = g.xsel, vol->dev.vsel = g.vsel, vol->dev.frame = g.dev_frame;
+  vol->have_fp = false;
+  vol->dl_nv = -1;
+}
+
+// One phase of vm_extract_batch: replay its graph, capturing it first when
+// there is none for these arguments; plain launches where a graph cannot
+// be captured (a stream under capture already, the legacy default stream)
+// or would hold profiling events.
+int batch_phase(vm_volume* vol, const vm_batch_io& io, int ph, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s != nullptr && hipStreamIsCapturing(s, &cs) != hipSuccess) return VM_ERR_HIP;
+  if (s == nullptr || cs != hipStreamCaptureStatusNone || vol->prof != 0)
+    return batch_enqueue(vol, io, ph, s);
+  vm_volume::BatchGraph& g = vol->bgraph[ph];
+  const bool same = g.exec && memcmp(&g.io, &io, sizeof(io)) == 0 &&
+                    memcmp(&g.launch, &vol->launch, sizeof(vm_launch)) == 0 &&
+                    g.d == vol->dev.d && g.w == vol->dev.w;
+  if (!same) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return VM_ERR_HIP;
+    const int r = batch_enqueue(vol, io, ph, s);
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (r != VM_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r != VM_OK ? r : VM_ERR_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiateWithFlags(&g.exec, graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g.exec = nullptr;
+      return VM_ERR_HIP;
+    }
+    g.io = io;
+    g.launch = vol->launch;
+    g.d = vol->dev.d;
+    g.w = vol->dev.w;
+    save_host_state(vol, g);
+  }
+  const hipError_t e = hipGraphLaunch(g.exec, s);
+  if (e != hipSuccess) return VM_ERR_HIP;
+  if (ph == 0) load_host_state(vol, g);
+  return VM_OK;
+}
+
 // Set up a volume handle over the workspace mem (bytes long, already
 // checked against the configuration) and clear the workspace on `stream`.
 int init_volume(vm_volume* vol, const vm_config* cfg, char* mem, size_t bytes,
@@ -365,6 +445,8 @@ int vm_create_volume_noalloc(const vm_config* cfg, hipStream_t stream, vm_volume
 
 int vm_destroy_volume(vm_volume* vol) {
   if (!vol) return VM_ERR_ARG;
+  for (auto& g : vol->bgraph)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   for (auto& r : vol->recs) vol->ev_free.push_back(r.a), vol->ev_free.push_back(r.b);
   for (hipEvent_t e : vol->ev_free) (void)hipEventDestroy(e);
   const int sdev = vol->scratch_dev;
@@ -639,12 +721,14 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   const Counters& c = sn.c;
   const uint32_t B = vol->dev.max_blocks;
   uint32_t st_new = 0, st_upd = 0, st_freed = 0, st_chg = 0, st_ref = 0;
-  int64_t vh = 0, vf = 0, tris = 0, tcubes = 0;
+  int64_t vh = 0, vf = 0, tris = 0, tcubes = 0, seg_live = 0;
   for (int k = 0; k < kSegs; ++k) {
     st_new += sn.vseg[k].st_new, st_upd += sn.vseg[k].st_upd, st_freed += sn.vseg[k].st_freed;
     st_chg += sn.cseg[k].st_chg, st_ref += sn.cseg[k].st_ref;
     vh += sn.vseg[k].hwm, vf += sn.vseg[k].count;
     tris += sn.cseg[k].st_tri, tcubes += sn.cseg[k].st_tcube;
+    const int64_t live = (int64_t)sn.vseg[k].hwm - (int64_t)sn.vseg[k].count;
+    seg_live = live > seg_live ? live : seg_live;
   }
   memset(out, 0, sizeof(*out));
   out->error = error_code(c.error);
@@ -664,6 +748,9 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   out->updated_vertices = st_upd - c.base_upd;
   out->freed_vertices = st_freed - c.base_freed;
   out->refined_cubes = st_ref - c.base_ref;
+  out->vertex_segments = vol->dev.nseg;
+  out->segment_capacity = vol->dev.vseg_cap;
+  out->max_segment_live = seg_live;
   return out->error;
 }
 
@@ -772,6 +859,17 @@ int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream) {
   }
   for (int i = 0; i < n; ++i) out[i] = (int64_t)t[i];
   return VM_OK;
+}
+
+int vm_extract_batch(vm_volume* vol, const vm_batch_io* io, int phase, hipStream_t stream) {
+  if (!vol || !io || (phase != VM_BATCH_FORWARD && phase != VM_BATCH_BACKWARD) || io->n < 1 ||
+      io->n > (int64_t)vol->dev.max_blocks || !io->coords || !io->tsdf || !io->weight ||
+      !io->rows || (vol->dev.batch != 0) != (io->slots != nullptr))
+    return VM_ERR_ARG;
+  if (phase == VM_BATCH_FORWARD && !io->pos) return VM_ERR_ARG;
+  if (phase == VM_BATCH_BACKWARD && (!io->dL_dpos || !io->dL_dtsdf)) return VM_ERR_ARG;
+  if (io->pos_cap < (int64_t)vol->dev.max_vertices) return VM_ERR_CAPACITY;
+  return batch_phase(vol, *io, phase == VM_BATCH_FORWARD ? 0 : 1, stream);
 }
 
 int vm_profile_mask(vm_volume* vol, uint32_t mask) {

@@ -27,7 +27,8 @@ def test_header_declares_the_method_calls():
                      "vm_refine_mesh", "vm_gc", "vm_download_mesh", "vm_extract_backward",
                      "vm_integrate_backward", "vm_import_batch", "vm_export_positions",
                      "vm_extract_backward_slots", "vm_set_launch", "vm_download_normals",
-                     "vm_download_births", "vm_bind_tsdf", "vm_create_volume_noalloc"]:
+                     "vm_download_births", "vm_bind_tsdf", "vm_create_volume_noalloc",
+                     "vm_extract_batch"]:
         assert required in names
 
 
@@ -57,6 +58,8 @@ int main() {
   F(vm_intrinsics, max_depth_m)
   printf("vm_launch %zu\n", sizeof(vm_launch));
   F(vm_launch, block_order)
+  printf("vm_batch_io %zu\n", sizeof(vm_batch_io));
+  F(vm_batch_io, n) F(vm_batch_io, pos_cap) F(vm_batch_io, dL_dtsdf)
   return 0;
 }
 """
@@ -83,6 +86,10 @@ def test_struct_layouts_match_the_binding(tmp_path):
         "vm_intrinsics.max_depth_m": binding.vm_intrinsics.max_depth_m.offset,
         "vm_launch": ctypes.sizeof(binding.vm_launch),
         "vm_launch.block_order": binding.vm_launch.block_order.offset,
+        "vm_batch_io": ctypes.sizeof(binding.vm_batch_io),
+        "vm_batch_io.n": binding.vm_batch_io.n.offset,
+        "vm_batch_io.pos_cap": binding.vm_batch_io.pos_cap.offset,
+        "vm_batch_io.dL_dtsdf": binding.vm_batch_io.dL_dtsdf.offset,
     }
     assert {k: int(v) for k, v in got.items()} == want
 
@@ -138,6 +145,7 @@ def test_null_arguments_are_rejected():
     assert L.vm_download_normals(None, None, 0, None) == -1
     assert L.vm_download_births(None, None, 0, None) == -1
     assert L.vm_bind_tsdf(None, None, None) == -1
+    assert L.vm_extract_batch(None, None, 1, None) == -1
 
 
 def test_noalloc_volume_rejects_sizes_beyond_its_workspace():

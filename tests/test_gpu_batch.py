@@ -15,6 +15,7 @@ import torch
 import oracle
 import scenes
 from paper_1803_03949_amd import Volume, VmError
+from paper_1803_03949_amd.binding import VM_BATCH_BACKWARD, VM_BATCH_FORWARD
 from paper_1803_03949_amd.batch import (BatchMesher, PlainMesher, canonical_vertices,
                                         sphere_loss_grad)
 from tests.gpu_compare import batch_vertices, compare_slot_vertices
@@ -160,3 +161,49 @@ def test_batch_range_errors():
     b.reset()
     with pytest.raises(VmError, match="VM_ERR_ARG"):
         b.import_blocks(torch.zeros((1, 3), dtype=torch.int32, device="cuda"), z, z)
+
+
+def test_extract_batch_entry_replays_its_graphs():
+    """vm_extract_batch through the C ABI on a stream of the mesher's own, so
+    that the library captures its forward and backward graphs on the first
+    step and replays them after: every step gives the per-volume path's
+    gradient bit for bit and the oracle's vertices, with other work between
+    steps, and status and download read the replayed mesh."""
+    vols, coords, tsdf, weight, centers, radii = workload(n=5, seed=12)
+    print(f"[batch-entry] sizes {[len(c) for c in coords]}", flush=True)
+    b = BatchMesher(S, coords, tsdf, weight, sphere_loss_grad(centers, radii))
+    p = plain_for(coords, tsdf, weight, centers, radii)
+    p.run()
+    torch.cuda.synchronize()
+    want = p.grad().clone()
+    for rep in range(3):
+        b.grad.fill_(float("nan"))
+        b.step()
+        torch.cuda.synchronize()
+        assert torch.equal(b.grad, want), rep
+        p.run()
+        torch.cuda.synchronize()
+    st = b.vol.status()
+    assert st["error"] == 0 and st["blocks"] == b.n_blocks and st["dirty_blocks"] == b.n_blocks
+    bv = batch_vertices(b.vol)
+    for k, v in enumerate(vols):
+        c, d, w = v.blocks()
+        o = oracle.OracleVolume(S)
+        o.import_blocks(c, d, w)
+        o.extract(scope_all=True)
+        compare_slot_vertices(bv, k, o)
+    verts, tris, _ = b.vol.download()
+    assert len(verts) == int((b.slot >= 0).sum()) and len(tris) == st["triangles"]
+
+
+def test_extract_batch_rejects_bad_phases():
+    """One phase per call: both bits, none or another value are refused
+    before anything is enqueued."""
+    vols, coords, tsdf, weight, centers, radii = workload(n=2, seed=13)
+    b = BatchMesher(S, coords, tsdf, weight, sphere_loss_grad(centers, radii))
+    for phase in (0, VM_BATCH_FORWARD | VM_BATCH_BACKWARD, 4):
+        with pytest.raises(VmError, match="VM_ERR_ARG"):
+            b.vol.extract_batch(b.io, phase, b.stream)
+    b.step()
+    torch.cuda.synchronize()
+    assert b.vol.status()["error"] == 0
