@@ -874,20 +874,21 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
 // block, and the recycled slots it takes are fetched in one batch.  The
 // edges with work (a count to write, or a vertex to free) are gathered into
 // a list in LDS while the counts are formed, with a bit telling whether the
-// edge has a vertex; the write pass runs over that list, 64 edges per step,
-// instead of over all 1536 edges.  Only a vertex being freed needs its slot,
-// which it reads again; the block's slots never occupy LDS, which keeps the
-// wave's LDS small enough for seven waves per SIMD (with four waves per
-// workgroup; scalar registers then limit it).
+// edge has a vertex; the write pass runs over that list, 64 edges per step
+// (lanes of a step hold neighbouring edges, so its stores are coalesced),
+// in chunks of kWorkCap edges.  Each chunk first requests everything it
+// reads, the freed vertices' slots and the end point TSDF values of the
+// others, and only then stores: on this hardware a load issued after stores
+// waits for them too.  A block with no vertex and no cube with triangles
+// around its edges (one in free space) stops after the type staging.
 constexpr int kRingBatch = 256;  // recycled slots fetched per block at once
-constexpr int kWorkCap = 256;    // listed edges per block; more take the row-by-row pass
+constexpr int kWorkCap = 512;    // listed edges per chunk of the write pass
 
 template <int W>
-__global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) void k_vertices(VolDev v) {
   __shared__ uint8_t suses[256 * 12];
   __shared__ uint32_t st_all[W][kRingBatch];  // cube types at local -1..7, then slots
-  __shared__ uint32_t swork_all[W][kWorkCap]; // edge a * 512 + l | count << 11
-  __shared__ float sd_all[W][729];            // TSDF at local 0..8
+  __shared__ uint32_t swork_all[W][kWorkCap]; // edge a * 512 + l | count << 11 | vertex << 19
   __shared__ int32_t snb_all[W][27];
   static_assert(kRingBatch * 4 >= 732, "type staging fits the slot batch");
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -900,7 +901,6 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
   uint8_t* st = reinterpret_cast<uint8_t*>(st_all[wave]);
   uint32_t* sring = st_all[wave];
   uint32_t* swork = swork_all[wave];
-  float* sd = sd_all[wave];
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_vblocks[v.vsel], v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
@@ -912,18 +912,17 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     const uint32_t idx = uniform(v.vblocks[it.i]);
     const uint32_t sg = uniform(idx % v.nseg);
     // the block's edge arrays, addressed by block-local edge a * 512 + l;
-    // pool and halo arrays by 32-bit byte offsets from their bases (every
-    // index here is below 2^30 entries of 4 bytes)
+    // pool arrays by 32-bit byte offsets from their bases (every index here
+    // is below 2^30 entries of 4 bytes)
     const size_t eb = (size_t)idx * (3 * kVox);
     int32_t* evtx_b = v.evtx + eb;
     float* et_b = v.et + eb;
     uint8_t* eref_b = v.eref + eb;
     const uint8_t* tcur_bytes = v.tcur;
-    const char* d_bytes = reinterpret_cast<const char*>(v.d);
     auto pool32 = [](uint32_t* base, uint32_t s) -> uint32_t& {
       return *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + s * 4u);
     };
-    // requested at once: the neighbour table, the block's edge slots and
+    // requested at once: the neighbour table, the block's edge counts and
     // its pool segment (fixed during this kernel)
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
     const Seg& g = v.vseg[sg];
@@ -944,53 +943,17 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
     }
     if (q < 27) snb[q] = mynb;
     wave_sync();
-    // The TSDF (own block and +x/+y/+z halo) serves only edges with work: it
-    // is requested with the types when the block already carries a vertex,
-    // else only once the counts show work (a block that neither has nor
-    // needs a vertex reads none of it).
-    const bool d_early = __ballot(has_slot != 0u) != 0ull;
-    auto d_halo = [&](int r) -> float {
-      const int h = q + 64 * r;
-      if (h >= 217) return 0.f;
-      int x, y, z;
-      halo_cell(h, 8, x, y, z);
-      const int nb2 = snb[nbr_dir(x >> 3, y >> 3, z >> 3)];
-      if (nb2 < 0) return 0.f;
-      return *reinterpret_cast<const float*>(
-          d_bytes + ((uint32_t)nb2 * 2048u + (uint32_t)((x & 7) + 8 * (y & 7) + 64 * (z & 7)) * 4u));
-    };
-    auto d_store = [&](const float* dv, const float* dh) {
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz) sd[lx + 9 * ly + 81 * lz] = dv[lz];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int h = q + 64 * r;
-        if (h < 217) {
-          int x, y, z;
-          halo_cell(h, 8, x, y, z);
-          sd[x + 9 * y + 81 * z] = dh[r];
-        }
-      }
-    };
+    // cube types into LDS: the block's own (local 0..7) and the -x/-y/-z
+    // neighbours' halo (local -1, 217 cells)
+    uint32_t surf = 0;  // a staged cube with triangles
     {
-      // own block into LDS: cube types at local 0..7, TSDF at local 0..7
-      uint32_t tv[8];
-      float dv[8], dh[4];
+      uint32_t tv[8], th[4];
 #pragma unroll
-      for (int lz = 0; lz < 8; ++lz) {
-        tv[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
-        dv[lz] = d_early ? v.d[(size_t)idx * kVox + q + 64 * lz] : 0.f;
-      }
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz) st[(lx + 1) + 9 * (ly + 1) + 81 * (lz + 1)] = (uint8_t)tv[lz];
-      // halos: cube types of the -x/-y/-z neighbours (local -1) and TSDF of
-      // the +x/+y/+z neighbours (local 8), 217 cells each
-      uint32_t th[4];
+      for (int lz = 0; lz < 8; ++lz) tv[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int h = q + 64 * r;
         th[r] = 0;
-        dh[r] = d_early ? d_halo(r) : 0.f;
         if (h < 217) {
           int x, y, z;
           halo_cell(h, -1, x, y, z);
@@ -1000,15 +963,27 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
         }
       }
 #pragma unroll
+      for (int lz = 0; lz < 8; ++lz) {
+        st[(lx + 1) + 9 * (ly + 1) + 81 * (lz + 1)] = (uint8_t)tv[lz];
+        surf |= (uint32_t)(tv[lz] != 0u && tv[lz] != 255u);
+      }
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int h = q + 64 * r;
         if (h < 217) {
           int x, y, z;
           halo_cell(h, -1, x, y, z);
           st[(x + 1) + 9 * (y + 1) + 81 * (z + 1)] = (uint8_t)th[r];
+          surf |= (uint32_t)(th[r] != 0u && th[r] != 255u);
         }
       }
-      if (d_early) d_store(dv, dh);
+    }
+    // no cube around the block's edges has triangles and no edge holds a
+    // vertex: every count stays zero and there is nothing to write (about a
+    // third of the blocks of a frame of the room sequence lie in free space)
+    if (__ballot(has_slot != 0u || surf != 0u) == 0ull) {
+      wave_sync();
+      continue;
     }
     wave_sync();
     // 8 counts of 8 bits per axis: an edge can carry up to 16 triangles (four
@@ -1040,14 +1015,6 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
           swork[pos] = (uint32_t)(a * kVox + q + 64 * lz) | (rr[a] << 11) | (((hs >> a) & 1u) << 19);
         nwork += (uint32_t)__popcll(b);
       }
-    }
-    if (!d_early && nwork > 0) {
-      float dv[8], dh[4];
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz) dv[lz] = v.d[(size_t)idx * kVox + q + 64 * lz];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) dh[r] = d_halo(r);
-      d_store(dv, dh);
     }
     // one allocation and one recycling atomic per block, issued together;
     // a vertex whose count dropped to zero goes back to the segment's ring
@@ -1083,13 +1050,68 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
       pool32(v.vowner, (uint32_t)s) = kNone;
       eref_b[e] = 0;
     };
-    if (nwork <= (uint32_t)kWorkCap) {
-      uint32_t knew = 0, kfree = 0;
-      for (uint32_t i0 = 0; i0 < nwork; i0 += 64) {
-        const bool act = i0 + q < nwork;
+    uint32_t knew = 0, kfree = 0;
+    for (uint32_t c0 = 0; c0 < nwork; c0 += kWorkCap) {
+      if (c0 > 0) {
+        // the list's next chunk, listed again from the counts
+        wave_sync();
+        uint32_t pos = 0;
+#pragma unroll 2
+        for (int lz = 0; lz < 8; ++lz) {
+          const uint32_t hs = has_slot >> (3 * lz);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u, has = (hs >> a) & 1u;
+            const bool w = ref > 0 || has;
+            const uint64_t b = __ballot(w);
+            const uint32_t p = pos + (uint32_t)__popcll(b & below);
+            if (w && p >= c0 && p < c0 + (uint32_t)kWorkCap)
+              swork[p - c0] = (uint32_t)(a * kVox + q + 64 * lz) | (ref << 11) | (has << 19);
+            pos += (uint32_t)__popcll(b);
+          }
+        }
+        wave_sync();
+      }
+      const uint32_t m = min(nwork - c0, (uint32_t)kWorkCap);
+      // the chunk's loads: per item of the lane, the slot of the vertex it
+      // frees, or the TSDF at its edge's two end points (the far one in the
+      // +axis neighbour when the owner sits on the block's +axis face)
+      constexpr int kSteps = kWorkCap / 64;
+      int32_t fslot[kSteps];
+      float da[kSteps], db[kSteps];
+#pragma unroll
+      for (int k = 0; k < kSteps; ++k) {
+        fslot[k] = -1;
+        da[k] = 0.f;
+        db[k] = 0.f;
+        const uint32_t i = (uint32_t)(64 * k + q);
+        if (i < m) {
+          const uint32_t item = swork[i];
+          const uint32_t e = item & 2047u, ref = (item >> 11) & 255u;
+          if (ref == 0) {
+            fslot[k] = evtx_b[e];
+          } else {
+            const uint32_t a = e >> 9, l = e & 511u;
+            const uint32_t c = a == 0 ? (l & 7u) : (a == 1 ? ((l >> 3) & 7u) : (l >> 6));
+            const uint32_t stp = a == 0 ? 1u : (a == 1 ? 8u : 64u);
+            int32_t fb = (int32_t)idx;
+            uint32_t fl = l + stp;
+            if (c == 7u) {
+              fb = snb[nbr_dir(a == 0, a == 1, a == 2)];
+              fl = l - 7u * stp;
+            }
+            da[k] = v.d[(size_t)idx * kVox + l];
+            db[k] = fb >= 0 ? v.d[(size_t)fb * kVox + fl] : 0.f;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kSteps; ++k) {
+        const uint32_t i0 = 64u * (uint32_t)k;
+        if (i0 >= m) break;
+        const bool act = i0 + q < m;
         const uint32_t item = act ? swork[i0 + q] : 0u;
         const uint32_t e = item & 2047u, ref = (item >> 11) & 255u, has = item >> 19;
-        const uint32_t a = e >> 9, l = e & 511u;
         const bool is_new = act && ref > 0 && !has, is_free = act && ref == 0;
         const uint64_t bn = __ballot(is_new), bf = __ballot(is_free);
         const uint32_t myk = knew + (uint32_t)__popcll(bn & below);
@@ -1114,48 +1136,10 @@ __global__ __launch_bounds__(64 * W, W == 8 ? 2 : 3) void k_vertices(VolDev v) {
           } else {
             ++nupd;
           }
-          const int sdb = (int)(l & 7u) + 9 * (int)((l >> 3) & 7u) + 81 * (int)(l >> 6);
-          const int stp = a == 0 ? 1 : (a == 1 ? 9 : 81);
-          et_b[e] = edge_param(sd[sdb], sd[sdb + stp]);
+          et_b[e] = edge_param(da[k], db[k]);
           eref_b[e] = (uint8_t)ref;
         } else {
-          free_vertex(e, evtx_b[e], myf);
-        }
-      }
-    } else {
-      // many edges with work (dense sign fields): row by row over all edges
-      uint32_t dummy;
-      uint32_t rank = wave_scan(nneed, &dummy), frank = wave_scan(nfree, &dummy);
-      const int step[3] = {1, 9, 81};
-#pragma unroll 2
-      for (int lz = 0; lz < 8; ++lz) {
-        const int sdb = lx + 9 * ly + 81 * lz;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u;
-          if (ref == 0 && !((has_slot >> (3 * lz + a)) & 1u)) continue;
-          const uint32_t e = (uint32_t)(a * kVox + q + 64 * lz);
-          const bool has = (has_slot >> (3 * lz + a)) & 1u;
-          if (ref > 0) {
-            if (!has) {
-              const uint32_t ns = new_slot(rank++);
-              if (ns == kNone) {
-                atomicOr(&v.cnt->error, kErrVertices);
-                evtx_b[e] = -1;
-                continue;
-              }
-              evtx_b[e] = (int32_t)ns;
-              pool32(v.vowner, ns) = (uint32_t)eb + e;
-              pool32(v.vbirth, ns) = v.frame;
-              ++nnew;
-            } else {
-              ++nupd;
-            }
-            et_b[e] = edge_param(sd[sdb], sd[sdb + step[a]]);
-            eref_b[e] = (uint8_t)ref;
-          } else {
-            free_vertex(e, evtx_b[e], frank++);
-          }
+          free_vertex(e, fslot[k], myf);
         }
       }
     }
