@@ -122,6 +122,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->et = (float*)take(4 * 3 * kVox * B);
   v->eref = (uint8_t*)take(3 * kVox * B);
   v->wmask = (uint64_t*)take(8 * 8 * B);
+  v->smask = (uint64_t*)take(8 * 8 * B);
   v->st_pending = (uint32_t*)take(4 * B);
   v->st_dirty = (uint32_t*)take(4 * B);
   v->st_vtx = (uint32_t*)take(4 * B);

@@ -12,7 +12,8 @@
 //             weight f32[512], previous/current cube type u8[512],
 //             per owned edge (three per voxel): vertex slot i32, the
 //             vertex's t f32 and reference count u8; observed-voxel
-//             (weight > 0) bitmask u64[8]; pass stamps.
+//             (weight > 0) and negative-TSDF bitmasks u64[8] each; pass
+//             stamps.
 //   vertices  per pool slot: owner edge (index into the edge arrays, kNone
 //             when free), recycle ring, download row, birth frame.
 //   triangles no storage of their own: a cube's applied type names its
@@ -133,6 +134,7 @@ struct VolDev {
   float* et;                  // [B][3][512] t of the edge's vertex
   uint8_t* eref;              // [B][3][512] reference count of the edge's vertex
   uint64_t* wmask;            // [B][8] per z layer: voxels with weight > 0 (bit x + 8y)
+  uint64_t* smask;            // [B][8] per z layer: voxels with TSDF < 0 (bit x + 8y)
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
   uint32_t* st_vtx;           // [B] pass that listed the block for vertices

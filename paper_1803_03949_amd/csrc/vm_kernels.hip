@@ -507,25 +507,31 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
       pr[lz] = fuse_project(v, fp, 8 * bx + lx, 8 * by + ly, 8 * bz + lz);
       D[lz] = depth[pr[lz].pix >= 0 ? pr[lz].pix : 0];
     }
-    uint64_t mine = 0;  // lane lz < 8 keeps the observed mask of layer lz
+    // lane lz < 8 keeps the observed and the negative-TSDF mask of layer lz
+    uint64_t mine = 0, mneg = 0;
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
       const FuseSample fs = fuse_finish(v, fp, pr[lz], D[lz]);
       const size_t o = (size_t)idx * kVox + q + 64 * lz;
+      float dn = d[lz];
       if (fs.upd) {
         float num = d[lz] * w[lz];
         num = num + fs.dt;
         const float den = w[lz] + 1.0f;
-        v.d[o] = num / den;
+        dn = num / den;
+        v.d[o] = dn;
         v.w[o] = den;
       } else if (isnew) {
         v.d[o] = d[lz];
         v.w[o] = w[lz];
       }
-      const uint64_t m = __ballot(fs.upd || w[lz] > 0.f);
-      if (q == lz) mine = m;
+      const uint64_t m = __ballot(fs.upd || w[lz] > 0.f), mn = __ballot(dn < 0.f);
+      if (q == lz) mine = m, mneg = mn;
     }
-    if (q < 8) v.wmask[(size_t)idx * 8 + q] = mine;
+    if (q < 8) {
+      v.wmask[(size_t)idx * 8 + q] = mine;
+      v.smask[(size_t)idx * 8 + q] = mneg;
+    }
     if (q == 0) v.st_frame[idx] = fp.frame;
   }
 }
@@ -533,8 +539,8 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
 // One wave per imported block, eight voxels per lane: the caller's rows are
 // read first, then the new block is initialised and linked while they
 // arrive.  With bound arrays (the caller's rows are the volume's TSDF and
-// weights) a block must land on its own row, and only the weights are read,
-// for the observed-voxel mask.
+// weights) a block must land on its own row, and nothing is copied: the
+// rows are read only for the observed-voxel and negative-TSDF masks.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* __restrict__ tsdf,
                                                         const float* __restrict__ weight,
@@ -557,7 +563,7 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
     float d[8], w[8];
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
-      d[lz] = v.bound ? 0.f : tsdf[(size_t)row * kVox + q + 64 * lz];
+      d[lz] = tsdf[(size_t)row * kVox + q + 64 * lz];
       w[lz] = weight[(size_t)row * kVox + q + 64 * lz];
     }
     if (e & kNewFlag) {
@@ -571,8 +577,11 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
         v.d[(size_t)idx * kVox + q + 64 * lz] = d[lz];
         v.w[(size_t)idx * kVox + q + 64 * lz] = w[lz];
       }
-      const uint64_t m = __ballot(w[lz] > 0.f);
-      if (q == 0) v.wmask[(size_t)idx * 8 + lz] = m;
+      const uint64_t m = __ballot(w[lz] > 0.f), mn = __ballot(d[lz] < 0.f);
+      if (q == 0) {
+        v.wmask[(size_t)idx * 8 + lz] = m;
+        v.smask[(size_t)idx * 8 + lz] = mn;
+      }
     }
     if (q == 0) {
       v.st_frame[idx] = frame;
@@ -708,13 +717,50 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
     if (q < 8) snb[q] = mynb;
     wave_sync();
-    {
-      // all loads of the 9^3 halo first, then the LDS stores; whether a
-      // corner is observed comes from its block's weight mask (one 64-byte
-      // line per block) rather than from the weights
+    if (!refine) {
+      // the corners' signs and whether they are observed come from the
+      // eight blocks' negative-TSDF and observed masks (64 bytes each per
+      // block, kept by fusion and import): lane q requests layer q & 7 of
+      // block q >> 3 (x | y << 1 | z << 2) and stages it in LDS (in the
+      // refinement TSDF's space), then every lane forms its corner cells
+      uint32_t* smk = reinterpret_cast<uint32_t*>(sd);  // [2][64][2] mask halves
+      {
+        const int32_t nb = snb[q >> 3];
+        uint64_t sn = 0, ob = 0;
+        if (nb >= 0) {
+          sn = v.smask[(size_t)nb * 8 + (q & 7)];
+          ob = v.wmask[(size_t)nb * 8 + (q & 7)];
+        }
+        smk[2 * q] = (uint32_t)sn;
+        smk[2 * q + 1] = (uint32_t)(sn >> 32);
+        smk[128 + 2 * q] = (uint32_t)ob;
+        smk[128 + 2 * q + 1] = (uint32_t)(ob >> 32);
+      }
+      wave_sync();
       // cell j = q + 64 it sits at x + 9y + 81z; as j steps by 64 = 7*9 + 1,
-      // (x, y, z) steps by (1, 7, 0) with carries.  Byte offsets from the
-      // arrays' bases fit 32 bits (at most 2^21 blocks of 2 KiB).
+      // (x, y, z) steps by (1, 7, 0) with carries
+      int x = q % 9, y = q / 9, z = 0;
+#pragma unroll
+      for (int it = 0; it < 12; ++it) {
+        const int j = q + 64 * it;
+        if (j < 729) {
+          const int w = (((x >> 3) | ((y >> 3) << 1) | ((z >> 3) << 2)) << 3) + (z & 7);
+          const uint32_t bit = (uint32_t)((x & 7) + 8 * (y & 7));
+          const uint32_t h = 2 * (uint32_t)w + (bit >> 5);
+          const uint32_t sb = (smk[h] >> (bit & 31u)) & 1u, ob = (smk[128 + h] >> (bit & 31u)) & 1u;
+          sbits[j] = (uint8_t)(sb | (ob << 1));
+        }
+        x += 1;
+        y += 7;
+        if (x == 9) x = 0, ++y;
+        if (y >= 9) y -= 9, ++z;
+      }
+    } else {
+      // refinement needs the corners' TSDF values: all loads of the 9^3
+      // halo first, then the LDS stores; whether a corner is observed comes
+      // from its block's weight mask (one 64-byte line per block) rather
+      // than from the weights.  Byte offsets from the arrays' bases fit 32
+      // bits (at most 2^21 blocks of 2 KiB).
       const char* dbase = reinterpret_cast<const char*>(v.d);
       const char* mbase = reinterpret_cast<const char*>(v.wmask);
       float dv[12];
@@ -744,7 +790,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       for (int it = 0; it < 12; ++it) {
         const int j = q + 64 * it;
         if (j < 729) {
-          if (refine) sd[j] = dv[it];
+          sd[j] = dv[it];
           sbits[j] = (uint8_t)((dv[it] < 0.f ? 1u : 0u) | (((ok >> it) & 1u) << 1));
         }
       }
