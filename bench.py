@@ -43,10 +43,10 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 4854.7, "write_kib": 907.3, "source_sha1": "e5dd002ceb0c"},
-    "fuse": {"fetch_kib": 10376.8, "write_kib": 11794.2, "source_sha1": "07b4fdca9c04"},
-    "classify": {"fetch_kib": 12089.7, "write_kib": 3453.3, "source_sha1": "b6e9291df145"},
-    "vertices": {"fetch_kib": 16642.0, "write_kib": 9037.7, "source_sha1": "b06e1d73e560"},
+    "collect": {"fetch_kib": 5503.3, "write_kib": 1012.5, "source_sha1": "e5dd002ceb0c"},
+    "fuse": {"fetch_kib": 11792.4, "write_kib": 13675.0, "source_sha1": "713321bf3994"},
+    "classify": {"fetch_kib": 3763.6, "write_kib": 3774.9, "source_sha1": "f43b169b34aa"},
+    "vertices": {"fetch_kib": 12319.7, "write_kib": 10297.1, "source_sha1": "3a3165b67427"},
 }
 
 
@@ -115,19 +115,24 @@ def algorithmic_bytes(tot, npix, refine=False):
     return kernels, sum(kernels.values()) + triangles
 
 
-def touched_bytes(tot, npix):
+def touched_bytes(tot, npix, refine=False):
     """Bytes each kernel reads and writes by design (its own inputs and
     outputs, once each, halo re-reads excluded), the figure a kernel's
     speed of light is judged by: the vertex pass, for one, reads the types
     and TSDF of every block it recomputes, which the method's figure charges
-    to classification alone."""
-    return {
+    to classification alone.  With refine, half the dirty-block total is the
+    refinement's (TSDF, observed mask, both types read, types written)."""
+    dirty = tot["dirty_blocks"] // 2 if refine else tot["dirty_blocks"]
+    out = {
         "collect": 4 * npix * tot["frames"],
         "fuse": 4 * npix * tot["frames"] + 8192 * tot["frame_blocks"],
-        "classify": 5632 * tot["dirty_blocks"],
+        "classify": 5632 * dirty,
         "vertices": 4096 * tot["vertex_blocks"] + 5 * tot["updated_vertices"]
         + 13 * tot["new_vertices"] + 13 * tot["freed_vertices"],
     }
+    if refine:
+        out["refine"] = 3648 * dirty
+    return out
 
 
 def frac(nbytes, ms):
@@ -414,6 +419,7 @@ def room_fine(args, dev):
     prof = vol.profile_read()
     npix = depth.shape[1] * depth.shape[2]
     algo, step_total = algorithmic_bytes(tot, npix, refine=True)
+    touched = touched_bytes(tot, npix, refine=True)
     kernels = {}
     for k, (n, ms) in prof.items():
         e = {"launches": n, "us_per_launch": round(1000 * ms / n, 3)}
@@ -421,6 +427,8 @@ def room_fine(args, dev):
             e["bytes_per_launch"] = algo[k] // max(n, 1)
             e["GBps"] = round(algo[k] / (ms * 1e-3) / 1e9, 2)
             e["frac"] = round(frac(algo[k], ms), 5)
+            e["touched_bytes_per_launch"] = touched[k] // max(n, 1)
+            e["touched_frac"] = round(frac(touched[k], ms), 5)
         kernels[k] = e
     out = {"frames_per_s": args.fine_frames / dt, "ms_per_frame": 1000 * dt / args.fine_frames,
            "frames": args.fine_frames, "blocks": st["blocks"],
