@@ -118,17 +118,18 @@ def algorithmic_bytes(tot, npix, refine=False):
 def touched_bytes(tot, npix, refine=False):
     """Bytes each kernel reads and writes by design (its own inputs and
     outputs, once each, halo re-reads excluded), the figure a kernel's
-    speed of light is judged by: the vertex pass, for one, reads the types
-    and TSDF of every block it recomputes, which the method's figure charges
-    to classification alone.  With refine, half the dirty-block total is the
+    speed of light is judged by: the vertex pass, for one, reads the types,
+    TSDF and edge-vertex bits of every block it recomputes (2816 bytes),
+    which the method's figure charges to classification alone, and writes
+    t only for the kept vertices whose end points moved.  With refine, half the dirty-block total is the
     refinement's (TSDF, observed mask, both types read, types written)."""
     dirty = tot["dirty_blocks"] // 2 if refine else tot["dirty_blocks"]
     out = {
         "collect": 4 * npix * tot["frames"],
         "fuse": 4 * npix * tot["frames"] + 8192 * tot["frame_blocks"],
         "classify": 5632 * dirty,
-        "vertices": 4096 * tot["vertex_blocks"] + 5 * tot["updated_vertices"]
-        + 13 * tot["new_vertices"] + 13 * tot["freed_vertices"],
+        "vertices": 2816 * tot["vertex_blocks"] + 4 * tot["moved_vertices"]
+        + 16 * tot["new_vertices"] + 12 * tot["freed_vertices"],
     }
     if refine:
         out["refine"] = 3648 * dirty

@@ -77,9 +77,10 @@ enum {
 enum { VM_SCOPE_DIRTY = 0, VM_SCOPE_ALL = 1 };
 
 /* Volume configuration.  Sizes are capacities of the caller buffer: per
- * block of max_blocks about 18.9 KiB (TSDF and weight 4 KiB, types 1 KiB,
- * vertex slot, t and count of its 1536 owned edges 13.5 KiB, a 64-byte mask
- * of its observed voxels, lists and stamps), per vertex of max_vertices 16
+ * block of max_blocks about 17.6 KiB (TSDF and weight 4 KiB, types 1 KiB,
+ * vertex slot and t of its 1536 owned edges 12 KiB, one bit per edge for
+ * whether it holds a vertex, 64-byte masks of its observed and of its
+ * negative-TSDF voxels, lists and stamps), per vertex of max_vertices 16
  * bytes, plus 16 bytes per hash slot.  Triangles take no memory of their
  * own: a cube's type names them (see vm_extract_mesh). */
 typedef struct vm_config {
@@ -144,13 +145,16 @@ enum {
   VM_TOTAL_DIRTY_BLOCKS = 2,    /* blocks classified (extract and refine) */
   VM_TOTAL_VERTEX_BLOCKS = 3,   /* blocks whose owned edges were recomputed */
   VM_TOTAL_NEW_VERTICES = 4,
-  VM_TOTAL_UPDATED_VERTICES = 5,
+  VM_TOTAL_UPDATED_VERTICES = 5, /* vertices of recomputed edges that stay */
   VM_TOTAL_CHANGED_CUBES = 6,   /* cubes whose triangles were replaced */
   VM_TOTAL_NEW_TRIANGLES = 7,   /* triangles of those cubes' new types */
   VM_TOTAL_FREED_VERTICES = 8,
   VM_TOTAL_REFINED_CUBES = 9,
   VM_TOTAL_DROPPED_TRIANGLES = 10, /* triangles of those cubes' old types */
-  VM_TOTAL_COUNT = 11
+  VM_TOTAL_MOVED_VERTICES = 11, /* updated vertices whose t was rewritten (an end
+                                   point's block fused or imported since the last
+                                   extraction); the others keep their t */
+  VM_TOTAL_COUNT = 12
 };
 
 /* Kernels, for vm_profile_read. */

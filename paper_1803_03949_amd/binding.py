@@ -77,7 +77,7 @@ _STATUS_FIELDS = ["blocks", "frame_blocks", "pending_blocks", "dirty_blocks", "v
 
 TOTALS = ["frames", "frame_blocks", "dirty_blocks", "vertex_blocks", "new_vertices",
           "updated_vertices", "changed_cubes", "new_triangles", "freed_vertices",
-          "refined_cubes", "dropped_triangles"]
+          "refined_cubes", "dropped_triangles", "moved_vertices"]
 KERNELS = ["collect", "assign", "fuse", "import", "dirty", "classify", "refine", "vertices",
            "download", "backward", "counters", "ablation", "positions"]
 

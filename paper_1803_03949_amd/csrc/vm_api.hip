@@ -63,7 +63,27 @@ namespace {
 
 uint8_t g_tri[256 * 16];
 uint8_t g_uses[256 * 12];
+uint32_t g_roles[4 * 256];
 std::once_flag g_tables_once;
+
+// The vertex pass's edge-use table: for each cube type, by the cube's place
+// around a voxel (role 0: cube (x, y), 1: (x, y-1), 2: (x-1, y), 3:
+// (x-1, y-1), all in the voxel's layer), how many of the type's triangles
+// use the voxel's x, y and z edge (6-bit fields at bits 0, 6, 12) and the x
+// and y edge of the voxel one layer up (bits 18, 24), which the same cube
+// also touches.  The cube edges follow the cyclic numbering: a voxel's x
+// edge is e0 of cube (x, y), e2 of (x, y-1), e4 and e6 of those one layer
+// down; its y edge e3 of (x, y), e1 of (x-1, y), e7 and e5 one layer down;
+// its z edge e8, e11, e9, e10 of (x, y), (x, y-1), (x-1, y), (x-1, y-1).
+void build_roles(const uint8_t* uses, uint32_t* roles) {
+  for (int t = 0; t < 256; ++t) {
+    const uint8_t* u = uses + 12 * t;
+    roles[t] = u[0] | u[3] << 6 | u[8] << 12 | u[4] << 18 | u[7] << 24;
+    roles[256 + t] = u[2] | u[11] << 12 | u[6] << 18;
+    roles[512 + t] = u[1] << 6 | u[9] << 12 | u[5] << 24;
+    roles[768 + t] = u[10] << 12;
+  }
+}
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -109,6 +129,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->cseg = (Seg*)take(sizeof(Seg) * kSegs);
   v->tri_table = (const uint8_t*)take(256 * 16);
   v->edge_uses = (const uint8_t*)take(256 * 12);
+  v->edge_roles = (const uint32_t*)take(4 * 4 * 256);
   v->slots = (unsigned long long*)take(8 * H);
   v->slot_stamp = (uint32_t*)take(4 * H);
   v->slot_src = (uint32_t*)take(4 * H);
@@ -120,7 +141,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->tcur = (uint8_t*)take(kVox * B);
   v->evtx = (int32_t*)take(4 * 3 * kVox * B);
   v->et = (float*)take(4 * 3 * kVox * B);
-  v->eref = (uint8_t*)take(3 * kVox * B);
+  v->emask = (uint32_t*)take(4 * 64 * B);
   v->wmask = (uint64_t*)take(8 * 8 * B);
   v->smask = (uint64_t*)take(8 * 8 * B);
   v->st_pending = (uint32_t*)take(4 * B);
@@ -184,6 +205,9 @@ int clear_state(vm_volume* vol, hipStream_t stream, bool full) {
       e = hipMemcpyAsync((void*)v.tri_table, g_tri, sizeof(g_tri), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync((void*)v.edge_uses, g_uses, sizeof(g_uses), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)v.edge_roles, g_roles, sizeof(g_roles), hipMemcpyHostToDevice,
+                         stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
   }
   vol->frame = 0;
@@ -347,7 +371,10 @@ int batch_phase(vm_volume* vol, const vm_batch_io& io, int ph, hipStream_t s) {
 // checked against the configuration) and clear the workspace on `stream`.
 int init_volume(vm_volume* vol, const vm_config* cfg, char* mem, size_t bytes,
                 hipStream_t stream) {
-  std::call_once(g_tables_once, [] { build_mc_tables(g_tri, g_uses); });
+  std::call_once(g_tables_once, [] {
+    build_mc_tables(g_tri, g_uses);
+    build_roles(g_uses, g_roles);
+  });
   vol->cfg = *cfg;
   vol->mem = mem;
   vol->bytes = bytes;
@@ -559,6 +586,9 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
   vol->dev.frame = vol->frame;
   vol->dev.vsel = ++vol->vcount & 1u;
   const VolDev& v = vol->dev;
+  // the vertex pass re-places the vertices whose end points' blocks were
+  // fused or imported since the last extraction (every block for ALL)
+  const uint32_t moved = scope == VM_SCOPE_ALL ? kMovedAll : vol->epoch;
   if (scope == VM_SCOPE_ALL)
     VM_LAUNCH(vol, VM_K_DIRTY, k_dirty_all, dim3(vol->grid_items), dim3(256), stream, v, pass);
   else
@@ -567,7 +597,7 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
   ++vol->epoch;
   VM_LAUNCH_W(vol, VM_K_CLASSIFY, k_classify, stream, v, pass, 0);
   VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
-  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
+  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v, moved);
   return launched();
 }
 
@@ -581,7 +611,9 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   prep(vol, VM_OP_REFINE, stream);
   VM_LAUNCH_W(vol, VM_K_REFINE, k_classify, stream, v, pass, 1);
   VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
-  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v);
+  // refinement changes types only: the end points that moved are those in
+  // blocks fused or imported since the last extraction (normally none)
+  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v, vol->epoch);
   return launched();
 }
 
@@ -852,6 +884,7 @@ int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream) {
   for (int k = 0; k < kSegs; ++k) {
     t[VM_TOTAL_NEW_VERTICES] += sn.vseg[k].st_new;
     t[VM_TOTAL_UPDATED_VERTICES] += sn.vseg[k].st_upd;
+    t[VM_TOTAL_MOVED_VERTICES] += sn.vseg[k].st_mov;
     t[VM_TOTAL_FREED_VERTICES] += sn.vseg[k].st_freed;
     t[VM_TOTAL_CHANGED_CUBES] += sn.cseg[k].st_chg;
     t[VM_TOTAL_REFINED_CUBES] += sn.cseg[k].st_ref;

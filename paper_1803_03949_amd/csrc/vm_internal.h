@@ -10,10 +10,13 @@
 //             stamp marks the blocks a frame collected.
 //   blocks    key u64, 27-neighbour index table, TSDF f32[512],
 //             weight f32[512], previous/current cube type u8[512],
-//             per owned edge (three per voxel): vertex slot i32, the
-//             vertex's t f32 and reference count u8; observed-voxel
+//             per owned edge (three per voxel): vertex slot i32 and the
+//             vertex's t f32; which owned edges hold a vertex, one 32-bit
+//             word per column of voxels (u32[64]); observed-voxel
 //             (weight > 0) and negative-TSDF bitmasks u64[8] each; pass
-//             stamps.
+//             stamps.  Reference counts are not stored: a cube's type
+//             fixes how many of its triangles use each of its edges, so an
+//             edge's count is formed from the four cubes around it.
 //   vertices  per pool slot: owner edge (index into the edge arrays, kNone
 //             when free), recycle ring, download row, birth frame.
 //   triangles no storage of their own: a cube's applied type names its
@@ -53,6 +56,12 @@ constexpr int kTilePer = kTile / 256;        // items per lane
 constexpr int count_bits(int n) { return n < 2 ? 1 : (n < 4 ? 2 : (n < 8 ? 3 : 4)); }
 constexpr int kTileBits = count_bits(kTilePer);  // bits of a lane's count
 
+// Which blocks' TSDF may have changed since the vertices were last placed,
+// for the vertex pass: kMovedAll (every block: extraction of everything),
+// or else an extraction epoch (epochs start at 1): the blocks stamped
+// pending with it, i.e. fused or imported since the last extraction.
+constexpr uint32_t kMovedAll = 0u;
+
 // Error bits (bit k <-> VM error code -(k+2)).
 constexpr uint32_t kErrHash = 1u << 0;
 constexpr uint32_t kErrBlocks = 1u << 1;
@@ -77,7 +86,8 @@ struct Seg {
   int32_t st_tcube;  // running change of the number of cubes with triangles
   uint32_t st_fnew;  // running count of triangles of changed cubes' new types
   uint32_t st_fold;  // running count of triangles of changed cubes' old types
-  uint32_t pad[18];
+  uint32_t st_mov;   // running count of kept vertices whose t was rewritten
+  uint32_t pad[17];
 };
 static_assert(sizeof(Seg) == 128, "segment record size");
 
@@ -120,6 +130,7 @@ struct VolDev {
   Seg* cseg;                  // [kSegs] cube statistics (changed, refined, triangles)
   const uint8_t* tri_table;   // [256][16]: count, then 15 cube-edge ids
   const uint8_t* edge_uses;   // [256][12]: triangles of the type using the edge
+  const uint32_t* edge_roles; // [4][256]: the same counts packed by role (vertex pass)
   unsigned long long* slots;  // [hash]
   uint32_t* slot_stamp;       // [hash] frame that last collected the slot
   uint32_t* slot_src;         // [hash] import: source row of the slot's block
@@ -129,10 +140,12 @@ struct VolDev {
   float* w;                   // [B][512]
   uint8_t* tprev;             // [B][512]
   uint8_t* tcur;              // [B][512]
-  int32_t* evtx;              // [B][3][512] vertex slot of the edge: valid where eref > 0
-                              // (-1 after a failed allocation), stale elsewhere
+  int32_t* evtx;              // [B][3][512] vertex slot of the edge: valid where the
+                              // edge's emask bit is set (-1 after a failed
+                              // allocation), stale elsewhere
   float* et;                  // [B][3][512] t of the edge's vertex
-  uint8_t* eref;              // [B][3][512] reference count of the edge's vertex
+  uint32_t* emask;            // [B][64] word q: edges (a, q + 64 lz) that hold a
+                              // vertex, bit 8a + lz
   uint64_t* wmask;            // [B][8] per z layer: voxels with weight > 0 (bit x + 8y)
   uint64_t* smask;            // [B][8] per z layer: voxels with TSDF < 0 (bit x + 8y)
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
@@ -363,6 +376,27 @@ __device__ inline uint32_t wave_sum_bits(uint32_t x) {
   return s;
 }
 
+// Lanes below this one whose bit is set in the wave mask m, plus acc.
+__device__ inline uint32_t mask_rank(uint64_t m, uint32_t acc = 0) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, acc));
+}
+
+// Exclusive prefix over the wave of per-lane values in [0, 2^B), and the
+// wave's total: one ballot per bit.
+template <int B>
+__device__ inline uint32_t wave_prefix_bits(uint32_t x, uint32_t* total) {
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const uint64_t m = __ballot((x >> b) & 1u);
+    pre += mask_rank(m) << b;
+    tot += (uint32_t)__popcll(m) << b;
+  }
+  *total = tot;
+  return pre;
+}
+
 __device__ inline uint64_t shfl64(uint64_t x, int src) {
   const uint32_t lo = __shfl((uint32_t)x, src), hi = __shfl((uint32_t)(x >> 32), src);
   return ((uint64_t)hi << 32) | lo;
@@ -552,7 +586,7 @@ template <int W>
 __global__ void k_classify(VolDev v, uint32_t pass, int refine);
 __global__ void k_vblock_compact(VolDev v);
 template <int W>
-__global__ void k_vertices(VolDev v);
+__global__ void k_vertices(VolDev v, uint32_t moved);
 __global__ void k_dl_count(VolDev v, int what);
 __global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
 __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,

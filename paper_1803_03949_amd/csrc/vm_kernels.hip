@@ -69,6 +69,7 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
   const uint32_t sum_freed = wave_sum(vs.st_freed);
   const uint32_t sum_chg = wave_sum(cs.st_chg), sum_ref = wave_sum(cs.st_ref);
   const uint32_t sum_fnew = wave_sum(cs.st_fnew), sum_fold = wave_sum(cs.st_fold);
+  const uint32_t sum_mov = wave_sum(vs.st_mov);
   if (s != 0) return;
   Counters* c = v.cnt;
   switch (op) {
@@ -77,6 +78,7 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
       c->acc[VM_TOTAL_DROPPED_TRIANGLES] += sum_fold;
       c->acc[VM_TOTAL_NEW_VERTICES] += sum_new;
       c->acc[VM_TOTAL_UPDATED_VERTICES] += sum_upd;
+      c->acc[VM_TOTAL_MOVED_VERTICES] += sum_mov;
       c->acc[VM_TOTAL_FREED_VERTICES] += sum_freed;
       c->acc[VM_TOTAL_CHANGED_CUBES] += sum_chg;
       c->acc[VM_TOTAL_REFINED_CUBES] += sum_ref;
@@ -440,14 +442,17 @@ __device__ inline void link_block(const VolDev& v, uint32_t idx, int l, bool for
   v.nbr[(size_t)nb * 27 + (26 - l)] = (int32_t)idx;
 }
 
-// A new block's cube l: no type, and its three edges carry no vertex (a
-// count of zero; the slot is meaningful only under a nonzero count, so it
-// is not written).
-__device__ inline void init_cube(const VolDev& v, uint32_t idx, int l) {
-  const size_t o = (size_t)idx * kVox + l;
-  v.tprev[o] = 0;
-  v.tcur[o] = 0;
-  for (int a = 0; a < 3; ++a) v.eref[((size_t)idx * 3 + a) * kVox + l] = 0;
+// A new block's column q of cubes: no type, and none of the column's edges
+// holds a vertex (an edge's slot is meaningful only under its set bit, so
+// the slots are not written).
+__device__ inline void init_column(const VolDev& v, uint32_t idx, int q) {
+#pragma unroll
+  for (int lz = 0; lz < 8; ++lz) {
+    const size_t o = (size_t)idx * kVox + q + 64 * lz;
+    v.tprev[o] = 0;
+    v.tcur[o] = 0;
+  }
+  v.emask[(size_t)idx * 64 + q] = 0;
 }
 
 // ============================================================================
@@ -485,11 +490,9 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
     unpack_key(key, bx, by, bz);
     float d[8], w[8];
     if (isnew) {
+      init_column(v, idx, q);
 #pragma unroll
-      for (int lz = 0; lz < 8; ++lz) {
-        init_cube(v, idx, q + 64 * lz);
-        d[lz] = 0.f, w[lz] = 0.f;
-      }
+      for (int lz = 0; lz < 8; ++lz) d[lz] = 0.f, w[lz] = 0.f;
       link_block(v, idx, q);
     } else {
 #pragma unroll
@@ -567,8 +570,7 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
       w[lz] = weight[(size_t)row * kVox + q + 64 * lz];
     }
     if (e & kNewFlag) {
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz) init_cube(v, idx, q + 64 * lz);
+      init_column(v, idx, q);
       link_block(v, idx, q, forward_only);
     }
 #pragma unroll
@@ -914,43 +916,48 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
 // +y, +z.  The reference count of an edge is the number of triangles, over
 // the four cubes around it, that use it; a positive count needs a vertex
 // (created here on first use, Sec. V-C), whose parameter t is rewritten
-// from the end point TSDF values.  The counts come from cube types staged
-// in LDS with the -x/-y/-z halo, so no per-triangle increments are needed.
-// New vertices take slots from the block's pool segment, one atomic per
-// block, and the recycled slots it takes are fetched in one batch.  The
-// edges with work (a count to write, or a vertex to free) are gathered into
-// a list in LDS while the counts are formed, with a bit telling whether the
-// edge has a vertex; the write pass runs over that list, 64 edges per step
-// (lanes of a step hold neighbouring edges, so its stores are coalesced),
-// in chunks of kWorkCap edges.  Each chunk first requests everything it
-// reads, the freed vertices' slots and the end point TSDF values of the
-// others, and only then stores: on this hardware a load issued after stores
-// waits for them too.  A block with no vertex and no cube with triangles
-// around its edges (one in free space) stops after the type staging.
+// from the end point TSDF values when either end point may have changed
+// since the last extraction.  Counts are formed, never stored: the cube
+// types are staged in LDS with the -x/-y/-z halo, and a per-type table of
+// edge uses packed by the cube's place around the voxel (four roles, three
+// 6-bit counts each, plus the counts the cube gives the voxel one layer up)
+// gives a lane the three counts of a voxel from four table reads, walking
+// up its column.  Which edges hold a vertex is one 24-bit word per lane
+// (bit 8a + lz), read at the start and written back when it changes.  New
+// vertices take slots from the block's pool segment, one atomic per block,
+// and the recycled slots it takes are fetched in one batch.  The edges with
+// work (a vertex to create, to free, or to move) are listed in LDS lane by
+// lane, each lane's place from a prefix sum of the lanes' counts; the
+// write pass runs over that list, 64 edges per step, in chunks of kWorkCap
+// edges.  Each chunk first requests everything it reads, the freed
+// vertices' slots and the end point TSDF values of the others, and only
+// then stores: on this hardware a load issued after stores waits for them
+// too.  A block with no vertex and no cube with triangles around its edges
+// (one in free space) stops after the type staging.
 constexpr int kRingBatch = 256;  // recycled slots fetched per block at once
 constexpr int kWorkCap = 512;    // listed edges per chunk of the write pass
 
 template <int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) void k_vertices(VolDev v) {
-  __shared__ uint8_t suses[256 * 12];
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) void k_vertices(VolDev v, uint32_t moved) {
+  __shared__ uint32_t srole[4 * 256];  // edge uses by role, per cube type
   __shared__ uint32_t st_all[W][kRingBatch];  // cube types at local -1..7, then slots
-  __shared__ uint32_t swork_all[W][kWorkCap]; // edge a * 512 + l | count << 11 | vertex << 19
+  __shared__ uint32_t swork_all[W][kWorkCap]; // edge 64k + q | count > 0 << 11 | has vertex << 12
   __shared__ int32_t snb_all[W][27];
   static_assert(kRingBatch * 4 >= 732, "type staging fits the slot batch");
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t n = min(v.cnt->n_vblocks[v.vsel], v.max_blocks);
+  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
   {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(v.edge_uses);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(suses);
-    for (int j = threadIdx.x; j < 256 * 12 / 4; j += blockDim.x) dst[j] = src[j];
+    // a workgroup whose first wave has no block has none at all
+    const ItemLoop first = item_loop(v, n, W, 0);
+    if (first.i >= first.end) return;
   }
+  for (int j = threadIdx.x; j < 4 * 256; j += blockDim.x) srole[j] = v.edge_roles[j];
   __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint8_t* st = reinterpret_cast<uint8_t*>(st_all[wave]);
   uint32_t* sring = st_all[wave];
   uint32_t* swork = swork_all[wave];
   int32_t* snb = snb_all[wave];
-  const uint32_t n = min(v.cnt->n_vblocks[v.vsel], v.max_blocks);
-  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
-  const uint64_t below = lanes_below();
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
     // lane addressing is formed again per block rather than held in
     // registers across the loop
@@ -963,111 +970,106 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) voi
     const size_t eb = (size_t)idx * (3 * kVox);
     int32_t* evtx_b = v.evtx + eb;
     float* et_b = v.et + eb;
-    uint8_t* eref_b = v.eref + eb;
-    const uint8_t* tcur_bytes = v.tcur;
     auto pool32 = [](uint32_t* base, uint32_t s) -> uint32_t& {
       return *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + s * 4u);
     };
-    // requested at once: the neighbour table, the block's edge counts and
-    // its pool segment (fixed during this kernel)
+    // requested at once: the neighbour table, which edges hold a vertex,
+    // the block's cube types and its pool segment (fixed during this kernel)
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
+    const uint32_t has = v.emask[(size_t)idx * 64 + q];
+    uint32_t tv[8];
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) tv[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
     const Seg& g = v.vseg[sg];
     const uint32_t head = g.head, count = g.count, hwm = g.hwm;
-    // which of the voxel's edges have a vertex (bit 3*lz + a): those with a
-    // nonzero count; the slots themselves are read only for the vertices
-    // that get freed
-    uint32_t has_slot = 0;
-    {
-      uint32_t er[24];
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) er[3 * lz + a] = eref_b[a * kVox + q + 64 * lz];
-#pragma unroll
-      for (int k = 23; k >= 0; --k)  // shifted in, so no per-bit mask constants
-        has_slot = (has_slot << 1) | (uint32_t)(er[k] != 0);
-    }
     if (q < 27) snb[q] = mynb;
     wave_sync();
-    // cube types into LDS: the block's own (local 0..7) and the -x/-y/-z
-    // neighbours' halo (local -1, 217 cells)
-    uint32_t surf = 0;  // a staged cube with triangles
+    // the -x/-y/-z halo of types (217 cells): the three faces, one cell per
+    // lane each, then the three edges and the corner (lanes 0..24); and,
+    // after an extraction of pending blocks, which of this block and its
+    // +x/+y/+z neighbours were pending
+    const uint8_t* tcur = v.tcur;
+    const int32_t bnx = snb[nbr_dir(-1, 0, 0)], bny = snb[nbr_dir(0, -1, 0)],
+                  bnz = snb[nbr_dir(0, 0, -1)];
+    const uint32_t hx = bnx >= 0 ? tcur[(uint32_t)bnx * 512u + 7u + 8u * (uint32_t)q] : 0u;
+    const uint32_t hy = bny >= 0 ? tcur[(uint32_t)bny * 512u + 56u + (uint32_t)(lx + 64 * ly)] : 0u;
+    const uint32_t hz = bnz >= 0 ? tcur[(uint32_t)bnz * 512u + 448u + (uint32_t)q] : 0u;
+    uint32_t he = 0;
+    int hcell = -1;
     {
-      uint32_t tv[8], th[4];
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz) tv[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int h = q + 64 * r;
-        th[r] = 0;
-        if (h < 217) {
-          int x, y, z;
-          halo_cell(h, -1, x, y, z);
-          const int nb = snb[nbr_dir(x < 0 ? -1 : 0, y < 0 ? -1 : 0, z < 0 ? -1 : 0)];
-          if (nb >= 0)
-            th[r] = tcur_bytes[(uint32_t)nb * 512u + (uint32_t)((x & 7) + 8 * (y & 7) + 64 * (z & 7))];
-        }
-      }
-#pragma unroll
-      for (int lz = 0; lz < 8; ++lz) {
-        st[(lx + 1) + 9 * (ly + 1) + 81 * (lz + 1)] = (uint8_t)tv[lz];
-        surf |= (uint32_t)(tv[lz] != 0u && tv[lz] != 255u);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int h = q + 64 * r;
-        if (h < 217) {
-          int x, y, z;
-          halo_cell(h, -1, x, y, z);
-          st[(x + 1) + 9 * (y + 1) + 81 * (z + 1)] = (uint8_t)th[r];
-          surf |= (uint32_t)(th[r] != 0u && th[r] != 255u);
-        }
+      int dir = -1;
+      uint32_t off = 0;
+      if (q < 8) dir = nbr_dir(-1, -1, 0), off = 63u + 64u * (uint32_t)q, hcell = 81 * (q + 1);
+      else if (q < 16) dir = nbr_dir(-1, 0, -1), off = 7u + 8u * (uint32_t)(q - 8) + 448u, hcell = 9 * (q - 7);
+      else if (q < 24) dir = nbr_dir(0, -1, -1), off = (uint32_t)(q - 16) + 504u, hcell = q - 15;
+      else if (q == 24) dir = nbr_dir(-1, -1, -1), off = 511u, hcell = 0;
+      const int32_t nb = dir >= 0 ? snb[dir] : -1;
+      if (nb >= 0) he = tcur[(uint32_t)nb * 512u + off];
+    }
+    uint32_t mv = 0xFFFFFFu;  // edges whose end points may have moved (bit 8a + lz)
+    if (moved != kMovedAll) {
+      const bool pend = q < 27 && mynb >= 0 && v.st_pending[mynb] == moved;
+      const uint64_t pm = __ballot(pend);
+      if (!((pm >> kSelf) & 1u)) {
+        mv = (lx == 7 && ((pm >> nbr_dir(1, 0, 0)) & 1u) ? 0xFFu : 0u) |
+             (ly == 7 && ((pm >> nbr_dir(0, 1, 0)) & 1u) ? 0xFF00u : 0u) |
+             (((pm >> nbr_dir(0, 0, 1)) & 1u) ? 0x800000u : 0u);
       }
     }
+    // types into LDS (local -1..7 per axis); whether a staged cube has
+    // triangles (a type other than 0 and 255)
+    uint32_t surf = 0;
+#pragma unroll
+    for (int lz = 0; lz < 8; ++lz) {
+      st[(lx + 1) + 9 * (ly + 1) + 81 * (lz + 1)] = (uint8_t)tv[lz];
+      surf |= (uint32_t)(tv[lz] - 1u < 254u);
+    }
+    st[9 * (lx + 1) + 81 * (ly + 1)] = (uint8_t)hx;      // (-1, y, z), y = q & 7
+    st[(lx + 1) + 81 * (ly + 1)] = (uint8_t)hy;          // (x, -1, z)
+    st[(lx + 1) + 9 * (ly + 1)] = (uint8_t)hz;           // (x, y, -1)
+    if (hcell >= 0) st[hcell] = (uint8_t)he;
+    surf |= (uint32_t)(hx - 1u < 254u) | (uint32_t)(hy - 1u < 254u) | (uint32_t)(hz - 1u < 254u) |
+            (uint32_t)(he - 1u < 254u);
     // no cube around the block's edges has triangles and no edge holds a
     // vertex: every count stays zero and there is nothing to write (about a
     // third of the blocks of a frame of the room sequence lie in free space)
-    if (__ballot(has_slot != 0u || surf != 0u) == 0ull) {
+    if (__ballot(has != 0u || surf != 0u) == 0ull) {
       wave_sync();
       continue;
     }
     wave_sync();
-    // 8 counts of 8 bits per axis: an edge can carry up to 16 triangles (four
-    // in each of its four cubes)
-    uint64_t refs[3] = {0, 0, 0};
-    uint32_t nneed = 0, nfree = 0, nwork = 0;
-#pragma unroll 2
-    for (int lz = 0; lz < 8; ++lz) {
-      const int tb = (lx + 1) + 9 * (ly + 1) + 81 * (lz + 1);
-#define USES(c, e) ((uint32_t)suses[(uint32_t)st[c] * 12 + (e)])
-      const uint32_t r0 = USES(tb, 0) + USES(tb - 9, 2) + USES(tb - 81, 4) + USES(tb - 90, 6);
-      const uint32_t r1 = USES(tb, 3) + USES(tb - 1, 1) + USES(tb - 81, 7) + USES(tb - 82, 5);
-      const uint32_t r2 = USES(tb, 8) + USES(tb - 1, 9) + USES(tb - 10, 10) + USES(tb - 9, 11);
-#undef USES
-      refs[0] |= (uint64_t)r0 << (8 * lz);
-      refs[1] |= (uint64_t)r1 << (8 * lz);
-      refs[2] |= (uint64_t)r2 << (8 * lz);
-      const uint32_t hs = has_slot >> (3 * lz);
-      nneed += (r0 > 0 && !(hs & 1u)) + (r1 > 0 && !(hs & 2u)) + (r2 > 0 && !(hs & 4u));
-      nfree += (r0 == 0 && (hs & 1u)) + (r1 == 0 && (hs & 2u)) + (r2 == 0 && (hs & 4u));
-      // list the layer's edges with work, axis by axis
-      const uint32_t rr[3] = {r0, r1, r2};
+    // counts, layer by layer up the lane's column.  A table entry holds,
+    // for a cube in its role, the uses of the x, y, z edges of the voxel in
+    // bits 0, 6, 12 and, from bit 18, those of the x and y edges of the
+    // voxel one layer up; no 6-bit field can overflow (at most 4 x 7).
+    const int cb = (lx + 1) + 9 * (ly + 1);
+    auto cell_sum = [&](int b) -> uint32_t {
+      return srole[st[b]] + srole[256 + st[b - 9]] + srole[512 + st[b - 1]] +
+             srole[768 + st[b - 10]];
+    };
+    uint32_t carry = cell_sum(cb) >> 18;  // the layer below the block
+    uint32_t R = 0;  // edges with a positive count, bit 8a + lz
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const bool w = rr[a] > 0 || ((hs >> a) & 1u);
-        const uint64_t b = __ballot(w);
-        const uint32_t pos = nwork + (uint32_t)__popcll(b & below);
-        if (w && pos < (uint32_t)kWorkCap)
-          swork[pos] = (uint32_t)(a * kVox + q + 64 * lz) | (rr[a] << 11) | (((hs >> a) & 1u) << 19);
-        nwork += (uint32_t)__popcll(b);
-      }
+    for (int lz = 0; lz < 8; ++lz) {
+      const uint32_t sum = cell_sum(cb + 81 * (lz + 1));
+      const uint32_t r = (sum & 0x3FFFFu) + carry;
+      carry = sum >> 18;
+      // bit 5 of each field of r + 31 is set iff the count is nonzero;
+      // times 0x15 places the three bits at 5, 13 and 21 (no carries)
+      const uint32_t nz = ((r + 0x1F7DFu) & 0x20820u) * 0x15u & 0x202020u;
+      R |= lz <= 5 ? nz >> (5 - lz) : nz << (lz - 5);
     }
+    const uint32_t need = R & ~has, freed = has & ~R, kept = R & has;
+    const uint32_t work = need | freed | (kept & mv);
     // one allocation and one recycling atomic per block, issued together;
     // a vertex whose count dropped to zero goes back to the segment's ring
     // at once (Sec. V-E), where it can be taken again once the ring is
     // closed, never by this pass
     // per lane at most 24 of each (its three edges in eight layers)
-    const uint32_t total = wave_sum_bits<5>(nneed), tfree = wave_sum_bits<5>(nfree);
+    const uint32_t total = wave_sum_bits<5>((uint32_t)__popc(need));
+    const uint32_t tfree = wave_sum_bits<5>((uint32_t)__popc(freed));
+    uint32_t nwork;
+    const uint32_t wpos = wave_prefix_bits<5>((uint32_t)__popc(work), &nwork);
     uint32_t base = 0, fbase = 0;
     if (q == 0) {
       if (total) base = atomicAdd(&v.vseg[sg].ticket, total);
@@ -1083,41 +1085,32 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) voi
     const uint32_t batch = min(total, (uint32_t)kRingBatch);
     for (uint32_t k = q; k < batch; k += 64)
       sring[k] = seg_slot(head, count, hwm, base + k, v.vring, gbase, gsize);
-    wave_sync();
-    uint32_t nnew = 0, nupd = 0;
     // slot of allocation k of this block (k counted from 0)
     auto new_slot = [&](uint32_t k) -> uint32_t {
       return k < batch ? sring[k] : seg_slot(head, count, hwm, base + k, v.vring, gbase, gsize);
     };
     // the edge's vertex is no longer used: back to the ring (k-th free of
-    // this block), the edge forgets it
-    auto free_vertex = [&](uint32_t e, int32_t s, uint32_t k) {
+    // this block).  A slot of -1 (the edge's allocation had failed) goes in
+    // as kNone, which whoever takes it reports as a full segment.
+    auto free_vertex = [&](int32_t s, uint32_t k) {
       pool32(v.vring, gbase + ring_pos(rtail, fbase + k, gsize)) = (uint32_t)s;
-      pool32(v.vowner, (uint32_t)s) = kNone;
-      eref_b[e] = 0;
+      if (s >= 0) pool32(v.vowner, (uint32_t)s) = kNone;
     };
-    uint32_t knew = 0, kfree = 0;
+    uint32_t nnew = 0, nmov = 0, knew = 0, kfree = 0;
     for (uint32_t c0 = 0; c0 < nwork; c0 += kWorkCap) {
-      if (c0 > 0) {
-        // the list's next chunk, listed again from the counts
-        wave_sync();
-        uint32_t pos = 0;
-#pragma unroll 2
-        for (int lz = 0; lz < 8; ++lz) {
-          const uint32_t hs = has_slot >> (3 * lz);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const uint32_t ref = (uint32_t)(refs[a] >> (8 * lz)) & 255u, has = (hs >> a) & 1u;
-            const bool w = ref > 0 || has;
-            const uint64_t b = __ballot(w);
-            const uint32_t p = pos + (uint32_t)__popcll(b & below);
-            if (w && p >= c0 && p < c0 + (uint32_t)kWorkCap)
-              swork[p - c0] = (uint32_t)(a * kVox + q + 64 * lz) | (ref << 11) | (has << 19);
-            pos += (uint32_t)__popcll(b);
-          }
+      // the lane's items of this chunk, at its place in the list
+      wave_sync();
+      {
+        uint32_t p = wpos - c0, rem = work;
+        while (rem) {
+          const uint32_t k = (uint32_t)__builtin_ctz(rem);
+          rem &= rem - 1u;
+          if (p < (uint32_t)kWorkCap)
+            swork[p] = (k << 6 | (uint32_t)q) | ((R >> k) & 1u) << 11 | ((has >> k) & 1u) << 12;
+          ++p;
         }
-        wave_sync();
       }
+      wave_sync();
       const uint32_t m = min(nwork - c0, (uint32_t)kWorkCap);
       // the chunk's loads: per item of the lane, the slot of the vertex it
       // frees, or the TSDF at its edge's two end points (the far one in the
@@ -1133,8 +1126,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) voi
         const uint32_t i = (uint32_t)(64 * k + q);
         if (i < m) {
           const uint32_t item = swork[i];
-          const uint32_t e = item & 2047u, ref = (item >> 11) & 255u;
-          if (ref == 0) {
+          const uint32_t e = item & 2047u;
+          if (!((item >> 11) & 1u)) {
             fslot[k] = evtx_b[e];
           } else {
             const uint32_t a = e >> 9, l = e & 511u;
@@ -1157,16 +1150,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) voi
         if (i0 >= m) break;
         const bool act = i0 + q < m;
         const uint32_t item = act ? swork[i0 + q] : 0u;
-        const uint32_t e = item & 2047u, ref = (item >> 11) & 255u, has = item >> 19;
-        const bool is_new = act && ref > 0 && !has, is_free = act && ref == 0;
+        const uint32_t e = item & 2047u;
+        const bool cnt = (item >> 11) & 1u, hv = (item >> 12) & 1u;
+        const bool is_new = act && cnt && !hv, is_free = act && !cnt;
         const uint64_t bn = __ballot(is_new), bf = __ballot(is_free);
-        const uint32_t myk = knew + (uint32_t)__popcll(bn & below);
-        const uint32_t myf = kfree + (uint32_t)__popcll(bf & below);
+        const uint32_t myk = mask_rank(bn, knew), myf = mask_rank(bf, kfree);
         knew += (uint32_t)__popcll(bn);
         kfree += (uint32_t)__popcll(bf);
         if (!act) continue;
-        if (ref > 0) {
-          if (!has) {
+        if (cnt) {
+          if (!hv) {
             const uint32_t ns = new_slot(myk);
             if (ns == kNone) {
               // pool exhausted: the edge stays without a vertex, and its
@@ -1180,20 +1173,22 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) voi
             pool32(v.vbirth, ns) = v.frame;
             ++nnew;
           } else {
-            ++nupd;
+            ++nmov;
           }
           et_b[e] = edge_param(da[k], db[k]);
-          eref_b[e] = (uint8_t)ref;
         } else {
-          free_vertex(e, fslot[k], myf);
+          free_vertex(fslot[k], myf);
         }
       }
     }
+    if (R != has) v.emask[(size_t)idx * 64 + q] = R;
     nnew = wave_sum_bits<5>(nnew);
-    nupd = wave_sum_bits<5>(nupd);
+    nmov = wave_sum_bits<5>(nmov);
+    const uint32_t nupd = wave_sum_bits<5>((uint32_t)__popc(kept));
     if (q == 0) {
       if (nnew) atomicAdd(&v.vseg[sg].st_new, nnew);
       if (nupd) atomicAdd(&v.vseg[sg].st_upd, nupd);
+      if (nmov) atomicAdd(&v.vseg[sg].st_mov, nmov);
       if (tfree) atomicAdd(&v.vseg[sg].st_freed, tfree);
     }
     wave_sync();
@@ -1521,9 +1516,10 @@ __global__ __launch_bounds__(256) void k_dl_births(VolDev v, uint32_t* __restric
 // edge (the voxel is the first end point), then the edge owned by the voxel
 // one step back (the voxel is the second); each contribution is the vertex
 // gradient along the axis times s times dt/dd.  Only edges that carry a
-// vertex contribute, about one in a hundred: the block's 8-bit counts and
-// those of the three back faces are staged in LDS, the (voxel, edge) pairs
-// with a vertex are listed, and slots, end-point TSDF values and upstream
+// vertex contribute, about one in a hundred: which edges hold a vertex
+// comes from the block's edge masks (one word per lane), its neighbours'
+// lanes and the three back faces' words, the (voxel, edge) pairs with a
+// vertex are listed, and slots, end-point TSDF values and upstream
 // gradients are fetched for the listed pairs alone.  The list is worked
 // through layer by layer when it would overflow (dense sign fields).
 constexpr int kGradCap = 384;  // listed pairs per step; one layer has at most 6 * 64
@@ -1532,13 +1528,11 @@ template <int W>
 __global__ __launch_bounds__(64 * W) void k_bwd_tsdf(VolDev v, const float* __restrict__ dL_dv,
                                                      int by_slot, const int32_t* __restrict__ rows,
                                                      uint32_t n_rows, float* __restrict__ out) {
-  __shared__ __align__(4) uint8_t ser_all[W][3 * kVox + 3 * 64];  // own [a][l], back faces [a][64]
   __shared__ uint16_t slist_all[W][kGradCap];  // lane | lz << 6 | k << 9 (k = 2a + back)
   __shared__ float sc_all[W][kGradCap];        // contribution of each listed pair
   __shared__ uint8_t sf_all[W][kGradCap];      // whether it contributes
   __shared__ int32_t snb_all[W][27];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint8_t* ser = ser_all[wave];
   uint16_t* slist = slist_all[wave];
   float* sc = sc_all[wave];
   uint8_t* sf = sf_all[wave];
@@ -1556,40 +1550,31 @@ __global__ __launch_bounds__(64 * W) void k_bwd_tsdf(VolDev v, const float* __re
       for (int lz = 0; lz < 8; ++lz) o[q + 64 * lz] = 0.f;
       continue;
     }
-    // the block's counts (3 x 512 bytes, six words per lane) and its
-    // neighbours; then the back faces: the -a neighbour's counts at
-    // coordinate 7 along a, indexed by the two other coordinates
+    // the block's edge masks (lane q: the edges of its column, bit 8a +
+    // lz) and its neighbours; an edge ending at a voxel from behind is
+    // owned by the voxel one step back: the lane at x - 1 (y - 1) of this
+    // block or, on the block's back face, the -x (-y) neighbour's lane at
+    // x = 7 (y = 7); along z, the layer below or the -z neighbour's top
     const int32_t mynb = q < 27 ? v.nbr[(size_t)idx * 27 + q] : -1;
-    const uint32_t* er32 = reinterpret_cast<const uint32_t*>(v.eref + (size_t)idx * 3 * kVox);
-    uint32_t ownw[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) ownw[j] = er32[q + 64 * j];
+    const uint32_t hm = v.emask[(size_t)idx * 64 + q];
     if (q < 27) snb[q] = mynb;
     wave_sync();
     const int32_t bnx = snb[nbr_dir(-1, 0, 0)], bny = snb[nbr_dir(0, -1, 0)],
                   bnz = snb[nbr_dir(0, 0, -1)];
-    const uint8_t fx = bnx >= 0 ? v.eref[((size_t)bnx * 3 + 0) * kVox + 7 + 8 * lx + 64 * ly] : 0;
-    const uint8_t fy = bny >= 0 ? v.eref[((size_t)bny * 3 + 1) * kVox + lx + 56 + 64 * ly] : 0;
-    const uint8_t fz = bnz >= 0 ? v.eref[((size_t)bnz * 3 + 2) * kVox + 448 + q] : 0;
-    uint32_t* ser32 = reinterpret_cast<uint32_t*>(ser);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) ser32[q + 64 * j] = ownw[j];
-    ser[3 * kVox + q] = fx;
-    ser[3 * kVox + 64 + q] = fy;
-    ser[3 * kVox + 128 + q] = fz;
-    wave_sync();
+    const uint32_t fx = bnx >= 0 ? v.emask[(size_t)bnx * 64 + (q | 7)] : 0u;
+    const uint32_t fy = bny >= 0 ? v.emask[(size_t)bny * 64 + (q | 56)] : 0u;
+    const uint32_t fz = bnz >= 0 ? v.emask[(size_t)bnz * 64 + q] : 0u;
+    const uint32_t hx = __shfl(hm, (q - 1) & 63), hy = __shfl(hm, (q - 8) & 63);
+    const uint32_t bxm = lx > 0 ? hx : fx, bym = ly > 0 ? hy : fy;
     // which incident edges of the lane's eight voxels carry a vertex
     uint64_t act = 0;  // bit 6 * lz + k
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
-      const int l = q + 64 * lz;
-      const uint32_t r0 = ser[l], r1 = ser[kVox + l], r2 = ser[2 * kVox + l];
-      const uint32_t b0 = lx > 0 ? ser[l - 1] : ser[3 * kVox + ly + 8 * lz];
-      const uint32_t b1 = ly > 0 ? ser[kVox + l - 8] : ser[3 * kVox + 64 + lx + 8 * lz];
-      const uint32_t b2 = lz > 0 ? ser[2 * kVox + l - 64] : ser[3 * kVox + 128 + q];
-      const uint64_t m = (uint64_t)(r0 != 0) | (uint64_t)(b0 != 0) << 1 | (uint64_t)(r1 != 0) << 2 |
-                         (uint64_t)(b1 != 0) << 3 | (uint64_t)(r2 != 0) << 4 |
-                         (uint64_t)(b2 != 0) << 5;
+      const uint32_t b2 = lz > 0 ? (hm >> (15 + lz)) & 1u : (fz >> 23) & 1u;
+      const uint64_t m = (uint64_t)((hm >> lz) & 1u) | (uint64_t)((bxm >> lz) & 1u) << 1 |
+                         (uint64_t)((hm >> (8 + lz)) & 1u) << 2 |
+                         (uint64_t)((bym >> (8 + lz)) & 1u) << 3 |
+                         (uint64_t)((hm >> (16 + lz)) & 1u) << 4 | (uint64_t)b2 << 5;
       act |= m << (6 * lz);
     }
     if (__ballot(act != 0ull) == 0ull) {
@@ -1731,16 +1716,41 @@ __global__ void k_zero_f32(float* p, uint64_t n) {
 // ============================================================================
 // inspection
 // ============================================================================
+// Reference count of edge (axis a, voxel l) of block blk, formed from the
+// applied types of the four cubes around it (in this block or its -x/-y/-z
+// neighbours; a missing block's cubes have no type).
+__device__ inline int32_t edge_count(const VolDev& v, uint32_t blk, int a, int l) {
+  // per axis, the four cubes as offsets from the voxel and the cube edge
+  // that is this edge in each: x (0,0,0) e0, (0,-1,0) e2, (0,0,-1) e4,
+  // (0,-1,-1) e6; y (0,0,0) e3, (-1,0,0) e1, (0,0,-1) e7, (-1,0,-1) e5;
+  // z (0,0,0) e8, (-1,0,0) e9, (-1,-1,0) e10, (0,-1,0) e11
+  const int8_t off[3][4][4] = {{{0, 0, 0, 0}, {0, -1, 0, 2}, {0, 0, -1, 4}, {0, -1, -1, 6}},
+                               {{0, 0, 0, 3}, {-1, 0, 0, 1}, {0, 0, -1, 7}, {-1, 0, -1, 5}},
+                               {{0, 0, 0, 8}, {-1, 0, 0, 9}, {-1, -1, 0, 10}, {0, -1, 0, 11}}};
+  const int x = l & 7, y = (l >> 3) & 7, z = l >> 6;
+  int32_t c = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int cx = x + off[a][j][0], cy = y + off[a][j][1], cz = z + off[a][j][2];
+    const int32_t b = v.nbr[(size_t)blk * 27 + nbr_dir(cx < 0 ? -1 : 0, cy < 0 ? -1 : 0, cz < 0 ? -1 : 0)];
+    if (b < 0) continue;
+    const uint32_t t = v.tcur[(size_t)b * kVox + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7)];
+    c += v.edge_uses[t * 12 + off[a][j][3]];
+  }
+  return c;
+}
+
 __global__ void k_export_vertices(VolDev v, uint64_t* keys, float* t, int32_t* ref, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t owner = slot_in_use(v.vseg, v.vseg_cap, i) ? v.vowner[i] : kNone;
     uint64_t k = ~0ull;
+    int32_t r = -1;
     if (owner != kNone) {
       const uint32_t blk = owner / (3 * kVox), rem = owner % (3 * kVox);
       k = edge_key(v.block_key[blk], (int)(rem % kVox), (int)(rem / kVox));
+      r = edge_count(v, blk, (int)(rem / kVox), (int)(rem % kVox));
     }
     keys[i] = k;
-    ref[i] = owner != kNone ? (int32_t)v.eref[owner] : -1;
+    ref[i] = r;
     t[i] = owner != kNone ? v.et[owner] : 0.f;
   }
 }
@@ -1756,9 +1766,9 @@ __global__ void k_lookup(VolDev v, const int32_t* __restrict__ coords, int32_t* 
 template __global__ void k_classify<2>(VolDev, uint32_t, int);
 template __global__ void k_classify<4>(VolDev, uint32_t, int);
 template __global__ void k_classify<8>(VolDev, uint32_t, int);
-template __global__ void k_vertices<2>(VolDev);
-template __global__ void k_vertices<4>(VolDev);
-template __global__ void k_vertices<8>(VolDev);
+template __global__ void k_vertices<2>(VolDev, uint32_t);
+template __global__ void k_vertices<4>(VolDev, uint32_t);
+template __global__ void k_vertices<8>(VolDev, uint32_t);
 template __global__ void k_fuse<2>(VolDev, FrameParams, const float*);
 template __global__ void k_fuse<4>(VolDev, FrameParams, const float*);
 template __global__ void k_fuse<8>(VolDev, FrameParams, const float*);

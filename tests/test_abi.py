@@ -110,12 +110,13 @@ def volume_bytes(c):
 def test_volume_bytes_grows_with_every_capacity():
     r, base = volume_bytes(cfg())
     assert r == binding.VM_OK and base > 0
-    # per block: TSDF + weight + two types per voxel, vertex slot, t and
-    # count of its three edges, masks, lists and stamps; no triangle storage
-    # (the header's figure of about 18.9 KiB)
+    # per block: TSDF + weight + two types per voxel, vertex slot and t of
+    # its three edges, the edge-vertex bits (32 per column), masks, lists and
+    # stamps; no counts, no triangle storage (the header's figure of about
+    # 17.6 KiB)
     r, more = volume_bytes(cfg(max_blocks=8192))
     per_block = (more - base) / 4096
-    assert r == 0 and 512 * (4 + 4 + 1 + 1 + 3 * (4 + 4 + 1)) <= per_block < 19 * 1024
+    assert r == 0 and 512 * (4 + 4 + 1 + 1 + 3 * (4 + 4)) + 64 * 4 <= per_block < 18 * 1024
     r, more = volume_bytes(cfg(max_vertices=1 << 19))
     assert r == 0 and 16 * (1 << 18) <= more - base < 17 * (1 << 18)
     r, more = volume_bytes(cfg(hash_log2=17))
