@@ -524,8 +524,9 @@ int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* 
   fp.frame = ++vol->frame;
   vol->dl_nv = -1;
   const VolDev& v = vol->dev;
-  const int npix = K->width * K->height;
-  VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3((npix + 1023) / 1024), dim3(1024), stream, v, fp, depth,
+  // one workgroup per 32 x 16 pixel tile
+  const unsigned tiles = (unsigned)((K->width + 31) / 32) * (unsigned)((K->height + 15) / 16);
+  VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3(tiles), dim3(512), stream, v, fp, depth,
             vol->epoch);
   VM_LAUNCH_W(vol, VM_K_FUSE, k_fuse, stream, v, fp, depth);
   vol->last_fp = fp;

@@ -93,17 +93,23 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
 // block collection (Eq. 1)
 // ============================================================================
 
-// One lane per pixel.  Each valid pixel spans the integer box of blocks
-// between its ray points at camera depth D - mu and D + mu.  Per box cell,
-// the lanes of a wave first agree on the distinct keys (ballot/shuffle),
-// then the lanes holding distinct keys insert them into the hash and claim
-// the slot for this frame (exchange of the slot's frame stamp): the one
-// claim that wins lists the block.  The workgroup gathers its claims in LDS
-// and appends them with one atomic per list: the frame list, the pending
-// list (blocks touched since the last extraction) and, for blocks new to
-// the hash, pool indices, given here with their neighbour tables cleared.
-constexpr int kClaimCap = 1024;  // claims per workgroup gathered in LDS
-constexpr int kWaveKeys = 128;   // distinct keys a wave gathers before claiming them
+// One lane per pixel, one wave per 8 x 8 tile of pixels, a workgroup per
+// 32 x 16 tile.  Each valid pixel spans the integer box of blocks between
+// its ray points at camera depth D - mu and D + mu.  Neighbouring pixels
+// span nearly the same blocks, so the wave first forms the union of its
+// pixels' boxes as a bit mask over a 4 x 4 x 4 window of blocks placed at
+// one pixel's box (an OR over the wave), and its lanes then take the
+// distinct blocks one each; a pixel whose box leaves the window (a depth
+// edge inside the tile) has its blocks agreed on by a slower ballot loop.
+// The lanes holding distinct blocks insert them into the hash and claim the
+// slot for this frame (exchange of the slot's frame stamp): the one claim
+// that wins lists the block.  The workgroup gathers its claims in LDS and
+// appends them with one atomic per list: the frame list, the pending list
+// (blocks touched since the last extraction) and, for blocks new to the
+// hash, pool indices, given here with their neighbour tables cleared.
+constexpr int kTileW = 32, kTileH = 16;  // pixels per workgroup (8 waves of 8 x 8)
+constexpr int kClaimCap = 512;   // claims per workgroup gathered in LDS
+constexpr int kWaveKeys = 128;   // keys a wave gathers in its slow loop before claiming them
 
 // List a claimed block: frame list entry, pending list entry (once per
 // extraction epoch) and, for a block new to the hash, its pool index (slot
@@ -137,17 +143,19 @@ __device__ inline void list_claim(const VolDev& v, uint32_t s, unsigned long lon
   }
 }
 
-__global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
-                                                 const float* __restrict__ depth, uint32_t epoch) {
+__global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
+                                                const float* __restrict__ depth, uint32_t epoch) {
   __shared__ unsigned long long sseen[kClaimCap];  // slot contents seen by the claim
-  __shared__ uint32_t sslot[kClaimCap];
-  __shared__ unsigned long long skeys_all[16][kWaveKeys];  // each wave's gathered keys
+  __shared__ uint32_t sslot[kClaimCap];            // slot | pending << 31
+  __shared__ unsigned long long skeys_all[8][kWaveKeys];  // each wave's slow-loop keys
   __shared__ uint32_t nclaim;
-  __shared__ uint32_t swave[16];
+  __shared__ uint32_t swave[8];
   __shared__ uint32_t sbase[3];
-  const int npix = fp.W * fp.H;
-  const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pix == 0) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), q = __lane_id();
+  const int tiles_x = (fp.W + kTileW - 1) / kTileW;
+  const int px = (int)(blockIdx.x % tiles_x) * kTileW + (wave & 3) * 8 + (q & 7);
+  const int py = (int)(blockIdx.x / tiles_x) * kTileH + (wave >> 2) * 8 + (q >> 3);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     // the other parity's list is the next frame's
     v.cnt->n_frame[(fp.frame + 1) & 1] = 0;
     v.cnt->acc[VM_TOTAL_FRAMES] += 1;
@@ -156,9 +164,8 @@ __global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
   __syncthreads();
   int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
   int nbox = 0;
-  if (pix < npix) {
-    const int px = pix % fp.W, py = pix / fp.W;
-    const float D = depth[pix];
+  if (px < fp.W && py < fp.H) {
+    const float D = depth[py * fp.W + px];
     if (depth_ok(D, fp.dmin, fp.dmax)) {
       const float xn = ((float)px - fp.cx) / fp.fx;
       const float yn = ((float)py - fp.cy) / fp.fy;
@@ -190,103 +197,162 @@ __global__ __launch_bounds__(1024) void k_collect(VolDev v, FrameParams fp,
       }
     }
   }
-  // The wave first gathers the distinct keys of its pixels' boxes in LDS
-  // (duplicates between box positions j are left to the claim below), then
-  // its lanes insert and claim them together: the hash probes and claims of
-  // all positions overlap instead of following one another.
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  unsigned long long* skeys = skeys_all[wave];
-  uint32_t nkeys = 0;
-  auto claim_keys = [&]() {
-    wave_sync();
-    for (uint32_t i0 = 0; i0 < nkeys; i0 += 64) {
-      const uint32_t i = i0 + __lane_id();
-      if (i >= nkeys) continue;
-      const uint64_t key = skeys[i];
-      unsigned long long seen = 0;
-      const int64_t s = hash_insert_seen(v, key, &seen);
-      if (s < 0) {
-        atomicOr(&v.cnt->error, kErrHash);
-        continue;
-      }
-      // one claim per block and frame wins
-      if (v.slot_stamp[s] == fp.frame || atomicExch(&v.slot_stamp[s], fp.frame) == fp.frame)
-        continue;
-      const uint32_t c = atomicAdd(&nclaim, 1u);
-      if (c < kClaimCap) {
-        sslot[c] = (uint32_t)s;
-        sseen[c] = seen;
-      } else {
-        // more claims than the workgroup gathers: list this one alone
-        const bool isnew = (uint32_t)(seen & kIdxMask) == kPending;
-        const bool pend = isnew || v.st_pending[(uint32_t)(seen & kIdxMask)] != epoch;
-        list_claim(v, (uint32_t)s, seen, pend, atomicAdd(&v.cnt->n_frame[fp.frame & 1], 1u),
-                   pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], 1u) : 0u,
-                   isnew ? atomicAdd(&v.cnt->n_blocks, 1u) : 0u, epoch);
-      }
-    }
-    nkeys = 0;
-    wave_sync();
-  };
-  // the box's blocks in x-fastest order, stepped with carries (no division)
-  int cx = 0, cy = 0, cz = 0;
-  const uint64_t below = lanes_below();
-  for (int j = 0; __ballot(j < nbox); ++j) {
-    bool has = j < nbox;
-    uint64_t key = 0;
-    if (has) {
-      key = pack_key(lo[0] + cx, lo[1] + cy, lo[2] + cz);
-      if (++cx == ext[0]) {
-        cx = 0;
-        if (++cy == ext[1]) cy = 0, ++cz;
-      }
-    }
-    bool mine = false;  // this lane holds the first copy of its key
-    uint64_t todo = __ballot(has);
-    while (todo) {
-      // the leader is wave-uniform: its key is read lane to scalar
-      const int leader = __builtin_ctzll(todo);
-      const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, leader);
-      const uint32_t khi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), leader);
-      const uint64_t lk = ((uint64_t)khi << 32) | klo;
-      const bool same = has && key == lk;
-      todo &= ~__ballot(same);
-      if ((int)__lane_id() == leader) mine = true;
-      if (same) has = false;
-    }
-    const uint64_t bm = __ballot(mine);
-    const uint32_t nm = (uint32_t)__popcll(bm);
-    if (nkeys + nm > (uint32_t)kWaveKeys) claim_keys();
-    if (mine) skeys[nkeys + (uint32_t)__popcll(bm & below)] = key;
-    nkeys += nm;
-  }
-  claim_keys();
-  __syncthreads();
-  const uint32_t nc = min(nclaim, (uint32_t)kClaimCap);
-  for (uint32_t c0 = 0; c0 < nc; c0 += blockDim.x) {
-    const uint32_t c = c0 + threadIdx.x;
+  // Claim one key per lane (has: the lane holds one): insert it, take the
+  // slot's frame stamp, and gather the winners in the workgroup's list with
+  // whether each must join the pending list.
+  auto claim = [&](bool has, uint64_t key) {
     unsigned long long seen = 0;
-    bool isnew = false, pend = false;
-    if (c < nc) {
-      seen = sseen[c];
-      isnew = (uint32_t)(seen & kIdxMask) == kPending;
-      pend = isnew || v.st_pending[(uint32_t)(seen & kIdxMask)] != epoch;
+    int64_t s = -1;
+    if (has) {
+      s = hash_insert_seen(v, key, &seen);
+      if (s < 0) atomicOr(&v.cnt->error, kErrHash);
     }
-    uint32_t t_hit, t_new, t_pend;
-    const uint32_t r_hit = wg_scan_bits<1>(c < nc ? 1u : 0u, swave, &t_hit);
-    const uint32_t r_new = wg_scan_bits<1>(isnew ? 1u : 0u, swave, &t_new);
-    const uint32_t r_pend = wg_scan_bits<1>(pend ? 1u : 0u, swave, &t_pend);
-    if (threadIdx.x == 0) {
-      sbase[0] = atomicAdd(&v.cnt->n_frame[fp.frame & 1], t_hit);
-      sbase[1] = t_new ? atomicAdd(&v.cnt->n_blocks, t_new) : 0u;
-      sbase[2] = t_pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], t_pend) : 0u;
+    // one claim per block and frame wins
+    const bool won = s >= 0 && v.slot_stamp[s] != fp.frame &&
+                     atomicExch(&v.slot_stamp[s], fp.frame) != fp.frame;
+    bool pend = false;
+    if (won) {
+      const uint32_t idx = (uint32_t)(seen & kIdxMask);
+      pend = idx == kPending || v.st_pending[idx] != epoch;
     }
-    __syncthreads();
-    if (c < nc)
-      list_claim(v, sslot[c], seen, pend, sbase[0] + r_hit, sbase[2] + r_pend, sbase[1] + r_new,
-                 epoch);
-    __syncthreads();
+    const uint64_t bw = __ballot(won);
+    if (bw == 0ull) return;
+    uint32_t c0 = 0;
+    if (q == 0) c0 = atomicAdd(&nclaim, (uint32_t)__popcll(bw));
+    const uint32_t c = uniform(c0) + mask_rank(bw);
+    if (!won) return;
+    if (c < (uint32_t)kClaimCap) {
+      sslot[c] = (uint32_t)s | (pend ? 0x80000000u : 0u);
+      sseen[c] = seen;
+    } else {
+      // more claims than the workgroup gathers: list this one alone
+      const bool isnew = (uint32_t)(seen & kIdxMask) == kPending;
+      list_claim(v, (uint32_t)s, seen, pend, atomicAdd(&v.cnt->n_frame[fp.frame & 1], 1u),
+                 pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], 1u) : 0u,
+                 isnew ? atomicAdd(&v.cnt->n_blocks, 1u) : 0u, epoch);
+    }
+  };
+  // the union of the boxes that fit the window, over the wave
+  const uint64_t act = __ballot(nbox > 0);
+  bool fits = true;
+  if (act) {
+    const int lead = __builtin_ctzll(act);
+    const int w0 = __builtin_amdgcn_readlane(lo[0], lead) - 1;
+    const int w1 = __builtin_amdgcn_readlane(lo[1], lead) - 1;
+    const int w2 = __builtin_amdgcn_readlane(lo[2], lead) - 1;
+    const int ox = lo[0] - w0, oy = lo[1] - w1, oz = lo[2] - w2;
+    uint64_t m = 0;
+    if (nbox > 0) {
+      fits = ox >= 0 && oy >= 0 && oz >= 0 && ox + ext[0] <= 4 && oy + ext[1] <= 4 &&
+             oz + ext[2] <= 4;
+      if (fits) {
+        // the box's rows along x as runs of bits
+        const uint64_t row = ((1ull << ext[0]) - 1ull) << ox;
+        for (int z = 0; z < ext[2]; ++z)
+          for (int y = 0; y < ext[1]; ++y) m |= row << (4 * (oy + y) + 16 * (oz + z));
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) m |= shfl64(m, q ^ off);
+    // lane k takes the union's k-th block
+    const uint64_t u = ((uint64_t)uniform((uint32_t)(m >> 32)) << 32) | uniform((uint32_t)m);
+    uint64_t rest = u;
+    int cell = -1;
+    for (int k = 0; rest != 0ull; ++k) {
+      const int c = __builtin_ctzll(rest);
+      rest &= rest - 1ull;
+      if (q == k) cell = c;
+    }
+    claim(cell >= 0, cell >= 0 ? pack_key(w0 + (cell & 3), w1 + ((cell >> 2) & 3), w2 + (cell >> 4))
+                               : 0ull);
   }
+  // boxes that leave the window: the wave agrees on their distinct keys per
+  // box position (duplicates between positions are left to the claim) and
+  // claims them kWaveKeys at a time
+  if (__ballot(!fits) != 0ull) {
+    unsigned long long* skeys = skeys_all[wave];
+    uint32_t nkeys = 0;
+    auto claim_keys = [&]() {
+      wave_sync();
+      for (uint32_t i0 = 0; i0 < nkeys; i0 += 64) {
+        const uint32_t i = i0 + (uint32_t)q;
+        claim(i < nkeys, i < nkeys ? skeys[i] : 0ull);
+      }
+      nkeys = 0;
+      wave_sync();
+    };
+    const int nslow = fits ? 0 : nbox;
+    int cx = 0, cy = 0, cz = 0;
+    const uint64_t below = lanes_below();
+    for (int j = 0; __ballot(j < nslow); ++j) {
+      bool has = j < nslow;
+      uint64_t key = 0;
+      if (has) {
+        key = pack_key(lo[0] + cx, lo[1] + cy, lo[2] + cz);
+        if (++cx == ext[0]) {
+          cx = 0;
+          if (++cy == ext[1]) cy = 0, ++cz;
+        }
+      }
+      bool mine = false;  // this lane holds the first copy of its key
+      uint64_t todo = __ballot(has);
+      while (todo) {
+        // the leader is wave-uniform: its key is read lane to scalar
+        const int leader = __builtin_ctzll(todo);
+        const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, leader);
+        const uint32_t khi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), leader);
+        const uint64_t lk = ((uint64_t)khi << 32) | klo;
+        const bool same = has && key == lk;
+        todo &= ~__ballot(same);
+        if (q == leader) mine = true;
+        if (same) has = false;
+      }
+      const uint64_t bm = __ballot(mine);
+      const uint32_t nm = (uint32_t)__popcll(bm);
+      if (nkeys + nm > (uint32_t)kWaveKeys) claim_keys();
+      if (mine) skeys[nkeys + (uint32_t)__popcll(bm & below)] = key;
+      nkeys += nm;
+    }
+    claim_keys();
+  }
+  __syncthreads();
+  // one claim per thread: the three lists' positions from one workgroup
+  // scan of packed counts (fields of 10 bits, at most 512 each)
+  const uint32_t nc = min(nclaim, (uint32_t)kClaimCap);
+  const uint32_t c = threadIdx.x;
+  const bool hit = c < nc;
+  unsigned long long seen = 0;
+  uint32_t slot = 0;
+  bool isnew = false, pend = false;
+  if (hit) {
+    seen = sseen[c];
+    slot = sslot[c];
+    pend = (slot >> 31) != 0u;
+    slot &= 0x7FFFFFFFu;
+    isnew = (uint32_t)(seen & kIdxMask) == kPending;
+  }
+  const uint64_t bh = __ballot(hit), bn = __ballot(isnew), bp = __ballot(pend);
+  if (q == 0)
+    swave[wave] = (uint32_t)__popcll(bh) | (uint32_t)__popcll(bn) << 10 |
+                  (uint32_t)__popcll(bp) << 20;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  const int nwave = (int)(blockDim.x >> 6);
+  for (int w = 0; w < nwave; ++w) {
+    const uint32_t cw = swave[w];
+    if (w < wave) before += cw;
+    all += cw;
+  }
+  if (threadIdx.x == 0 && (all & 1023u)) {
+    sbase[0] = atomicAdd(&v.cnt->n_frame[fp.frame & 1], all & 1023u);
+    sbase[1] = (all >> 10) & 1023u ? atomicAdd(&v.cnt->n_blocks, (all >> 10) & 1023u) : 0u;
+    sbase[2] = all >> 20 ? atomicAdd(&v.cnt->n_pending[epoch & 1], all >> 20) : 0u;
+  }
+  __syncthreads();
+  if (hit)
+    list_claim(v, slot, seen, pend, sbase[0] + (before & 1023u) + mask_rank(bh),
+               sbase[2] + (before >> 20) + mask_rank(bp),
+               sbase[1] + ((before >> 10) & 1023u) + mask_rank(bn), epoch);
 }
 
 __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
