@@ -528,7 +528,7 @@ int vm_integrate_depth(vm_volume* vol, const float* depth, const vm_intrinsics* 
   const unsigned tiles = (unsigned)((K->width + 31) / 32) * (unsigned)((K->height + 15) / 16);
   VM_LAUNCH(vol, VM_K_COLLECT, k_collect, dim3(tiles), dim3(512), stream, v, fp, depth,
             vol->epoch);
-  VM_LAUNCH_W(vol, VM_K_FUSE, k_fuse, stream, v, fp, depth);
+  VM_LAUNCH_W(vol, VM_K_FUSE, k_fuse, stream, v, fp, depth, vol->epoch);
   vol->last_fp = fp;
   vol->have_fp = true;
   return launched();

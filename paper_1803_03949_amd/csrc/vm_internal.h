@@ -107,12 +107,29 @@ struct Counters {
   // segment totals when the last extract / refine started
   uint32_t base_new, base_upd, base_freed, base_chg, base_ref;
   uint32_t import_base;    // blocks in the pool before the last import
-  uint32_t pad[13];
+  uint32_t pad0;
+  // collection's appends, by frame parity, packed so that a workgroup
+  // reserves its places in all three lists with one atomic (fields below);
+  // the fusion that follows folds them into n_frame, n_pending, n_blocks
+  unsigned long long collect_acc[2];
+  uint32_t pad[8];
   // running totals since the volume was created (not cleared by a reset)
   unsigned long long acc[12];
   unsigned long long pad2[4];
 };
 static_assert(sizeof(Counters) == 256, "counter record size");
+static_assert(offsetof(Counters, collect_acc) < offsetof(Counters, acc), "cleared by a reset");
+
+// Fields of a collection append: frame-list entries (bits 0..20),
+// pending-list entries (21..41), new blocks (42..63).  A frame's counts
+// stay below 2^21 while it has fewer claims than that; a larger frame
+// exceeds the block capacity (at most 2^21) first, and that is reported.
+__host__ __device__ inline uint64_t collect_pack(uint32_t frame, uint32_t pend, uint32_t fresh) {
+  return (uint64_t)frame | (uint64_t)pend << 21 | (uint64_t)fresh << 42;
+}
+__host__ __device__ inline uint32_t collect_frame(uint64_t p) { return (uint32_t)(p & 0x1FFFFFu); }
+__host__ __device__ inline uint32_t collect_pend(uint64_t p) { return (uint32_t)((p >> 21) & 0x1FFFFFu); }
+__host__ __device__ inline uint32_t collect_new(uint64_t p) { return (uint32_t)(p >> 42); }
 
 // Everything a kernel needs, passed by value.
 struct VolDev {
@@ -575,7 +592,7 @@ __global__ void k_import_scan(VolDev v, uint32_t nparts, uint32_t frame, uint32_
 __global__ void k_import_assign(VolDev v, uint32_t n, uint32_t nparts, uint32_t epoch);
 constexpr int kImportRows = 256;  // import rows per workgroup of the row-order compaction
 template <int W>
-__global__ void k_fuse(VolDev v, FrameParams fp, const float* __restrict__ depth);
+__global__ void k_fuse(VolDev v, FrameParams fp, const float* __restrict__ depth, uint32_t epoch);
 template <int W>
 __global__ void k_import_copy(VolDev v, const float* __restrict__ tsdf,
                               const float* __restrict__ weight, uint32_t frame,

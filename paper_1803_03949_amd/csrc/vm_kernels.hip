@@ -106,7 +106,9 @@ __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
 // that wins lists the block.  The workgroup gathers its claims in LDS and
 // appends them with one atomic per list: the frame list, the pending list
 // (blocks touched since the last extraction) and, for blocks new to the
-// hash, pool indices, given here with their neighbour tables cleared.
+// hash, pool indices, given here with their neighbour tables cleared.  The
+// three appends are one packed 64-bit atomic (one per workgroup): atomics
+// on one address from every workgroup are what limits this kernel.
 constexpr int kTileW = 32, kTileH = 16;  // pixels per workgroup (8 waves of 8 x 8)
 constexpr int kClaimCap = 512;   // claims per workgroup gathered in LDS
 constexpr int kWaveKeys = 128;   // keys a wave gathers in its slow loop before claiming them
@@ -156,10 +158,16 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
   const int px = (int)(blockIdx.x % tiles_x) * kTileW + (wave & 3) * 8 + (q & 7);
   const int py = (int)(blockIdx.x / tiles_x) * kTileH + (wave >> 2) * 8 + (q >> 3);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    // the other parity's list is the next frame's
+    // the other parity's list and appends are the next frame's
     v.cnt->n_frame[(fp.frame + 1) & 1] = 0;
+    v.cnt->collect_acc[(fp.frame + 1) & 1] = 0;
     v.cnt->acc[VM_TOTAL_FRAMES] += 1;
   }
+  // the lists this frame appends to: the frame list starts empty, the
+  // pending list and the pool continue from where they stand (nothing else
+  // changes them during this kernel)
+  unsigned long long* acc = &v.cnt->collect_acc[fp.frame & 1];
+  const uint32_t pend_base = v.cnt->n_pending[epoch & 1], blk_base = v.cnt->n_blocks;
   if (threadIdx.x == 0) nclaim = 0;
   __syncthreads();
   int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
@@ -227,9 +235,9 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
     } else {
       // more claims than the workgroup gathers: list this one alone
       const bool isnew = (uint32_t)(seen & kIdxMask) == kPending;
-      list_claim(v, (uint32_t)s, seen, pend, atomicAdd(&v.cnt->n_frame[fp.frame & 1], 1u),
-                 pend ? atomicAdd(&v.cnt->n_pending[epoch & 1], 1u) : 0u,
-                 isnew ? atomicAdd(&v.cnt->n_blocks, 1u) : 0u, epoch);
+      const uint64_t p = atomicAdd(acc, (unsigned long long)collect_pack(1u, pend, isnew));
+      list_claim(v, (uint32_t)s, seen, pend, collect_frame(p), pend_base + collect_pend(p),
+                 blk_base + collect_new(p), epoch);
     }
   };
   // the union of the boxes that fit the window, over the wave
@@ -344,9 +352,11 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
     all += cw;
   }
   if (threadIdx.x == 0 && (all & 1023u)) {
-    sbase[0] = atomicAdd(&v.cnt->n_frame[fp.frame & 1], all & 1023u);
-    sbase[1] = (all >> 10) & 1023u ? atomicAdd(&v.cnt->n_blocks, (all >> 10) & 1023u) : 0u;
-    sbase[2] = all >> 20 ? atomicAdd(&v.cnt->n_pending[epoch & 1], all >> 20) : 0u;
+    const uint64_t p = atomicAdd(
+        acc, (unsigned long long)collect_pack(all & 1023u, all >> 20, (all >> 10) & 1023u));
+    sbase[0] = collect_frame(p);
+    sbase[1] = blk_base + collect_new(p);
+    sbase[2] = pend_base + collect_pend(p);
   }
   __syncthreads();
   if (hit)
@@ -360,9 +370,12 @@ __global__ void k_import_insert(VolDev v, const int32_t* __restrict__ slots,
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     // this import's list starts empty, and so does the next frame's: an
-    // integration appends to its own parity's list without clearing it
+    // integration appends to its own parity's list (and packed appends)
+    // without clearing them
     v.cnt->n_frame[frame & 1] = 0;
     v.cnt->n_frame[(frame + 1) & 1] = 0;
+    v.cnt->collect_acc[0] = 0;
+    v.cnt->collect_acc[1] = 0;
     v.cnt->acc[VM_TOTAL_FRAMES] += 1;
   }
   if (i >= n) return;
@@ -530,10 +543,18 @@ __device__ inline void init_column(const VolDev& v, uint32_t idx, int q) {
 // ahead, so a block waits only for its TSDF, weights and depth samples.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
-                                                 const float* __restrict__ depth) {
-  const uint32_t n = min(v.cnt->n_frame[fp.frame & 1], v.max_blocks);
+                                                 const float* __restrict__ depth, uint32_t epoch) {
+  // the collection's appends: its frame list length, and (one thread) the
+  // lengths the later kernels read
+  const uint64_t app = v.cnt->collect_acc[fp.frame & 1];
+  const uint32_t n = min(collect_frame(app), v.max_blocks);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
+    v.cnt->n_frame[fp.frame & 1] = collect_frame(app);
+    v.cnt->n_pending[epoch & 1] += collect_pend(app);
+    v.cnt->n_blocks += collect_new(app);
+  }
   ItemLoop it = item_loop(v, n, W, wave);
   auto entry = [&](uint32_t i) -> uint32_t { return i < it.end ? v.frame_list[i] : kNone; };
   auto key_of = [&](uint32_t e) -> uint64_t {
@@ -1835,9 +1856,9 @@ template __global__ void k_classify<8>(VolDev, uint32_t, int);
 template __global__ void k_vertices<2>(VolDev, uint32_t);
 template __global__ void k_vertices<4>(VolDev, uint32_t);
 template __global__ void k_vertices<8>(VolDev, uint32_t);
-template __global__ void k_fuse<2>(VolDev, FrameParams, const float*);
-template __global__ void k_fuse<4>(VolDev, FrameParams, const float*);
-template __global__ void k_fuse<8>(VolDev, FrameParams, const float*);
+template __global__ void k_fuse<2>(VolDev, FrameParams, const float*, uint32_t);
+template __global__ void k_fuse<4>(VolDev, FrameParams, const float*, uint32_t);
+template __global__ void k_fuse<8>(VolDev, FrameParams, const float*, uint32_t);
 template __global__ void k_import_copy<2>(VolDev, const float*, const float*, uint32_t, int32_t*);
 template __global__ void k_import_copy<4>(VolDev, const float*, const float*, uint32_t, int32_t*);
 template __global__ void k_import_copy<8>(VolDev, const float*, const float*, uint32_t, int32_t*);
