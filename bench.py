@@ -242,10 +242,40 @@ def room_fusion(args, dev):
     fps_noev = args.frames * args.steps / (time.perf_counter() - t0)
     st = vol.status()
     log(f"{fps:.1f} frames/s ({fps_noev:.1f} without events), blocks {st['blocks']}")
+
+    # the same step captured once as a HIP graph (poses and frame numbers
+    # baked into its launches) and replayed: what launching costs per frame
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph.replay()
+    torch.cuda.synchronize()
+    st_g = vol.status()
+    reps = max(args.steps, 3)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt_g = time.perf_counter() - t0
+    # the pool slots a block's vertices take depend on the order blocks were
+    # numbered in, so compare blocks, triangles and live vertices
+    same = (st_g["blocks"] == st["blocks"] and st_g["triangles"] == st["triangles"] and
+            st_g["vertex_slots"] - st_g["free_vertex_slots"] ==
+            st["vertex_slots"] - st["free_vertex_slots"])
+    graph_fields = {"frames_per_s": args.frames * reps / dt_g,
+                    "us_per_frame": 1e6 * dt_g / (args.frames * reps), "replays": reps,
+                    "same_mesh_counts": same}
+    log(f"graph replay: {graph_fields}")
+    del graph
     for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_total"]):
         log(f"  {k:10s} {e}")
     fields = {"value": fps, "ms_per_step": 1000.0 * dt / args.steps, "roofline": roofline,
-              "frame": frame, "value_without_events": fps_noev, "blocks": st["blocks"],
+              "frame": frame, "value_without_events": fps_noev, "graph_replay": graph_fields,
+              "blocks": st["blocks"],
               "blocks_meshed_per_s": tot["dirty_blocks"] / dt,
               "totals_per_step": {k: v // args.steps for k, v in tot.items()},
               "kernels": kernels}
