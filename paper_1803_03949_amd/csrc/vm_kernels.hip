@@ -168,8 +168,8 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
   // changes them during this kernel)
   unsigned long long* acc = &v.cnt->collect_acc[fp.frame & 1];
   const uint32_t pend_base = v.cnt->n_pending[epoch & 1], blk_base = v.cnt->n_blocks;
+  // cleared here, first used after the barrier below
   if (threadIdx.x == 0) nclaim = 0;
-  __syncthreads();
   int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
   int nbox = 0;
   if (px < fp.W && py < fp.H) {
@@ -215,13 +215,16 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
       s = hash_insert_seen(v, key, &seen);
       if (s < 0) atomicOr(&v.cnt->error, kErrHash);
     }
-    // one claim per block and frame wins
-    const bool won = s >= 0 && v.slot_stamp[s] != fp.frame &&
-                     atomicExch(&v.slot_stamp[s], fp.frame) != fp.frame;
-    bool pend = false;
-    if (won) {
+    // one claim per block and frame wins; the block's pending stamp is
+    // requested with the frame stamp (only the winner of this frame's claim
+    // writes it)
+    bool won = false, pend = false;
+    if (s >= 0) {
       const uint32_t idx = (uint32_t)(seen & kIdxMask);
-      pend = idx == kPending || v.st_pending[idx] != epoch;
+      const uint32_t stamp = v.slot_stamp[s];
+      const uint32_t pst = idx != kPending ? v.st_pending[idx] : 0u;
+      won = stamp != fp.frame && atomicExch(&v.slot_stamp[s], fp.frame) != fp.frame;
+      pend = won && (idx == kPending || pst != epoch);
     }
     const uint64_t bw = __ballot(won);
     if (bw == 0ull) return;
@@ -243,11 +246,12 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
   // the union of the boxes that fit the window, over the wave
   const uint64_t act = __ballot(nbox > 0);
   bool fits = true;
+  int w0 = 0, w1 = 0, w2 = 0, cell = -1;
   if (act) {
     const int lead = __builtin_ctzll(act);
-    const int w0 = __builtin_amdgcn_readlane(lo[0], lead) - 1;
-    const int w1 = __builtin_amdgcn_readlane(lo[1], lead) - 1;
-    const int w2 = __builtin_amdgcn_readlane(lo[2], lead) - 1;
+    w0 = __builtin_amdgcn_readlane(lo[0], lead) - 1;
+    w1 = __builtin_amdgcn_readlane(lo[1], lead) - 1;
+    w2 = __builtin_amdgcn_readlane(lo[2], lead) - 1;
     const int ox = lo[0] - w0, oy = lo[1] - w1, oz = lo[2] - w2;
     uint64_t m = 0;
     if (nbox > 0) {
@@ -265,15 +269,16 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
     // lane k takes the union's k-th block
     const uint64_t u = ((uint64_t)uniform((uint32_t)(m >> 32)) << 32) | uniform((uint32_t)m);
     uint64_t rest = u;
-    int cell = -1;
     for (int k = 0; rest != 0ull; ++k) {
       const int c = __builtin_ctzll(rest);
       rest &= rest - 1ull;
       if (q == k) cell = c;
     }
+  }
+  __syncthreads();  // the claim count is cleared
+  if (act)
     claim(cell >= 0, cell >= 0 ? pack_key(w0 + (cell & 3), w1 + ((cell >> 2) & 3), w2 + (cell >> 4))
                                : 0ull);
-  }
   // boxes that leave the window: the wave agrees on their distinct keys per
   // box position (duplicates between positions are left to the claim) and
   // claims them kWaveKeys at a time
@@ -781,8 +786,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
   __shared__ float sd_all[W][729];     // TSDF (refinement only)
   __shared__ uint8_t sbits_all[W][732]; // bit 0: TSDF < 0, bit 1: observed
   __shared__ int32_t snb_all[W][8];
-  __shared__ uint8_t sntri[256];  // triangles of each cube type
-  for (int j = threadIdx.x; j < 256; j += blockDim.x) sntri[j] = v.tri_table[j * 16];
+  // per cube type: its triangles, and in bit 8 whether it has any
+  __shared__ uint16_t sntri[256];
+  for (int j = threadIdx.x; j < 256; j += blockDim.x) {
+    const uint32_t nt = v.tri_table[j * 16];
+    sntri[j] = (uint16_t)(nt | (nt ? 256u : 0u));
+  }
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* sd = sd_all[wave];
@@ -806,12 +815,18 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
     if (q < 8) snb[q] = mynb;
     wave_sync();
+    // extraction: the corners' signs and observed flags as rows, row (y, z)
+    // of the 9 x 9 x 9 corners holding x = 0..8 in bits 0..8 (TSDF < 0) and
+    // 16..24 (observed); refinement: one byte per corner (bit 0: TSDF < 0,
+    // bit 1: observed) beside the corners' TSDF
+    uint32_t* srow = reinterpret_cast<uint32_t*>(sbits);
     if (!refine) {
-      // the corners' signs and whether they are observed come from the
-      // eight blocks' negative-TSDF and observed masks (64 bytes each per
-      // block, kept by fusion and import): lane q requests layer q & 7 of
-      // block q >> 3 (x | y << 1 | z << 2) and stages it in LDS (in the
-      // refinement TSDF's space), then every lane forms its corner cells
+      // the rows come from the eight blocks' negative-TSDF and observed masks
+      // (64 bytes each per block, kept by fusion and import): lane q
+      // requests layer q & 7 of block q >> 3 (x | y << 1 | z << 2) and
+      // stages it in LDS (in the refinement TSDF's space); then lane j forms
+      // row j (and j + 64), bits 0..7 from the block of its y and z, bit 8
+      // from the +x one
       uint32_t* smk = reinterpret_cast<uint32_t*>(sd);  // [2][64][2] mask halves
       {
         const int32_t nb = snb[q >> 3];
@@ -826,23 +841,14 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
         smk[128 + 2 * q + 1] = (uint32_t)(ob >> 32);
       }
       wave_sync();
-      // cell j = q + 64 it sits at x + 9y + 81z; as j steps by 64 = 7*9 + 1,
-      // (x, y, z) steps by (1, 7, 0) with carries
-      int x = q % 9, y = q / 9, z = 0;
-#pragma unroll
-      for (int it = 0; it < 12; ++it) {
-        const int j = q + 64 * it;
-        if (j < 729) {
-          const int w = (((x >> 3) | ((y >> 3) << 1) | ((z >> 3) << 2)) << 3) + (z & 7);
-          const uint32_t bit = (uint32_t)((x & 7) + 8 * (y & 7));
-          const uint32_t h = 2 * (uint32_t)w + (bit >> 5);
-          const uint32_t sb = (smk[h] >> (bit & 31u)) & 1u, ob = (smk[128 + h] >> (bit & 31u)) & 1u;
-          sbits[j] = (uint8_t)(sb | (ob << 1));
-        }
-        x += 1;
-        y += 7;
-        if (x == 9) x = 0, ++y;
-        if (y >= 9) y -= 9, ++z;
+      for (int j = q; j < 81; j += 64) {
+        const int y = j % 9, z = j / 9;
+        const int w0 = (((y >> 3) << 1 | (z >> 3) << 2) << 3) + (z & 7), w1 = w0 + 8;
+        const uint32_t sh = 8u * (uint32_t)(y & 7), h = sh >> 5, b = sh & 31u;
+        const uint32_t sr = ((smk[2 * w0 + h] >> b) & 255u) | ((smk[2 * w1 + h] >> b) & 1u) << 8;
+        const uint32_t orow =
+            ((smk[128 + 2 * w0 + h] >> b) & 255u) | ((smk[128 + 2 * w1 + h] >> b) & 1u) << 8;
+        srow[j] = sr | orow << 16;
       }
     } else {
       // refinement needs the corners' TSDF values: all loads of the 9^3
@@ -886,13 +892,19 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
     wave_sync();
     uint32_t flags = 0, nchanged = 0;
-    int dtri = 0, dtcube = 0;  // change of the triangle and triangle-cube counts
-    uint32_t fnew = 0, fold = 0;  // triangles of changed cubes' new and old types
+    // triangles (bits 0..7) and triangle-carrying cubes (from bit 8) of the
+    // changed cubes' new and old types
+    uint32_t fnew = 0, fold = 0;
     // the lane's column of cubes shares corner faces between layers: face
     // z holds the signs of corners (x, y), (x+1, y), (x+1, y+1), (x, y+1) at
     // height z in bits 0..3 (the cyclic corner order) and, in bit 4, whether
     // all four are observed; cube z is faces z and z+1
     auto face = [&](int z) -> uint32_t {
+      if (!refine) {
+        const uint32_t r0 = srow[ly + 9 * z] >> lx, r1 = srow[ly + 1 + 9 * z] >> lx;
+        return (r0 & 3u) | ((r1 & 2u) << 1) | ((r1 & 1u) << 3) |
+               ((((r0 & r1) >> 16) & 3u) == 3u ? 16u : 0u);
+      }
       const int b = lx + 9 * ly + 81 * z;
       const uint32_t c0 = sbits[b], c1 = sbits[b + 1], c2 = sbits[b + 10], c3 = sbits[b + 9];
       return (c0 & 1u) | ((c1 & 1u) << 1) | ((c2 & 1u) << 2) | ((c3 & 1u) << 3) |
@@ -918,11 +930,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
         nt = valid ? refine_type(old[lz], prev[lz], dc, v.eps) : old[lz];
       }
       if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
-      const int ntri_old = sntri[old[lz]], ntri_new = sntri[nt];
-      const bool tri_change = nt != old[lz] && (ntri_old || ntri_new);
-      dtri += ntri_new - ntri_old;
-      dtcube += (ntri_new > 0) - (ntri_old > 0);
-      if (tri_change) fnew += ntri_new, fold += ntri_old;
+      // an unchanged cube keeps its triangles: only changed ones count
+      const uint32_t tri_old = sntri[old[lz]], tri_new = sntri[nt];
+      const bool tri_change = nt != old[lz] && (tri_old | tri_new) != 0u;
+      if (tri_change) fnew += tri_new, fold += tri_old;
       nchanged += (uint32_t)__popcll(__ballot(tri_change));
       if (tri_change) {
         // owners of this cube's edges: this block and, on its +x/+y/+z
@@ -945,12 +956,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       }
       v.vcand[(size_t)i * 8 + q] = out;
     }
-    // per lane dtri is in [-40, 40] and dtcube in [-8, 8]: summed offset
-    dtri = (int)wave_sum_bits<7>((uint32_t)(dtri + 40)) - 64 * 40;
-    dtcube = (int)wave_sum_bits<5>((uint32_t)(dtcube + 8)) - 64 * 8;
-    // per lane fnew and fold are at most 40 (5 triangles in 8 cubes)
-    fnew = wave_sum_bits<6>(fnew);
-    fold = wave_sum_bits<6>(fold);
+    // per lane at most 40 triangles (5 in 8 cubes) and 8 cubes each
+    const uint32_t cnew = wave_sum_bits<4>(fnew >> 8), cold = wave_sum_bits<4>(fold >> 8);
+    fnew = wave_sum_bits<6>(fnew & 255u);
+    fold = wave_sum_bits<6>(fold & 255u);
+    const int dtri = (int)fnew - (int)fold, dtcube = (int)cnew - (int)cold;
     if (q == 0 && nchanged) {
       const uint32_t sg = idx % v.nseg;
       atomicAdd(&v.cseg[sg].st_chg, nchanged);
