@@ -144,6 +144,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->emask = (uint32_t*)take(4 * 64 * B);
   v->wmask = (uint64_t*)take(8 * 8 * B);
   v->smask = (uint64_t*)take(8 * 8 * B);
+  v->nmask = (uint64_t*)take(8 * 8 * B);
   v->st_pending = (uint32_t*)take(4 * B);
   v->st_dirty = (uint32_t*)take(4 * B);
   v->st_vtx = (uint32_t*)take(4 * B);

@@ -165,6 +165,7 @@ struct VolDev {
                               // vertex, bit 8a + lz
   uint64_t* wmask;            // [B][8] per z layer: voxels with weight > 0 (bit x + 8y)
   uint64_t* smask;            // [B][8] per z layer: voxels with TSDF < 0 (bit x + 8y)
+  uint64_t* nmask;            // [B][8] per z layer: voxels with |TSDF| < eps (bit x + 8y)
   uint32_t* st_pending;       // [B] extraction epoch that listed the block
   uint32_t* st_dirty;         // [B] pass that listed the block as dirty
   uint32_t* st_vtx;           // [B] pass that listed the block for vertices

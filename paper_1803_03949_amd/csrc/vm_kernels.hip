@@ -602,8 +602,9 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
       pr[lz] = fuse_project(v, fp, 8 * bx + lx, 8 * by + ly, 8 * bz + lz);
       D[lz] = depth[pr[lz].pix >= 0 ? pr[lz].pix : 0];
     }
-    // lane lz < 8 keeps the observed and the negative-TSDF mask of layer lz
-    uint64_t mine = 0, mneg = 0;
+    // lane lz < 8 keeps the observed, negative-TSDF and near-zero (|TSDF| <
+    // eps, the refinement's test) masks of layer lz
+    uint64_t mine = 0, mneg = 0, mnear = 0;
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
       const FuseSample fs = fuse_finish(v, fp, pr[lz], D[lz]);
@@ -621,11 +622,13 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
         v.w[o] = w[lz];
       }
       const uint64_t m = __ballot(fs.upd || w[lz] > 0.f), mn = __ballot(dn < 0.f);
-      if (q == lz) mine = m, mneg = mn;
+      const uint64_t mz = __ballot(fabsf(dn) < v.eps);
+      if (q == lz) mine = m, mneg = mn, mnear = mz;
     }
     if (q < 8) {
       v.wmask[(size_t)idx * 8 + q] = mine;
       v.smask[(size_t)idx * 8 + q] = mneg;
+      v.nmask[(size_t)idx * 8 + q] = mnear;
     }
     if (q == 0) v.st_frame[idx] = fp.frame;
   }
@@ -672,9 +675,11 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
         v.w[(size_t)idx * kVox + q + 64 * lz] = w[lz];
       }
       const uint64_t m = __ballot(w[lz] > 0.f), mn = __ballot(d[lz] < 0.f);
+      const uint64_t mz = __ballot(fabsf(d[lz]) < v.eps);
       if (q == 0) {
         v.wmask[(size_t)idx * 8 + lz] = m;
         v.smask[(size_t)idx * 8 + lz] = mn;
+        v.nmask[(size_t)idx * 8 + lz] = mz;
       }
     }
     if (q == 0) {
@@ -744,7 +749,8 @@ __global__ __launch_bounds__(256) void k_dirty_all(VolDev v, uint32_t pass) {
   }
 }
 
-__device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc[8], float eps) {
+// near: bit k set when corner k's |TSDF| < eps (Eq. 5).
+__device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, uint32_t near8) {
   // Eqs. (3)-(5); regular types in the order the paper lists them.
   const uint32_t kRegular[6] = {0xCCu, 0x33u, 0x99u, 0x66u, 0xF0u, 0x0Fu};
   if (__popc(t ^ prev) > 3) return t;
@@ -755,11 +761,8 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
     const uint32_t x = t ^ kRegular[j];
     const int dist = __popc(x);
     if (dist > 3) continue;
-    bool near = true;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (((x >> k) & 1u) && !(fabsf(dc[k]) < eps)) near = false;
-    if (!near) continue;
+    // every corner whose sign would flip must be near zero
+    if (x & ~near8) continue;
     if (kRegular[j] == prev) keep_prev = true;
     if (dist < best_d) best_d = dist, best = j;
   }
@@ -770,8 +773,11 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
 // One wave per dirty block, four blocks per workgroup, no workgroup
 // barriers: per-block work is a chain of dependent memory round trips, and
 // many independent waves hide it better than one wide workgroup.  Lane q
-// owns the column (q & 7, q >> 3) of cubes, z = 0..7.  The block's corners
-// plus the +x/+y/+z halo layer (9^3) are staged in the wave's LDS.
+// owns the column (q & 7, q >> 3) of cubes, z = 0..7.  What the cubes need
+// of their corners, the block's and its +x/+y/+z halo layer (9^3), is one
+// bit each, read from per-block masks that fusion and import keep and
+// staged in the wave's LDS: the sign, whether the corner is observed and,
+// for refinement, whether |TSDF| < eps; the TSDF itself is never read.
 // refine = 0: new cube types from the signs (Sec. V-B), previous type
 // saved.  refine = 1: Eqs. (3)-(5) applied to the current types (Sec. V-F).
 // Writing a cube's new type replaces its triangles (Sec. V-D): the type
@@ -783,8 +789,8 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, const float dc
 // +x/+y/+z faces, neighbours).
 template <int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(VolDev v, uint32_t pass, int refine) {
-  __shared__ float sd_all[W][729];     // TSDF (refinement only)
-  __shared__ uint8_t sbits_all[W][732]; // bit 0: TSDF < 0, bit 1: observed
+  __shared__ uint32_t smk_all[W][3 * 128];  // the eight blocks' masks, in 32-bit halves
+  __shared__ uint32_t srow_all[W][2 * 81];  // corner rows: signs | observed << 16, near
   __shared__ int32_t snb_all[W][8];
   // per cube type: its triangles, and in bit 8 whether it has any
   __shared__ uint16_t sntri[256];
@@ -794,11 +800,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
   }
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  float* sd = sd_all[wave];
-  uint8_t* sbits = sbits_all[wave];
+  uint32_t* smk = smk_all[wave];
+  uint32_t* srow = srow_all[wave];
+  uint32_t* nrow = srow_all[wave] + 81;
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
-  const int coff[8] = {0, 1, 1 + 9, 9, 81, 1 + 81, 1 + 9 + 81, 9 + 81};
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
     // lane addressing is formed again per block (fewer registers)
     const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
@@ -815,80 +821,40 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
     if (q < 8) snb[q] = mynb;
     wave_sync();
-    // extraction: the corners' signs and observed flags as rows, row (y, z)
-    // of the 9 x 9 x 9 corners holding x = 0..8 in bits 0..8 (TSDF < 0) and
-    // 16..24 (observed); refinement: one byte per corner (bit 0: TSDF < 0,
-    // bit 1: observed) beside the corners' TSDF
-    uint32_t* srow = reinterpret_cast<uint32_t*>(sbits);
-    if (!refine) {
-      // the rows come from the eight blocks' negative-TSDF and observed masks
-      // (64 bytes each per block, kept by fusion and import): lane q
-      // requests layer q & 7 of block q >> 3 (x | y << 1 | z << 2) and
-      // stages it in LDS (in the refinement TSDF's space); then lane j forms
-      // row j (and j + 64), bits 0..7 from the block of its y and z, bit 8
-      // from the +x one
-      uint32_t* smk = reinterpret_cast<uint32_t*>(sd);  // [2][64][2] mask halves
-      {
-        const int32_t nb = snb[q >> 3];
-        uint64_t sn = 0, ob = 0;
-        if (nb >= 0) {
-          sn = v.smask[(size_t)nb * 8 + (q & 7)];
-          ob = v.wmask[(size_t)nb * 8 + (q & 7)];
-        }
-        smk[2 * q] = (uint32_t)sn;
-        smk[2 * q + 1] = (uint32_t)(sn >> 32);
-        smk[128 + 2 * q] = (uint32_t)ob;
-        smk[128 + 2 * q + 1] = (uint32_t)(ob >> 32);
+    // The corners' bits as rows: row (y, z) of the 9 x 9 x 9 corners holds
+    // x = 0..8 in bits 0..8: whether TSDF < 0, and from bit 16 whether the
+    // corner is observed; for refinement also whether |TSDF| < eps (Eq. 5).
+    // They come from the eight blocks' masks (64 bytes each per block and
+    // kind, kept by fusion and import): lane q requests layer q & 7 of block
+    // q >> 3 (x | y << 1 | z << 2) and stages it in LDS; then lane j forms
+    // row j (and j + 64), bits 0..7 from the block of its y and z, bit 8
+    // from the +x one.
+    {
+      const int32_t nb = snb[q >> 3];
+      uint64_t sn = 0, ob = 0, nz = 0;
+      if (nb >= 0) {
+        sn = v.smask[(size_t)nb * 8 + (q & 7)];
+        ob = v.wmask[(size_t)nb * 8 + (q & 7)];
+        if (refine) nz = v.nmask[(size_t)nb * 8 + (q & 7)];
       }
-      wave_sync();
-      for (int j = q; j < 81; j += 64) {
-        const int y = j % 9, z = j / 9;
-        const int w0 = (((y >> 3) << 1 | (z >> 3) << 2) << 3) + (z & 7), w1 = w0 + 8;
-        const uint32_t sh = 8u * (uint32_t)(y & 7), h = sh >> 5, b = sh & 31u;
-        const uint32_t sr = ((smk[2 * w0 + h] >> b) & 255u) | ((smk[2 * w1 + h] >> b) & 1u) << 8;
-        const uint32_t orow =
-            ((smk[128 + 2 * w0 + h] >> b) & 255u) | ((smk[128 + 2 * w1 + h] >> b) & 1u) << 8;
-        srow[j] = sr | orow << 16;
-      }
-    } else {
-      // refinement needs the corners' TSDF values: all loads of the 9^3
-      // halo first, then the LDS stores; whether a corner is observed comes
-      // from its block's weight mask (one 64-byte line per block) rather
-      // than from the weights.  Byte offsets from the arrays' bases fit 32
-      // bits (at most 2^21 blocks of 2 KiB).
-      const char* dbase = reinterpret_cast<const char*>(v.d);
-      const char* mbase = reinterpret_cast<const char*>(v.wmask);
-      float dv[12];
-      uint32_t ok = 0;
-      int x = q % 9, y = q / 9, z = 0;
-#pragma unroll
-      for (int it = 0; it < 12; ++it) {
-        const int j = q + 64 * it;
-        dv[it] = 0.f;
-        if (j < 729) {
-          const int nb = snb[(x >> 3) | ((y >> 3) << 1) | ((z >> 3) << 2)];
-          if (nb >= 0) {
-            const uint32_t l = (uint32_t)((x & 7) + 8 * (y & 7)), lz = (uint32_t)(z & 7);
-            dv[it] = *reinterpret_cast<const float*>(dbase + ((uint32_t)nb * 2048u +
-                                                              (l + 64u * lz) * 4u));
-            const uint32_t mword = *reinterpret_cast<const uint32_t*>(
-                mbase + ((uint32_t)nb * 64u + lz * 8u + (l >> 5) * 4u));
-            ok |= ((mword >> (l & 31u)) & 1u) << it;
-          }
-        }
-        x += 1;
-        y += 7;
-        if (x == 9) x = 0, ++y;
-        if (y >= 9) y -= 9, ++z;
-      }
-#pragma unroll
-      for (int it = 0; it < 12; ++it) {
-        const int j = q + 64 * it;
-        if (j < 729) {
-          sd[j] = dv[it];
-          sbits[j] = (uint8_t)((dv[it] < 0.f ? 1u : 0u) | (((ok >> it) & 1u) << 1));
-        }
-      }
+      smk[2 * q] = (uint32_t)sn;
+      smk[2 * q + 1] = (uint32_t)(sn >> 32);
+      smk[128 + 2 * q] = (uint32_t)ob;
+      smk[128 + 2 * q + 1] = (uint32_t)(ob >> 32);
+      smk[256 + 2 * q] = (uint32_t)nz;
+      smk[256 + 2 * q + 1] = (uint32_t)(nz >> 32);
+    }
+    wave_sync();
+    for (int j = q; j < 81; j += 64) {
+      const int y = j % 9, z = j / 9;
+      const int w0 = (((y >> 3) << 1 | (z >> 3) << 2) << 3) + (z & 7), w1 = w0 + 8;
+      const uint32_t sh = 8u * (uint32_t)(y & 7), h = sh >> 5, b = sh & 31u;
+      auto row = [&](int kind) -> uint32_t {
+        const uint32_t* m = smk + 128 * kind;
+        return ((m[2 * w0 + h] >> b) & 255u) | ((m[2 * w1 + h] >> b) & 1u) << 8;
+      };
+      srow[j] = row(0) | row(1) << 16;
+      if (refine) nrow[j] = row(2);
     }
     wave_sync();
     uint32_t flags = 0, nchanged = 0;
@@ -900,15 +866,14 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     // height z in bits 0..3 (the cyclic corner order) and, in bit 4, whether
     // all four are observed; cube z is faces z and z+1
     auto face = [&](int z) -> uint32_t {
-      if (!refine) {
-        const uint32_t r0 = srow[ly + 9 * z] >> lx, r1 = srow[ly + 1 + 9 * z] >> lx;
-        return (r0 & 3u) | ((r1 & 2u) << 1) | ((r1 & 1u) << 3) |
-               ((((r0 & r1) >> 16) & 3u) == 3u ? 16u : 0u);
-      }
-      const int b = lx + 9 * ly + 81 * z;
-      const uint32_t c0 = sbits[b], c1 = sbits[b + 1], c2 = sbits[b + 10], c3 = sbits[b + 9];
-      return (c0 & 1u) | ((c1 & 1u) << 1) | ((c2 & 1u) << 2) | ((c3 & 1u) << 3) |
-             ((c0 & c1 & c2 & c3 & 2u) << 3);
+      const uint32_t r0 = srow[ly + 9 * z] >> lx, r1 = srow[ly + 1 + 9 * z] >> lx;
+      return (r0 & 3u) | ((r1 & 2u) << 1) | ((r1 & 1u) << 3) |
+             ((((r0 & r1) >> 16) & 3u) == 3u ? 16u : 0u);
+    };
+    // the same corners' near-zero bits (refinement)
+    auto near_face = [&](int z) -> uint32_t {
+      const uint32_t r0 = nrow[ly + 9 * z] >> lx, r1 = nrow[ly + 1 + 9 * z] >> lx;
+      return (r0 & 3u) | ((r1 & 2u) << 1) | ((r1 & 1u) << 3);
     };
     uint32_t f_lo = face(0);
 #pragma unroll
@@ -923,11 +888,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
         v.tprev[o] = (uint8_t)old[lz];
         nt = t;
       } else {
-        const int base = lx + 9 * ly + 81 * lz;
-        float dc[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) dc[k] = sd[base + coff[k]];
-        nt = valid ? refine_type(old[lz], prev[lz], dc, v.eps) : old[lz];
+        nt = valid ? refine_type(old[lz], prev[lz], near_face(lz) | near_face(lz + 1) << 4)
+                   : old[lz];
       }
       if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
       // an unchanged cube keeps its triangles: only changed ones count
