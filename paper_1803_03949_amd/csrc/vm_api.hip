@@ -47,6 +47,7 @@ struct vm_volume {
   uint32_t vcount;  // extractions and refinements so far (vertex-list length)
   FrameParams last_fp;
   bool have_fp;
+  bool last_refine = false;  // the last extraction-side call was a refinement
   int cus;          // compute units of the device
   vm_launch launch; // workgroup mapping (see vm_set_launch)
   int grid_blocks;  // workgroups of per-block kernels
@@ -214,6 +215,7 @@ int clear_state(vm_volume* vol, hipStream_t stream, bool full) {
   vol->frame = 0;
   vol->epoch = 1;
   vol->pass = 0;
+  vol->last_refine = false;
   vol->have_fp = false;
   vol->dl_nv = -1;
   return hip_status(e);
@@ -598,8 +600,8 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
               vol->epoch);
   ++vol->epoch;
   VM_LAUNCH_W(vol, VM_K_CLASSIFY, k_classify, stream, v, pass, 0);
-  VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
-  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v, moved);
+  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v, moved, 1);
+  vol->last_refine = false;
   return launched();
 }
 
@@ -615,7 +617,8 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
   // refinement changes types only: the end points that moved are those in
   // blocks fused or imported since the last extraction (normally none)
-  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v, vol->epoch);
+  VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v, vol->epoch, 0);
+  vol->last_refine = true;
   return launched();
 }
 
@@ -773,7 +776,7 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
   out->frame_blocks = nf < B ? nf : B;
   out->pending_blocks = c.n_pending[vol->epoch & 1];
   out->dirty_blocks = c.n_dirty[vol->dev.xsel];
-  out->vertex_blocks = c.n_vblocks[vol->dev.vsel];
+  out->vertex_blocks = c.n_vblocks[vol->dev.vsel] + (vol->last_refine ? 0u : c.n_dirty[vol->dev.xsel]);
   out->changed_cubes = st_chg - c.base_chg;
   out->vertex_slots = vh;
   out->free_vertex_slots = vf;

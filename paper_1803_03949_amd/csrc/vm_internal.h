@@ -176,7 +176,8 @@ struct VolDev {
   uint32_t* pending;          // [B]
   uint32_t* dirty;            // [B]
   uint32_t* vcand;            // [8B] vertex-block candidates of each dirty block
-  uint32_t* vblocks;          // [B]
+  uint32_t* vblocks;          // [B] vertex pass: after a refinement its blocks, after an
+                              // extraction the extra ones beyond the dirty list
   uint32_t* vowner;           // [V] index into the edge arrays, kNone if free
   uint32_t* vring;            // [V]
   int32_t* vdl;               // [V] row in the last download, -1 if none
@@ -604,7 +605,7 @@ template <int W>
 __global__ void k_classify(VolDev v, uint32_t pass, int refine);
 __global__ void k_vblock_compact(VolDev v);
 template <int W>
-__global__ void k_vertices(VolDev v, uint32_t moved);
+__global__ void k_vertices(VolDev v, uint32_t moved, int walk_dirty);
 __global__ void k_dl_count(VolDev v, int what);
 __global__ void k_dl_scan(VolDev v, int what, uint32_t nparts);
 __global__ void k_dl_write_vertices(VolDev v, float* __restrict__ verts,

@@ -782,11 +782,12 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, uint32_t near8
 // saved.  refine = 1: Eqs. (3)-(5) applied to the current types (Sec. V-F).
 // Writing a cube's new type replaces its triangles (Sec. V-D): the type
 // names them and the edges they use, and a cube whose type is unchanged
-// keeps them.  The blocks whose vertices must be recomputed are claimed
-// (once per pass) and written as candidates at fixed positions 8i..8i+7: on
-// extraction this block (its edges' end points may have moved), and the
-// owners of the edges of changed cubes (this block and, for cubes on its
-// +x/+y/+z faces, neighbours).
+// keeps them.  The blocks whose vertices must be recomputed: on extraction
+// every dirty block (its edges' end points may have moved) and the
+// neighbours, not dirty themselves, that own edges of changed cubes on its
+// +x/+y/+z faces, appended to a short list; on refinement the owners of the
+// edges of changed cubes (this block and neighbours), claimed once per pass
+// and written as candidates at fixed positions 8i..8i+7 for compaction.
 template <int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(VolDev v, uint32_t pass, int refine) {
   __shared__ uint32_t smk_all[W][3 * 128];  // the eight blocks' masks, in 32-bit halves
@@ -805,6 +806,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
   uint32_t* nrow = srow_all[wave] + 81;
   int32_t* snb = snb_all[wave];
   const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
+  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_DIRTY_BLOCKS] += n;
   for (ItemLoop it = item_loop(v, n, W, wave); it.i < it.end; it.i += it.step) {
     // lane addressing is formed again per block (fewer registers)
     const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
@@ -909,7 +911,26 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     uint32_t wflags = refine ? 0u : 1u;
     for (int b = 0; b < 7; ++b)
       if (__ballot((flags >> b) & 1u)) wflags |= 1u << b;
-    if (q < 8) {
+    if (!refine) {
+      // extraction: the vertex pass walks every dirty block, this one
+      // included; a +x/+y/+z neighbour that owns edges of changed cubes and
+      // is not dirty itself joins as an extra block, claimed once per pass
+      // and appended with one atomic per wave
+      bool extra = false;
+      if (q >= 1 && q < 8 && ((wflags >> q) & 1u) && mynb >= 0)
+        extra = v.st_dirty[mynb] != pass && v.st_vtx[mynb] != pass &&
+                atomicMax(&v.st_vtx[mynb], pass) < pass;
+      const uint64_t be = __ballot(extra);
+      if (be) {
+        uint32_t b0 = 0;
+        if (q == 0) b0 = atomicAdd(&v.cnt->n_vblocks[v.vsel], (uint32_t)__popcll(be));
+        const uint32_t pos = uniform(b0) + mask_rank(be);
+        if (extra) {
+          if (pos < v.max_blocks) v.vblocks[pos] = (uint32_t)mynb;
+          else atomicOr(&v.cnt->error, kErrBlocks);
+        }
+      }
+    } else if (q < 8) {
       uint32_t out = kNone;
       if ((wflags >> q) & 1u) {
         const int32_t nb = q == 0 ? (int32_t)idx : mynb;
@@ -936,8 +957,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
   }
 }
 
-// Compact the vertex-block candidates (8 per dirty block, already claimed),
-// one atomic per tile.
+// Compact the vertex-block candidates a refinement wrote (8 per dirty
+// block, already claimed), one atomic per tile.
 // The candidate list is 8 entries per dirty block and mostly empty, and
 // can be long (every block of a large import), so each lane takes 8 entries
 // (coalesced: entry k of a lane sits k * 256 past the first) and a tile of
@@ -947,7 +968,6 @@ __global__ __launch_bounds__(256) void k_vblock_compact(VolDev v) {
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase;
   const uint32_t n = min(v.cnt->n_dirty[v.xsel], v.max_blocks);
-  if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_DIRTY_BLOCKS] += n;
   const uint32_t total = n * 8u;
   constexpr uint32_t kT = 256 * kVbPer;
   for (uint32_t t0 = blockIdx.x * kT; t0 < total; t0 += gridDim.x * kT) {
@@ -997,13 +1017,16 @@ constexpr int kRingBatch = 256;  // recycled slots fetched per block at once
 constexpr int kWorkCap = 512;    // listed edges per chunk of the write pass
 
 template <int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) void k_vertices(VolDev v, uint32_t moved) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) void k_vertices(VolDev v, uint32_t moved, int walk_dirty) {
   __shared__ uint32_t srole[4 * 256];  // edge uses by role, per cube type
   __shared__ uint32_t st_all[W][kRingBatch];  // cube types at local -1..7, then slots
   __shared__ uint32_t swork_all[W][kWorkCap]; // edge 64k + q | count > 0 << 11 | has vertex << 12
   __shared__ int32_t snb_all[W][27];
   static_assert(kRingBatch * 4 >= 732, "type staging fits the slot batch");
-  const uint32_t n = min(v.cnt->n_vblocks[v.vsel], v.max_blocks);
+  // the blocks: after an extraction the dirty list and then the extra
+  // blocks classification appended; after a refinement the compacted list
+  const uint32_t nd = walk_dirty ? min(v.cnt->n_dirty[v.xsel], v.max_blocks) : 0u;
+  const uint32_t n = nd + min(v.cnt->n_vblocks[v.vsel], v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->acc[VM_TOTAL_VERTEX_BLOCKS] += n;
   {
     // a workgroup whose first wave has no block has none at all
@@ -1021,7 +1044,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) voi
     // lane addressing is formed again per block rather than held in
     // registers across the loop
     const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
-    const uint32_t idx = uniform(v.vblocks[it.i]);
+    const uint32_t idx = uniform(it.i < nd ? v.dirty[it.i] : v.vblocks[it.i - nd]);
     const uint32_t sg = uniform(idx % v.nseg);
     // the block's edge arrays, addressed by block-local edge a * 512 + l;
     // pool arrays by 32-bit byte offsets from their bases (every index here
@@ -1825,9 +1848,9 @@ __global__ void k_lookup(VolDev v, const int32_t* __restrict__ coords, int32_t* 
 template __global__ void k_classify<2>(VolDev, uint32_t, int);
 template __global__ void k_classify<4>(VolDev, uint32_t, int);
 template __global__ void k_classify<8>(VolDev, uint32_t, int);
-template __global__ void k_vertices<2>(VolDev, uint32_t);
-template __global__ void k_vertices<4>(VolDev, uint32_t);
-template __global__ void k_vertices<8>(VolDev, uint32_t);
+template __global__ void k_vertices<2>(VolDev, uint32_t, int);
+template __global__ void k_vertices<4>(VolDev, uint32_t, int);
+template __global__ void k_vertices<8>(VolDev, uint32_t, int);
 template __global__ void k_fuse<2>(VolDev, FrameParams, const float*, uint32_t);
 template __global__ void k_fuse<4>(VolDev, FrameParams, const float*, uint32_t);
 template __global__ void k_fuse<8>(VolDev, FrameParams, const float*, uint32_t);
