@@ -77,8 +77,11 @@ struct Seg {
   uint32_t count;    // free slots in the ring, from head on (wrapping)
   uint32_t ticket;   // allocations taken since the last finalise
   uint32_t push;     // frees pushed since the last finalise
+  uint32_t pad0;
+  // the vertex pass adds to each pair with one 64-bit atomic
   uint32_t st_new;   // running count of allocations
-  uint32_t st_upd;   // running count of rewritten vertices
+  uint32_t st_upd;   // running count of kept vertices
+  uint32_t st_mov;   // running count of kept vertices whose t was rewritten
   uint32_t st_freed; // running count of frees
   uint32_t st_chg;   // running count of cubes whose triangles changed
   uint32_t st_ref;   // running count of cubes re-typed by refinement
@@ -86,8 +89,7 @@ struct Seg {
   int32_t st_tcube;  // running change of the number of cubes with triangles
   uint32_t st_fnew;  // running count of triangles of changed cubes' new types
   uint32_t st_fold;  // running count of triangles of changed cubes' old types
-  uint32_t st_mov;   // running count of kept vertices whose t was rewritten
-  uint32_t pad[17];
+  uint32_t pad[16];
 };
 static_assert(sizeof(Seg) == 128, "segment record size");
 

@@ -215,15 +215,14 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
       s = hash_insert_seen(v, key, &seen);
       if (s < 0) atomicOr(&v.cnt->error, kErrHash);
     }
-    // one claim per block and frame wins; the block's pending stamp is
-    // requested with the frame stamp (only the winner of this frame's claim
-    // writes it)
+    // one claim per block and frame wins (an exchange of the slot's frame
+    // stamp); the block's pending stamp is requested with it (only the
+    // winner of this frame's claim writes it)
     bool won = false, pend = false;
     if (s >= 0) {
       const uint32_t idx = (uint32_t)(seen & kIdxMask);
-      const uint32_t stamp = v.slot_stamp[s];
       const uint32_t pst = idx != kPending ? v.st_pending[idx] : 0u;
-      won = stamp != fp.frame && atomicExch(&v.slot_stamp[s], fp.frame) != fp.frame;
+      won = atomicExch(&v.slot_stamp[s], fp.frame) != fp.frame;
       pend = won && (idx == kPending || pst != epoch);
     }
     const uint64_t bw = __ballot(won);
@@ -717,7 +716,7 @@ __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t
       if (idx == kNone) continue;
       const int32_t nb =
           v.nbr[(size_t)idx * 27 + nbr_dir(-(int)(o & 1), -(int)((o >> 1) & 1), -(int)(o >> 2))];
-      if (nb >= 0 && v.st_dirty[nb] != pass && atomicMax(&v.st_dirty[nb], pass) < pass) {
+      if (nb >= 0 && atomicMax(&v.st_dirty[nb], pass) < pass) {
         got[k] = nb;
         ++cnt;
       }
@@ -1268,10 +1267,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) voi
     nmov = wave_sum_bits<5>(nmov);
     const uint32_t nupd = wave_sum_bits<5>((uint32_t)__popc(kept));
     if (q == 0) {
-      if (nnew) atomicAdd(&v.vseg[sg].st_new, nnew);
-      if (nupd) atomicAdd(&v.vseg[sg].st_upd, nupd);
-      if (nmov) atomicAdd(&v.vseg[sg].st_mov, nmov);
-      if (tfree) atomicAdd(&v.vseg[sg].st_freed, tfree);
+      if (nnew | nupd)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&v.vseg[sg].st_new),
+                  (unsigned long long)nnew | (unsigned long long)nupd << 32);
+      if (nmov | tfree)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&v.vseg[sg].st_mov),
+                  (unsigned long long)nmov | (unsigned long long)tfree << 32);
     }
     wave_sync();
   }
