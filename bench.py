@@ -43,10 +43,10 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 5503.3, "write_kib": 1012.5, "source_sha1": "e5dd002ceb0c"},
-    "fuse": {"fetch_kib": 11792.4, "write_kib": 13675.0, "source_sha1": "713321bf3994"},
-    "classify": {"fetch_kib": 3763.6, "write_kib": 3774.9, "source_sha1": "f43b169b34aa"},
-    "vertices": {"fetch_kib": 12319.7, "write_kib": 10297.1, "source_sha1": "3a3165b67427"},
+    "collect": {"fetch_kib": 1522.4, "write_kib": 1562.1, "source_sha1": "cb2f335e2101"},
+    "fuse": {"fetch_kib": 11706.2, "write_kib": 13602.4, "source_sha1": "2175dd92f78f"},
+    "classify": {"fetch_kib": 3500.2, "write_kib": 3398.8, "source_sha1": "7103f4e681b5"},
+    "vertices": {"fetch_kib": 8487.5, "write_kib": 8703.0, "source_sha1": "b5a56eeccdf5"},
 }
 
 
@@ -753,6 +753,7 @@ def main():
                     if "batched_64_volumes" in extras else None),
         "cpu_baseline": cpu,
         "value_without_events": head["value_without_events"],
+        "graph_replay": head["graph_replay"],
         "blocks": head["blocks"],
         "totals_per_step": head["totals_per_step"],
         "kernels": head["kernels"],
