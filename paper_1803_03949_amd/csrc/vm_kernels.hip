@@ -1016,7 +1016,7 @@ constexpr int kRingBatch = 256;  // recycled slots fetched per block at once
 constexpr int kWorkCap = 512;    // listed edges per chunk of the write pass
 
 template <int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(7))) void k_vertices(VolDev v, uint32_t moved, int walk_dirty) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(6))) void k_vertices(VolDev v, uint32_t moved, int walk_dirty) {
   __shared__ uint32_t srole[4 * 256];  // edge uses by role, per cube type
   __shared__ uint32_t st_all[W][kRingBatch];  // cube types at local -1..7, then slots
   __shared__ uint32_t swork_all[W][kWorkCap]; // edge 64k + q | count > 0 << 11 | has vertex << 12
