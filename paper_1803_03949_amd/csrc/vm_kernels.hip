@@ -6,8 +6,9 @@
 // wave's own LDS, so waves of a workgroup never wait for each other.  Work
 // lists live on the device and every kernel loops over its list on a grid
 // sized to the device, so the host never waits for a count.  Lists are
-// compacted with one atomic per workgroup; pool allocations take one atomic
-// per block on the block's pool segment.
+// appended to with at most one atomic per workgroup (per wave for the short
+// list of extra vertex blocks); pool allocations take one atomic per block
+// on the block's pool segment.
 #include "voxmesh.h"
 #include "vm_internal.h"
 
