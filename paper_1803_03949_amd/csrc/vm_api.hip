@@ -764,7 +764,8 @@ int vm_get_status(vm_volume* vol, vm_status* out, hipStream_t stream) {
     st_new += sn.vseg[k].st_new, st_upd += sn.vseg[k].st_upd, st_freed += sn.vseg[k].st_freed;
     st_chg += sn.cseg[k].st_chg, st_ref += sn.cseg[k].st_ref;
     vh += sn.vseg[k].hwm, vf += sn.vseg[k].count;
-    tris += sn.cseg[k].st_tri, tcubes += sn.cseg[k].st_tcube;
+    tris += (int64_t)sn.cseg[k].st_fnew - (int64_t)sn.cseg[k].st_fold;
+    tcubes += (int64_t)sn.cseg[k].st_cnew - (int64_t)sn.cseg[k].st_cold;
     const int64_t live = (int64_t)sn.vseg[k].hwm - (int64_t)sn.vseg[k].count;
     seg_live = live > seg_live ? live : seg_live;
   }

@@ -83,10 +83,12 @@ struct Seg {
   uint32_t st_upd;   // running count of kept vertices
   uint32_t st_mov;   // running count of kept vertices whose t was rewritten
   uint32_t st_freed; // running count of frees
+  // classification adds to each pair with one 64-bit atomic; a segment's
+  // triangles are st_fnew - st_fold, its cubes with triangles st_cnew - st_cold
   uint32_t st_chg;   // running count of cubes whose triangles changed
   uint32_t st_ref;   // running count of cubes re-typed by refinement
-  int32_t st_tri;    // running change of the number of triangles
-  int32_t st_tcube;  // running change of the number of cubes with triangles
+  uint32_t st_cnew;  // running count of changed cubes whose new type has triangles
+  uint32_t st_cold;  // running count of changed cubes whose old type had triangles
   uint32_t st_fnew;  // running count of triangles of changed cubes' new types
   uint32_t st_fold;  // running count of triangles of changed cubes' old types
   uint32_t pad[16];

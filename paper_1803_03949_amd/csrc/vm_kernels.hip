@@ -943,15 +943,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     const uint32_t cnew = wave_sum_bits<4>(fnew >> 8), cold = wave_sum_bits<4>(fold >> 8);
     fnew = wave_sum_bits<6>(fnew & 255u);
     fold = wave_sum_bits<6>(fold & 255u);
-    const int dtri = (int)fnew - (int)fold, dtcube = (int)cnew - (int)cold;
     if (q == 0 && nchanged) {
-      const uint32_t sg = idx % v.nseg;
-      atomicAdd(&v.cseg[sg].st_chg, nchanged);
-      if (refine) atomicAdd(&v.cseg[sg].st_ref, nchanged);
-      if (dtri) atomicAdd(&v.cseg[sg].st_tri, dtri);
-      if (dtcube) atomicAdd(&v.cseg[sg].st_tcube, dtcube);
-      if (fnew) atomicAdd(&v.cseg[sg].st_fnew, fnew);
-      if (fold) atomicAdd(&v.cseg[sg].st_fold, fold);
+      Seg& cs = v.cseg[idx % v.nseg];
+      auto add2 = [](uint32_t* lo, uint32_t a, uint32_t b) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(lo),
+                  (unsigned long long)a | (unsigned long long)b << 32);
+      };
+      add2(&cs.st_chg, nchanged, refine ? nchanged : 0u);
+      if (cnew | cold) add2(&cs.st_cnew, cnew, cold);
+      if (fnew | fold) add2(&cs.st_fnew, fnew, fold);
     }
     wave_sync();
   }
