@@ -43,10 +43,10 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 1522.4, "write_kib": 1562.1, "source_sha1": "cb2f335e2101"},
-    "fuse": {"fetch_kib": 11706.2, "write_kib": 13602.4, "source_sha1": "2175dd92f78f"},
-    "classify": {"fetch_kib": 3500.2, "write_kib": 3398.8, "source_sha1": "7103f4e681b5"},
-    "vertices": {"fetch_kib": 8487.5, "write_kib": 8703.0, "source_sha1": "b5a56eeccdf5"},
+    "collect": {"fetch_kib": 1522.5, "write_kib": 1560.9, "source_sha1": "cb2f335e2101"},
+    "fuse": {"fetch_kib": 11709.3, "write_kib": 13602.1, "source_sha1": "2175dd92f78f"},
+    "classify": {"fetch_kib": 3504.4, "write_kib": 3249.7, "source_sha1": "5333a45c165a"},
+    "vertices": {"fetch_kib": 8487.4, "write_kib": 8703.6, "source_sha1": "126c89769ee0"},
 }
 
 
