@@ -53,6 +53,7 @@ def lib():
             "orc_restrict_blocks": (None, [vp, P, i]),
             "orc_import_blocks": (i, [vp, P, P, P, i]),
             "orc_extract": (i, [vp, i]),
+            "orc_extract_refine": (i, [vp, i]),
             "orc_refine": (i, [vp]),
             "orc_gc": (i, [vp]),
             "orc_num_blocks": (i, [vp]),
@@ -195,8 +196,10 @@ class OracleVolume:
             raise ValueError("block coordinate out of range")
         return r
 
-    def extract(self, scope_all: bool = False) -> int:
-        return lib().orc_extract(self._h, 1 if scope_all else 0)
+    def extract(self, scope_all: bool = False, refine: bool = False) -> int:
+        """Sec. V-B..V-D; with refine, Eqs. 3-5 applied to each new type first (Sec. V-F)."""
+        f = lib().orc_extract_refine if refine else lib().orc_extract
+        return f(self._h, 1 if scope_all else 0)
 
     def refine(self) -> int:
         return lib().orc_refine(self._h)

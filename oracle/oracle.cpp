@@ -447,12 +447,15 @@ void stamp_births(Volume& v) {
 }
 
 // Extraction over a set of blocks: cube types, then vertices, then
-// triangles, in the paper's order (Sec. V-B to V-D).  The per-block work of
+// triangles, in the paper's order (Sec. V-B to V-D).  With refine, each new
+// type goes through the Hamming refinement (Eqs. 3-5, against the type it
+// replaces) before the vertices and triangles are made from it: Sec. V-F
+// applies the regular type before marching cubes.  The per-block work of
 // each step (types; edge keys and t of the vertices to create or update;
 // triangles of changed cubes) runs over blocks in parallel, and the
 // vertex and triangle maps are then updated in one thread in block, cube
 // and edge order.
-void extract_blocks(Volume& v, const std::set<I3>& dirty) {
+void extract_blocks(Volume& v, const std::set<I3>& dirty, bool refine) {
   const std::vector<I3> list(dirty.begin(), dirty.end());
   const long n = (long)list.size();
 #pragma omp parallel for schedule(dynamic, 4) num_threads(v.threads)
@@ -465,6 +468,7 @@ void extract_blocks(Volume& v, const std::set<I3>& dirty) {
       float dc[8];
       bool valid = classify(v, c, type, dc);
       blk->prev[l] = blk->cur[l];
+      if (valid && refine) type = refine_type(type, blk->prev[l], dc, v.eps);
       blk->cur[l] = valid ? (uint8_t)type : 0;
     }
   }
@@ -686,8 +690,7 @@ int orc_import_blocks(void* h, const int* coords, const float* d, const float* w
 // Mesh extraction.  scope 0: the blocks touched since the last extraction
 // (by integrations or imports) plus their allocated neighbours in the -x/-y/-z directions (the
 // cubes whose corners moved); scope 1: every allocated block.
-int orc_extract(void* h, int scope) {
-  Volume& v = *(Volume*)h;
+static int extract_scope(Volume& v, int scope, bool refine) {
   std::set<I3> dirty;
   if (scope == 1) {
     for (auto& kv : v.blocks) dirty.insert(kv.first);
@@ -700,11 +703,20 @@ int orc_extract(void* h, int scope) {
             if (find_block(v, nb)) dirty.insert(nb);
           }
   }
-  extract_blocks(v, dirty);
+  extract_blocks(v, dirty, refine);
   v.pending_touched.clear();
   stamp_births(v);
   return (int)dirty.size();
 }
+
+int orc_extract(void* h, int scope) { return extract_scope(*(Volume*)h, scope, false); }
+
+// Extraction with the refinement applied to each new type before its
+// vertices and triangles are made (Sec. V-F).  Types, vertices, t and
+// triangles end as after orc_extract followed by orc_refine; a vertex the
+// unrefined types would have dropped and the refined ones keep is never
+// dropped, so it keeps its birth frame.
+int orc_extract_refine(void* h, int scope) { return extract_scope(*(Volume*)h, scope, true); }
 
 // Hamming refinement (Eqs. 3-5) over the cubes of the last extraction.
 // Returns the number of cubes whose type changed.

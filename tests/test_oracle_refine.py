@@ -88,3 +88,39 @@ def test_refine_twice_equals_once_and_regularises():
     vv = vol.vertices(live_only=False)
     assert (vv["ref"] > 0).all()
     assert vv["ref"].sum() == 3 * len(vol.triangles())
+
+
+def test_refining_extraction_equals_extract_then_refine():
+    """Sec. V-F applies the regular type before marching cubes: extraction
+    with the refinement folded in ends with the types, vertices, t, counts
+    and triangles of a plain extraction followed by a refinement pass, and
+    differs from the plain extraction alone."""
+    seq = scenes.room_sequence(seed=3, n_frames=500, voxel_m=0.04, holes=True)
+    fused = oracle.OracleVolume(seq.voxel_m, 4.0, EPS)
+    two = oracle.OracleVolume(seq.voxel_m, 4.0, EPS)
+    plain = oracle.OracleVolume(seq.voxel_m, 4.0, EPS)
+    differs = False
+    for k in (0, 4, 8, 12, 16, 20):
+        for v in (fused, two, plain):
+            v.integrate(seq.frame(k), scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        fused.extract(refine=True)
+        two.extract()
+        two.refine()
+        plain.extract()
+        bf, bt, bp = fused.blocks(), two.blocks(), plain.blocks()
+        assert np.array_equal(bf["coords"], bt["coords"])
+        assert np.array_equal(bf["cur"], bt["cur"]) and np.array_equal(bf["prev"], bt["prev"])
+        differs |= not np.array_equal(bf["cur"], bp["cur"])
+        vf, vt = fused.vertices(), two.vertices()
+        assert np.array_equal(vf["keys"], vt["keys"])
+        assert np.array_equal(vf["t"], vt["t"]) and np.array_equal(vf["ref"], vt["ref"])
+        tf, tt = fused.triangles(), two.triangles()
+        assert len(tf) == len(tt)
+        assert sorted(map(bytes, tf)) == sorted(map(bytes, tt))
+        # a vertex the unrefined types drop and the refined ones keep is
+        # re-born by the two passes but never dropped by the fused one
+        nf, nt = fused.births(), two.births()
+        assert (nf <= nt).all()
+        for v in (fused, two, plain):
+            v.gc()
+    assert differs
