@@ -409,11 +409,11 @@ def sphere_extract(dev):
 
 
 def room_fine(args, dev):
-    """4 mm, holes, refinement after every extraction."""
+    """4 mm, holes, refinement at every extraction: as a separate pass after
+    it, and applied inside it to each new type."""
     import torch
 
     import scenes
-    from paper_1803_03949_amd import Volume
 
     seq = scenes.room_sequence(seed=3, n_frames=args.fine_frames, voxel_m=0.004, holes=True)
     t0 = time.time()
@@ -422,14 +422,31 @@ def room_fine(args, dev):
     depth = torch.from_numpy(np.stack(frames)).to(dev)
     poses = list(seq.poses)
     del frames
+    out = fine_pass(args, seq, depth, poses, dev, fused=False)
+    out["refining_extraction"] = fine_pass(args, seq, depth, poses, dev, fused=True)
+    del depth
+    torch.cuda.empty_cache()
+    return out
+
+
+def fine_pass(args, seq, depth, poses, dev, fused):
+    """The 4 mm sequence on resident depth frames: each frame integrate,
+    extract and gc, with a refinement pass after the extraction, or (fused)
+    the refinement applied to each new type inside the extraction."""
+    import torch
+
+    import scenes
+    from paper_1803_03949_amd import Volume
+
     vol = Volume(seq.voxel_m, hash_log2=22, max_blocks=1 << 19, max_vertices=1 << 24, device=dev)
 
     def step():
         vol.reset()
         for k in range(args.fine_frames):
             vol.integrate(depth[k], scenes.K, poses[k], seq.min_depth, seq.max_depth)
-            vol.extract()
-            vol.refine()
+            vol.extract(refine=fused)
+            if not fused:
+                vol.refine()
             vol.gc()
 
     step()
@@ -449,8 +466,8 @@ def room_fine(args, dev):
     vol.profile(False)
     prof = vol.profile_read()
     npix = depth.shape[1] * depth.shape[2]
-    algo, step_total = algorithmic_bytes(tot, npix, refine=True)
-    touched = touched_bytes(tot, npix, refine=True)
+    algo, step_total = algorithmic_bytes(tot, npix, refine=not fused)
+    touched = touched_bytes(tot, npix, refine=not fused)
     kernels = {}
     for k, (n, ms) in prof.items():
         e = {"launches": n, "us_per_launch": round(1000 * ms / n, 3)}
@@ -463,16 +480,17 @@ def room_fine(args, dev):
         kernels[k] = e
     out = {"frames_per_s": args.fine_frames / dt, "ms_per_frame": 1000 * dt / args.fine_frames,
            "frames": args.fine_frames, "blocks": st["blocks"],
-           "blocks_meshed_per_s": tot["dirty_blocks"] // 2 / dt,
-           "refined_cubes": tot["refined_cubes"],
+           "blocks_meshed_per_s": (tot["dirty_blocks"] if fused else tot["dirty_blocks"] // 2) / dt,
+           "refined_cubes": tot["refined_cubes"], "totals": tot,
            "frame": {"bytes_per_frame": step_total // args.fine_frames,
                      "us_per_frame": 1e6 * dt / args.fine_frames,
                      "frac": frac(step_total, 1e3 * dt)},
            "kernels": kernels}
-    log(f"4 mm + refine: {out['frames_per_s']:.1f} frames/s, blocks {st['blocks']}")
+    what = "refining extraction" if fused else "extraction + refinement pass"
+    log(f"4 mm, {what}: {out['frames_per_s']:.1f} frames/s, blocks {st['blocks']}")
     for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["us_per_launch"] * kv[1]["launches"]):
         log(f"  {k:10s} {e}")
-    del vol, depth
+    del vol
     torch.cuda.empty_cache()
     return out
 

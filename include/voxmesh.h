@@ -75,6 +75,9 @@ enum {
 };
 
 enum { VM_SCOPE_DIRTY = 0, VM_SCOPE_ALL = 1 };
+/* Flag OR-ed into vm_extract_mesh's scope: refine each new type (Sec. V-F)
+ * before its vertices and triangles are made. */
+enum { VM_EXTRACT_REFINE = 0x100 };
 
 /* Volume configuration.  Sizes are capacities of the caller buffer: per
  * block of max_blocks about 17.6 KiB (TSDF and weight 4 KiB, types 1 KiB,
@@ -130,7 +133,7 @@ typedef struct vm_status {
   int64_t new_vertices;     /* vertices created by the last extract/refine */
   int64_t updated_vertices; /* vertices whose position was rewritten */
   int64_t freed_vertices;   /* vertices recycled by the last extract/refine */
-  int64_t refined_cubes;    /* cubes re-typed by the last vm_refine_mesh */
+  int64_t refined_cubes;    /* cubes the last extract/refine re-typed by Eqs. 3-5 */
   int64_t vertex_segments;  /* segments of the vertex pool (see max_vertices) */
   int64_t segment_capacity; /* vertex slots per segment */
   int64_t max_segment_live; /* live vertices of the fullest segment */
@@ -253,7 +256,14 @@ int vm_import_blocks(vm_volume* vol, const int32_t* coords, const float* tsdf,
  * resolved to vertex indices only by a download.  Every edge used by some
  * cube's triangles holds one vertex at t = d(g)/(d(g) - d(g+a)) (0.5 if
  * equal), created on first use and updated when its end points move; each
- * vertex's reference count is the number of triangles using it. */
+ * vertex's reference count is the number of triangles using it.  With
+ * VM_EXTRACT_REFINE in scope, each valid cube's new type t is first replaced
+ * by the refinement of vm_refine_mesh against the type it replaces (the
+ * paper applies the regular type before marching cubes, Sec. V-F): types,
+ * vertices, t, counts and triangles end as after this extraction without
+ * the flag followed by vm_refine_mesh, but no vertex is dropped and created
+ * again between the two, so none is re-born.  Other scope bits:
+ * VM_ERR_ARG. */
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream);
 
 /* Hamming-distance refinement (Sec. V-F, Eqs. 3-5) of the cubes of the last

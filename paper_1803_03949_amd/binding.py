@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("VOXMESH_LIBRARY") or os.path.join(
 
 VM_OK = 0
 VM_SCOPE_DIRTY, VM_SCOPE_ALL = 0, 1
+VM_EXTRACT_REFINE = 0x100
 ERRORS = {
     -1: "VM_ERR_ARG", -2: "VM_ERR_HASH_FULL", -3: "VM_ERR_BLOCK_POOL_FULL",
     -4: "VM_ERR_VERTEX_POOL_FULL", -6: "VM_ERR_CAPACITY",
@@ -257,9 +258,10 @@ class Volume:
         _check(lib().vm_import_batch(self.h, _ptr(slots), _ptr(coords), _ptr(tsdf), _ptr(weight),
                                      n, _ptr(rows), _stream(stream)), "vm_import_batch")
 
-    def extract(self, scope_all: bool = False, stream=None):
-        """Mesh extraction (dirty blocks, or every block with scope_all)."""
-        scope = VM_SCOPE_ALL if scope_all else VM_SCOPE_DIRTY
+    def extract(self, scope_all: bool = False, stream=None, refine: bool = False):
+        """Mesh extraction (dirty blocks, or every block with scope_all); with
+        refine, each new type is refined (Eqs. 3-5) before it is meshed."""
+        scope = (VM_SCOPE_ALL if scope_all else VM_SCOPE_DIRTY) | (VM_EXTRACT_REFINE if refine else 0)
         _check(lib().vm_extract_mesh(self.h, scope, _stream(stream)), "vm_extract_mesh")
 
     def refine(self, stream=None):

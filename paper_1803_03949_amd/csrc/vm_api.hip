@@ -281,6 +281,17 @@ void prof_end(vm_volume* vol, int kid, hipEvent_t a, hipStream_t s) {
     }                                                                                   \
   } while (0)
 
+// The same for kernels with a second, compile-time mode argument.
+#define VM_LAUNCH_WM(vol, kid, kernel, mode, stream, ...)                                     \
+  do {                                                                                      \
+    const dim3 vm_g_((vol)->grid_waves);                                                    \
+    switch ((vol)->launch.wave_group_size) {                                                \
+      case 2: VM_LAUNCH(vol, kid, (kernel<2, mode>), vm_g_, dim3(128), stream, __VA_ARGS__); break; \
+      case 8: VM_LAUNCH(vol, kid, (kernel<8, mode>), vm_g_, dim3(512), stream, __VA_ARGS__); break; \
+      default: VM_LAUNCH(vol, kid, (kernel<4, mode>), vm_g_, dim3(256), stream, __VA_ARGS__); break; \
+    }                                                                                       \
+  } while (0)
+
 void prep(vm_volume* vol, int op, hipStream_t s) {
   VM_LAUNCH(vol, VM_K_COUNTERS, k_prep, dim3(1), dim3(kSegs), s, vol->dev, op, 0u);
 }
@@ -582,6 +593,8 @@ int vm_bind_tsdf(vm_volume* vol, float* tsdf, float* weight) {
 }
 
 int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
+  const bool refine = (scope & VM_EXTRACT_REFINE) != 0;
+  scope &= ~VM_EXTRACT_REFINE;
   if (!vol || (scope != VM_SCOPE_DIRTY && scope != VM_SCOPE_ALL)) return VM_ERR_ARG;
   const uint32_t pass = ++vol->pass;
   vol->dl_nv = -1;
@@ -599,7 +612,10 @@ int vm_extract_mesh(vm_volume* vol, int scope, hipStream_t stream) {
     VM_LAUNCH(vol, VM_K_DIRTY, k_dirty, dim3(vol->grid_items), dim3(256), stream, v, pass,
               vol->epoch);
   ++vol->epoch;
-  VM_LAUNCH_W(vol, VM_K_CLASSIFY, k_classify, stream, v, pass, 0);
+  if (refine)
+    VM_LAUNCH_WM(vol, VM_K_CLASSIFY, k_classify, kExtractRefined, stream, v, pass);
+  else
+    VM_LAUNCH_WM(vol, VM_K_CLASSIFY, k_classify, kExtract, stream, v, pass);
   VM_LAUNCH_W(vol, VM_K_VERTICES, k_vertices, stream, v, moved, 1);
   vol->last_refine = false;
   return launched();
@@ -613,7 +629,7 @@ int vm_refine_mesh(vm_volume* vol, hipStream_t stream) {
   vol->dev.frame = vol->frame;
   const VolDev& v = vol->dev;
   prep(vol, VM_OP_REFINE, stream);
-  VM_LAUNCH_W(vol, VM_K_REFINE, k_classify, stream, v, pass, 1);
+  VM_LAUNCH_WM(vol, VM_K_REFINE, k_classify, kRefine, stream, v, pass);
   VM_LAUNCH(vol, VM_K_DIRTY, k_vblock_compact, dim3(vol->grid_items), dim3(256), stream, v);
   // refinement changes types only: the end points that moved are those in
   // blocks fused or imported since the last extraction (normally none)

@@ -605,8 +605,10 @@ __global__ void k_import_copy(VolDev v, const float* __restrict__ tsdf,
                               int32_t* __restrict__ rows);
 __global__ void k_dirty(VolDev v, uint32_t pass, uint32_t epoch);
 __global__ void k_dirty_all(VolDev v, uint32_t pass);
-template <int W>
-__global__ void k_classify(VolDev v, uint32_t pass, int refine);
+// classification modes (k_classify's second template argument)
+constexpr int kExtract = 0, kRefine = 1, kExtractRefined = 2;
+template <int W, int mode>
+__global__ void k_classify(VolDev v, uint32_t pass);
 __global__ void k_vblock_compact(VolDev v);
 template <int W>
 __global__ void k_vertices(VolDev v, uint32_t moved, int walk_dirty);

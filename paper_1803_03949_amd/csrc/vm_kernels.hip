@@ -52,7 +52,7 @@ __device__ inline void begin_call(const VolDev& v, bool refine) {
   c->base_upd = sum_upd;
   c->base_freed = sum_freed;
   c->base_chg = sum_chg;
-  if (refine) c->base_ref = sum_ref;
+  c->base_ref = sum_ref;
 }
 
 // One wave: lane s closes vertex pool segment s, the lanes sum the segment
@@ -749,25 +749,48 @@ __global__ __launch_bounds__(256) void k_dirty_all(VolDev v, uint32_t pass) {
   }
 }
 
-// near: bit k set when corner k's |TSDF| < eps (Eq. 5).
-__device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, uint32_t near8) {
-  // Eqs. (3)-(5); regular types in the order the paper lists them.
-  const uint32_t kRegular[6] = {0xCCu, 0x33u, 0x99u, 0x66u, 0xF0u, 0x0Fu};
-  if (__popc(t ^ prev) > 3) return t;
-  int best = -1, best_d = 9;
-  bool keep_prev = false;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    const uint32_t x = t ^ kRegular[j];
-    const int dist = __popc(x);
-    if (dist > 3) continue;
-    // every corner whose sign would flip must be near zero
-    if (x & ~near8) continue;
-    if (kRegular[j] == prev) keep_prev = true;
-    if (dist < best_d) best_d = dist, best = j;
+// Eqs. (3)-(5) in two halves.  The paper lists the regular types as three
+// complementary pairs, 11001100/00110011, 10011001/01100110,
+// 11110000/00001111: a type's distances to the two members of a pair add to
+// 8, so at most one member is within 3.  Per type t, refine_candidates
+// gives those members as corner flips x = t ^ r (bytes 0..2, nearest first,
+// ties in the listed order) and, in the high word, bit 8k + 7 set when byte
+// k holds one and bit 31 set when t is itself a regular type.
+__host__ __device__ inline uint64_t refine_candidates(uint32_t t) {
+  uint32_t xs[3] = {0u, 0u, 0u}, ds[3] = {0u, 0u, 0u};
+  int n = 0;
+  for (int j = 0; j < 3; ++j) {
+    const uint32_t r = j == 0 ? 0xCCu : (j == 1 ? 0x99u : 0xF0u);
+    uint32_t x = t ^ r, d = 0;
+    for (int k = 0; k < 8; ++k) d += (x >> k) & 1u;
+    if (d > 4u) x ^= 0xFFu, d = 8u - d;  // the complementary member
+    if (d > 3u) continue;
+    int i = n++;
+    for (; i > 0 && ds[i - 1] > d; --i) xs[i] = xs[i - 1], ds[i] = ds[i - 1];  // stable
+    xs[i] = x, ds[i] = d;
   }
-  if (best < 0) return t;
-  return keep_prev ? prev : kRegular[best];
+  uint32_t lo = 0, hi = 0;
+  for (int k = 0; k < n; ++k) lo |= xs[k] << (8 * k), hi |= 0x80u << (8 * k);
+  if (n > 0 && ds[0] == 0u) hi |= 0x80000000u;
+  return (uint64_t)hi << 32 | lo;
+}
+
+// The refined type of a valid cube of type t, previous type prev (whether
+// that is a regular type: prev_regular), with near8 bit k set when corner
+// k's |TSDF| < eps (Eq. 5), from t's candidates: prev if it is one whose
+// flipped corners are all near zero, else the first such candidate, else t;
+// t itself when d_H(t, prev) > 3.
+__device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, bool prev_regular, uint32_t near8,
+                                       uint64_t cand) {
+  // evaluated without branches: most lanes of a wave take every path
+  const uint32_t xp = t ^ prev, far = ~near8 & 0xFFu;
+  // bit 8k + 7 of bad: candidate k flips a corner that is not near zero
+  const uint32_t m = (uint32_t)cand & far * 0x010101u;
+  const uint32_t bad = (((m & 0x7F7F7Fu) + 0x7F7F7Fu) | m) & 0x808080u;
+  const uint32_t ok = (uint32_t)(cand >> 32) & 0x808080u & ~bad;
+  const uint32_t first = t ^ (((uint32_t)cand >> (__builtin_ctz(ok | 0x80000000u) & 0x18u)) & 0xFFu);
+  const uint32_t r = prev_regular && !(xp & far) ? prev : (ok ? first : t);
+  return __popc(xp) > 3 ? t : r;
 }
 
 // One wave per dirty block, four blocks per workgroup, no workgroup
@@ -778,8 +801,12 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, uint32_t near8
 // bit each, read from per-block masks that fusion and import keep and
 // staged in the wave's LDS: the sign, whether the corner is observed and,
 // for refinement, whether |TSDF| < eps; the TSDF itself is never read.
-// refine = 0: new cube types from the signs (Sec. V-B), previous type
-// saved.  refine = 1: Eqs. (3)-(5) applied to the current types (Sec. V-F).
+// Mode, fixed at compile time so that each keeps only its own code:
+// kExtract: new cube types from the signs (Sec. V-B), previous type saved;
+// kExtractRefined: the same, each new type refined by Eqs. (3)-(5) against
+// the type it replaces before it is written (Sec. V-F applies the regular
+// type before marching cubes); kRefine: Eqs. (3)-(5) applied to the current
+// types (Sec. V-F).
 // Writing a cube's new type replaces its triangles (Sec. V-D): the type
 // names them and the edges they use, and a cube whose type is unchanged
 // keeps them.  The blocks whose vertices must be recomputed: on extraction
@@ -788,18 +815,29 @@ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, uint32_t near8
 // +x/+y/+z faces, appended to a short list; on refinement the owners of the
 // edges of changed cubes (this block and neighbours), claimed once per pass
 // and written as candidates at fixed positions 8i..8i+7 for compaction.
-template <int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(VolDev v, uint32_t pass, int refine) {
+template <int W, int refine>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(VolDev v, uint32_t pass) {
   __shared__ uint32_t smk_all[W][3 * 128];  // the eight blocks' masks, in 32-bit halves
   __shared__ uint32_t srow_all[W][2 * 81];  // corner rows: signs | observed << 16, near
   __shared__ int32_t snb_all[W][8];
-  // per cube type: its triangles, and in bit 8 whether it has any
+  // per cube type: its triangles, and in bit 8 whether it has any; for
+  // refinement its regular-type candidates
   __shared__ uint16_t sntri[256];
+  __shared__ uint32_t scand_lo[refine ? 256 : 1], scand_hi[refine ? 256 : 1];
   for (int j = threadIdx.x; j < 256; j += blockDim.x) {
     const uint32_t nt = v.tri_table[j * 16];
     sntri[j] = (uint16_t)(nt | (nt ? 256u : 0u));
+    if (refine) {
+      const uint64_t c = refine_candidates((uint32_t)j);
+      scand_lo[j] = (uint32_t)c;
+      scand_hi[j] = (uint32_t)(c >> 32);
+    }
   }
   __syncthreads();
+  auto refined = [&](uint32_t t, uint32_t prev, uint32_t near8) -> uint32_t {
+    const uint64_t cand = (uint64_t)scand_hi[t] << 32 | scand_lo[t];
+    return refine_type(t, prev, (scand_hi[prev] >> 31) != 0u, near8, cand);
+  };
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t* smk = smk_all[wave];
   uint32_t* srow = srow_all[wave];
@@ -819,7 +857,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
       old[lz] = v.tcur[(size_t)idx * kVox + q + 64 * lz];
-      prev[lz] = refine ? v.tprev[(size_t)idx * kVox + q + 64 * lz] : 0u;
+      prev[lz] = refine == 1 ? v.tprev[(size_t)idx * kVox + q + 64 * lz] : 0u;
     }
     if (q < 8) snb[q] = mynb;
     wave_sync();
@@ -859,7 +897,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       if (refine) nrow[j] = row(2);
     }
     wave_sync();
-    uint32_t flags = 0, nchanged = 0;
+    uint32_t flags = 0, nchanged = 0, nrefined = 0;
     // triangles (bits 0..7) and triangle-carrying cubes (from bit 8) of the
     // changed cubes' new and old types
     uint32_t fnew = 0, fold = 0;
@@ -877,21 +915,26 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       const uint32_t r0 = nrow[ly + 9 * z] >> lx, r1 = nrow[ly + 1 + 9 * z] >> lx;
       return (r0 & 3u) | ((r1 & 2u) << 1) | ((r1 & 1u) << 3);
     };
-    uint32_t f_lo = face(0);
+    uint32_t f_lo = face(0), n_lo = refine ? near_face(0) : 0u;
 #pragma unroll
     for (int lz = 0; lz < 8; ++lz) {
-      const uint32_t f_hi = face(lz + 1);
+      const uint32_t f_hi = face(lz + 1), n_hi = refine ? near_face(lz + 1) : 0u;
       const bool valid = (f_lo & f_hi & 16u) != 0;
       const uint32_t t = valid ? (f_lo & 15u) | ((f_hi & 15u) << 4) : 0u;
+      const uint32_t near8 = n_lo | n_hi << 4;
       f_lo = f_hi;
+      n_lo = n_hi;
       const size_t o = (size_t)idx * kVox + q + 64 * lz;
       uint32_t nt;
-      if (!refine) {
+      if (refine != 1) {
         v.tprev[o] = (uint8_t)old[lz];
         nt = t;
+        if (refine == 2) {
+          if (valid) nt = refined(t, old[lz], near8);
+          nrefined += (uint32_t)__popcll(__ballot(nt != t));
+        }
       } else {
-        nt = valid ? refine_type(old[lz], prev[lz], near_face(lz) | near_face(lz + 1) << 4)
-                   : old[lz];
+        nt = valid ? refined(old[lz], prev[lz], near8) : old[lz];
       }
       if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
       // an unchanged cube keeps its triangles: only changed ones count
@@ -908,10 +951,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       }
     }
     // wave-wide OR of the owner flags
-    uint32_t wflags = refine ? 0u : 1u;
+    uint32_t wflags = refine == 1 ? 0u : 1u;
     for (int b = 0; b < 7; ++b)
       if (__ballot((flags >> b) & 1u)) wflags |= 1u << b;
-    if (!refine) {
+    if (refine != 1) {
       // extraction: the vertex pass walks every dirty block, this one
       // included; a +x/+y/+z neighbour that owns edges of changed cubes and
       // is not dirty itself joins as an extra block, claimed once per pass
@@ -943,13 +986,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     const uint32_t cnew = wave_sum_bits<4>(fnew >> 8), cold = wave_sum_bits<4>(fold >> 8);
     fnew = wave_sum_bits<6>(fnew & 255u);
     fold = wave_sum_bits<6>(fold & 255u);
-    if (q == 0 && nchanged) {
+    if (q == 0 && (nchanged | nrefined)) {
       Seg& cs = v.cseg[idx % v.nseg];
       auto add2 = [](uint32_t* lo, uint32_t a, uint32_t b) {
         atomicAdd(reinterpret_cast<unsigned long long*>(lo),
                   (unsigned long long)a | (unsigned long long)b << 32);
       };
-      add2(&cs.st_chg, nchanged, refine ? nchanged : 0u);
+      add2(&cs.st_chg, nchanged, refine == 1 ? nchanged : nrefined);
       if (cnew | cold) add2(&cs.st_cnew, cnew, cold);
       if (fnew | fold) add2(&cs.st_fnew, fnew, fold);
     }
@@ -1847,9 +1890,13 @@ __global__ void k_lookup(VolDev v, const int32_t* __restrict__ coords, int32_t* 
   }
 }
 
-template __global__ void k_classify<2>(VolDev, uint32_t, int);
-template __global__ void k_classify<4>(VolDev, uint32_t, int);
-template __global__ void k_classify<8>(VolDev, uint32_t, int);
+#define VM_CLASSIFY_MODES(W)                                      \
+  template __global__ void k_classify<W, kExtract>(VolDev, uint32_t); \
+  template __global__ void k_classify<W, kRefine>(VolDev, uint32_t);  \
+  template __global__ void k_classify<W, kExtractRefined>(VolDev, uint32_t);
+VM_CLASSIFY_MODES(2)
+VM_CLASSIFY_MODES(4)
+VM_CLASSIFY_MODES(8)
 template __global__ void k_vertices<2>(VolDev, uint32_t, int);
 template __global__ void k_vertices<4>(VolDev, uint32_t, int);
 template __global__ void k_vertices<8>(VolDev, uint32_t, int);

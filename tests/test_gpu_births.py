@@ -32,9 +32,9 @@ def run(seq, frames, refine):
         depth = seq.frame(k)
         g.integrate(to_dev(depth)[0], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
         o.integrate(depth, scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
-        g.extract()
-        o.extract()
-        if refine:
+        g.extract(refine=refine == "fused")
+        o.extract(refine=refine == "fused")
+        if refine is True:
             g.refine()
             o.refine()
         g.gc()
@@ -56,6 +56,12 @@ def test_room_sequence_births():
 def test_refinement_sequence_births():
     seq = scenes.room_sequence(seed=3, n_frames=500, voxel_m=0.03, holes=True)
     b = run(seq, range(0, 12, 2), refine=True)
+    assert len(np.unique(b)) > 3
+
+
+def test_refining_extraction_births():
+    seq = scenes.room_sequence(seed=3, n_frames=500, voxel_m=0.03, holes=True)
+    b = run(seq, range(0, 12, 2), refine="fused")
     assert len(np.unique(b)) > 3
 
 

@@ -77,6 +77,8 @@ def test_dirty_extraction_after_import_equals_all():
 
 
 def run_sequence(seq, frames, gkw, refine=False, check_every=True):
+    """refine: False, True (a refinement pass after each extraction) or
+    "fused" (extraction with the refinement applied to each new type)."""
     g = new_volume(seq.voxel_m, **gkw)
     o = oracle.OracleVolume(seq.voxel_m, 4.0, 0.5)
     for k in frames:
@@ -89,12 +91,12 @@ def run_sequence(seq, frames, gkw, refine=False, check_every=True):
         assert gf == of, "collected blocks differ"
         if check_every:
             compare_blocks(g, o, types=False)
-        g.extract()
-        o.extract()
+        g.extract(refine=refine == "fused")
+        o.extract(refine=refine == "fused")
         gd = {tuple(x) for x in g.block_list("dirty").tolist()}
         od = {tuple(x) for x in o.block_set("dirty").tolist()}
         assert gd == od, "dirty blocks differ"
-        if refine:
+        if refine is True:
             g.refine()
             o.refine()
         if check_every:
@@ -126,6 +128,44 @@ def test_room_sequence_with_holes_and_refinement():
     g, o = run_sequence(seq, [0, 4, 8, 12], dict(hash_log2=16, max_blocks=1 << 14), refine=True)
     compare_all(g, o)
     assert g.status()["refined_cubes"] >= 0
+
+
+def test_room_sequence_with_holes_and_refining_extraction():
+    seq = scenes.room_sequence(seed=3, n_frames=500, voxel_m=0.03, holes=True)
+    g, o = run_sequence(seq, [0, 4, 8, 12, 16], dict(hash_log2=16, max_blocks=1 << 14), refine="fused")
+    info = compare_all(g, o)
+    assert info["nv"] > 5000 and g.status()["error"] == 0
+
+
+def test_refining_extraction_counts_and_later_refinement_pass():
+    """The refined-cube count of a refining extraction equals the cubes the
+    oracle's separate refinement pass re-types; a refinement pass after it
+    changes nothing on either side (Eqs. 3-5 are idempotent)."""
+    seq = scenes.room_sequence(seed=5, n_frames=500, voxel_m=0.02, holes=True)
+    g = new_volume(seq.voxel_m)
+    o = oracle.OracleVolume(seq.voxel_m, 4.0, 0.5)
+    o2 = oracle.OracleVolume(seq.voxel_m, 4.0, 0.5)
+    total = 0
+    for k in (0, 3, 6):
+        print(f"[parity] refining extraction frame {k}", flush=True)
+        depth = seq.frame(k)
+        g.integrate(to_dev(depth)[0], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        for ov in (o, o2):
+            ov.integrate(depth, scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
+        g.extract(refine=True)
+        o.extract(refine=True)
+        o2.extract()
+        n_ref = o2.refine()
+        assert g.status()["refined_cubes"] == n_ref
+        total += n_ref
+        g.refine()
+        assert o.refine() == 0
+        assert g.status()["refined_cubes"] == 0
+        compare_all(g, o)
+        g.gc()
+        o.gc()
+        o2.gc()
+    assert total > 0
 
 
 def test_collide_hash_mode_gives_same_volume():
