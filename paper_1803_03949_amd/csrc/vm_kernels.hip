@@ -151,6 +151,7 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
   __shared__ unsigned long long sseen[kClaimCap];  // slot contents seen by the claim
   __shared__ uint32_t sslot[kClaimCap];            // slot | pending << 31
   __shared__ unsigned long long skeys_all[8][kWaveKeys];  // each wave's slow-loop keys
+  __shared__ uint8_t sunion_all[8][64];                   // each wave's union, as cells
   __shared__ uint32_t nclaim;
   __shared__ uint32_t swave[8];
   __shared__ uint32_t sbase[3];
@@ -266,14 +267,13 @@ __global__ __launch_bounds__(512) void k_collect(VolDev v, FrameParams fp,
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) m |= shfl64(m, q ^ off);
-    // lane k takes the union's k-th block
+    // lane k takes the union's k-th block: lane c, for a cell c in the
+    // union, places it at its rank among the union's cells
     const uint64_t u = ((uint64_t)uniform((uint32_t)(m >> 32)) << 32) | uniform((uint32_t)m);
-    uint64_t rest = u;
-    for (int k = 0; rest != 0ull; ++k) {
-      const int c = __builtin_ctzll(rest);
-      rest &= rest - 1ull;
-      if (q == k) cell = c;
-    }
+    uint8_t* sunion = sunion_all[wave];
+    if ((u >> q) & 1ull) sunion[mask_rank(u)] = (uint8_t)q;
+    wave_sync();
+    if (q < __popcll(u)) cell = sunion[q];
   }
   __syncthreads();  // the claim count is cleared
   if (act)
