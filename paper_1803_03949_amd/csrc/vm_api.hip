@@ -152,6 +152,7 @@ size_t carve(const vm_config& c, char* base, VolDev* v) {
   v->st_frame = (uint32_t*)take(4 * B);
   v->frame_list = (uint32_t*)take(4 * B);
   v->frame_src = (uint32_t*)take(4 * B);
+  v->frame_key = (uint64_t*)take(8 * B);
   v->row_slot = (uint32_t*)take(4 * B);
   v->pending = (uint32_t*)take(4 * B);
   v->dirty = (uint32_t*)take(4 * B);

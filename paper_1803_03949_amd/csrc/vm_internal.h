@@ -176,6 +176,7 @@ struct VolDev {
   uint32_t* st_frame;         // [B] last frame that fused the block
   uint32_t* frame_list;       // [B] pool index | kNewFlag
   uint32_t* frame_src;        // [B] import: source row of each entry
+  uint64_t* frame_key;        // [B] collection: block key of each entry
   uint32_t* row_slot;         // [B] import: hash slot of each source row (kNone if refused)
   uint32_t* pending;          // [B]
   uint32_t* dirty;            // [B]

@@ -137,8 +137,12 @@ __device__ inline void list_claim(const VolDev& v, uint32_t s, unsigned long lon
       entry = kNone;
     }
   }
-  if (fpos < v.max_blocks) v.frame_list[fpos] = entry;
-  else atomicOr(&v.cnt->error, kErrBlocks);
+  if (fpos < v.max_blocks) {
+    v.frame_list[fpos] = entry;
+    v.frame_key[fpos] = seen >> kIdxBits;
+  } else {
+    atomicOr(&v.cnt->error, kErrBlocks);
+  }
   if (pend) {
     if (idx != kNone) v.st_pending[idx] = epoch;
     if (ppos < v.max_blocks) v.pending[ppos] = idx;
@@ -544,16 +548,24 @@ __device__ inline void init_column(const VolDev& v, uint32_t idx, int q) {
 // ============================================================================
 // One wave per collected block, eight voxels per lane (one column of the
 // block), so that many blocks are in flight per CU.  The list entry and
-// block key of the wave's next blocks are requested two and one blocks
-// ahead, so a block waits only for its TSDF, weights and depth samples.
+// block key of the wave's next block are requested one block ahead, so a
+// block waits only for its TSDF, weights and depth samples; with the
+// strided mapping a wave's first item does not depend on the list length,
+// and its entry and key are requested together with it (an entry past the
+// length is ignored).
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
                                                  const float* __restrict__ depth, uint32_t epoch) {
   // the collection's appends: its frame list length, and (one thread) the
   // lengths the later kernels read
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool strided = (v.order & 3u) == 0u;
+  const uint32_t i0 = blockIdx.x * W + (uint32_t)wave;
+  uint32_t e0 = kNone;
+  uint64_t k0 = 0;
+  if (strided && i0 < v.max_blocks) e0 = v.frame_list[i0], k0 = v.frame_key[i0];
   const uint64_t app = v.cnt->collect_acc[fp.frame & 1];
   const uint32_t n = min(collect_frame(app), v.max_blocks);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     v.cnt->acc[VM_TOTAL_FRAME_BLOCKS] += n;
     v.cnt->n_frame[fp.frame & 1] = collect_frame(app);
@@ -562,18 +574,15 @@ __global__ __launch_bounds__(64 * W) void k_fuse(VolDev v, FrameParams fp,
   }
   ItemLoop it = item_loop(v, n, W, wave);
   auto entry = [&](uint32_t i) -> uint32_t { return i < it.end ? v.frame_list[i] : kNone; };
-  auto key_of = [&](uint32_t e) -> uint64_t {
-    return e != kNone ? v.block_key[e & ~kNewFlag] : 0ull;
-  };
-  uint32_t e1 = uniform(entry(it.i));  // this block's entry and key
-  uint64_t k1 = key_of(e1);
-  uint32_t e2 = entry(it.i + it.step);  // the next block's entry
+  auto key_at = [&](uint32_t i) -> uint64_t { return i < it.end ? v.frame_key[i] : 0ull; };
+  // this block's entry and key
+  uint32_t e1 = strided ? (it.i < it.end ? e0 : kNone) : entry(it.i);
+  uint64_t k1 = strided ? k0 : key_at(it.i);
   for (; it.i < it.end; it.i += it.step) {
-    const uint32_t e = e1;
+    const uint32_t e = uniform(e1);
     const uint64_t key = ((uint64_t)uniform((uint32_t)(k1 >> 32)) << 32) | uniform((uint32_t)k1);
-    e1 = uniform(e2);
-    k1 = key_of(e1);
-    e2 = entry(it.i + 2 * it.step);
+    e1 = entry(it.i + it.step);
+    k1 = key_at(it.i + it.step);
     if (e == kNone) continue;
     const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
     const uint32_t idx = e & ~kNewFlag;
@@ -696,12 +705,14 @@ __global__ __launch_bounds__(64 * W) void k_import_copy(VolDev v, const float* _
 // Dirty = pending blocks and their allocated neighbours at offsets {-1,0}^3.
 // Candidates (8 per pending block) are claimed through a per-block pass
 // stamp and compacted tile by tile, one atomic per tile.
-// The first wave also starts the extraction (segments, statistics, next
-// list lengths): nothing else in this kernel touches them.
+// The last workgroup's first wave also starts the extraction (segments,
+// statistics, next list lengths): nothing else in this kernel touches them,
+// and the last workgroup has the fewest candidates (usually none), so the
+// chain of dependent accesses this takes runs beside the claims.
 __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t epoch) {
   __shared__ uint32_t swave[16];
   __shared__ uint32_t sbase;
-  if (blockIdx.x == 0 && threadIdx.x < 64) begin_call(v, false);
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x < 64) begin_call(v, false);
   const uint32_t np = min(v.cnt->n_pending[epoch & 1], v.max_blocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) v.cnt->n_pending[(epoch + 1) & 1] = 0;
   const uint32_t total = np * 8u;
@@ -736,7 +747,7 @@ __global__ __launch_bounds__(256) void k_dirty(VolDev v, uint32_t pass, uint32_t
 }
 
 __global__ __launch_bounds__(256) void k_dirty_all(VolDev v, uint32_t pass) {
-  if (blockIdx.x == 0 && threadIdx.x < 64) begin_call(v, false);
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x < 64) begin_call(v, false);
   const uint32_t n = min(v.cnt->n_blocks, v.max_blocks);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     v.dirty[i] = i;
@@ -824,6 +835,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
   // refinement its regular-type candidates
   __shared__ uint16_t sntri[256];
   __shared__ uint32_t scand_lo[refine ? 256 : 1], scand_hi[refine ? 256 : 1];
+  // with the strided mapping the wave's first block is requested at once,
+  // before the list length (an entry past the length is ignored)
+  const bool strided = (v.order & 3u) == 0u;
+  const uint32_t i0 = blockIdx.x * W + (threadIdx.x >> 6);
+  const uint32_t d0 = strided && i0 < v.max_blocks ? v.dirty[i0] : kNone;
   for (int j = threadIdx.x; j < 256; j += blockDim.x) {
     const uint32_t nt = v.tri_table[j * 16];
     sntri[j] = (uint16_t)(nt | (nt ? 256u : 0u));
@@ -849,7 +865,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
     // lane addressing is formed again per block (fewer registers)
     const int q = fresh_lane(), lx = q & 7, ly = q >> 3;
     const uint32_t i = it.i;
-    const uint32_t idx = uniform(v.dirty[i]);
+    const uint32_t idx = uniform(strided && i == i0 ? d0 : v.dirty[i]);
     const int32_t mynb = q < 8 ? v.nbr[(size_t)idx * 27 + nbr_dir(q & 1, (q >> 1) & 1, q >> 2)] : -1;
     // the block's own types, independent of the halo: load them now (the
     // previous applied types only for refinement)
