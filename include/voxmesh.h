@@ -93,7 +93,7 @@ typedef struct vm_config {
   int32_t hash_log2;    /* hash table holds 2^hash_log2 slots, 10..28 */
   int32_t max_blocks;   /* block pool capacity, 1 .. 2^21 */
   int32_t max_vertices; /* vertex pool capacity, 1 .. 2^30, split into
-                           n = clamp(max_blocks / 256, 1, 64) segments of
+                           n = clamp(max_blocks / 256, 1, 256) segments of
                            ceil(max_vertices / n) slots (the last one the
                            remainder): the block at pool
                            row b creates its vertices in segment b mod n

@@ -294,7 +294,7 @@ void prof_end(vm_volume* vol, int kid, hipEvent_t a, hipStream_t s) {
   } while (0)
 
 void prep(vm_volume* vol, int op, hipStream_t s) {
-  VM_LAUNCH(vol, VM_K_COUNTERS, k_prep, dim3(1), dim3(kSegs), s, vol->dev, op, 0u);
+  VM_LAUNCH(vol, VM_K_COUNTERS, k_prep, dim3(1), dim3(64), s, vol->dev, op, 0u);
 }
 
 // Host copy of the counters and both segment tables.

@@ -49,7 +49,7 @@ constexpr int kKeyBias = 8192;               // block coords in [-8192, 8191]
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kNewFlag = 0x80000000u;   // frame-list entry: block is new
 constexpr int kMaxBlocks = 1 << 21;
-constexpr int kSegs = 64;                    // pool segments
+constexpr int kSegs = 256;                   // pool segments
 constexpr int kTile = 256;                   // list items per compaction workgroup (256 lanes)
 constexpr int kTilePer = kTile / 256;        // items per lane
 // bits that hold a count in [0, n]

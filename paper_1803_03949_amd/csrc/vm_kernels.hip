@@ -31,20 +31,51 @@ __device__ inline void finalise_seg(Seg& g, uint32_t size) {
   g.push = 0;
 }
 
+// Segment statistics summed over all segments (running counts, modulo 2^32).
+struct SegSums {
+  uint32_t nw, upd, freed, mov, chg, ref, fnew, fold;
+};
+
+// One full wave closes every vertex pool segment (lane q takes segments q,
+// q + 64, ...: slots freed by earlier passes become available) and sums the
+// segment statistics; every lane receives the sums.
+__device__ inline SegSums close_segments(const VolDev& v) {
+  static_assert(kSegs % 64 == 0, "whole waves of segments");
+  constexpr int kPer = kSegs / 64;
+  SegSums r{0, 0, 0, 0, 0, 0, 0, 0};
+  // every lane's segments are read before any is written back
+  Seg g[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int s = __lane_id() + 64 * j;
+    g[j] = v.vseg[s];
+    const Seg& cs = v.cseg[s];
+    r.chg += cs.st_chg, r.ref += cs.st_ref, r.fnew += cs.st_fnew, r.fold += cs.st_fold;
+  }
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int s = __lane_id() + 64 * j;
+    r.nw += g[j].st_new, r.upd += g[j].st_upd, r.freed += g[j].st_freed, r.mov += g[j].st_mov;
+    finalise_seg(g[j], seg_size(s, v.vseg_cap, v.max_vertices));
+    Seg& vs = v.vseg[s];
+    vs.hwm = g[j].hwm, vs.head = g[j].head, vs.count = g[j].count;
+    vs.ticket = 0, vs.push = 0;
+  }
+  r.nw = wave_sum(r.nw), r.upd = wave_sum(r.upd), r.freed = wave_sum(r.freed);
+  r.mov = wave_sum(r.mov), r.chg = wave_sum(r.chg), r.ref = wave_sum(r.ref);
+  r.fnew = wave_sum(r.fnew), r.fold = wave_sum(r.fold);
+  return r;
+}
+
 // Start of an extraction (refine = false) or refinement, done by one full
-// wave while nothing else touches the segments: lane s closes vertex pool
-// segment s (slots freed by earlier passes become available), the lanes sum
-// the segment statistics the call reports per call, and lane 0 records them
-// and clears the list lengths of the next call.
+// wave while nothing else touches the segments: the segments are closed,
+// and lane 0 records the statistics the call reports per call and clears
+// the list lengths of the next call.
 __device__ inline void begin_call(const VolDev& v, bool refine) {
-  const int s = __lane_id();
-  Seg& vs = v.vseg[s];
-  Seg& cs = v.cseg[s];
-  finalise_seg(vs, seg_size(s, v.vseg_cap, v.max_vertices));
-  const uint32_t sum_new = wave_sum(vs.st_new), sum_upd = wave_sum(vs.st_upd);
-  const uint32_t sum_freed = wave_sum(vs.st_freed);
-  const uint32_t sum_chg = wave_sum(cs.st_chg), sum_ref = wave_sum(cs.st_ref);
-  if (s != 0) return;
+  const SegSums m = close_segments(v);
+  const uint32_t sum_new = m.nw, sum_upd = m.upd, sum_freed = m.freed, sum_chg = m.chg,
+                 sum_ref = m.ref;
+  if (__lane_id() != 0) return;
   Counters* c = v.cnt;
   if (!refine) c->n_dirty[v.xsel ^ 1u] = 0;
   c->n_vblocks[v.vsel ^ 1u] = 0;
@@ -55,34 +86,26 @@ __device__ inline void begin_call(const VolDev& v, bool refine) {
   c->base_ref = sum_ref;
 }
 
-// One wave: lane s closes vertex pool segment s, the lanes sum the segment
-// statistics, then lane 0 does the operation's resets and snapshots.
+// One wave: the segments are closed and their statistics summed, then lane
+// 0 does the operation's resets and snapshots.
 __global__ __launch_bounds__(64) void k_prep(VolDev v, int op, uint32_t arg) {
   if (op == VM_OP_REFINE) {
     begin_call(v, true);
     return;
   }
-  const int s = threadIdx.x;
-  Seg& vs = v.vseg[s];
-  Seg& cs = v.cseg[s];
-  finalise_seg(vs, seg_size(s, v.vseg_cap, v.max_vertices));
-  const uint32_t sum_new = wave_sum(vs.st_new), sum_upd = wave_sum(vs.st_upd);
-  const uint32_t sum_freed = wave_sum(vs.st_freed);
-  const uint32_t sum_chg = wave_sum(cs.st_chg), sum_ref = wave_sum(cs.st_ref);
-  const uint32_t sum_fnew = wave_sum(cs.st_fnew), sum_fold = wave_sum(cs.st_fold);
-  const uint32_t sum_mov = wave_sum(vs.st_mov);
-  if (s != 0) return;
+  const SegSums m = close_segments(v);
+  if (threadIdx.x != 0) return;
   Counters* c = v.cnt;
   switch (op) {
     case VM_OP_RESET:
-      c->acc[VM_TOTAL_NEW_TRIANGLES] += sum_fnew;
-      c->acc[VM_TOTAL_DROPPED_TRIANGLES] += sum_fold;
-      c->acc[VM_TOTAL_NEW_VERTICES] += sum_new;
-      c->acc[VM_TOTAL_UPDATED_VERTICES] += sum_upd;
-      c->acc[VM_TOTAL_MOVED_VERTICES] += sum_mov;
-      c->acc[VM_TOTAL_FREED_VERTICES] += sum_freed;
-      c->acc[VM_TOTAL_CHANGED_CUBES] += sum_chg;
-      c->acc[VM_TOTAL_REFINED_CUBES] += sum_ref;
+      c->acc[VM_TOTAL_NEW_TRIANGLES] += m.fnew;
+      c->acc[VM_TOTAL_DROPPED_TRIANGLES] += m.fold;
+      c->acc[VM_TOTAL_NEW_VERTICES] += m.nw;
+      c->acc[VM_TOTAL_UPDATED_VERTICES] += m.upd;
+      c->acc[VM_TOTAL_MOVED_VERTICES] += m.mov;
+      c->acc[VM_TOTAL_FREED_VERTICES] += m.freed;
+      c->acc[VM_TOTAL_CHANGED_CUBES] += m.chg;
+      c->acc[VM_TOTAL_REFINED_CUBES] += m.ref;
       break;
     default:
       break;
