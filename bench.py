@@ -7,8 +7,9 @@ volume that starts empty.  The reported value is fused frames per second
 over the timed steps, with every depth frame already resident in HBM.
 
 Prints one JSON line.  Beside the headline value it reports:
-  - the roofline of the dominant kernel, timed with HIP events around that
-    kernel's launches inside the timed region, on the bytes the method must
+  - the roofline of the dominant kernel, timed with HIP events that its
+    launches inside the timed region record at their start and end (the
+    launch records them itself: hipExtLaunchKernel), on the bytes the method must
     move per unit of work (`algorithmic_bytes`), with the bytes the kernel
     itself reads and writes beside them;
   - the whole frame (fusion + extraction + garbage collection) against the

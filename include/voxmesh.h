@@ -519,14 +519,14 @@ int vm_export_block_list(vm_volume* vol, int which, int32_t* coords,
 int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream);
 
 /* Kernel timing for benchmarks.  While enabled, each kernel launch of the
- * volume is bracketed by two HIP events recorded on its stream (events are
- * created by the library on first use and reused).  vm_profile(vol, 1)
- * clears previous records; vm_profile_read synchronises the recorded
- * events and writes, per VM_K_* kernel, the launch count and the summed
- * event-to-event milliseconds (arrays of VM_K_COUNT entries, host).
- * vm_profile_mask records only the kernels whose bit (1 << VM_K_*) is set
- * in mask (0 stops recording), so that timing one kernel adds events
- * around that kernel alone. */
+ * volume records its start and end in two HIP events on its stream, set by
+ * the launch itself (hipExtLaunchKernel; events are created by the library
+ * on first use and reused).  vm_profile(vol, 1) clears previous records;
+ * vm_profile_read synchronises the recorded events and writes, per VM_K_*
+ * kernel, the launch count and the summed start-to-end milliseconds
+ * (arrays of VM_K_COUNT entries, host).  vm_profile_mask records only the
+ * kernels whose bit (1 << VM_K_*) is set in mask (0 stops recording), so
+ * that timing one kernel touches that kernel's launches alone. */
 int vm_profile(vm_volume* vol, int enable);
 int vm_profile_mask(vm_volume* vol, uint32_t mask);
 int vm_profile_read(vm_volume* vol, int64_t* launches, double* ms);

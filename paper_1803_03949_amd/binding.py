@@ -378,8 +378,9 @@ class Volume:
         return dict(zip(TOTALS, (int(x) for x in out)))
 
     def profile(self, enable: bool, kernels=None):
-        """Bracket kernel launches with events: all kernels, or only those
-        named in `kernels` (names as in KERNELS)."""
+        """Time kernel launches (each launch records its start and end in two
+        events): all kernels, or only those named in `kernels` (names as in
+        KERNELS)."""
         if kernels is None or not enable:
             _check(lib().vm_profile(self.h, 1 if enable else 0), "vm_profile")
         else:

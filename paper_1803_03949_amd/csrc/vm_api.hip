@@ -5,8 +5,12 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <hip/hip_ext.h>
+
 #include <mutex>
 #include <new>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "voxmesh.h"
@@ -234,41 +238,58 @@ int error_code(uint32_t bits) {
   return VM_OK;
 }
 
-hipEvent_t prof_event(vm_volume* vol, hipStream_t s) {
-  hipEvent_t e = nullptr;
-  if (!vol->ev_free.empty()) {
-    e = vol->ev_free.back();
-    vol->ev_free.pop_back();
-  } else if (hipEventCreate(&e) != hipSuccess) {
-    return nullptr;
+// Two events for timing a launch of kernel kid while it is profiled.
+bool prof_pair(vm_volume* vol, int kid, hipEvent_t* a, hipEvent_t* b) {
+  if (!((vol->prof >> kid) & 1u)) return false;
+  hipEvent_t e[2] = {nullptr, nullptr};
+  for (hipEvent_t& x : e) {
+    if (!vol->ev_free.empty()) {
+      x = vol->ev_free.back();
+      vol->ev_free.pop_back();
+    } else if (hipEventCreate(&x) != hipSuccess) {
+      x = nullptr;
+    }
   }
-  if (hipEventRecord(e, s) != hipSuccess) {
-    vol->ev_free.push_back(e);
-    return nullptr;
+  if (!e[0] || !e[1]) {
+    for (hipEvent_t x : e)
+      if (x) vol->ev_free.push_back(x);
+    return false;
   }
-  return e;
+  *a = e[0], *b = e[1];
+  return true;
 }
 
-hipEvent_t prof_begin(vm_volume* vol, int kid, hipStream_t s) {
-  return (vol->prof >> kid) & 1u ? prof_event(vol, s) : nullptr;
+// A launch whose start and end the launch itself records in two events
+// (hipExtLaunchKernel): no marker packets between kernels, and the time is
+// the kernel's own.  The arguments are converted to the kernel's parameter
+// types first.
+template <typename... P, typename... A, size_t... I>
+hipError_t launch_timed_at(void (*k)(P...), dim3 g, dim3 b, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1, std::index_sequence<I...>, A&&... a) {
+  std::tuple<P...> t(std::forward<A>(a)...);
+  void* args[] = {(void*)&std::get<I>(t)...};
+  return hipExtLaunchKernel((const void*)k, g, b, args, 0, s, e0, e1, 0);
+}
+template <typename... P, typename... A>
+hipError_t launch_timed(void (*k)(P...), dim3 g, dim3 b, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1, A&&... a) {
+  return launch_timed_at(k, g, b, s, e0, e1, std::index_sequence_for<P...>{},
+                         std::forward<A>(a)...);
 }
 
-void prof_end(vm_volume* vol, int kid, hipEvent_t a, hipStream_t s) {
-  if (!a) return;
-  hipEvent_t b = prof_event(vol, s);
-  if (!b) {
-    vol->ev_free.push_back(a);
-    return;
-  }
-  vol->recs.push_back({kid, a, b});
-}
-
-// Launch a kernel, bracketed by timing events while profiling is enabled.
-#define VM_LAUNCH(vol, kid, kernel, grid, block, stream, ...)       \
-  do {                                                              \
-    hipEvent_t vm_ev_ = prof_begin((vol), (kid), (stream));         \
-    hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__); \
-    prof_end((vol), (kid), vm_ev_, (stream));                       \
+// Launch a kernel; while it is profiled, the launch records its start and
+// end.
+#define VM_LAUNCH(vol, kid, kernel, grid, block, stream, ...)                                \
+  do {                                                                                     \
+    hipEvent_t vm_a_ = nullptr, vm_b_ = nullptr;                                           \
+    if (prof_pair((vol), (kid), &vm_a_, &vm_b_)) {                                         \
+      if (launch_timed(kernel, grid, block, stream, vm_a_, vm_b_, __VA_ARGS__) == hipSuccess) \
+        (vol)->recs.push_back({(kid), vm_a_, vm_b_});                                      \
+      else                                                                                 \
+        (vol)->ev_free.push_back(vm_a_), (vol)->ev_free.push_back(vm_b_);                  \
+    } else {                                                                               \
+      hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                     \
+    }                                                                                      \
   } while (0)
 
 // Launch a wave-per-block kernel instantiated for the volume's group size.
