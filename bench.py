@@ -44,10 +44,10 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 1522.5, "write_kib": 1560.9, "source_sha1": "cb2f335e2101"},
-    "fuse": {"fetch_kib": 11709.3, "write_kib": 13602.1, "source_sha1": "2175dd92f78f"},
-    "classify": {"fetch_kib": 3504.4, "write_kib": 3249.7, "source_sha1": "5333a45c165a"},
-    "vertices": {"fetch_kib": 8487.4, "write_kib": 8703.6, "source_sha1": "126c89769ee0"},
+    "collect": {"fetch_kib": 1525.7, "write_kib": 1605.9, "source_sha1": "ae25bb272f48"},
+    "fuse": {"fetch_kib": 12000.4, "write_kib": 13602.2, "source_sha1": "2f4eb3ca2b89"},
+    "classify": {"fetch_kib": 3631.4, "write_kib": 3249.7, "source_sha1": "416fecc21883"},
+    "vertices": {"fetch_kib": 8573.4, "write_kib": 8502.1, "source_sha1": "126c89769ee0"},
 }
 
 
@@ -184,7 +184,7 @@ def room_fusion(args, dev):
     torch.cuda.synchronize()
     npix = depth.shape[1] * depth.shape[2]
 
-    # profiling pass: every kernel bracketed by events, to find the dominant one
+    # profiling pass: every kernel timed, to find the dominant one
     tot0 = vol.totals()
     vol.profile(True)
     for _ in range(args.steps):
@@ -459,7 +459,7 @@ def fine_pass(args, seq, depth, poses, dev, fused):
     dt = time.perf_counter() - t0
     tot = {k: v - tot0[k] for k, v in vol.totals().items()}
     st = vol.status()
-    # one more pass with every kernel bracketed by events: per-kernel rates
+    # one more pass with every kernel timed: per-kernel rates
     # against algorithmic bytes
     vol.profile(True)
     step()
