@@ -1,8 +1,9 @@
 """Full-size parity: the workloads at the sizes and launch configuration the
 benchmark times.  The 8 mm sequence is replayed by the whole oracle and the
-final states are compared in full; the 4 mm sequence with refinement is
-checked on 50 sampled neighbourhoods the oracle computes alone, plus
-properties that hold at any size.
+final states are compared in full; the 4 mm sequence with refinement (as a
+pass after each extraction, and inside it) is checked on 50 sampled
+neighbourhoods the oracle computes alone, plus properties that hold at any
+size.
 
 Sampling: collection and fusion of a block depend only on the depth frames
 and on the block itself, and the mesh inside a block (cube types and their
@@ -78,29 +79,39 @@ def test_room_sequence_8mm_full_size():
     assert info["nv"] > 10 ** 6
 
 
-def test_room_sequence_4mm_refine_full_size():
-    """500 frames, 4 mm, holes, refinement after every extraction, 2^22 hash
-    slots, the benchmark's volume configuration."""
+_FRAMES_4MM = {}
+
+
+@pytest.mark.parametrize("mode", ["pass", "inside"])
+def test_room_sequence_4mm_refine_full_size(mode):
+    """500 frames, 4 mm, holes, refinement at every extraction (a refinement
+    pass after it, or inside it: VM_EXTRACT_REFINE), 2^22 hash slots, the
+    benchmark's volume configuration."""
     seq = scenes.room_sequence(seed=3, n_frames=500, voxel_m=0.004, holes=True)
-    frames = render(seq, 500)
-    print("[full] room 4 mm + refine: GPU", flush=True)
+    if "frames" not in _FRAMES_4MM:
+        _FRAMES_4MM["frames"] = render(seq, 500)
+    frames = _FRAMES_4MM["frames"]
+    inside = mode == "inside"
+    print(f"[full] room 4 mm + refine ({mode}): GPU", flush=True)
     g = Volume(0.004, hash_log2=22, max_blocks=1 << 19, max_vertices=1 << 24)
     depth = to_dev(np.stack(frames))[0]
     for k in range(500):
         g.integrate(depth[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
-        g.extract()
-        g.refine()
+        g.extract(refine=inside)
+        if not inside:
+            g.refine()
         g.gc()
     state = gpu_state(g)
     check_invariants(state)
     assert g.totals()["refined_cubes"] > 0
     samples = sample_blocks(state[1], np.random.default_rng(22), 40, 10)
-    print(f"[full] room 4 mm: oracle on {len(samples)} sampled neighbourhoods", flush=True)
+    print(f"[full] room 4 mm ({mode}): oracle on {len(samples)} sampled neighbourhoods", flush=True)
     o = oracle.OracleVolume(0.004, threads=min(16, os.cpu_count() or 1), keep_fusion=False)
     o.restrict(neighbourhood(samples.tolist()))
     for k in range(500):
         o.integrate(frames[k], scenes.K, seq.poses[k], seq.min_depth, seq.max_depth)
-        o.extract()
-        o.refine()
+        o.extract(refine=inside)
+        if not inside:
+            o.refine()
         o.gc()
     check_samples(state, o, samples)
