@@ -89,8 +89,8 @@ def render_frames(seq, ks, workers):
 
 def algorithmic_bytes(tot, npix, refine=False):
     """Bytes the method must move for the work in `tot` (differences of the
-    device's running totals), per kernel and per step, after the survey's
-    per-unit figures: fusion 4*W*H per frame (the depth image, charged to
+    device's running totals), per kernel and per step, from per-unit
+    figures: fusion 4*W*H per frame (the depth image, charged to
     collection, which reads it first) + 8192 per collected block (TSDF and
     weight read and written); extraction 4096 per dirty block (TSDF and
     weight) + 1024 (t_{i-1} and t_i read and written), 20 per new or updated
@@ -553,8 +553,8 @@ def batch_workload(dev):
 
 
 def batch_step_bytes(tot):
-    """Bytes the batched forward + backward must move per step, after the
-    survey's per-unit figures: the extraction of every block (as for a
+    """Bytes the batched forward + backward must move per step, from
+    per-unit figures: the extraction of every block (as for a
     frame) and the backward, 12 per vertex (dL/dv) + 4096 per block (TSDF
     and edge reads) + 2048 per block (dL/dTSDF written)."""
     f_new, f_drop = tot["new_triangles"], tot["dropped_triangles"]
@@ -660,7 +660,7 @@ def cpu_model() -> str:
 def cpu_baseline(frames, seq, budget_s=20.0, single_budget_s=12.0):
     """The oracle on the host cores over the headline sequence from its first
     frame, integrate + extract + gc per frame, until a time budget is spent:
-    threads over blocks on every core the box gives (at most 16), then a
+    threads over blocks on every core the host gives (at most 16), then a
     single thread.  The oracle's results do not depend on its thread
     count."""
     import oracle
