@@ -968,12 +968,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(8))) voi
       if (refine != 1) {
         v.tprev[o] = (uint8_t)old[lz];
         nt = t;
-        if (refine == 2) {
+        // types 0 and 255 are at distance 4 from every regular type, so a
+        // layer with no other type has nothing to refine
+        if (refine == 2 && __ballot(valid && t - 1u < 254u)) {
           if (valid) nt = refined(t, old[lz], near8);
           nrefined += (uint32_t)__popcll(__ballot(nt != t));
         }
       } else {
-        nt = valid ? refined(old[lz], prev[lz], near8) : old[lz];
+        nt = old[lz];
+        if (__ballot(valid && old[lz] - 1u < 254u) && valid) nt = refined(old[lz], prev[lz], near8);
       }
       if (nt != old[lz]) v.tcur[o] = (uint8_t)nt;
       // an unchanged cube keeps its triangles: only changed ones count
