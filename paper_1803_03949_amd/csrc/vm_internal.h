@@ -50,7 +50,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kNewFlag = 0x80000000u;   // frame-list entry: block is new
 constexpr int kMaxBlocks = 1 << 21;
 constexpr int kSegs = 256;                   // pool segments
-constexpr int kTile = 256;                   // list items per compaction workgroup (256 lanes)
+constexpr int kTile = 512;                   // list items per compaction workgroup (256 lanes)
 constexpr int kTilePer = kTile / 256;        // items per lane
 // bits that hold a count in [0, n]
 constexpr int count_bits(int n) { return n < 2 ? 1 : (n < 4 ? 2 : (n < 8 ? 3 : 4)); }
