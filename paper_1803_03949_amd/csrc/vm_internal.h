@@ -13,8 +13,8 @@
 //             per owned edge (three per voxel): vertex slot i32 and the
 //             vertex's t f32; which owned edges hold a vertex, one 32-bit
 //             word per column of voxels (u32[64]); observed-voxel
-//             (weight > 0) and negative-TSDF bitmasks u64[8] each; pass
-//             stamps.  Reference counts are not stored: a cube's type
+//             (weight > 0), negative-TSDF and near-zero (|TSDF| < eps)
+//             bitmasks u64[8] each; pass stamps.  Reference counts are not stored: a cube's type
 //             fixes how many of its triangles use each of its edges, so an
 //             edge's count is formed from the four cubes around it.
 //   vertices  per pool slot: owner edge (index into the edge arrays, kNone
