@@ -44,10 +44,10 @@ HBM_PEAK_GBPS = 8000.0
 # when the counters were taken; a kernel changed since reports no traffic.
 COUNTER_SCALE = {"fetch": 262144 / 131088.1875, "write": 1.0}
 MEASURED_TRAFFIC = {
-    "collect": {"fetch_kib": 1525.2, "write_kib": 1606.9, "source_sha1": "ae25bb272f48"},
-    "fuse": {"fetch_kib": 12004.6, "write_kib": 13602.3, "source_sha1": "2f4eb3ca2b89"},
-    "classify": {"fetch_kib": 3628.9, "write_kib": 3249.7, "source_sha1": "45183c9ad8c4"},
-    "vertices": {"fetch_kib": 8578.9, "write_kib": 8500.6, "source_sha1": "126c89769ee0"},
+    "collect": {"fetch_kib": 1525.4, "write_kib": 1606.5, "source_sha1": "ae25bb272f48"},
+    "fuse": {"fetch_kib": 12003.7, "write_kib": 13602.3, "source_sha1": "2f4eb3ca2b89"},
+    "classify": {"fetch_kib": 3633.4, "write_kib": 3249.7, "source_sha1": "45183c9ad8c4"},
+    "vertices": {"fetch_kib": 8678.7, "write_kib": 8507.0, "source_sha1": "e9287b86bfa5"},
 }
 
 

@@ -1264,6 +1264,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(6))) voi
       if (s >= 0) pool32(v.vowner, (uint32_t)s) = kNone;
     };
     uint32_t nnew = 0, nmov = 0, knew = 0, kfree = 0;
+    // the blocks with the longest write pass finish last and so set the
+    // kernel's end: their waves take issue priority over the others on the
+    // SIMD until their writes are done
+    if (nwork > 128u) __builtin_amdgcn_s_setprio(2);
     for (uint32_t c0 = 0; c0 < nwork; c0 += kWorkCap) {
       // the lane's items of this chunk, at its place in the list
       wave_sync();
@@ -1348,6 +1352,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(6))) voi
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     if (R != has) v.emask[(size_t)idx * 64 + q] = R;
     nnew = wave_sum_bits<5>(nnew);
     nmov = wave_sum_bits<5>(nmov);
