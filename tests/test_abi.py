@@ -162,3 +162,38 @@ def test_noalloc_volume_rejects_sizes_beyond_its_workspace():
     assert L.vm_create_volume_noalloc(ctypes.byref(cfg(voxel_m=0.0)), None, ctypes.byref(h)) == -1
     assert L.vm_create_volume_noalloc(None, None, ctypes.byref(h)) == -1
     assert L.vm_create_volume_noalloc(ctypes.byref(cfg(max_blocks=64)), None, None) == -1
+
+
+CONSTANT_PROBE = r"""
+#include <stdio.h>
+#include "voxmesh.h"
+#define C(x) printf(#x " %d\n", (int)(x));
+int main() {
+  C(VM_SCOPE_DIRTY) C(VM_SCOPE_ALL) C(VM_EXTRACT_REFINE)
+  C(VM_BATCH_FORWARD) C(VM_BATCH_BACKWARD) C(VM_TOTAL_COUNT) C(VM_K_COUNT)
+  C(VM_ERR_ARG) C(VM_ERR_HASH_FULL) C(VM_ERR_BLOCK_POOL_FULL) C(VM_ERR_VERTEX_POOL_FULL)
+  C(VM_ERR_CAPACITY) C(VM_ERR_HIP) C(VM_ERR_RANGE)
+  return 0;
+}
+"""
+
+
+def test_constants_match_the_binding(tmp_path):
+    src = tmp_path / "consts.cpp"
+    src.write_text(CONSTANT_PROBE)
+    exe = tmp_path / "consts"
+    r = subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                        "-I", "/opt/rocm/include", str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = {k: int(v) for k, v in (line.split() for line in subprocess.run(
+        [str(exe)], capture_output=True, text=True).stdout.splitlines())}
+    assert got == {
+        "VM_SCOPE_DIRTY": binding.VM_SCOPE_DIRTY, "VM_SCOPE_ALL": binding.VM_SCOPE_ALL,
+        "VM_EXTRACT_REFINE": binding.VM_EXTRACT_REFINE,
+        "VM_BATCH_FORWARD": binding.VM_BATCH_FORWARD, "VM_BATCH_BACKWARD": binding.VM_BATCH_BACKWARD,
+        "VM_TOTAL_COUNT": len(binding.TOTALS), "VM_K_COUNT": len(binding.KERNELS),
+        **{name: code for code, name in binding.ERRORS.items()},
+    }
+    # the refinement flag is a bit of its own, clear of both scopes
+    assert binding.VM_EXTRACT_REFINE & (binding.VM_SCOPE_DIRTY | binding.VM_SCOPE_ALL) == 0

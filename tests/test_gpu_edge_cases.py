@@ -2,8 +2,8 @@
 an empty volume, a frame without a valid pixel, an import of no blocks, a
 single valid pixel, extraction with nothing new, refinement applied twice,
 a camera at the edge of the representable block range (pixels whose box
-leaves [-8192, 8191] are skipped, reading 4 of the collection band), and
-the triangle pass on a second stream."""
+leaves [-8192, 8191] are skipped, reading 4 of the collection band), the
+triangle pass on a second stream, and the extraction's scope flags."""
 import numpy as np
 import pytest
 import torch
@@ -46,6 +46,23 @@ def test_empty_volume_calls():
     assert len(g.download_normals()) == 0 and len(g.download_births()) == 0
     st = g.status()
     assert st["blocks"] == 0 and st["triangles"] == 0 and st["error"] == 0
+
+
+def test_extraction_scope_flags():
+    """Only VM_SCOPE_DIRTY or VM_SCOPE_ALL, each with or without
+    VM_EXTRACT_REFINE, are accepted; anything else is VM_ERR_ARG and
+    launches nothing."""
+    from paper_1803_03949_amd import binding
+    g, _ = pair()
+    L = binding.lib()
+    stream = torch.cuda.current_stream().cuda_stream
+    err_arg = next(k for k, name in binding.ERRORS.items() if name == "VM_ERR_ARG")
+    for scope in (2, -1, 0x200, binding.VM_EXTRACT_REFINE | 2, binding.VM_EXTRACT_REFINE << 1):
+        assert L.vm_extract_mesh(g.h, scope, stream) == err_arg, scope
+    for scope in (binding.VM_SCOPE_DIRTY, binding.VM_SCOPE_ALL):
+        assert L.vm_extract_mesh(g.h, scope | binding.VM_EXTRACT_REFINE, stream) == 0
+        assert L.vm_extract_mesh(g.h, scope, stream) == 0
+    assert g.status()["error"] == 0
 
 
 def test_frame_without_valid_pixels():
