@@ -579,6 +579,50 @@ __device__ inline FuseSample fuse_sample(const VolDev& v, const FrameParams& fp,
   return fuse_finish(v, fp, p, p.pix >= 0 ? depth[p.pix] : 0.f);
 }
 
+// Eqs. (3)-(5) in two halves.  The paper lists the regular types as three
+// complementary pairs, 11001100/00110011, 10011001/01100110,
+// 11110000/00001111: a type's distances to the two members of a pair add to
+// 8, so at most one member is within 3.  Per type t, refine_candidates
+// gives those members as corner flips x = t ^ r (bytes 0..2, nearest first,
+// ties in the listed order) and, in the high word, bit 8k + 7 set when byte
+// k holds one and bit 31 set when t is itself a regular type.
+__host__ __device__ inline uint64_t refine_candidates(uint32_t t) {
+  uint32_t xs[3] = {0u, 0u, 0u}, ds[3] = {0u, 0u, 0u};
+  int n = 0;
+  for (int j = 0; j < 3; ++j) {
+    const uint32_t r = j == 0 ? 0xCCu : (j == 1 ? 0x99u : 0xF0u);
+    uint32_t x = t ^ r, d = 0;
+    for (int k = 0; k < 8; ++k) d += (x >> k) & 1u;
+    if (d > 4u) x ^= 0xFFu, d = 8u - d;  // the complementary member
+    if (d > 3u) continue;
+    int i = n++;
+    for (; i > 0 && ds[i - 1] > d; --i) xs[i] = xs[i - 1], ds[i] = ds[i - 1];  // stable
+    xs[i] = x, ds[i] = d;
+  }
+  uint32_t lo = 0, hi = 0;
+  for (int k = 0; k < n; ++k) lo |= xs[k] << (8 * k), hi |= 0x80u << (8 * k);
+  if (n > 0 && ds[0] == 0u) hi |= 0x80000000u;
+  return (uint64_t)hi << 32 | lo;
+}
+
+// The refined type of a valid cube of type t, previous type prev (whether
+// that is a regular type: prev_regular), with near8 bit k set when corner
+// k's |TSDF| < eps (Eq. 5), from t's candidates: prev if it is one whose
+// flipped corners are all near zero, else the first such candidate, else t;
+// t itself when d_H(t, prev) > 3.
+__host__ __device__ inline uint32_t refine_type(uint32_t t, uint32_t prev, bool prev_regular,
+                                                uint32_t near8, uint64_t cand) {
+  // evaluated without branches: most lanes of a wave take every path
+  const uint32_t xp = t ^ prev, far = ~near8 & 0xFFu;
+  // bit 8k + 7 of bad: candidate k flips a corner that is not near zero
+  const uint32_t m = (uint32_t)cand & far * 0x010101u;
+  const uint32_t bad = (((m & 0x7F7F7Fu) + 0x7F7F7Fu) | m) & 0x808080u;
+  const uint32_t ok = (uint32_t)(cand >> 32) & 0x808080u & ~bad;
+  const uint32_t first = t ^ (((uint32_t)cand >> (__builtin_ctz(ok | 0x80000000u) & 0x18u)) & 0xFFu);
+  const uint32_t r = prev_regular && !(xp & far) ? prev : (ok ? first : t);
+  return __builtin_popcount(xp) > 3 ? t : r;
+}
+
 __device__ inline float edge_param(float da, float db) {
   if (da == db) return 0.5f;
   return da / (da - db);
