@@ -526,7 +526,8 @@ int vm_get_totals(vm_volume* vol, int64_t* out, int n, hipStream_t stream);
  * kernel, the launch count and the summed start-to-end milliseconds
  * (arrays of VM_K_COUNT entries, host).  vm_profile_mask records only the
  * kernels whose bit (1 << VM_K_*) is set in mask (0 stops recording), so
- * that timing one kernel touches that kernel's launches alone. */
+ * that timing one kernel touches that kernel's launches alone.  Launches on
+ * a stream under graph capture are not timed. */
 int vm_profile(vm_volume* vol, int enable);
 int vm_profile_mask(vm_volume* vol, uint32_t mask);
 int vm_profile_read(vm_volume* vol, int64_t* launches, double* ms);

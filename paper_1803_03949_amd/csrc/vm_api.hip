@@ -238,9 +238,14 @@ int error_code(uint32_t bits) {
   return VM_OK;
 }
 
-// Two events for timing a launch of kernel kid while it is profiled.
-bool prof_pair(vm_volume* vol, int kid, hipEvent_t* a, hipEvent_t* b) {
+// Two events for timing a launch of kernel kid while it is profiled (not
+// on a stream under capture: such launches run untimed).
+bool prof_pair(vm_volume* vol, int kid, hipStream_t s, hipEvent_t* a, hipEvent_t* b) {
   if (!((vol->prof >> kid) & 1u)) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s != nullptr && (hipStreamIsCapturing(s, &cs) != hipSuccess ||
+                       cs != hipStreamCaptureStatusNone))
+    return false;
   hipEvent_t e[2] = {nullptr, nullptr};
   for (hipEvent_t& x : e) {
     if (!vol->ev_free.empty()) {
@@ -278,18 +283,22 @@ hipError_t launch_timed(void (*k)(P...), dim3 g, dim3 b, hipStream_t s, hipEvent
 }
 
 // Launch a kernel; while it is profiled, the launch records its start and
-// end.
+// end (a timed launch that fails is made again untimed, so that timing
+// never drops a kernel).
 #define VM_LAUNCH(vol, kid, kernel, grid, block, stream, ...)                                \
   do {                                                                                     \
     hipEvent_t vm_a_ = nullptr, vm_b_ = nullptr;                                           \
-    if (prof_pair((vol), (kid), &vm_a_, &vm_b_)) {                                         \
-      if (launch_timed(kernel, grid, block, stream, vm_a_, vm_b_, __VA_ARGS__) == hipSuccess) \
+    bool vm_done_ = false;                                                                 \
+    if (prof_pair((vol), (kid), (stream), &vm_a_, &vm_b_)) {                               \
+      if (launch_timed(kernel, grid, block, stream, vm_a_, vm_b_, __VA_ARGS__) == hipSuccess) { \
         (vol)->recs.push_back({(kid), vm_a_, vm_b_});                                      \
-      else                                                                                 \
+        vm_done_ = true;                                                                   \
+      } else {                                                                             \
         (vol)->ev_free.push_back(vm_a_), (vol)->ev_free.push_back(vm_b_);                  \
-    } else {                                                                               \
-      hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                     \
+        (void)hipGetLastError();                                                           \
+      }                                                                                    \
     }                                                                                      \
+    if (!vm_done_) hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);        \
   } while (0)
 
 // Launch a wave-per-block kernel instantiated for the volume's group size.
